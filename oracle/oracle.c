@@ -1,0 +1,270 @@
+/*
+ * oracle.c -- plain FP64 CPU reference for the Jacobi-PCG hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg use it. It shares no code with the HIP library.
+ *
+ * What it computes (the paper's Sec. VII: PCG for a 3D seven-point
+ * finite-difference operator with zero Dirichlet boundaries, applied
+ * matrix-free, with a Jacobi preconditioner):
+ *   - the constant-coefficient operator (Ax)_p = 6 x_p - sum of the six
+ *     face neighbours, neighbours outside the grid read as 0 (Sec. VI and
+ *     Sec. VII; weights 6/-1 with no h^2 scaling);
+ *   - the variable-coefficient operator (A_k u)_p = sum_f k_f (u_p - u_nb),
+ *     k_f the harmonic mean of the two cell values, k_f = k_p on a boundary
+ *     face, u = 0 outside, and its diagonal D_p = sum_f k_f;
+ *   - axpy, dot (Sec. IV, Sec. V: element-wise update and global sum);
+ *   - Jacobi-preconditioned CG in the Hestenes-Stiefel form (Saad,
+ *     Iterative Methods for Sparse Linear Systems, 2nd ed., Alg. 9.1),
+ *     stopping on the recursive residual relative to ||b||.
+ *
+ * Arrays are C-order [nz][ny][nx], x contiguous. All arithmetic is FP64.
+ * Reductions use a fixed order (contiguous chunks summed left to right, chunk
+ * sums added in index order), so results do not depend on the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_NOCONV 3
+#define ORACLE_BREAKDOWN 4
+#define ORACLE_NOMEM 5
+
+#define CHUNK 65536
+
+static inline double nb_val(const double *x, int nx, int ny, int nz, int i, int j, int k)
+{
+    if (i < 0 || i >= nx || j < 0 || j >= ny || k < 0 || k >= nz)
+        return 0.0;
+    return x[((int64_t)k * ny + j) * nx + i];
+}
+
+/* y = A x, constant coefficients: diagonal 6, six face neighbours -1. */
+void oracle_stencil(int nx, int ny, int nz, const double *x, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double s = 6.0 * x[((int64_t)k * ny + j) * nx + i];
+                s -= nb_val(x, nx, ny, nz, i - 1, j, k);
+                s -= nb_val(x, nx, ny, nz, i + 1, j, k);
+                s -= nb_val(x, nx, ny, nz, i, j - 1, k);
+                s -= nb_val(x, nx, ny, nz, i, j + 1, k);
+                s -= nb_val(x, nx, ny, nz, i, j, k - 1);
+                s -= nb_val(x, nx, ny, nz, i, j, k + 1);
+                y[((int64_t)k * ny + j) * nx + i] = s;
+            }
+}
+
+static const int FACE[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+
+/* Face coefficient between cell p (value kp) and the cell across face f;
+ * returns kp on a boundary face and sets *inside accordingly. */
+static inline double face_k(const double *kc, int nx, int ny, int nz, int i, int j, int k, int f,
+                            int *inside)
+{
+    double kp = kc[((int64_t)k * ny + j) * nx + i];
+    int a = i + FACE[f][0], b = j + FACE[f][1], c = k + FACE[f][2];
+    if (a < 0 || a >= nx || b < 0 || b >= ny || c < 0 || c >= nz) {
+        *inside = 0;
+        return kp;
+    }
+    *inside = 1;
+    double kq = kc[((int64_t)c * ny + b) * nx + a];
+    return 2.0 * kp * kq / (kp + kq);
+}
+
+/* y = A_k u, variable coefficients (harmonic-mean faces, k_f = k_p on the boundary). */
+void oracle_vstencil(int nx, int ny, int nz, const double *kc, const double *u, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double up = u[((int64_t)k * ny + j) * nx + i];
+                double s = 0.0;
+                for (int f = 0; f < 6; ++f) {
+                    int inside;
+                    double kf = face_k(kc, nx, ny, nz, i, j, k, f, &inside);
+                    double un = inside ? nb_val(u, nx, ny, nz, i + FACE[f][0], j + FACE[f][1],
+                                                k + FACE[f][2])
+                                       : 0.0;
+                    s += kf * (up - un);
+                }
+                y[((int64_t)k * ny + j) * nx + i] = s;
+            }
+}
+
+/* d = diag(A_k): the sum of the six face coefficients. */
+void oracle_vdiag(int nx, int ny, int nz, const double *kc, double *d)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double s = 0.0;
+                for (int f = 0; f < 6; ++f) {
+                    int inside;
+                    s += face_k(kc, nx, ny, nz, i, j, k, f, &inside);
+                }
+                d[((int64_t)k * ny + j) * nx + i] = s;
+            }
+}
+
+/* z = a x + y */
+void oracle_axpy(int64_t n, double a, const double *x, const double *y, double *z)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        z[i] = a * x[i] + y[i];
+}
+
+/* sum_i x_i y_i in a fixed order. */
+double oracle_dot(int64_t n, const double *x, const double *y)
+{
+    int64_t nc = (n + CHUNK - 1) / CHUNK;
+    if (nc == 0)
+        return 0.0;
+    double *part = (double *)malloc(sizeof(double) * (size_t)nc);
+    if (!part)
+        return NAN;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        int64_t lo = c * CHUNK, hi = lo + CHUNK < n ? lo + CHUNK : n;
+        double s = 0.0;
+        for (int64_t i = lo; i < hi; ++i)
+            s += x[i] * y[i];
+        part[c] = s;
+    }
+    double s = 0.0;
+    for (int64_t c = 0; c < nc; ++c)
+        s += part[c];
+    free(part);
+    return s;
+}
+
+static void apply_op(int nx, int ny, int nz, const double *kc, const double *x, double *y)
+{
+    if (kc)
+        oracle_vstencil(nx, ny, nz, kc, x, y);
+    else
+        oracle_stencil(nx, ny, nz, x, y);
+}
+
+/*
+ * Jacobi-PCG (Saad Alg. 9.1 with M = D):
+ *   r = b - A x0; if ||b|| = 0 then x = 0 and stop;
+ *   z = D^-1 r; p = z; rho = r.z
+ *   for k = 1..maxit:
+ *     q = A p; sigma = p.q; breakdown if sigma <= 0 or not finite
+ *     alpha = rho / sigma; x += alpha p; r -= alpha q
+ *     stop when ||r|| <= rtol ||b||   (recursive residual, tested before z)
+ *     z = D^-1 r; rho' = r.z; beta = rho'/rho; rho = rho'; p = z + beta p
+ *
+ * kc: cell coefficients (NULL for the constant operator, D = 6 I).
+ * x: in = x0, out = final iterate. hist (optional, maxit+1 entries) receives
+ * ||r_k|| / ||b|| for k = 0..iters. *iters = number of A p products.
+ * Returns ORACLE_OK, ORACLE_NOCONV (maxit reached, last iterate kept) or
+ * ORACLE_BREAKDOWN.
+ */
+int oracle_pcg(int nx, int ny, int nz, const double *kc, const double *b, double *x, double rtol,
+               int maxit, double *hist, int *iters, double *relres)
+{
+    int64_t n = (int64_t)nx * ny * nz;
+    double *r = malloc(sizeof(double) * n), *z = malloc(sizeof(double) * n);
+    double *p = malloc(sizeof(double) * n), *q = malloc(sizeof(double) * n);
+    double *dinv = malloc(sizeof(double) * n);
+    if (!r || !z || !p || !q || !dinv) {
+        free(r); free(z); free(p); free(q); free(dinv);
+        return ORACLE_NOMEM;
+    }
+    if (kc) {
+        oracle_vdiag(nx, ny, nz, kc, dinv);
+        for (int64_t i = 0; i < n; ++i)
+            dinv[i] = 1.0 / dinv[i];
+    } else {
+        for (int64_t i = 0; i < n; ++i)
+            dinv[i] = 1.0 / 6.0;
+    }
+    int status = ORACLE_OK;
+    *iters = 0;
+    double nb = sqrt(oracle_dot(n, b, b));
+    if (nb == 0.0) {
+        memset(x, 0, sizeof(double) * n);
+        *relres = 0.0;
+        if (hist)
+            hist[0] = 0.0;
+        goto done;
+    }
+    apply_op(nx, ny, nz, kc, x, q);
+    for (int64_t i = 0; i < n; ++i)
+        r[i] = b[i] - q[i];
+    double rn = sqrt(oracle_dot(n, r, r));
+    if (hist)
+        hist[0] = rn / nb;
+    *relres = rn / nb;
+    if (rn <= rtol * nb)
+        goto done;
+    for (int64_t i = 0; i < n; ++i)
+        z[i] = dinv[i] * r[i];
+    memcpy(p, z, sizeof(double) * n);
+    double rho = oracle_dot(n, r, z);
+    status = ORACLE_NOCONV;
+    for (int k = 1; k <= maxit; ++k) {
+        apply_op(nx, ny, nz, kc, p, q);
+        double sigma = oracle_dot(n, p, q);
+        if (!(sigma > 0.0) || !isfinite(sigma)) {
+            status = ORACLE_BREAKDOWN;
+            break;
+        }
+        double alpha = rho / sigma;
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] += alpha * p[i];
+            r[i] -= alpha * q[i];
+        }
+        *iters = k;
+        rn = sqrt(oracle_dot(n, r, r));
+        *relres = rn / nb;
+        if (hist)
+            hist[k] = rn / nb;
+        if (!isfinite(rn)) {
+            status = ORACLE_BREAKDOWN;
+            break;
+        }
+        if (rn <= rtol * nb) {
+            status = ORACLE_OK;
+            break;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            z[i] = dinv[i] * r[i];
+        double rho_new = oracle_dot(n, r, z);
+        double beta = rho_new / rho;
+        rho = rho_new;
+        for (int64_t i = 0; i < n; ++i)
+            p[i] = z[i] + beta * p[i];
+    }
+done:
+    free(r); free(z); free(p); free(q); free(dinv);
+    return status;
+}
+
+/* r = b - A x (FP64) together with ||r||_2 and max_i |r_i|. */
+void oracle_residual(int nx, int ny, int nz, const double *kc, const double *b, const double *x,
+                     double *r, double *norm2, double *amax)
+{
+    int64_t n = (int64_t)nx * ny * nz;
+    apply_op(nx, ny, nz, kc, x, r);
+    double m = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        r[i] = b[i] - r[i];
+        double a = fabs(r[i]);
+        if (a > m)
+            m = a;
+    }
+    *norm2 = sqrt(oracle_dot(n, r, r));
+    *amax = m;
+}
