@@ -1,0 +1,221 @@
+"""Benchmark of the Jacobi-PCG hot path on one MI355X.
+
+Step = one full FP32 Jacobi-PCG solve (x0 = 0, recursive relative residual
+1e-6) of the 256^3 seven-point Poisson system b = A x*, x* = lowest sine mode
++ 1e-3 U[-1,1] noise (seed 4). `value` = seconds per solve (lower is better).
+
+Also reported on the same JSON line:
+  roofline      -- the dominant kernel (the PCG update kernel) measured with
+                   HIP events on the library's stream in an event-timed solve
+                   of the same workload, against 8 TB/s;
+  kernels_512   -- standalone stencil / axpy / dot at 512^3 (FP32 and BF16),
+                   achieved GB/s of algorithmic bytes;
+  cpu_baseline  -- the FP64 CPU oracle's Jacobi-PCG on the same system,
+                   timed on a bounded number of iterations and scaled.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PCG seconds to 1e-6 rel resid @256³; stencil/dot/axpy achieved HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per grid point of the two iteration kernels (FP32
+# storage, FP64 x accumulator): direction reads r, p_old and writes p;
+# update reads p, r, x(FP64) and writes r, x(FP64).
+BYTES_DIRECTION = 12
+BYTES_UPDATE = 28
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2603_23343_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """Counter-measured HBM bytes per launch from profiles/, if taken on the
+    current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = d.get(kernel)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def build_rhs(P, torch, n):
+    """b = A x* on the GPU in FP64 (the library's FP64 stencil), then rounded to FP32."""
+    import synthetic
+
+    xs = torch.from_numpy(synthetic.smooth_plus_noise(n)).cuda()
+    ctx64 = P.pcg_create(n, n, n, torch.float64)
+    b64 = torch.empty_like(xs)
+    P.stencil_apply(ctx64, xs, b64)
+    torch.cuda.synchronize()
+    P.pcg_destroy(ctx64)
+    return b64.to(torch.float32), b64
+
+
+def time_kernels_512(P, torch, n, reps):
+    """Standalone kernels at n^3: achieved GB/s of algorithmic bytes."""
+    import synthetic
+
+    out = {}
+    N = n ** 3
+    for name, dt, es in (("f32", torch.float32, 4), ("bf16", torch.bfloat16, 2)):
+        x = torch.from_numpy(synthetic.uniform_f32(synthetic.SEED_C2_X, N)).cuda().to(dt)
+        y = torch.from_numpy(synthetic.uniform_f32(synthetic.SEED_C2_Y, N)).cuda().to(dt)
+        z = torch.empty_like(x)
+        d = torch.zeros(1, dtype=torch.float32, device="cuda")
+        ctx = P.pcg_create(n, n, n, dt)
+        ops = {
+            "stencil": (lambda: P.stencil_apply(ctx, x, z), 2 * es),
+            "axpy": (lambda: P.axpy(ctx, N, 0.5, x, y, z), 3 * es),
+            "dot": (lambda: P.dot(ctx, N, x, y, d), 2 * es),
+        }
+        for op, (fn, bpp) in ops.items():
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            gbs = bpp * N / (ms * 1e-3) / 1e9
+            out[f"{op}_{name}"] = {"us": round(ms * 1e3, 2), "GB/s": round(gbs, 1),
+                                   "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        P.pcg_destroy(ctx)
+        del x, y, z
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(b64_host, n, gpu_iters, budget_s=15.0):
+    """The FP64 oracle's Jacobi-PCG on the same system: time a bounded number
+    of iterations and scale to the iteration count of the solve."""
+    import oracle
+
+    shape = (n, n, n)
+    t0 = time.perf_counter()
+    oracle.pcg(shape, b64_host, rtol=0.0, maxit=2)
+    t2 = time.perf_counter() - t0
+    per_iter = t2 / 2.0
+    m = int(max(2, min(gpu_iters, budget_s / max(per_iter, 1e-9))))
+    t0 = time.perf_counter()
+    out = oracle.pcg(shape, b64_host, rtol=1e-6, maxit=m)
+    tm = time.perf_counter() - t0
+    its = out["iters"]
+    full = out["status"] == oracle.OK
+    per_iter = tm / max(its, 1)
+    est = tm if full else per_iter * gpu_iters
+    return {"value": round(est, 3), "unit": "s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": (f"FP64 oracle Jacobi-PCG on the same {n}^3 system: "
+                       + (f"full solve, {its} iterations" if full else
+                          f"first {its} iterations timed ({tm:.1f} s), scaled to the GPU's {gpu_iters} iterations"))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--n-kernels", type=int, default=512)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernels", action="store_true")
+    ap.add_argument("--maxit", type=int, default=5000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver is single-GPU.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2603_23343_amd as P
+
+    n = args.n
+    N = n ** 3
+    b, b64 = build_rhs(P, torch, n)
+    ctx = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64)
+    x = torch.empty(N, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        P.pcg_solve(ctx, b, x, 1e-6, args.maxit)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        infos.append(P.pcg_solve(ctx, b, x, 1e-6, args.maxit))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    info = infos[-1]
+    iters = info["iters"]
+    print(f"# solve: {iters} iterations, {dt * 1e3:.2f} ms, recursive {info['rel_res_recursive']:.3e}, "
+          f"true {info['rel_res_true_fp64']:.3e}", file=sys.stderr, flush=True)
+
+    # Per-kernel durations: the same solve with HIP events around every
+    # iteration kernel (eager launches on the same stream).
+    tctx = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64, kernel_timing=1)
+    tinfo = P.pcg_solve(tctx, b, x, 1e-6, args.maxit)
+    k2_us = tinfo["k2_ms"] * 1e3 / max(tinfo["k2_launches"], 1)
+    k1_us = tinfo["k1_ms"] * 1e3 / max(tinfo["k1_launches"], 1)
+    achieved = BYTES_UPDATE * N / (k2_us * 1e-6) / 1e9
+    traffic = load_traffic("pcg_update")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "pcg_update (k_zmarch<..., OpUpdate, FinBeta>)",
+                "bytes_per_launch": BYTES_UPDATE * N, "avg_us": round(k2_us, 2),
+                "direction_kernel_avg_us": round(k1_us, 2),
+                "direction_kernel_GB/s": round(BYTES_DIRECTION * N / (k1_us * 1e-6) / 1e9, 1),
+                "event_timed_solve_ms": round(tinfo["seconds"] * 1e3, 2)}
+    P.pcg_destroy(tctx)
+
+    kern = None
+    if not args.no_kernels:
+        del ctx
+        torch.cuda.empty_cache()
+        kern = time_kernels_512(P, torch, args.n_kernels, args.kernel_reps)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(b64.cpu().numpy(), n, iters)
+
+    line = {
+        "metric": METRIC, "value": round(dt, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"{n}^3 seven-point Poisson, b = A x*, x* = sin*sin*sin + 1e-3 U[-1,1] "
+                                "(seed 4); FP32 Jacobi-PCG from x0 = 0 to recursive 1e-6, FP64 x accumulator"),
+                   "grid": [n, n, n], "iters": iters, "rel_res_recursive": info["rel_res_recursive"],
+                   "rel_res_true_fp64": info["rel_res_true_fp64"],
+                   "per_iteration_us": round(dt * 1e6 / max(iters, 1), 2)},
+        "roofline": roofline,
+        "kernels_512": kern,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,132 @@
+/*
+ * pcgmi.h -- C ABI of the MI355X (gfx950) Jacobi-PCG library.
+ *
+ * The method (paper Sec. VII): preconditioned conjugate gradients for the 3D
+ * seven-point finite-difference operator with zero Dirichlet boundaries,
+ *   (A x)_{i,j,k} = 6 x_{i,j,k} - x_{i+-1,j,k} - x_{i,j+-1,k} - x_{i,j,k+-1},
+ * neighbours outside the grid reading as 0 (no h^2 scaling), applied
+ * matrix-free (Sec. VI), with the Jacobi preconditioner D = diag(A) applied
+ * as element-wise scaling. PCG is composed of the element-wise update
+ * (Sec. IV), the global dot-product reduction (Sec. V) and the stencil
+ * (Sec. VI); here they are fused into two kernels per iteration.
+ *
+ * Conventions for every entry point:
+ *  - Grids are contiguous C-order [nz][ny][nx] arrays, x fastest.
+ *  - Every data pointer is a DEVICE pointer on the context's device, owned
+ *    by the caller, 16-byte aligned (PCG_E_ARG otherwise). The library owns
+ *    only its workspace (allocated in *_create, freed in *_destroy).
+ *  - Work is enqueued on the HIP stream given at creation (NULL = the
+ *    default stream). stencil_apply, axpy and dot are asynchronous;
+ *    pcg_solve returns after the solve has finished.
+ *  - Calls return a status and never abort; the message of the last failure
+ *    on the calling thread is available from pcg_last_error().
+ *  - Calls on one context must not overlap (the workspace is shared).
+ */
+#ifndef PCGMI_H
+#define PCGMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pcg_ctx_s *pcg_ctx;
+
+typedef enum {
+    PCG_OK = 0,
+    PCG_E_ARG = 1,         /* invalid argument: null/misaligned pointer, bad size, aliasing */
+    PCG_E_HIP = 2,         /* a HIP runtime call failed */
+    PCG_E_NOCONV = 3,      /* maxit reached; the last iterate is left in x */
+    PCG_E_BREAKDOWN = 4,   /* p.Ap <= 0 or a non-finite scalar (e.g. NaN in b) */
+    PCG_E_NOMEM = 5,       /* workspace allocation failed */
+    PCG_E_UNSUPPORTED = 6  /* combination not implemented (e.g. dtype for an op) */
+} pcg_status;
+
+/* Storage type of the vectors. Arithmetic is FP32 for F32/BF16/F16 (values
+ * widened on load, rounded to nearest-even on store) and FP64 for F64. */
+typedef enum { PCG_F32 = 0, PCG_BF16 = 1, PCG_F16 = 2, PCG_F64 = 3 } pcg_dtype;
+
+typedef struct {
+    int chunk_iters;   /* iterations per captured HIP graph chunk (default 16, even) */
+    int x_accum_f64;   /* 1 (default): x accumulated in FP64 workspace; 0: in storage type */
+    int x_dtype;       /* type of the caller's x in pcg_solve: PCG_F32 (default for F32
+                          storage) or PCG_F64; for BF16/F16 storage x is that type or F64 */
+    int use_x0;        /* 0 (default): x0 = 0; 1: x holds the initial guess on entry */
+    int use_graph;     /* 1 (default): replay captured graph chunks; 0: eager launches */
+    int kernel_timing; /* 1: eager launches with HIP events around every iteration
+                          kernel; sums are returned in pcg_info */
+    int tile_x;        /* stencil tile in x (points); 0 = autotuned default */
+    int tile_y;        /* stencil tile in y (rows); 0 = default */
+    int zchunk;        /* z planes per work-group; 0 = default */
+} pcg_options;
+
+typedef struct {
+    int iters;               /* A p products of the solve (inner iterations for refinement) */
+    int outer_iters;         /* refinement steps (pcg_solve_refined) */
+    int fallback_used;       /* reserved for the flexible solver */
+    int status;              /* pcg_status of the solve */
+    double rel_res_recursive;/* ||r_k|| / ||b|| from the recursion */
+    double rel_res_true_fp64;/* ||b - A x|| / ||b|| recomputed in FP64 on the GPU */
+    double seconds;          /* host wall time of the call */
+    double t_1e6;            /* refinement: seconds until the true residual <= 1e-6 */
+    double t_1e10;           /* refinement: seconds until the true residual <= 1e-10 */
+    double k1_ms, k2_ms;     /* kernel_timing: summed event time of the two iteration kernels */
+    int k1_launches, k2_launches;
+} pcg_info;
+
+/* Fill *opt with the defaults listed above. */
+pcg_status pcg_options_default(pcg_options *opt);
+
+/* Create a context for an nx*ny*nz grid whose vectors are stored as
+ * `storage`. hip_stream is a hipStream_t (NULL = default stream). opt may be
+ * NULL (defaults). Allocates the workspace: for F32 storage 3 vectors of
+ * the storage type (r, p twice) plus an FP64 x accumulator, plus reduction
+ * partials and a small scalar block. Errors: PCG_E_ARG (dims < 1 or
+ * nx*ny*nz > 2^33), PCG_E_NOMEM, PCG_E_HIP. */
+pcg_status pcg_create(pcg_ctx *out, int nx, int ny, int nz, pcg_dtype storage, void *hip_stream,
+                      const pcg_options *opt);
+
+/* Release the context and its workspace (waits for its stream). NULL is a no-op. */
+pcg_status pcg_destroy(pcg_ctx ctx);
+
+/* y = A x on the context's grid (paper Sec. VI), x and y of the storage type,
+ * x != y (PCG_E_ARG when they overlap). FP32 math for F32/BF16/F16 storage,
+ * FP64 for F64. */
+pcg_status stencil_apply(pcg_ctx ctx, const void *x, void *y);
+
+/* z = alpha x + y over n elements of the storage type (paper Sec. IV). z may
+ * equal x or y; other partial overlaps are PCG_E_ARG. n >= 0. */
+pcg_status axpy(pcg_ctx ctx, int64_t n, float alpha, const void *x, const void *y, void *z);
+
+/* *out_dev = sum_i x_i y_i over n elements of the storage type (paper Sec. V):
+ * per-lane FP32 accumulation (FP64 for F64 storage), wavefront and
+ * work-group reduction, then an FP64 sum of the work-group partials in a
+ * fixed order by the last work-group to finish (deterministic). out_dev is a
+ * DEVICE pointer to one float. n = 0 gives 0. */
+pcg_status dot(pcg_ctx ctx, int64_t n, const void *x, const void *y, float *out_dev);
+
+/* Same as dot with an FP64 device result. */
+pcg_status dot_f64(pcg_ctx ctx, int64_t n, const void *x, const void *y, double *out_dev);
+
+/* Solve A x = b with Jacobi-PCG (paper Sec. VII): b of the storage type, x
+ * of opt->x_dtype. Stops when the recursive residual satisfies
+ * ||r|| <= rtol ||b|| or after maxit iterations; then recomputes the true
+ * residual ||b - A x|| / ||b|| in FP64. b = 0 gives x = 0, iters = 0.
+ * Returns PCG_OK, PCG_E_NOCONV (last iterate left in x) or PCG_E_BREAKDOWN.
+ * info may be NULL. Blocks until the solve is finished. */
+pcg_status pcg_solve(pcg_ctx ctx, const void *b, void *x, double rtol, int maxit, pcg_info *info);
+
+/* Copy the recursive relative residuals ||r_k||/||b||, k = 0..iters of the
+ * last pcg_solve on this context, to the host array hist (n entries at most).
+ * *count receives the number written. */
+pcg_status pcg_get_history(pcg_ctx ctx, double *hist, int n, int *count);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *pcg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCGMI_H */

@@ -65,8 +65,14 @@ def _load():
     lib.oracle_pcg.restype = i
     lib.oracle_residual.argtypes = [i, i, i, _dp, _dp, _dp, _dp,
                                     ctypes.POINTER(d), ctypes.POINTER(d)]
+    lib.oracle_threads.restype = i
     _lib = lib
     return lib
+
+
+def threads() -> int:
+    """OpenMP threads used by the C oracle's loops."""
+    return int(_load().oracle_threads())
 
 
 def _f64(a) -> np.ndarray:

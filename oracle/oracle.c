@@ -35,6 +35,20 @@
 
 #define CHUNK 65536
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 static inline double nb_val(const double *x, int nx, int ny, int nz, int i, int j, int k)
 {
     if (i < 0 || i >= nx || j < 0 || j >= ny || k < 0 || k >= nz)

@@ -1,0 +1,194 @@
+"""ctypes binding of the C ABI in include/pcgmi.h.
+
+Argument marshalling only: torch tensors supply device pointers and the HIP
+stream; every step of the computation runs in the library's HIP kernels. The
+library must have been built (paper_2603_23343_amd/build.py); importing this
+module without it raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libpcgmi.so")
+
+PCG_OK, PCG_E_ARG, PCG_E_HIP, PCG_E_NOCONV, PCG_E_BREAKDOWN, PCG_E_NOMEM, PCG_E_UNSUPPORTED = range(7)
+PCG_F32, PCG_BF16, PCG_F16, PCG_F64 = range(4)
+
+STATUS_NAMES = {0: "PCG_OK", 1: "PCG_E_ARG", 2: "PCG_E_HIP", 3: "PCG_E_NOCONV", 4: "PCG_E_BREAKDOWN",
+                5: "PCG_E_NOMEM", 6: "PCG_E_UNSUPPORTED"}
+
+_TORCH_DT = {torch.float32: PCG_F32, torch.bfloat16: PCG_BF16, torch.float16: PCG_F16, torch.float64: PCG_F64}
+DT_TORCH = {v: k for k, v in _TORCH_DT.items()}
+
+
+class PcgOptions(ctypes.Structure):
+    _fields_ = [("chunk_iters", ctypes.c_int), ("x_accum_f64", ctypes.c_int), ("x_dtype", ctypes.c_int),
+                ("use_x0", ctypes.c_int), ("use_graph", ctypes.c_int), ("kernel_timing", ctypes.c_int),
+                ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int), ("zchunk", ctypes.c_int)]
+
+
+class PcgInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("fallback_used", ctypes.c_int),
+                ("status", ctypes.c_int), ("rel_res_recursive", ctypes.c_double),
+                ("rel_res_true_fp64", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("t_1e6", ctypes.c_double), ("t_1e10", ctypes.c_double), ("k1_ms", ctypes.c_double),
+                ("k2_ms", ctypes.c_double), ("k1_launches", ctypes.c_int), ("k2_launches", ctypes.c_int)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class PcgError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"{LIBPATH} is not built; run paper_2603_23343_amd/build.py (or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIBPATH)
+    vp, i, i64, d, f = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_float
+    sig = {
+        "pcg_options_default": ([ctypes.POINTER(PcgOptions)], i),
+        "pcg_create": ([ctypes.POINTER(vp), i, i, i, i, vp, ctypes.POINTER(PcgOptions)], i),
+        "pcg_destroy": ([vp], i),
+        "stencil_apply": ([vp, vp, vp], i),
+        "axpy": ([vp, i64, f, vp, vp, vp], i),
+        "dot": ([vp, i64, vp, vp, vp], i),
+        "dot_f64": ([vp, i64, vp, vp, vp], i),
+        "pcg_solve": ([vp, vp, vp, d, i, ctypes.POINTER(PcgInfo)], i),
+        "pcg_get_history": ([vp, ctypes.POINTER(d), i, ctypes.POINTER(i)], i),
+        "pcg_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def pcg_last_error() -> str:
+    return lib.pcg_last_error().decode()
+
+
+def _check(status):
+    if status != PCG_OK:
+        raise PcgError(status, pcg_last_error())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def dtype_code(dt) -> int:
+    if isinstance(dt, int):
+        return dt
+    return _TORCH_DT[dt]
+
+
+def pcg_options_default(**overrides) -> PcgOptions:
+    o = PcgOptions()
+    _check(lib.pcg_options_default(ctypes.byref(o)))
+    for k, v in overrides.items():
+        if k == "x_dtype":
+            v = dtype_code(v)
+        setattr(o, k, int(v))
+    return o
+
+
+class Context:
+    """Owns a pcg_ctx handle; destroyed with the object (or close())."""
+
+    def __init__(self, handle, nx, ny, nz, dtype, stream):
+        self.handle = handle
+        self.shape = (nz, ny, nx)
+        self.dtype = dtype
+        self.stream = stream
+
+    @property
+    def n(self):
+        nz, ny, nx = self.shape
+        return nx * ny * nz
+
+    def close(self):
+        if self.handle:
+            lib.pcg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def _as_parameter_(self):
+        return self.handle
+
+
+def pcg_create(nx, ny, nz, dtype=torch.float32, stream=None, options=None, **opts) -> Context:
+    if options is None and opts:
+        options = pcg_options_default(**opts)
+    h = ctypes.c_void_p()
+    s = _stream(stream)
+    _check(lib.pcg_create(ctypes.byref(h), int(nx), int(ny), int(nz), dtype_code(dtype), s,
+                          None if options is None else ctypes.byref(options)))
+    return Context(h, int(nx), int(ny), int(nz), dtype, s)
+
+
+def pcg_destroy(ctx: Context):
+    ctx.close()
+
+
+def stencil_apply(ctx: Context, x, y):
+    _check(lib.stencil_apply(ctx.handle, _ptr(x), _ptr(y)))
+
+
+def axpy(ctx: Context, n, alpha, x, y, z):
+    _check(lib.axpy(ctx.handle, int(n), float(alpha), _ptr(x), _ptr(y), _ptr(z)))
+
+
+def dot(ctx: Context, n, x, y, out):
+    _check(lib.dot(ctx.handle, int(n), _ptr(x), _ptr(y), _ptr(out)))
+
+
+def dot_f64(ctx: Context, n, x, y, out):
+    _check(lib.dot_f64(ctx.handle, int(n), _ptr(x), _ptr(y), _ptr(out)))
+
+
+def pcg_solve(ctx: Context, b, x, rtol=1e-6, maxit=500, raise_on_error=True) -> dict:
+    info = PcgInfo()
+    st = lib.pcg_solve(ctx.handle, _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(info))
+    out = info.as_dict()
+    out["status"] = st
+    if st != PCG_OK and (raise_on_error or st not in (PCG_E_NOCONV, PCG_E_BREAKDOWN)):
+        raise PcgError(st, pcg_last_error())
+    return out
+
+
+def pcg_get_history(ctx: Context, n=1 << 20):
+    import numpy as np
+
+    buf = np.zeros(n, dtype=np.float64)
+    cnt = ctypes.c_int(0)
+    _check(lib.pcg_get_history(ctx.handle, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n,
+                               ctypes.byref(cnt)))
+    return buf[: cnt.value].copy()

@@ -1,0 +1,226 @@
+// blas1.hip -- streaming kernels: axpy (paper Sec. IV's element-wise update),
+// dot (Sec. V's global reduction), the zero-guess start of a solve, fills and
+// type conversions.
+//
+// Each thread moves 16-byte vectors (4 FP32, 8 BF16/FP16, 2 FP64 elements);
+// consecutive threads touch consecutive vectors, so every wavefront access
+// is one contiguous 1 KiB segment. The dot keeps one accumulator per vector
+// lane in the compute type, reduces across the wavefront with a fixed
+// butterfly and across work-groups with the last-work-group ticket, so the
+// result is deterministic.
+#include "ops.hpp"
+#include "zkernel.hpp"
+
+namespace pcgmi {
+
+namespace {
+
+constexpr int NT = STREAM_THREADS;
+constexpr int AXPY_UNROLL = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_axpy(int64_t n, float alpha, const T* x, const T* y, T* z) {
+    using C = typename Traits<T>::C;
+    constexpr int W = Traits<T>::W;
+    const int64_t nvec = n / W;
+    const int64_t base = (int64_t)blockIdx.x * NT * AXPY_UNROLL + threadIdx.x;
+    C xv[AXPY_UNROLL][W], yv[AXPY_UNROLL][W];
+#pragma unroll
+    for (int u = 0; u < AXPY_UNROLL; ++u) {
+        const int64_t i = base + (int64_t)u * NT;
+        if (i < nvec) {
+            load_vec<T>(x + i * W, xv[u]);
+            load_vec<T>(y + i * W, yv[u]);
+        }
+    }
+    const C a = (C)alpha;
+#pragma unroll
+    for (int u = 0; u < AXPY_UNROLL; ++u) {
+        const int64_t i = base + (int64_t)u * NT;
+        if (i < nvec) {
+            C zv[W];
+#pragma unroll
+            for (int e = 0; e < W; ++e) zv[e] = a * xv[u][e] + yv[u][e];
+            store_vec<T>(z + i * W, zv);
+        }
+    }
+    // Ragged tail (fewer than W elements): block 0.
+    if (blockIdx.x == 0) {
+        const int64_t t = nvec * W + threadIdx.x;
+        if (t < n) z[t] = from_c<T>(a * to_c(x[t]) + to_c(y[t]));
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_dot(int64_t n, const T* __restrict__ x, const T* __restrict__ y,
+                                            float* out_f32, double* out_f64, Red red) {
+    using C = typename Traits<T>::C;
+    constexpr int W = Traits<T>::W;
+    __shared__ double scratch[16];
+    const int64_t nvec = n / W;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    C acc[W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) acc[e] = C(0);
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nvec; i += stride) {
+        C a[W], b[W];
+        load_vec<T>(x + i * W, a);
+        load_vec<T>(y + i * W, b);
+#pragma unroll
+        for (int e = 0; e < W; ++e) acc[e] += a[e] * b[e];
+    }
+    if (blockIdx.x == 0) {
+        const int64_t t = nvec * W + threadIdx.x;
+        if (t < n) acc[0] += to_c(x[t]) * to_c(y[t]);
+    }
+    double v[1] = {0.0}, tot[1];
+#pragma unroll
+    for (int e = 0; e < W; ++e) v[0] += (double)acc[e];
+    if (grid_reduce<1, 0u>(v, red.partials, red.ticket, gridDim.x, blockIdx.x, scratch, tot) &&
+        threadIdx.x == 0) {
+        if (out_f32) *out_f32 = (float)tot[0];
+        if (out_f64) *out_f64 = tot[0];
+    }
+}
+
+// r = b, x = 0, p0 = p1 = 0 and the totals {b.b, b.b} for the solve start.
+template <typename T, typename X>
+__global__ void __launch_bounds__(NT) k_start_zero(int64_t n, const T* __restrict__ b, T* __restrict__ r,
+                                                   X* __restrict__ x, T* __restrict__ p0, T* __restrict__ p1,
+                                                   SolveState* st, double* hist, Red red) {
+    using C = typename Traits<T>::C;
+    constexpr int W = Traits<T>::W;
+    __shared__ double scratch[32];
+    const int64_t nvec = n / W;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    C acc = C(0);
+    C zero[W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) zero[e] = C(0);
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nvec; i += stride) {
+        C a[W];
+        load_vec<T>(b + i * W, a);
+        store_vec<T>(r + i * W, a);
+        store_vec<T>(p0 + i * W, zero);
+        store_vec<T>(p1 + i * W, zero);
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            x[i * W + e] = from_c<X>((typename Traits<X>::C)0);
+            acc += a[e] * a[e];
+        }
+    }
+    if (blockIdx.x == 0) {
+        const int64_t t = nvec * W + threadIdx.x;
+        if (t < n) {
+            C a = to_c(b[t]);
+            r[t] = b[t];
+            p0[t] = from_c<T>(C(0));
+            p1[t] = from_c<T>(C(0));
+            x[t] = from_c<X>((typename Traits<X>::C)0);
+            acc += a * a;
+        }
+    }
+    double v[2] = {(double)acc, (double)acc}, tot[2];
+    if (grid_reduce<2, 0u>(v, red.partials, red.ticket, gridDim.x, blockIdx.x, scratch, tot) &&
+        threadIdx.x == 0)
+        FinStart{st, hist}(tot);
+}
+
+__global__ void __launch_bounds__(NT) k_zero_bytes(int64_t nbytes, unsigned char* p) {
+    const int64_t nvec = nbytes / 16;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    using U = __attribute__((__vector_size__(16))) unsigned int;
+    U z = {0u, 0u, 0u, 0u};
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nvec; i += stride)
+        reinterpret_cast<U*>(p)[i] = z;
+    if (blockIdx.x == 0) {
+        const int64_t t = nvec * 16 + threadIdx.x;
+        if (t < nbytes) p[t] = 0;
+    }
+}
+
+// dst = src through the compute type of the wider side: FP64 -> FP32 -> 16-bit
+// when narrowing from double to a 16-bit type (two roundings to nearest even).
+template <typename S, typename D>
+__global__ void __launch_bounds__(NT) k_convert(int64_t n, const S* __restrict__ src, D* __restrict__ dst) {
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
+        double v = (double)to_c(src[i]);
+        dst[i] = from_c<D>((typename Traits<D>::C)v);
+    }
+}
+
+inline unsigned stream_blocks(int64_t nvec, int64_t per_block, int64_t cap) {
+    int64_t b = (nvec + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_axpy(int dt, int64_t n, float alpha, const void* x, const void* y, void* z, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    return dispatch_dt(dt, [&](auto tag) {
+        using T = decltype(tag);
+        const int64_t nvec = n / Traits<T>::W;
+        const unsigned nb = stream_blocks(nvec, (int64_t)NT * AXPY_UNROLL, INT32_MAX);
+        hipLaunchKernelGGL(k_axpy<T>, dim3(nb), dim3(NT), 0, s, n, alpha, static_cast<const T*>(x),
+                           static_cast<const T*>(y), static_cast<T*>(z));
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_dot(int dt, int64_t n, const void* x, const void* y, float* out_f32, double* out_f64, Red red,
+                      hipStream_t s) {
+    return dispatch_dt(dt, [&](auto tag) {
+        using T = decltype(tag);
+        const int64_t nvec = n / Traits<T>::W;
+        const unsigned nb = stream_blocks(nvec, (int64_t)NT * 4, DOT_MAX_BLOCKS);
+        hipLaunchKernelGGL(k_dot<T>, dim3(nb), dim3(NT), 0, s, n, static_cast<const T*>(x),
+                           static_cast<const T*>(y), out_f32, out_f64, red);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_pcg_start_zero(int dt, int64_t n, const void* b, void* r, void* x, bool x64, void* p0, void* p1,
+                                 SolveState* st, double* hist, Red red, hipStream_t s) {
+    return dispatch_dt(dt, [&](auto tag) {
+        using T = decltype(tag);
+        const int64_t nvec = n / Traits<T>::W;
+        const unsigned nb = stream_blocks(nvec, (int64_t)NT * 4, DOT_MAX_BLOCKS);
+        if (x64)
+            hipLaunchKernelGGL((k_start_zero<T, double>), dim3(nb), dim3(NT), 0, s, n, static_cast<const T*>(b),
+                               static_cast<T*>(r), static_cast<double*>(x), static_cast<T*>(p0),
+                               static_cast<T*>(p1), st, hist, red);
+        else
+            hipLaunchKernelGGL((k_start_zero<T, T>), dim3(nb), dim3(NT), 0, s, n, static_cast<const T*>(b),
+                               static_cast<T*>(r), static_cast<T*>(x), static_cast<T*>(p0), static_cast<T*>(p1),
+                               st, hist, red);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_zero(int dt, int64_t n, void* p, hipStream_t s) {
+    const int64_t nbytes = n * (int64_t)dt_size(dt);
+    if (nbytes <= 0) return hipSuccess;
+    const unsigned nb = stream_blocks(nbytes / 16, (int64_t)NT * 4, 4096);
+    hipLaunchKernelGGL(k_zero_bytes, dim3(nb), dim3(NT), 0, s, nbytes, static_cast<unsigned char*>(p));
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int sdt, int ddt, int64_t n, const void* src, void* dst, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    return dispatch_dt(sdt, [&](auto stag) {
+        using S = decltype(stag);
+        return dispatch_dt(ddt, [&](auto dtag) {
+            using D = decltype(dtag);
+            const unsigned nb = stream_blocks(n, (int64_t)NT * 4, 8192);
+            hipLaunchKernelGGL((k_convert<S, D>), dim3(nb), dim3(NT), 0, s, n, static_cast<const S*>(src),
+                               static_cast<D*>(dst));
+            return hipGetLastError();
+        });
+    });
+}
+
+}  // namespace pcgmi

@@ -1,0 +1,85 @@
+// internal.hpp -- host-side interface between the C ABI layer and the
+// kernel launchers (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pcgmi.h"
+
+namespace pcgmi {
+
+struct SolveState;
+
+enum DT : int { DT_F32 = PCG_F32, DT_BF16 = PCG_BF16, DT_F16 = PCG_F16, DT_F64 = PCG_F64 };
+
+inline size_t dt_size(int dt) { return dt == DT_F64 ? 8 : dt == DT_F32 ? 4 : 2; }
+inline int dt_width(int dt) { return (int)(16 / dt_size(dt)); }  // elements per 16 bytes
+
+// Compiled work-group shapes of the z-march kernels: BX x BY threads, each
+// thread owning VX consecutive x points (VX = 16 bytes of the storage type,
+// or 1 for the scalar shape used when nx is not a multiple of that width).
+struct TileCfg {
+    int bx, by;
+    bool vec;
+};
+constexpr int NUM_TILE_CFG = 6;
+constexpr TileCfg TILE_CFGS[NUM_TILE_CFG] = {
+    {16, 16, true}, {32, 8, true}, {64, 4, true}, {16, 4, true}, {16, 8, true}, {64, 4, false}};
+
+struct Plan {
+    int cfg;  // index into TILE_CFGS
+    int zc;   // planes per work-group
+};
+
+// Tile extents of a plan for storage type dt.
+inline int plan_tx(const Plan& p, int dt) { return TILE_CFGS[p.cfg].bx * (TILE_CFGS[p.cfg].vec ? dt_width(dt) : 1); }
+inline int plan_ty(const Plan& p) { return TILE_CFGS[p.cfg].by; }
+
+struct Geometry {
+    int nx, ny, nz;
+    int ntx, nty, nzc, zc;
+    unsigned nblocks;
+};
+Geometry make_geometry(int nx, int ny, int nz, const Plan& p, int dt);
+
+struct Red {
+    double* partials;
+    unsigned* ticket;
+};
+
+// ---- z-march kernels (stencil family) ----
+hipError_t launch_stencil(int dt, const Plan& p, const Geometry& g, const void* x, void* y, hipStream_t s);
+
+// Iteration kernel 1: p_new = D^-1 r + beta p_old (rounded to storage), p.Ap -> alpha.
+hipError_t launch_pcg_direction(int dt, const Plan& p, const Geometry& g, const void* r, const void* pold,
+                                void* pnew, SolveState* st, Red red, hipStream_t s);
+// Iteration kernel 2: q = A p, x += alpha p, r -= alpha q, r.r -> convergence, beta.
+// x is FP64 when x64 is true, else of the storage type.
+hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, const void* pdir, void* x, bool x64,
+                             void* r, SolveState* st, double* hist, Red red, hipStream_t s);
+// r = stored(b - A x0) computed in FP64 (x0 of type xdt), totals {r.r, b.b}
+// -> solve start. Uses the FP64 residual shape (pres, gres).
+hipError_t launch_pcg_start_x0(int dt, int xdt, const Plan& pres, const Geometry& gres, const void* b,
+                               const void* x0, void* r, SolveState* st, double* hist, Red red, hipStream_t s);
+// FP64 residual of b (type bdt) and x (FP64 if x64 else type xdt): out = {||r||^2, max|r|}.
+hipError_t launch_residual64(int bdt, int xdt, const Plan& p, const Geometry& g, const void* b, const void* x,
+                             double* out, Red red, hipStream_t s);
+
+// ---- streaming kernels ----
+hipError_t launch_axpy(int dt, int64_t n, float alpha, const void* x, const void* y, void* z, hipStream_t s);
+// out_f32 and/or out_f64 (device) receive the dot; either may be null.
+hipError_t launch_dot(int dt, int64_t n, const void* x, const void* y, float* out_f32, double* out_f64, Red red,
+                      hipStream_t s);
+// r = b, x = 0, p0 = p1 = 0; totals {b.b, b.b} -> solve start.
+hipError_t launch_pcg_start_zero(int dt, int64_t n, const void* b, void* r, void* x, bool x64, void* p0, void* p1,
+                                 SolveState* st, double* hist, Red red, hipStream_t s);
+// Fill n elements of type dt (or FP64 when dt == DT_F64) with zero.
+hipError_t launch_zero(int dt, int64_t n, void* p, hipStream_t s);
+// Convert n elements: dst (type ddt) = src (type sdt), rounding to nearest even.
+hipError_t launch_convert(int sdt, int ddt, int64_t n, const void* src, void* dst, hipStream_t s);
+
+constexpr int DOT_MAX_BLOCKS = 2048;
+constexpr int STREAM_THREADS = 256;
+
+}  // namespace pcgmi

@@ -1,0 +1,308 @@
+// ops.hpp -- loaders, per-point operations and grid-reduction finishers that
+// turn the z-march skeleton into the stencil apply, the two fused PCG
+// iteration kernels and the FP64 true-residual kernel.
+#pragma once
+
+#include "zmarch.hpp"
+
+namespace pcgmi {
+
+// Device-resident scalars of one solve. Written only by the last work-group
+// of a kernel (or by the init kernel) and read by the next kernel, so kernel
+// boundaries order every access.
+struct SolveState {
+    double rho;    // r.z of the current residual
+    double alpha;  // rho / (p.Ap) of the current iteration
+    double beta;   // rho_new / rho_old for the next direction
+    double sigma;  // p.Ap
+    double rr;     // ||r||^2 of the current residual
+    double rr0;    // ||b||^2
+    double tol2;   // (rtol ||b||)^2
+    double dinv;   // 1 / diagonal (constant-coefficient operator)
+    int iters;     // completed iterations
+    int done;      // 0 running, 1 converged, 2 breakdown, 3 maxit reached
+    int maxit;
+    int pad;
+};
+
+// ---------------------------------------------------------------- loaders
+// A loader provides Raw<N> (registers of one fetch of N consecutive points),
+// fetch<N>(idx, raw) (issue the loads) and finish<N>(raw, out) (compute-type
+// values of the field at those points).
+
+// Plain load of a stored field of type T.
+template <typename T> struct LoadField {
+    using C = typename Traits<T>::C;
+    template <int N> using Raw = RawN<T, N>;
+    const T* __restrict__ x;
+    __device__ void init() {}
+    template <int N> __device__ __forceinline__ void fetch(int64_t i, Raw<N>& r) const { r.load(x + i); }
+    template <int N> __device__ __forceinline__ void finish(const Raw<N>& r, C* out) const {
+#pragma unroll
+        for (int v = 0; v < N; ++v) out[v] = r.get(v);
+    }
+};
+
+// Load of a field of type S widened to the compute type C (e.g. an FP32
+// iterate read by an FP64 kernel).
+template <typename S, typename C> struct LoadWiden {
+    template <int N> using Raw = RawN<S, N>;
+    const S* __restrict__ x;
+    __device__ void init() {}
+    template <int N> __device__ __forceinline__ void fetch(int64_t i, Raw<N>& r) const { r.load(x + i); }
+    template <int N> __device__ __forceinline__ void finish(const Raw<N>& r, C* out) const {
+#pragma unroll
+        for (int v = 0; v < N; ++v) out[v] = (C)r.get(v);
+    }
+};
+
+// New search direction computed on the fly: p = stored(dinv * r + beta * p_old).
+// beta comes from the solve state; dinv is the constant Jacobi scale.
+template <typename T> struct LoadDirection {
+    using C = typename Traits<T>::C;
+    template <int N> struct Raw {
+        RawN<T, N> r, p;
+    };
+    const T* __restrict__ r;
+    const T* __restrict__ pold;
+    const SolveState* st;
+    C beta, dinv;
+    __device__ void init() {
+        beta = (C)st->beta;
+        dinv = (C)st->dinv;
+    }
+    template <int N> __device__ __forceinline__ void fetch(int64_t i, Raw<N>& raw) const {
+        raw.r.load(r + i);
+        raw.p.load(pold + i);
+    }
+    template <int N> __device__ __forceinline__ void finish(const Raw<N>& raw, C* out) const {
+#pragma unroll
+        for (int v = 0; v < N; ++v) out[v] = stored<T>(dinv * raw.r.get(v) + beta * raw.p.get(v));
+    }
+};
+
+// ---------------------------------------------------------------- store helpers
+
+template <typename T, int VX>
+__device__ __forceinline__ void st_pts(T* __restrict__ p, int64_t i, const typename Traits<T>::C* in) {
+    if constexpr (VX == Traits<T>::W) store_vec<T>(p + i, in);
+    else {
+#pragma unroll
+        for (int v = 0; v < VX; ++v) p[i + v] = from_c<T>(in[v]);
+    }
+}
+
+// Store N values of compute type to X (a double accumulator or a storage type).
+template <typename X, int N>
+__device__ __forceinline__ void st_any(X* __restrict__ p, int64_t i, const double* in) {
+    constexpr int W = 16 / (int)sizeof(X);
+    if constexpr (N % W == 0) {
+#pragma unroll
+        for (int j = 0; j < N / W; ++j) {
+            typename Traits<X>::C t[W];
+#pragma unroll
+            for (int e = 0; e < W; ++e) t[e] = (typename Traits<X>::C)in[j * W + e];
+            store_vec<X>(p + i + j * W, t);
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < N; ++v) p[i + v] = from_c<X>((typename Traits<X>::C)in[v]);
+    }
+}
+
+// ---------------------------------------------------------------- ops
+// An op provides Raw (registers of its own streams at one thread's points of
+// one plane), fetch(idx, raw) and apply(idx, raw, c, ax, acc).
+
+struct NoRaw {};
+
+// y = A x
+template <typename T, int VX> struct OpStore {
+    using C = typename Traits<T>::C;
+    using Raw = NoRaw;
+    T* __restrict__ y;
+    __device__ void init() {}
+    __device__ __forceinline__ void fetch(int64_t, Raw&) const {}
+    template <int NC>
+    __device__ __forceinline__ void apply(int64_t i, const Raw&, const C* c, const C* ax, C (&acc)[NC]) const {
+        st_pts<T, VX>(y, i, ax);
+    }
+};
+
+// Iteration kernel 1: store the new direction p (already rounded to T by the
+// loader) and accumulate p.Ap.
+template <typename T, int VX> struct OpDirection {
+    using C = typename Traits<T>::C;
+    using Raw = NoRaw;
+    T* __restrict__ pnew;
+    __device__ void init() {}
+    __device__ __forceinline__ void fetch(int64_t, Raw&) const {}
+    template <int NC>
+    __device__ __forceinline__ void apply(int64_t i, const Raw&, const C* c, const C* ax, C (&acc)[NC]) const {
+        st_pts<T, VX>(pnew, i, c);
+#pragma unroll
+        for (int v = 0; v < VX; ++v) acc[0] += c[v] * ax[v];
+    }
+};
+
+// Iteration kernel 2: with q = A p recomputed from p, x += alpha p and
+// r = stored(r - alpha q); accumulate r.r of the stored residual.
+template <typename T, typename X, int VX> struct OpUpdate {
+    using C = typename Traits<T>::C;
+    struct Raw {
+        RawN<T, VX> r;
+        RawN<X, VX> x;
+    };
+    X* __restrict__ x;
+    T* __restrict__ r;
+    const SolveState* st;
+    C alpha;
+    double alpha_d;
+    __device__ void init() {
+        alpha = (C)st->alpha;
+        alpha_d = (double)alpha;
+    }
+    __device__ __forceinline__ void fetch(int64_t i, Raw& raw) const {
+        raw.r.load(r + i);
+        raw.x.load(x + i);
+    }
+    template <int NC>
+    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const C* c, const C* ax, C (&acc)[NC]) const {
+        C rv[VX];
+        double xv[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            xv[v] = (double)raw.x.get(v) + alpha_d * (double)c[v];
+            rv[v] = stored<T>(raw.r.get(v) - alpha * ax[v]);
+            acc[0] += rv[v] * rv[v];
+        }
+        st_any<X, VX>(x, i, xv);
+        st_pts<T, VX>(r, i, rv);
+    }
+};
+
+// FP64 true residual: r = b - A x (not stored); accumulate ||r||^2 and max |r|.
+template <typename B, int VX> struct OpResidual64 {
+    struct Raw {
+        RawN<B, VX> b;
+    };
+    const B* __restrict__ b;
+    __device__ void init() {}
+    __device__ __forceinline__ void fetch(int64_t i, Raw& raw) const { raw.b.load(b + i); }
+    template <int NC>
+    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const double* c, const double* ax,
+                                          double (&acc)[NC]) const {
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            double rv = (double)raw.b.get(v) - ax[v];
+            acc[0] += rv * rv;
+            double a = fabs(rv);
+            acc[1] = a > acc[1] ? a : acc[1];
+        }
+    }
+};
+
+// Residual of an initial guess, computed in FP64 and rounded to the storage
+// type (through FP32 for 16-bit types): r = stored(b - A x0); accumulates
+// r.r of the stored residual and b.b.
+template <typename T, int VX> struct OpInitResidual {
+    struct Raw {
+        RawN<T, VX> b;
+    };
+    const T* __restrict__ b;
+    T* __restrict__ r;
+    __device__ void init() {}
+    __device__ __forceinline__ void fetch(int64_t i, Raw& raw) const { raw.b.load(b + i); }
+    template <int NC>
+    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const double* c, const double* ax,
+                                          double (&acc)[NC]) const {
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            const double bv = (double)raw.b.get(v);
+            const T rs = from_c<T>((typename Traits<T>::C)(bv - ax[v]));
+            r[i + v] = rs;
+            const double rv = (double)to_c(rs);
+            acc[0] += rv * rv;
+            acc[1] += bv * bv;
+        }
+    }
+};
+
+// ---------------------------------------------------------------- finishers
+// Run by thread 0 of the last work-group with the FP64 grid totals.
+
+struct FinNone {
+    __device__ void operator()(const double*) const {}
+};
+
+// After p.Ap: alpha = rho / sigma, or breakdown.
+struct FinAlpha {
+    SolveState* st;
+    __device__ void operator()(const double* tot) const {
+        double sigma = tot[0];
+        st->sigma = sigma;
+        if (!(sigma > 0.0) || !isfinite(sigma)) {
+            st->done = 2;
+            return;
+        }
+        st->alpha = st->rho / sigma;
+    }
+};
+
+// After r.r: count the iteration, test convergence, form beta.
+struct FinBeta {
+    SolveState* st;
+    double* hist;  // relres per iteration (maxit + 1 entries) or null
+    __device__ void operator()(const double* tot) const {
+        double rr = tot[0];
+        int it = st->iters + 1;
+        st->iters = it;
+        st->rr = rr;
+        if (hist) hist[it] = sqrt(rr / st->rr0);
+        if (!isfinite(rr)) {
+            st->done = 2;
+            return;
+        }
+        if (rr <= st->tol2) {
+            st->done = 1;
+            return;
+        }
+        if (it >= st->maxit) {
+            st->done = 3;
+            return;
+        }
+        double rho_new = st->dinv * rr;
+        st->beta = rho_new / st->rho;
+        st->rho = rho_new;
+    }
+};
+
+// Start of a solve from r and ||b||^2: tot = {r.r, b.b}.
+struct FinStart {
+    SolveState* st;
+    double* hist;
+    __device__ void operator()(const double* tot) const {
+        double rr = tot[0], bb = tot[1];
+        st->rr0 = bb;
+        st->rr = rr;
+        st->tol2 = st->tol2 * bb;  // host stores rtol^2 here before the launch
+        st->iters = 0;
+        st->beta = 0.0;
+        st->rho = st->dinv * rr;
+        if (hist) hist[0] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+        if (!isfinite(rr) || !isfinite(bb)) st->done = 2;
+        else if (bb == 0.0 || rr <= st->tol2) st->done = 1;
+        else st->done = 0;
+    }
+};
+
+// FP64 residual norms: out[0] = ||r||^2, out[1] = max |r|.
+struct FinStore2 {
+    double* out;
+    __device__ void operator()(const double* tot) const {
+        out[0] = tot[0];
+        out[1] = tot[1];
+    }
+};
+
+}  // namespace pcgmi

@@ -1,0 +1,66 @@
+// pcg.hip -- the two fused kernels of one Jacobi-PCG iteration (paper
+// Sec. VII composes PCG from the stencil, the dot reduction and element-wise
+// updates; here they are fused so each iteration makes two passes over HBM):
+//
+//   kernel 1 (direction): p = D^-1 r + beta p_old, computed on the fly for the
+//            tile and its halo; stores p; sigma = p.Ap; the last work-group
+//            forms alpha = rho / sigma (or flags a breakdown).
+//   kernel 2 (update):    q = A p recomputed from p (cheaper than storing and
+//            re-reading q); x += alpha p; r = r - alpha q; rr = r.r; the last
+//            work-group counts the iteration, tests ||r|| <= rtol ||b|| and
+//            forms beta = rho_new / rho.
+//
+// p ping-pongs between two buffers: kernel 1 reads halo points of p_old that
+// neighbouring work-groups are overwriting in the same launch otherwise.
+#include "zkernel.hpp"
+
+namespace pcgmi {
+
+hipError_t launch_pcg_direction(int dt, const Plan& p, const Geometry& g, const void* r, const void* pold,
+                                void* pnew, SolveState* st, Red red, hipStream_t s) {
+    return dispatch_dt(dt, [&](auto tag) {
+        using T = decltype(tag);
+        using C = typename Traits<T>::C;
+        return dispatch_cfg<Traits<T>::W>(p.cfg, [&]<int BX, int BY, int VX>() {
+            LoadDirection<T> ld{static_cast<const T*>(r), static_cast<const T*>(pold), st, C(0), C(0)};
+            OpDirection<T, VX> op{static_cast<T*>(pnew)};
+            return run_zmarch<ZF_DIRECTION, C, BX, BY, VX, 1, 0u, true>(g, ld, op, FinAlpha{st}, red, &st->done, s);
+        });
+    });
+}
+
+hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, const void* pdir, void* x, bool x64,
+                             void* r, SolveState* st, double* hist, Red red, hipStream_t s) {
+    return dispatch_dt(dt, [&](auto tag) {
+        using T = decltype(tag);
+        using C = typename Traits<T>::C;
+        return dispatch_cfg<Traits<T>::W>(p.cfg, [&]<int BX, int BY, int VX>() {
+            LoadField<T> ld{static_cast<const T*>(pdir)};
+            if (x64) {
+                OpUpdate<T, double, VX> op{static_cast<double*>(x), static_cast<T*>(r), st, C(0), 0.0};
+                return run_zmarch<ZF_UPDATE, C, BX, BY, VX, 1, 0u, true>(g, ld, op, FinBeta{st, hist}, red, &st->done, s);
+            }
+            OpUpdate<T, T, VX> op{static_cast<T*>(x), static_cast<T*>(r), st, C(0), 0.0};
+            return run_zmarch<ZF_UPDATE, C, BX, BY, VX, 1, 0u, true>(g, ld, op, FinBeta{st, hist}, red, &st->done, s);
+        });
+    });
+}
+
+hipError_t launch_pcg_start_x0(int dt, int xdt, const Plan& pres, const Geometry& gres, const void* b,
+                               const void* x0, void* r, SolveState* st, double* hist, Red red, hipStream_t s) {
+    const int cfg = TILE_CFGS[pres.cfg].vec ? 2 : 5;
+    return dispatch_dt(dt, [&](auto tag) {
+        using T = decltype(tag);
+        return dispatch_dt(xdt, [&](auto xtag) {
+            using X = decltype(xtag);
+            return dispatch_cfg<2>(cfg, [&]<int BX, int BY, int VX>() {
+                LoadWiden<X, double> ld{static_cast<const X*>(x0)};
+                OpInitResidual<T, VX> op{static_cast<const T*>(b), static_cast<T*>(r)};
+                return run_zmarch<ZF_START_X0, double, BX, BY, VX, 2, 0u, true>(gres, ld, op, FinStart{st, hist}, red, nullptr,
+                                                                   s);
+            });
+        });
+    });
+}
+
+}  // namespace pcgmi

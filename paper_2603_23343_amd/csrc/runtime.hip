@@ -1,0 +1,488 @@
+// runtime.hip -- the C ABI (include/pcgmi.h): contexts, workspace, argument
+// checking, error reporting and the PCG driver loop.
+//
+// The driver keeps every scalar of the iteration on the device (paper Sec. VII
+// keeps the BF16 solver's residual norm on the device for the same reason:
+// no host round trip per iteration). Iterations are replayed as captured HIP
+// graph chunks of C iterations; after each chunk a 96-byte copy of the solve
+// state goes to pinned host memory. The host waits on the PREVIOUS chunk's
+// copy while the current one runs, so the GPU never idles on the check; the
+// kernels of a chunk that starts after convergence return at once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "internal.hpp"
+#include "ops.hpp"
+#include "pcgmi.h"
+
+using namespace pcgmi;
+
+namespace {
+
+thread_local std::string g_err;
+
+pcg_status fail(pcg_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+pcg_status fail(pcg_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                                     \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess) return fail(PCG_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Do [a, a + abytes) and [b, b + bbytes) intersect?
+bool overlap2(const void* a, size_t abytes, const void* b, size_t bbytes) {
+    auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return abytes > 0 && bbytes > 0 && x < y + bbytes && y < x + abytes;
+}
+
+bool overlap(const void* a, const void* b, size_t bytes) { return overlap2(a, bytes, b, bytes); }
+
+}  // namespace
+
+namespace pcgmi {
+
+Geometry make_geometry(int nx, int ny, int nz, const Plan& p, int dt) {
+    Geometry g{};
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    const int tx = plan_tx(p, dt), ty = plan_ty(p);
+    g.ntx = (nx + tx - 1) / tx;
+    g.nty = (ny + ty - 1) / ty;
+    g.zc = std::max(1, std::min(p.zc, nz));
+    g.nzc = (nz + g.zc - 1) / g.zc;
+    g.nblocks = (unsigned)g.ntx * (unsigned)g.nty * (unsigned)g.nzc;
+    return g;
+}
+
+}  // namespace pcgmi
+
+struct pcg_ctx_s {
+    int nx = 0, ny = 0, nz = 0;
+    int64_t n = 0;
+    int dt = DT_F32;
+    hipStream_t stream = nullptr;   // caller's stream
+    hipStream_t capture = nullptr;  // private stream used only to capture graphs
+    pcg_options opt{};
+    Plan plan{};
+    Geometry geo{};      // iteration kernels
+    Plan plan_res{};
+    Geometry geo_res{};  // FP64 residual kernel
+    // workspace
+    void* r = nullptr;
+    void* p[2] = {nullptr, nullptr};
+    void* xacc = nullptr;  // FP64 or storage type (opt.x_accum_f64)
+    double* partials = nullptr;
+    size_t partials_cap = 0;  // doubles
+    unsigned* ticket = nullptr;
+    SolveState* st = nullptr;
+    double* hist = nullptr;
+    int hist_cap = 0;
+    double* res2 = nullptr;  // {||r||^2, max|r|}
+    // pinned host mirrors
+    SolveState* hst = nullptr;  // [2] ping-pong copies of the device state
+    double* hres = nullptr;     // [2]
+    // graph chunk
+    hipGraphExec_t chunk = nullptr;
+    int chunk_iters = 0;
+    hipEvent_t ev_chunk[2] = {nullptr, nullptr};
+    int last_iters = 0;
+};
+
+namespace {
+
+Red red_of(pcg_ctx c) { return Red{c->partials, c->ticket}; }
+
+void free_ctx(pcg_ctx c) {
+    if (!c) return;
+    if (c->chunk) (void)hipGraphExecDestroy(c->chunk);
+    for (auto& e : c->ev_chunk)
+        if (e) (void)hipEventDestroy(e);
+    void* dev[] = {c->r, c->p[0], c->p[1], c->xacc, c->partials, c->ticket, c->st, c->hist, c->res2};
+    for (void* d : dev)
+        if (d) (void)hipFree(d);
+    if (c->hst) (void)hipHostFree(c->hst);
+    if (c->hres) (void)hipHostFree(c->hres);
+    if (c->capture) (void)hipStreamDestroy(c->capture);
+    delete c;
+}
+
+// Default plan: 16 x 16 threads (a 64 x 16 FP32 footprint) with the z chunk
+// chosen so that the launch has about 2048 work-groups (8 per CU); the scalar
+// shape when nx is not a multiple of the 16-byte vector width.
+Plan default_plan(int nx, int ny, int nz, int dt, const pcg_options& o) {
+    Plan p{0, 16};
+    if (nx % dt_width(dt) != 0) p.cfg = 5;
+    if (o.tile_x > 0 || o.tile_y > 0) {
+        for (int c = 0; c < NUM_TILE_CFG; ++c) {
+            Plan q{c, 1};
+            if ((o.tile_x <= 0 || plan_tx(q, dt) == o.tile_x) && (o.tile_y <= 0 || plan_ty(q) == o.tile_y) &&
+                (TILE_CFGS[c].vec == (p.cfg != 5))) {
+                p.cfg = c;
+                break;
+            }
+        }
+    }
+    const int64_t tiles = (int64_t)((nx + plan_tx(p, dt) - 1) / plan_tx(p, dt)) *
+                          ((ny + plan_ty(p) - 1) / plan_ty(p));
+    int64_t zc = tiles * nz / 2048;
+    zc = std::max<int64_t>(4, std::min<int64_t>(64, zc));
+    p.zc = o.zchunk > 0 ? o.zchunk : (int)zc;
+    return p;
+}
+
+pcg_status ensure_hist(pcg_ctx c, int maxit) {
+    if (maxit + 1 <= c->hist_cap) return PCG_OK;
+    if (c->hist) HIPCHK(hipFree(c->hist));
+    c->hist = nullptr;
+    int cap = std::max(maxit + 1, 1024);
+    HIPCHK(hipMalloc(&c->hist, sizeof(double) * cap));
+    c->hist_cap = cap;
+    if (c->chunk) {  // captured kernels hold the old pointer
+        HIPCHK(hipGraphExecDestroy(c->chunk));
+        c->chunk = nullptr;
+    }
+    return PCG_OK;
+}
+
+// Enqueue iterations [first, first + count) on stream s. Iteration i reads
+// the direction buffer p[(i - 1) & 1] and writes p[i & 1].
+hipError_t enqueue_iters(pcg_ctx c, int first, int count, hipStream_t s, hipEvent_t* evs) {
+    const bool x64 = c->opt.x_accum_f64 != 0;
+    for (int i = first; i < first + count; ++i) {
+        void* pold = c->p[(i - 1) & 1];
+        void* pnew = c->p[i & 1];
+        if (evs) (void)hipEventRecord(evs[3 * (i - first)], s);
+        hipError_t e = launch_pcg_direction(c->dt, c->plan, c->geo, c->r, pold, pnew, c->st, red_of(c), s);
+        if (e != hipSuccess) return e;
+        if (evs) (void)hipEventRecord(evs[3 * (i - first) + 1], s);
+        e = launch_pcg_update(c->dt, c->plan, c->geo, pnew, c->xacc, x64, c->r, c->st, c->hist, red_of(c), s);
+        if (e != hipSuccess) return e;
+        if (evs) (void)hipEventRecord(evs[3 * (i - first) + 2], s);
+    }
+    return hipSuccess;
+}
+
+pcg_status ensure_chunk(pcg_ctx c) {
+    if (c->chunk) return PCG_OK;
+    if (!c->capture) HIPCHK(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_iters(c, 1, c->chunk_iters, c->capture, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(c->capture, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(PCG_E_HIP, "capturing the iteration chunk failed: %s", hipGetErrorString(e));
+    }
+    if (e2 != hipSuccess) return fail(PCG_E_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e2));
+    hipError_t e3 = hipGraphInstantiate(&c->chunk, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) {
+        c->chunk = nullptr;
+        return fail(PCG_E_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
+    }
+    return PCG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pcg_last_error(void) { return g_err.c_str(); }
+
+pcg_status pcg_options_default(pcg_options* o) {
+    if (!o) return fail(PCG_E_ARG, "pcg_options_default: null options");
+    std::memset(o, 0, sizeof *o);
+    o->chunk_iters = 16;
+    o->x_accum_f64 = 1;
+    o->x_dtype = -1;  // resolved at pcg_create: F32 storage -> F32, otherwise storage type
+    o->use_graph = 1;
+    return PCG_OK;
+}
+
+pcg_status pcg_create(pcg_ctx* out, int nx, int ny, int nz, pcg_dtype storage, void* hip_stream,
+                      const pcg_options* opt) {
+    if (!out) return fail(PCG_E_ARG, "pcg_create: null output handle");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(PCG_E_ARG, "pcg_create: dims must be >= 1 (got %d %d %d)", nx, ny, nz);
+    const int64_t n = (int64_t)nx * ny * nz;
+    if (n > (int64_t(1) << 33)) return fail(PCG_E_ARG, "pcg_create: grid too large (%lld points)", (long long)n);
+    if (storage < PCG_F32 || storage > PCG_F64) return fail(PCG_E_ARG, "pcg_create: bad storage dtype %d", (int)storage);
+    pcg_options o;
+    pcg_options_default(&o);
+    if (opt) o = *opt;
+    if (o.chunk_iters <= 0) o.chunk_iters = 16;
+    if (o.chunk_iters & 1) ++o.chunk_iters;
+    if (o.x_dtype < 0) o.x_dtype = storage;
+    if (o.x_dtype != storage && o.x_dtype != PCG_F64)
+        return fail(PCG_E_ARG, "pcg_create: x_dtype must be the storage type or PCG_F64");
+    if (storage == PCG_F64) o.x_accum_f64 = 1;
+
+    pcg_ctx c = new (std::nothrow) pcg_ctx_s();
+    if (!c) return fail(PCG_E_NOMEM, "pcg_create: out of host memory");
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->n = n;
+    c->dt = storage;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->opt = o;
+    c->plan = default_plan(nx, ny, nz, storage, o);
+    c->geo = make_geometry(nx, ny, nz, c->plan, storage);
+    c->plan_res = Plan{TILE_CFGS[c->plan.cfg].vec && (nx % 2 == 0) ? 2 : 5, c->plan.zc};
+    c->geo_res = make_geometry(nx, ny, nz, c->plan_res, DT_F64);
+    c->chunk_iters = o.chunk_iters;
+
+    const size_t es = dt_size(storage);
+    const size_t xs = o.x_accum_f64 ? 8 : es;
+    size_t maxblk = std::max<size_t>({(size_t)c->geo.nblocks, (size_t)c->geo_res.nblocks, (size_t)DOT_MAX_BLOCKS});
+    c->partials_cap = 2 * maxblk;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMalloc(&c->r, es * n);
+    if (e == hipSuccess) e = hipMalloc(&c->p[0], es * n);
+    if (e == hipSuccess) e = hipMalloc(&c->p[1], es * n);
+    if (e == hipSuccess) e = hipMalloc(&c->xacc, xs * n);
+    if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * c->partials_cap);
+    if (e == hipSuccess) e = hipMalloc(&c->ticket, 256);
+    if (e == hipSuccess) e = hipMalloc(&c->st, sizeof(SolveState));
+    if (e == hipSuccess) e = hipMalloc(&c->res2, 2 * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc(&c->hst, 2 * sizeof(SolveState), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&c->hres, 2 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_chunk[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_chunk[1], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        free_ctx(c);
+        return fail(e == hipErrorOutOfMemory ? PCG_E_NOMEM : PCG_E_HIP, "pcg_create: %s", hipGetErrorString(e));
+    }
+    e = launch_zero(DT_F64, 32, c->ticket, c->stream);  // 256 bytes
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        free_ctx(c);
+        return fail(PCG_E_HIP, "pcg_create: %s", hipGetErrorString(e));
+    }
+    pcg_status s = ensure_hist(c, 1023);
+    if (s != PCG_OK) {
+        free_ctx(c);
+        return s;
+    }
+    *out = c;
+    return PCG_OK;
+}
+
+pcg_status pcg_destroy(pcg_ctx c) {
+    if (!c) return PCG_OK;
+    (void)hipStreamSynchronize(c->stream);
+    free_ctx(c);
+    return PCG_OK;
+}
+
+pcg_status stencil_apply(pcg_ctx c, const void* x, void* y) {
+    if (!c) return fail(PCG_E_ARG, "stencil_apply: null context");
+    if (!x || !y) return fail(PCG_E_ARG, "stencil_apply: null pointer");
+    if (!aligned16(x) || !aligned16(y)) return fail(PCG_E_ARG, "stencil_apply: pointers must be 16-byte aligned");
+    if (overlap(x, y, (size_t)c->n * dt_size(c->dt))) return fail(PCG_E_ARG, "stencil_apply: x and y overlap");
+    HIPCHK(launch_stencil(c->dt, c->plan, c->geo, x, y, c->stream));
+    return PCG_OK;
+}
+
+pcg_status axpy(pcg_ctx c, int64_t n, float alpha, const void* x, const void* y, void* z) {
+    if (!c) return fail(PCG_E_ARG, "axpy: null context");
+    if (n < 0) return fail(PCG_E_ARG, "axpy: negative length");
+    if (n == 0) return PCG_OK;
+    if (!x || !y || !z) return fail(PCG_E_ARG, "axpy: null pointer");
+    if (!aligned16(x) || !aligned16(y) || !aligned16(z)) return fail(PCG_E_ARG, "axpy: pointers must be 16-byte aligned");
+    const size_t bytes = (size_t)n * dt_size(c->dt);
+    if ((z != x && overlap(z, x, bytes)) || (z != y && overlap(z, y, bytes)))
+        return fail(PCG_E_ARG, "axpy: z partially overlaps an input");
+    HIPCHK(launch_axpy(c->dt, n, alpha, x, y, z, c->stream));
+    return PCG_OK;
+}
+
+static pcg_status dot_common(pcg_ctx c, int64_t n, const void* x, const void* y, float* of, double* od,
+                             const char* name) {
+    if (!c) return fail(PCG_E_ARG, "%s: null context", name);
+    if (n < 0) return fail(PCG_E_ARG, "%s: negative length", name);
+    if (!of && !od) return fail(PCG_E_ARG, "%s: null output", name);
+    if (n > 0 && (!x || !y)) return fail(PCG_E_ARG, "%s: null pointer", name);
+    if ((n > 0 && (!aligned16(x) || !aligned16(y))))
+        return fail(PCG_E_ARG, "%s: pointers must be 16-byte aligned", name);
+    HIPCHK(launch_dot(c->dt, n, x, y, of, od, red_of(c), c->stream));
+    return PCG_OK;
+}
+
+pcg_status dot(pcg_ctx c, int64_t n, const void* x, const void* y, float* out_dev) {
+    return dot_common(c, n, x, y, out_dev, nullptr, "dot");
+}
+
+pcg_status dot_f64(pcg_ctx c, int64_t n, const void* x, const void* y, double* out_dev) {
+    return dot_common(c, n, x, y, nullptr, out_dev, "dot_f64");
+}
+
+pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, pcg_info* info) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!c) return fail(PCG_E_ARG, "pcg_solve: null context");
+    if (!b || !x) return fail(PCG_E_ARG, "pcg_solve: null pointer");
+    if (!aligned16(b) || !aligned16(x)) return fail(PCG_E_ARG, "pcg_solve: pointers must be 16-byte aligned");
+    if (!(rtol >= 0.0) || maxit < 0) return fail(PCG_E_ARG, "pcg_solve: rtol must be >= 0 and maxit >= 0");
+    const size_t xbytes = (size_t)c->n * dt_size(c->opt.x_dtype);
+    if (overlap2(b, (size_t)c->n * dt_size(c->dt), x, xbytes))
+        return fail(PCG_E_ARG, "pcg_solve: b and x overlap");
+    pcg_status s = ensure_hist(c, maxit);
+    if (s != PCG_OK) return s;
+    hipStream_t st = c->stream;
+    const bool x64 = c->opt.x_accum_f64 != 0;
+    const int xacc_dt = x64 ? DT_F64 : c->dt;
+
+    // Host-side initial state: rtol^2 (scaled by ||b||^2 on the device), 1/6, maxit.
+    SolveState init{};
+    init.tol2 = rtol * rtol;
+    init.dinv = 1.0 / 6.0;
+    init.maxit = maxit;
+    c->hst[0] = init;
+    HIPCHK(hipMemcpyAsync(c->st, &c->hst[0], sizeof(SolveState), hipMemcpyHostToDevice, st));
+    if (c->opt.use_x0) {
+        HIPCHK(launch_convert(c->opt.x_dtype, xacc_dt, c->n, x, c->xacc, st));
+        HIPCHK(launch_zero(c->dt, c->n, c->p[0], st));
+        HIPCHK(launch_zero(c->dt, c->n, c->p[1], st));
+        HIPCHK(launch_pcg_start_x0(c->dt, xacc_dt, c->plan_res, c->geo_res, b, c->xacc, c->r, c->st, c->hist,
+                                   red_of(c), st));
+    } else {
+        HIPCHK(launch_pcg_start_zero(c->dt, c->n, b, c->r, c->xacc, x64, c->p[0], c->p[1], c->st, c->hist,
+                                     red_of(c), st));
+    }
+
+    const int C = c->chunk_iters;
+    const bool timing = c->opt.kernel_timing != 0;
+    const bool graph = c->opt.use_graph && !timing;
+    if (graph) {
+        s = ensure_chunk(c);
+        if (s != PCG_OK) return s;
+    }
+    hipEvent_t* evs = nullptr;
+    std::string err;
+    double k1 = 0.0, k2 = 0.0;
+    int nk = 0;
+    if (timing) {
+        evs = new hipEvent_t[3 * C];
+        for (int i = 0; i < 3 * C; ++i) (void)hipEventCreate(&evs[i]);
+    }
+    auto cleanup = [&]() {
+        if (evs) {
+            for (int i = 0; i < 3 * C; ++i) (void)hipEventDestroy(evs[i]);
+            delete[] evs;
+            evs = nullptr;
+        }
+    };
+
+    // Chunk loop: launch chunk k, queue its state copy, then wait for chunk k-1's copy.
+    int launched = 0, slot = 0;
+    bool finished = false;
+    SolveState fin{};
+    HIPCHK(hipMemcpyAsync(&c->hst[1], c->st, sizeof(SolveState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(c->ev_chunk[1], st));
+    HIPCHK(hipEventSynchronize(c->ev_chunk[1]));
+    fin = c->hst[1];
+    if (fin.done != 0) finished = true;
+    bool pending = false;
+    int pend_slot = 0;
+    while (!finished) {
+        if (launched < maxit) {
+            hipError_t e;
+            if (graph) e = hipGraphLaunch(c->chunk, st);
+            else e = enqueue_iters(c, launched + 1, C, st, evs);
+            if (e != hipSuccess) {
+                cleanup();
+                return fail(PCG_E_HIP, "pcg_solve: launching iterations failed: %s", hipGetErrorString(e));
+            }
+            launched += C;
+            if (timing) {
+                // Eager timing mode: wait for this chunk and sum its kernel times.
+                (void)hipEventSynchronize(evs[3 * C - 1]);
+                for (int i = 0; i < C; ++i) {
+                    float a = 0.f, b2 = 0.f;
+                    (void)hipEventElapsedTime(&a, evs[3 * i], evs[3 * i + 1]);
+                    (void)hipEventElapsedTime(&b2, evs[3 * i + 1], evs[3 * i + 2]);
+                    k1 += a;
+                    k2 += b2;
+                }
+                nk += C;
+            }
+            HIPCHK(hipMemcpyAsync(&c->hst[slot], c->st, sizeof(SolveState), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipEventRecord(c->ev_chunk[slot], st));
+        }
+        if (pending) {
+            HIPCHK(hipEventSynchronize(c->ev_chunk[pend_slot]));
+            fin = c->hst[pend_slot];
+            if (fin.done != 0) finished = true;
+        }
+        if (launched >= maxit && !finished) {
+            // Nothing more to launch: wait for the last chunk.
+            HIPCHK(hipEventSynchronize(c->ev_chunk[slot]));
+            fin = c->hst[slot];
+            finished = true;
+        }
+        pending = true;
+        pend_slot = slot;
+        slot ^= 1;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(&fin, c->st, sizeof(SolveState), hipMemcpyDeviceToHost));
+    cleanup();
+
+    // Result to the caller's x, then the FP64 true residual of what is returned.
+    if (c->opt.x_dtype == xacc_dt) HIPCHK(hipMemcpyAsync(x, c->xacc, xbytes, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(launch_convert(xacc_dt, c->opt.x_dtype, c->n, c->xacc, x, st));
+    if (fin.rr0 == 0.0) HIPCHK(launch_zero(c->opt.x_dtype, c->n, x, st));
+    HIPCHK(launch_residual64(c->dt, c->opt.x_dtype, c->plan_res, c->geo_res, b, x, c->res2, red_of(c), st));
+    HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    c->last_iters = fin.iters;
+
+    pcg_status ret = PCG_OK;
+    if (fin.done == 2) ret = PCG_E_BREAKDOWN;
+    else if (fin.done != 1) ret = PCG_E_NOCONV;
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->iters = fin.iters;
+        info->status = ret;
+        info->rel_res_recursive = fin.rr0 > 0 ? std::sqrt(fin.rr / fin.rr0) : 0.0;
+        info->rel_res_true_fp64 = fin.rr0 > 0 ? std::sqrt(c->hres[0] / fin.rr0) : 0.0;
+        info->k1_ms = k1;
+        info->k2_ms = k2;
+        info->k1_launches = nk;
+        info->k2_launches = nk;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (ret == PCG_E_BREAKDOWN) fail(ret, "pcg_solve: breakdown (p.Ap <= 0 or a non-finite value) at iteration %d", fin.iters + 1);
+    else if (ret == PCG_E_NOCONV) fail(ret, "pcg_solve: no convergence in %d iterations", maxit);
+    return ret;
+}
+
+pcg_status pcg_get_history(pcg_ctx c, double* hist, int n, int* count) {
+    if (!c || !hist || !count || n < 0) return fail(PCG_E_ARG, "pcg_get_history: bad argument");
+    int m = std::min(n, c->last_iters + 1);
+    m = std::min(m, c->hist_cap);
+    HIPCHK(hipMemcpy(hist, c->hist, sizeof(double) * m, hipMemcpyDeviceToHost));
+    *count = m;
+    return PCG_OK;
+}
+
+}  // extern "C"

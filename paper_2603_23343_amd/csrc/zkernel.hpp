@@ -1,0 +1,98 @@
+// zkernel.hpp -- the generic z-march kernel and the dispatch over storage
+// types and compiled work-group shapes.
+#pragma once
+
+#include "ops.hpp"
+
+namespace pcgmi {
+
+// One work-group per (x-y tile, z chunk). NC reduction components are
+// combined over the grid (component c maxed when bit c of MM is set) and
+// handed to fin by the last work-group. A set *done skips the launch's work:
+// captured PCG iterations after convergence cost only the launch.
+template <typename C, int BX, int BY, int VX, int NC, unsigned MM, bool RED, class L, class O, class F>
+__device__ __forceinline__ void zmarch_body(const Grid3& g, const L& ld, const O& op, const F& fin, Red red,
+                                            const int* done) {
+    if (done != nullptr && *done != 0) return;
+    using ZT = ZTile<C, BX, BY, VX>;
+    __shared__ __attribute__((aligned(16))) C lds[2 * ZT::PLANE];
+    __shared__ double rscratch[NC * 16];
+    L l = ld;
+    O o = op;
+    l.init();
+    o.init();
+    const unsigned tile = xcd_remap(blockIdx.x, g.nblocks);
+    C acc[NC];
+    zmarch<C, BX, BY, VX, NC>(g, tile, l, o, acc, lds);
+    if constexpr (RED) {
+        double v[NC], tot[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = (double)acc[c];
+        if (grid_reduce<NC, MM>(v, red.partials, red.ticket, g.nblocks, blockIdx.x, rscratch, tot) &&
+            threadIdx.x == 0)
+            fin(tot);
+    }
+}
+
+// One __global__ name per kernel family (so profiles tell them apart), all
+// running the same body.
+#define PCGMI_ZKERNEL(NAME)                                                                                 \
+    template <typename C, int BX, int BY, int VX, int NC, unsigned MM, bool RED, class L, class O, class F> \
+    __global__ void __launch_bounds__(BX* BY) NAME(Grid3 g, L ld, O op, F fin, Red red, const int* done) {  \
+        zmarch_body<C, BX, BY, VX, NC, MM, RED>(g, ld, op, fin, red, done);                                 \
+    }
+PCGMI_ZKERNEL(k_stencil)
+PCGMI_ZKERNEL(k_pcg_direction)
+PCGMI_ZKERNEL(k_pcg_update)
+PCGMI_ZKERNEL(k_residual64)
+PCGMI_ZKERNEL(k_start_x0)
+PCGMI_ZKERNEL(k_zgeneric)
+
+enum ZFamily { ZF_STENCIL, ZF_DIRECTION, ZF_UPDATE, ZF_RESIDUAL64, ZF_START_X0, ZF_GENERIC };
+
+template <int FAM, typename C, int BX, int BY, int VX, int NC, unsigned MM, bool RED, class L, class O, class F>
+hipError_t run_zmarch(const Grid3& g, const L& ld, const O& op, const F& fin, Red red, const int* done,
+                      hipStream_t s) {
+    if (g.nblocks == 0) return hipSuccess;
+    const dim3 grid(g.nblocks), block(BX * BY);
+    if constexpr (FAM == ZF_STENCIL)
+        hipLaunchKernelGGL((k_stencil<C, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+    else if constexpr (FAM == ZF_DIRECTION)
+        hipLaunchKernelGGL((k_pcg_direction<C, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+    else if constexpr (FAM == ZF_UPDATE)
+        hipLaunchKernelGGL((k_pcg_update<C, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+    else if constexpr (FAM == ZF_RESIDUAL64)
+        hipLaunchKernelGGL((k_residual64<C, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+    else if constexpr (FAM == ZF_START_X0)
+        hipLaunchKernelGGL((k_start_x0<C, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+    else
+        hipLaunchKernelGGL((k_zgeneric<C, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+    return hipGetLastError();
+}
+
+// Calls f.template operator()<BX, BY, VX>() for compiled shape cfg, W being
+// the 16-byte vector width of the kernel's storage type.
+template <int W, class F> hipError_t dispatch_cfg(int cfg, F&& f) {
+    switch (cfg) {
+        case 0: return f.template operator()<16, 16, W>();
+        case 1: return f.template operator()<32, 8, W>();
+        case 2: return f.template operator()<64, 4, W>();
+        case 3: return f.template operator()<16, 4, W>();
+        case 4: return f.template operator()<16, 8, W>();
+        case 5: return f.template operator()<64, 4, 1>();
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Calls f(T{}) with T the storage type of dt.
+template <class F> hipError_t dispatch_dt(int dt, F&& f) {
+    switch (dt) {
+        case DT_F32: return f(float{});
+        case DT_BF16: return f(bf16{});
+        case DT_F16: return f(_Float16{});
+        case DT_F64: return f(double{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace pcgmi

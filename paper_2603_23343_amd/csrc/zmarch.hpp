@@ -1,0 +1,236 @@
+// zmarch.hpp -- the z-pencil streaming skeleton of every seven-point kernel.
+//
+// The paper (Sec. VI-A) gives each Tensix core a column of tiles: its x-y
+// footprint over all z. Here a work-group owns a TX x TY footprint and a
+// chunk of ZC planes and marches up z:
+//   * z neighbours live in registers (planes k-1, k, k+1 of the thread's own
+//     points), so each plane is read from HBM once;
+//   * x/y neighbours come from a double-buffered LDS copy of plane k with a
+//     one-point halo ring; halo rows/columns are loaded by a few threads and
+//     mostly hit L2, since neighbouring tiles run on the same XCD;
+//   * loads run D planes ahead of use through a register pipeline. Every
+//     load is issued unconditionally (out-of-grid lanes read element 0 and
+//     are zeroed when the value is consumed), so the compiler's wait for a
+//     load lands where its value is used, D planes later, not at the load;
+//   * points outside the grid read as 0 (zero Dirichlet ghosts, Sec. VII),
+//     which replaces the paper's zero-fill pass.
+// One __syncthreads per plane: a thread can only overwrite an LDS buffer two
+// planes later, after every thread has passed the barrier of the plane in
+// between.
+//
+// A kernel is the skeleton plus two functors:
+//   Loader -- produces the values of the field the stencil is applied to
+//             (a plain load, or p = D^-1 r + beta p_old computed on the fly,
+//             halo included). fetch() issues loads into a raw register set,
+//             finish() turns a raw set into compute-type values.
+//   Op     -- fetch() issues the loads of the op's own streams for a plane;
+//             apply() consumes, per thread and plane, those raw registers,
+//             the centre values c[] and the stencil result ax[] of VX
+//             consecutive points, and may accumulate NC reduction components.
+#pragma once
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace pcgmi {
+
+// Tiles in x and y, z chunks of zc planes, nblocks = ntx * nty * nzc.
+using Grid3 = Geometry;
+
+template <typename C, int VX> struct Pts {
+    C v[VX];
+};
+
+// N consecutive elements of T held as loaded (16-byte vector loads when the
+// run is a whole number of 16-byte vectors, element loads otherwise).
+template <typename T, int N, bool V = (N * sizeof(T) >= 16 && (N * sizeof(T)) % 16 == 0)> struct RawN;
+template <typename T, int N> struct RawN<T, N, true> {
+    static constexpr int W = 16 / (int)sizeof(T);
+    static constexpr int NV = N / W;
+    Vec16<T> v[NV];
+    __device__ __forceinline__ void load(const T* p) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = reinterpret_cast<const Vec16<T>*>(p)[i];
+    }
+    __device__ __forceinline__ typename Traits<T>::C get(int i) const { return to_c(v[i / W].e[i % W]); }
+};
+template <typename T, int N> struct RawN<T, N, false> {
+    T e[N];
+    __device__ __forceinline__ void load(const T* p) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) e[i] = p[i];
+    }
+    __device__ __forceinline__ typename Traits<T>::C get(int i) const { return to_c(e[i]); }
+};
+
+// LDS row pitch: interior starts at column PAD (16-byte aligned), left halo at
+// PAD-1, right halo at PAD+TX.
+template <typename C> struct LdsPad {
+    static constexpr int PAD = 16 / (int)sizeof(C);
+};
+
+template <typename C, int BX, int BY, int VX> struct ZTile {
+    static constexpr int TX = BX * VX, TY = BY, NT = BX * BY;
+    static constexpr int PAD = LdsPad<C>::PAD;
+    static constexpr int PITCH = TX + 2 * PAD;
+    static constexpr int PLANE = (TY + 2) * PITCH;
+    static_assert(2 * BX + 2 * TY <= NT, "not enough threads for the halo ring");
+};
+
+constexpr int ZM_DEPTH = 2;  // planes of look-ahead of every load
+
+// Runs the z-march for logical tile `tile`. Returns the op's accumulators in acc.
+template <typename C, int BX, int BY, int VX, int NC, class Loader, class Op>
+__device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Loader& ld, const Op& op,
+                                       C (&acc)[NC], C* lds /* 2 * ZTile::PLANE elements */) {
+    using ZT = ZTile<C, BX, BY, VX>;
+    using FRaw = typename Loader::template Raw<VX>;
+    using ORaw = typename Op::Raw;
+    constexpr int D = ZM_DEPTH;
+
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, ty = tid / BX;
+    const int bx = (int)(tile % (unsigned)g.ntx);
+    const int by = (int)((tile / (unsigned)g.ntx) % (unsigned)g.nty);
+    const int bz = (int)(tile / ((unsigned)g.ntx * (unsigned)g.nty));
+    const int x0 = bx * ZT::TX, y0 = by * ZT::TY;
+    const int z0 = bz * g.zc;
+    const int z1 = min(z0 + g.zc, g.nz);
+    const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+
+    const int xs = x0 + tx * VX, ys = y0 + ty;
+    const bool own = (xs < g.nx) && (ys < g.ny);  // nx % VX == 0 on the vector path
+    const int64_t col = (int64_t)ys * sy + xs;
+
+    // Halo duty: threads [0, 2BX) load one vector of the y-halo rows,
+    // threads [2BX, 2BX + 2TY) the aligned vector holding one point of the
+    // x-halo columns (left: last element of the vector before the tile,
+    // right: first element of the vector after it), so every halo load is
+    // the same 16-byte load and needs no branch.
+    int hkind = 0;  // 0 none, 1 y-row vector, 2 x-column point
+    int hvx = 0, hy = 0, lds_off = 0, hsel = 0;
+    bool hvalid = false;
+    if (tid < 2 * BX) {
+        hkind = 1;
+        int row = tid < BX ? -1 : ZT::TY;
+        int v = tid % BX;
+        hvx = x0 + v * VX;
+        hy = y0 + row;
+        hvalid = hvx < g.nx && hy >= 0 && hy < g.ny;
+        lds_off = (row + 1) * ZT::PITCH + ZT::PAD + v * VX;
+    } else if (tid < 2 * BX + 2 * ZT::TY) {
+        hkind = 2;
+        int t = tid - 2 * BX;
+        int side = t / ZT::TY, row = t % ZT::TY;
+        const int hx = side == 0 ? x0 - 1 : x0 + ZT::TX;
+        hvx = side == 0 ? x0 - VX : x0 + ZT::TX;
+        hsel = side == 0 ? VX - 1 : 0;
+        hy = y0 + row;
+        hvalid = hx >= 0 && hx < g.nx && hy < g.ny;
+        lds_off = (row + 1) * ZT::PITCH + (side == 0 ? ZT::PAD - 1 : ZT::PAD + ZT::TX);
+    }
+    const int64_t hcol = (int64_t)hy * sy + hvx;
+
+    // fvalid/hval_ok: the point exists (else it reads as 0). Fetches also skip
+    // planes the chunk never consumes (field planes above z1, halo and op
+    // planes from z1 on); skipped and invalid lanes read element 0.
+    auto fvalid = [&](int k) { return own && k >= 0 && k < g.nz; };
+    auto hval_ok = [&](int k) { return hvalid && k >= 0 && k < g.nz; };
+    auto fetch_plane = [&](int k, FRaw& r) {
+        ld.template fetch<VX>((fvalid(k) && k <= z1) ? col + k * sz : 0, r);
+    };
+    auto fetch_halo = [&](int k, FRaw& r) {
+        ld.template fetch<VX>((hval_ok(k) && k < z1) ? hcol + k * sz : 0, r);
+    };
+    auto finish_plane = [&](int k, const FRaw& r, Pts<C, VX>& out) {
+        ld.template finish<VX>(r, out.v);
+        const bool ok = fvalid(k);
+#pragma unroll
+        for (int i = 0; i < VX; ++i) out.v[i] = ok ? out.v[i] : C(0);
+    };
+    auto finish_halo = [&](int k, const FRaw& r, Pts<C, VX>& out) {
+        ld.template finish<VX>(r, out.v);
+        const bool ok = hval_ok(k);
+        if (hkind == 2) out.v[0] = hsel == 0 ? out.v[0] : out.v[VX - 1];
+#pragma unroll
+        for (int i = 0; i < VX; ++i) out.v[i] = ok ? out.v[i] : C(0);
+    };
+    auto fetch_op = [&](int k, ORaw& r) { op.fetch((fvalid(k) && k < z1) ? col + k * sz : 0, r); };
+
+    // Pipeline (two slots, D = 2 planes of look-ahead). At the top of step k:
+    //   zm, zcur, zp : values of planes k-1, k, k+1
+    //   f[s]         : raw loads of plane k+2   (s = (k - z0) & 1; the other
+    //                  slot holds plane k+3)
+    //   hv           : halo values of plane k;  h[s]: raw halo of plane k+1
+    //   o[s]         : raw op loads of plane k
+    // A slot is consumed first and then refilled with the plane two steps on,
+    // so no register of an in-flight load is ever copied (a copy would make
+    // the compiler wait for the load). The loop is unrolled by two so slot
+    // roles are static.
+    static_assert(ZM_DEPTH == 2, "the slot rotation below assumes two planes of look-ahead");
+    Pts<C, VX> zm, zcur, zp, hv;
+    FRaw f0, f1, h0, h1;
+    ORaw o0, o1;
+    {
+        FRaw t;
+        fetch_plane(z0 - 1, t);
+        finish_plane(z0 - 1, t, zm);
+        fetch_plane(z0, t);
+        finish_plane(z0, t, zcur);
+        fetch_plane(z0 + 1, t);
+        finish_plane(z0 + 1, t, zp);
+        fetch_halo(z0, t);
+        finish_halo(z0, t, hv);
+    }
+    fetch_plane(z0 + 2, f0);
+    fetch_plane(z0 + 3, f1);
+    fetch_halo(z0 + 1, h0);
+    fetch_halo(z0 + 2, h1);
+    fetch_op(z0, o0);
+    fetch_op(z0 + 1, o1);
+
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = C(0);
+
+    const int lrow = (ty + 1) * ZT::PITCH + ZT::PAD + tx * VX;
+    auto step = [&](int k, C* buf, FRaw& f, FRaw& h, ORaw& o) {
+        // Stage plane k: own points and halo.
+#pragma unroll
+        for (int i = 0; i < VX; ++i) buf[lrow + i] = zcur.v[i];
+        if (hkind == 1) {
+#pragma unroll
+            for (int i = 0; i < VX; ++i) buf[lds_off + i] = hv.v[i];
+        } else if (hkind == 2) {
+            buf[lds_off] = hv.v[0];
+        }
+        // Consume this slot's field and halo loads, refill it two planes on.
+        Pts<C, VX> znext, hnext;
+        finish_plane(k + 2, f, znext);
+        fetch_plane(k + 4, f);
+        finish_halo(k + 1, h, hnext);
+        fetch_halo(k + 3, h);
+        __syncthreads();
+        Pts<C, VX> ax;
+        const C* up = buf + lrow + ZT::PITCH;
+        const C* dn = buf + lrow - ZT::PITCH;
+        const C left = buf[lrow - 1], right = buf[lrow + VX];
+#pragma unroll
+        for (int i = 0; i < VX; ++i) {
+            C l = i == 0 ? left : zcur.v[i - 1];
+            C r = i == VX - 1 ? right : zcur.v[i + 1];
+            ax.v[i] = C(6) * zcur.v[i] - l - r - dn[i] - up[i] - zm.v[i] - zp.v[i];
+        }
+        if (own) op.apply(col + k * sz, o, zcur.v, ax.v, acc);
+        fetch_op(k + 2, o);
+        zm = zcur;
+        zcur = zp;
+        zp = znext;
+        hv = hnext;
+    };
+    for (int k = z0; k < z1; k += 2) {
+        step(k, lds, f0, h0, o0);
+        if (k + 1 < z1) step(k + 1, lds + ZT::PLANE, f1, h1, o1);
+    }
+}
+
+}  // namespace pcgmi
