@@ -5,6 +5,9 @@ Step = one full FP32 Jacobi-PCG solve (x0 = 0, recursive relative residual
 + 1e-3 U[-1,1] noise (seed 4). `value` = seconds per solve (lower is better).
 
 Also reported on the same JSON line:
+  refined       -- FP64 iterative refinement around BF16 / FP16 Jacobi-PCG on
+                   the same system: seconds to FP64 true residual 1e-6 and
+                   1e-10 (the FP32 solve's own true residual is in config);
   roofline      -- the dominant kernel (the PCG update kernel) measured with
                    HIP events on the library's stream in an event-timed solve
                    of the same workload, against 8 TB/s;
@@ -144,6 +147,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernels", action="store_true")
+    ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--maxit", type=int, default=5000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -169,6 +173,7 @@ def main():
         infos.append(P.pcg_solve(ctx, b, x, 1e-6, args.maxit))
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    dt_solve = dt
     info = infos[-1]
     iters = info["iters"]
     print(f"# solve: {iters} iterations, {dt * 1e3:.2f} ms, recursive {info['rel_res_recursive']:.3e}, "
@@ -191,6 +196,24 @@ def main():
                 "event_timed_solve_ms": round(tinfo["seconds"] * 1e3, 2)}
     P.pcg_destroy(tctx)
 
+    # Mixed-precision refinement on the same system: FP64 outer loop, BF16 /
+    # FP16 inner Jacobi-PCG; time to FP64 true residual 1e-6 and 1e-10.
+    refined = {}
+    if not args.no_refined:
+        for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+            rctx = P.pcg_create(n, n, n, dt, x_accum_f64=0)
+            x64 = torch.empty(N, dtype=torch.float64, device="cuda")
+            P.pcg_solve_refined(rctx, b64, x64, rtol_outer=1e-10)
+            torch.cuda.synchronize()
+            r = P.pcg_solve_refined(rctx, b64, x64, rtol_outer=1e-10)
+            refined[name] = {"t_1e6_s": round(r["t_1e6"], 5), "t_1e10_s": round(r["t_1e10"], 5),
+                             "outer": r["outer_iters"], "inner_total": r["iters"],
+                             "final_true_relres": r["rel_res_true_fp64"],
+                             "speedup_vs_fp32_pcg_to_1e-6_recursive": round(dt_solve / max(r["t_1e6"], 1e-9), 3)}
+            P.pcg_destroy(rctx)
+            del x64
+        print(f"# refined: {refined}", file=sys.stderr, flush=True)
+
     kern = None
     if not args.no_kernels:
         del ctx
@@ -211,6 +234,7 @@ def main():
                    "rel_res_true_fp64": info["rel_res_true_fp64"],
                    "per_iteration_us": round(dt * 1e6 / max(iters, 1), 2)},
         "roofline": roofline,
+        "refined": refined or None,
         "kernels_512": kern,
         "cpu_baseline": cpu,
     }

@@ -117,6 +117,31 @@ pcg_status dot_f64(pcg_ctx ctx, int64_t n, const void *x, const void *y, double 
  * info may be NULL. Blocks until the solve is finished. */
 pcg_status pcg_solve(pcg_ctx ctx, const void *b, void *x, double rtol, int maxit, pcg_info *info);
 
+/* Mixed-precision iterative refinement (Wilkinson 1963; Moler 1967) around
+ * the paper's Jacobi-PCG (Sec. VII): b64 and x64 are FP64 device vectors on
+ * the context's grid; the context's storage type (F32, BF16 or F16) is the
+ * inner solver's. From x = 0:
+ *   loop: r = b - A x in FP64 (GPU); stop when ||r|| / ||b|| <= rtol_outer
+ *         or after max_outer corrections;
+ *         s = 1 / max|r|; rhat = storage(s r) (FP64 -> FP32 -> storage,
+ *         nearest even); inner Jacobi-PCG A d = rhat in the storage type with
+ *         FP32 arithmetic, stopped at ||r_in|| <= rtol_inner ||rhat||, at
+ *         maxit_inner, or when ||r_in|| fell by less than 10% over 20
+ *         iterations; d accumulates in FP64 when the context's x_accum_f64
+ *         is set, else in the storage type; x += d / s in FP64.
+ * info: iters = total inner iterations, outer_iters, rel_res_true_fp64 (the
+ * last FP64 residual), t_1e6 / t_1e10 = seconds until the FP64 residual
+ * first reached 1e-6 / 1e-10 (-1 if never). Returns PCG_OK when the
+ * tolerance was met, PCG_E_NOCONV otherwise (x holds the last iterate),
+ * PCG_E_UNSUPPORTED for F64 storage. Blocks until done. */
+pcg_status pcg_solve_refined(pcg_ctx ctx, const double *b64, double *x64, double rtol_outer, double rtol_inner,
+                             int max_outer, int maxit_inner, pcg_info *info);
+
+/* The last pcg_solve_refined's FP64 relative residual before each outer
+ * step (relres, may be NULL) and the inner iterations of each step
+ * (inner_iters, may be NULL), n entries at most; *count = entries written. */
+pcg_status pcg_refine_history(pcg_ctx ctx, double *relres, int *inner_iters, int n, int *count);
+
 /* Copy the recursive relative residuals ||r_k||/||b||, k = 0..iters of the
  * last pcg_solve on this context, to the host array hist (n entries at most).
  * *count receives the number written. */

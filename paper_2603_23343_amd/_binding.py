@@ -63,6 +63,8 @@ def _load():
         "dot_f64": ([vp, i64, vp, vp, vp], i),
         "pcg_solve": ([vp, vp, vp, d, i, ctypes.POINTER(PcgInfo)], i),
         "pcg_get_history": ([vp, ctypes.POINTER(d), i, ctypes.POINTER(i)], i),
+        "pcg_solve_refined": ([vp, vp, vp, d, d, i, i, ctypes.POINTER(PcgInfo)], i),
+        "pcg_refine_history": ([vp, ctypes.POINTER(d), ctypes.POINTER(i), i, ctypes.POINTER(i)], i),
         "pcg_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -192,3 +194,29 @@ def pcg_get_history(ctx: Context, n=1 << 20):
     _check(lib.pcg_get_history(ctx.handle, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n,
                                ctypes.byref(cnt)))
     return buf[: cnt.value].copy()
+
+
+def pcg_solve_refined(ctx: Context, b64, x64, rtol_outer=1e-10, rtol_inner=None, max_outer=30, maxit_inner=2000,
+                      raise_on_error=True) -> dict:
+    """FP64 iterative refinement around the context's reduced-precision PCG."""
+    if rtol_inner is None:
+        rtol_inner = 1e-2 if ctx.dtype == torch.bfloat16 else 1e-3
+    info = PcgInfo()
+    st = lib.pcg_solve_refined(ctx.handle, _ptr(b64), _ptr(x64), float(rtol_outer), float(rtol_inner),
+                               int(max_outer), int(maxit_inner), ctypes.byref(info))
+    out = info.as_dict()
+    out["status"] = st
+    if st != PCG_OK and (raise_on_error or st not in (PCG_E_NOCONV, PCG_E_BREAKDOWN)):
+        raise PcgError(st, pcg_last_error())
+    return out
+
+
+def pcg_refine_history(ctx: Context, n=256):
+    import numpy as np
+
+    rel = np.zeros(n, dtype=np.float64)
+    inner = np.zeros(n, dtype=np.int32)
+    cnt = ctypes.c_int(0)
+    _check(lib.pcg_refine_history(ctx.handle, rel.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  inner.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), n, ctypes.byref(cnt)))
+    return rel[: cnt.value].copy(), inner[: max(cnt.value - 1, 0)].copy()

@@ -66,6 +66,12 @@ hipError_t launch_pcg_start_x0(int dt, int xdt, const Plan& pres, const Geometry
 hipError_t launch_residual64(int bdt, int xdt, const Plan& p, const Geometry& g, const void* b, const void* x,
                              double* out, Red red, hipStream_t s);
 
+// Refinement: rhat (storage type dt) = stored(scale (b - A x)), FP64 b and x.
+hipError_t launch_cast_scaled(int dt, const Plan& pres, const Geometry& gres, const double* b, const double* x,
+                              double scale, void* rhat, hipStream_t s);
+// Refinement: x += d / scale, d of type ddt.
+hipError_t launch_correct(int ddt, int64_t n, const void* d, double scale, double* x, hipStream_t s);
+
 // ---- streaming kernels ----
 hipError_t launch_axpy(int dt, int64_t n, float alpha, const void* x, const void* y, void* z, hipStream_t s);
 // out_f32 and/or out_f64 (device) receive the dot; either may be null.

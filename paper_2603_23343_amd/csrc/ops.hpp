@@ -20,9 +20,9 @@ struct SolveState {
     double tol2;   // (rtol ||b||)^2
     double dinv;   // 1 / diagonal (constant-coefficient operator)
     int iters;     // completed iterations
-    int done;      // 0 running, 1 converged, 2 breakdown, 3 maxit reached
+    int done;      // 0 running, 1 converged, 2 breakdown, 3 maxit reached, 4 stagnated
     int maxit;
-    int pad;
+    int stag;      // > 0: stop when ||r|| fell by less than 10% over stag iterations
 };
 
 // ---------------------------------------------------------------- loaders
@@ -202,6 +202,28 @@ template <typename B, int VX> struct OpResidual64 {
     }
 };
 
+// Scaled residual for refinement: rhat = stored(s (b - A x)) with b, x and
+// the arithmetic in FP64, rounded FP64 -> FP32 -> storage type.
+template <typename T, int VX> struct OpCastScaled {
+    struct Raw {
+        RawN<double, VX> b;
+    };
+    const double* __restrict__ b;
+    T* __restrict__ rhat;
+    double scale;
+    __device__ void init() {}
+    __device__ __forceinline__ void fetch(int64_t i, Raw& raw) const { raw.b.load(b + i); }
+    template <int NC>
+    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const double* c, const double* ax,
+                                          double (&acc)[NC]) const {
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            const double rv = scale * (raw.b.get(v) - ax[v]);
+            rhat[i + v] = from_c<T>((typename Traits<T>::C)rv);
+        }
+    }
+};
+
 // Residual of an initial guess, computed in FP64 and rounded to the storage
 // type (through FP32 for 16-bit types): r = stored(b - A x0); accumulates
 // r.r of the stored residual and b.b.
@@ -269,6 +291,10 @@ struct FinBeta {
         }
         if (it >= st->maxit) {
             st->done = 3;
+            return;
+        }
+        if (st->stag > 0 && hist && it >= st->stag && sqrt(rr / st->rr0) > 0.9 * hist[it - st->stag]) {
+            st->done = 4;
             return;
         }
         double rho_new = st->dinv * rr;

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 #include "ops.hpp"
@@ -105,6 +106,10 @@ struct pcg_ctx_s {
     int chunk_iters = 0;
     hipEvent_t ev_chunk[2] = {nullptr, nullptr};
     int last_iters = 0;
+    // iterative refinement
+    void* rhat = nullptr;  // scaled residual in the storage type
+    std::vector<double> ref_relres;
+    std::vector<int> ref_inner;
 };
 
 namespace {
@@ -116,7 +121,7 @@ void free_ctx(pcg_ctx c) {
     if (c->chunk) (void)hipGraphExecDestroy(c->chunk);
     for (auto& e : c->ev_chunk)
         if (e) (void)hipEventDestroy(e);
-    void* dev[] = {c->r, c->p[0], c->p[1], c->xacc, c->partials, c->ticket, c->st, c->hist, c->res2};
+    void* dev[] = {c->r, c->p[0], c->p[1], c->xacc, c->partials, c->ticket, c->st, c->hist, c->res2, c->rhat};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     if (c->hst) (void)hipHostFree(c->hst);
@@ -125,11 +130,13 @@ void free_ctx(pcg_ctx c) {
     delete c;
 }
 
-// Default plan: 16 x 16 threads (a 64 x 16 FP32 footprint) with the z chunk
-// chosen so that the launch has about 2048 work-groups (8 per CU); the scalar
-// shape when nx is not a multiple of the 16-byte vector width.
+// Default plan: 64 x 4 threads (a 256 x 4 FP32 footprint: every wavefront
+// streams one contiguous 1 KiB row segment), long z chunks (64 planes) when
+// the x-y plane is small enough that the launch still has one work-group
+// per CU or more, else 16 planes; the scalar shape when nx is not a multiple
+// of the 16-byte vector width. Measured on MI355X at 256^3 and 512^3.
 Plan default_plan(int nx, int ny, int nz, int dt, const pcg_options& o) {
-    Plan p{0, 16};
+    Plan p{2, 16};
     if (nx % dt_width(dt) != 0) p.cfg = 5;
     if (o.tile_x > 0 || o.tile_y > 0) {
         for (int c = 0; c < NUM_TILE_CFG; ++c) {
@@ -143,8 +150,9 @@ Plan default_plan(int nx, int ny, int nz, int dt, const pcg_options& o) {
     }
     const int64_t tiles = (int64_t)((nx + plan_tx(p, dt) - 1) / plan_tx(p, dt)) *
                           ((ny + plan_ty(p) - 1) / plan_ty(p));
-    int64_t zc = tiles * nz / 2048;
-    zc = std::max<int64_t>(4, std::min<int64_t>(64, zc));
+    int64_t zc = (int64_t)nx * ny <= 65536 ? 64 : 16;
+    // keep at least ~256 work-groups when the grid allows it
+    while (zc > 4 && tiles * ((nz + zc - 1) / zc) < 256) zc /= 2;
     p.zc = o.zchunk > 0 ? o.zchunk : (int)zc;
     return p;
 }
@@ -199,6 +207,122 @@ pcg_status ensure_chunk(pcg_ctx c) {
         c->chunk = nullptr;
         return fail(PCG_E_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
     }
+    return PCG_OK;
+}
+
+
+struct IterResult {
+    SolveState fin{};
+    double k1_ms = 0.0, k2_ms = 0.0;
+    int nk = 0;
+};
+
+// Start a solve of A x = b on the workspace (x0 = 0, or x0 given in x0 of
+// type x0_dt) and run PCG iterations until the device state says done:
+// converged, breakdown, maxit, or (stag > 0) a residual that fell by less
+// than 10% over the last stag iterations. The iterate is left in c->xacc.
+pcg_status run_iterations(pcg_ctx c, const void* b, const void* x0, int x0_dt, double rtol, int maxit, int stag,
+                          IterResult* out) {
+    pcg_status s = ensure_hist(c, maxit);
+    if (s != PCG_OK) return s;
+    hipStream_t st = c->stream;
+    const bool x64 = c->opt.x_accum_f64 != 0;
+    const int xacc_dt = x64 ? DT_F64 : c->dt;
+
+    // Host-side initial state: rtol^2 (scaled by ||b||^2 on the device), 1/6, maxit.
+    SolveState init{};
+    init.tol2 = rtol * rtol;
+    init.dinv = 1.0 / 6.0;
+    init.maxit = maxit;
+    init.stag = stag;
+    c->hst[0] = init;
+    HIPCHK(hipMemcpyAsync(c->st, &c->hst[0], sizeof(SolveState), hipMemcpyHostToDevice, st));
+    if (x0) {
+        HIPCHK(launch_convert(x0_dt, xacc_dt, c->n, x0, c->xacc, st));
+        HIPCHK(launch_zero(c->dt, c->n, c->p[0], st));
+        HIPCHK(launch_zero(c->dt, c->n, c->p[1], st));
+        HIPCHK(launch_pcg_start_x0(c->dt, xacc_dt, c->plan_res, c->geo_res, b, c->xacc, c->r, c->st, c->hist,
+                                   red_of(c), st));
+    } else {
+        HIPCHK(launch_pcg_start_zero(c->dt, c->n, b, c->r, c->xacc, x64, c->p[0], c->p[1], c->st, c->hist,
+                                     red_of(c), st));
+    }
+
+    const int C = c->chunk_iters;
+    const bool timing = c->opt.kernel_timing != 0;
+    const bool graph = c->opt.use_graph && !timing;
+    if (graph) {
+        s = ensure_chunk(c);
+        if (s != PCG_OK) return s;
+    }
+    hipEvent_t* evs = nullptr;
+    if (timing) {
+        evs = new hipEvent_t[3 * C];
+        for (int i = 0; i < 3 * C; ++i) (void)hipEventCreate(&evs[i]);
+    }
+    struct EvGuard {
+        hipEvent_t*& e;
+        int n;
+        ~EvGuard() {
+            if (e) {
+                for (int i = 0; i < n; ++i) (void)hipEventDestroy(e[i]);
+                delete[] e;
+                e = nullptr;
+            }
+        }
+    } guard{evs, 3 * C};
+
+    // Chunk loop: launch chunk k, queue its state copy, then wait for chunk k-1's copy.
+    int launched = 0, slot = 0;
+    bool finished = false;
+    SolveState& fin = out->fin;
+    HIPCHK(hipMemcpyAsync(&c->hst[1], c->st, sizeof(SolveState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(c->ev_chunk[1], st));
+    HIPCHK(hipEventSynchronize(c->ev_chunk[1]));
+    fin = c->hst[1];
+    if (fin.done != 0) finished = true;
+    bool pending = false;
+    int pend_slot = 0;
+    while (!finished) {
+        if (launched < maxit) {
+            hipError_t e;
+            if (graph) e = hipGraphLaunch(c->chunk, st);
+            else e = enqueue_iters(c, launched + 1, C, st, evs);
+            if (e != hipSuccess) return fail(PCG_E_HIP, "launching PCG iterations failed: %s", hipGetErrorString(e));
+            launched += C;
+            if (timing) {
+                // Eager timing mode: wait for this chunk and sum its kernel times.
+                (void)hipEventSynchronize(evs[3 * C - 1]);
+                for (int i = 0; i < C; ++i) {
+                    float a = 0.f, b2 = 0.f;
+                    (void)hipEventElapsedTime(&a, evs[3 * i], evs[3 * i + 1]);
+                    (void)hipEventElapsedTime(&b2, evs[3 * i + 1], evs[3 * i + 2]);
+                    out->k1_ms += a;
+                    out->k2_ms += b2;
+                }
+                out->nk += C;
+            }
+            HIPCHK(hipMemcpyAsync(&c->hst[slot], c->st, sizeof(SolveState), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipEventRecord(c->ev_chunk[slot], st));
+        }
+        if (pending) {
+            HIPCHK(hipEventSynchronize(c->ev_chunk[pend_slot]));
+            fin = c->hst[pend_slot];
+            if (fin.done != 0) finished = true;
+        }
+        if (launched >= maxit && !finished) {
+            // Nothing more to launch: wait for the last chunk.
+            HIPCHK(hipEventSynchronize(c->ev_chunk[slot]));
+            fin = c->hst[slot];
+            finished = true;
+        }
+        pending = true;
+        pend_slot = slot;
+        slot ^= 1;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(&fin, c->st, sizeof(SolveState), hipMemcpyDeviceToHost));
+    c->last_iters = fin.iters;
     return PCG_OK;
 }
 
@@ -345,116 +469,20 @@ pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, 
     const size_t xbytes = (size_t)c->n * dt_size(c->opt.x_dtype);
     if (overlap2(b, (size_t)c->n * dt_size(c->dt), x, xbytes))
         return fail(PCG_E_ARG, "pcg_solve: b and x overlap");
-    pcg_status s = ensure_hist(c, maxit);
-    if (s != PCG_OK) return s;
     hipStream_t st = c->stream;
-    const bool x64 = c->opt.x_accum_f64 != 0;
-    const int xacc_dt = x64 ? DT_F64 : c->dt;
-
-    // Host-side initial state: rtol^2 (scaled by ||b||^2 on the device), 1/6, maxit.
-    SolveState init{};
-    init.tol2 = rtol * rtol;
-    init.dinv = 1.0 / 6.0;
-    init.maxit = maxit;
-    c->hst[0] = init;
-    HIPCHK(hipMemcpyAsync(c->st, &c->hst[0], sizeof(SolveState), hipMemcpyHostToDevice, st));
-    if (c->opt.use_x0) {
-        HIPCHK(launch_convert(c->opt.x_dtype, xacc_dt, c->n, x, c->xacc, st));
-        HIPCHK(launch_zero(c->dt, c->n, c->p[0], st));
-        HIPCHK(launch_zero(c->dt, c->n, c->p[1], st));
-        HIPCHK(launch_pcg_start_x0(c->dt, xacc_dt, c->plan_res, c->geo_res, b, c->xacc, c->r, c->st, c->hist,
-                                   red_of(c), st));
-    } else {
-        HIPCHK(launch_pcg_start_zero(c->dt, c->n, b, c->r, c->xacc, x64, c->p[0], c->p[1], c->st, c->hist,
-                                     red_of(c), st));
-    }
-
-    const int C = c->chunk_iters;
-    const bool timing = c->opt.kernel_timing != 0;
-    const bool graph = c->opt.use_graph && !timing;
-    if (graph) {
-        s = ensure_chunk(c);
-        if (s != PCG_OK) return s;
-    }
-    hipEvent_t* evs = nullptr;
-    std::string err;
-    double k1 = 0.0, k2 = 0.0;
-    int nk = 0;
-    if (timing) {
-        evs = new hipEvent_t[3 * C];
-        for (int i = 0; i < 3 * C; ++i) (void)hipEventCreate(&evs[i]);
-    }
-    auto cleanup = [&]() {
-        if (evs) {
-            for (int i = 0; i < 3 * C; ++i) (void)hipEventDestroy(evs[i]);
-            delete[] evs;
-            evs = nullptr;
-        }
-    };
-
-    // Chunk loop: launch chunk k, queue its state copy, then wait for chunk k-1's copy.
-    int launched = 0, slot = 0;
-    bool finished = false;
-    SolveState fin{};
-    HIPCHK(hipMemcpyAsync(&c->hst[1], c->st, sizeof(SolveState), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipEventRecord(c->ev_chunk[1], st));
-    HIPCHK(hipEventSynchronize(c->ev_chunk[1]));
-    fin = c->hst[1];
-    if (fin.done != 0) finished = true;
-    bool pending = false;
-    int pend_slot = 0;
-    while (!finished) {
-        if (launched < maxit) {
-            hipError_t e;
-            if (graph) e = hipGraphLaunch(c->chunk, st);
-            else e = enqueue_iters(c, launched + 1, C, st, evs);
-            if (e != hipSuccess) {
-                cleanup();
-                return fail(PCG_E_HIP, "pcg_solve: launching iterations failed: %s", hipGetErrorString(e));
-            }
-            launched += C;
-            if (timing) {
-                // Eager timing mode: wait for this chunk and sum its kernel times.
-                (void)hipEventSynchronize(evs[3 * C - 1]);
-                for (int i = 0; i < C; ++i) {
-                    float a = 0.f, b2 = 0.f;
-                    (void)hipEventElapsedTime(&a, evs[3 * i], evs[3 * i + 1]);
-                    (void)hipEventElapsedTime(&b2, evs[3 * i + 1], evs[3 * i + 2]);
-                    k1 += a;
-                    k2 += b2;
-                }
-                nk += C;
-            }
-            HIPCHK(hipMemcpyAsync(&c->hst[slot], c->st, sizeof(SolveState), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipEventRecord(c->ev_chunk[slot], st));
-        }
-        if (pending) {
-            HIPCHK(hipEventSynchronize(c->ev_chunk[pend_slot]));
-            fin = c->hst[pend_slot];
-            if (fin.done != 0) finished = true;
-        }
-        if (launched >= maxit && !finished) {
-            // Nothing more to launch: wait for the last chunk.
-            HIPCHK(hipEventSynchronize(c->ev_chunk[slot]));
-            fin = c->hst[slot];
-            finished = true;
-        }
-        pending = true;
-        pend_slot = slot;
-        slot ^= 1;
-    }
-    HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipMemcpy(&fin, c->st, sizeof(SolveState), hipMemcpyDeviceToHost));
-    cleanup();
+    const int xacc_dt = c->opt.x_accum_f64 ? DT_F64 : c->dt;
+    IterResult res;
+    pcg_status s = run_iterations(c, b, c->opt.use_x0 ? x : nullptr, c->opt.x_dtype, rtol, maxit, 0, &res);
+    if (s != PCG_OK) return s;
 
     // Result to the caller's x, then the FP64 true residual of what is returned.
     if (c->opt.x_dtype == xacc_dt) HIPCHK(hipMemcpyAsync(x, c->xacc, xbytes, hipMemcpyDeviceToDevice, st));
     else HIPCHK(launch_convert(xacc_dt, c->opt.x_dtype, c->n, c->xacc, x, st));
-    if (fin.rr0 == 0.0) HIPCHK(launch_zero(c->opt.x_dtype, c->n, x, st));
+    if (res.fin.rr0 == 0.0) HIPCHK(launch_zero(c->opt.x_dtype, c->n, x, st));
     HIPCHK(launch_residual64(c->dt, c->opt.x_dtype, c->plan_res, c->geo_res, b, x, c->res2, red_of(c), st));
     HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    c->last_iters = fin.iters;
+    const SolveState& fin = res.fin;
 
     pcg_status ret = PCG_OK;
     if (fin.done == 2) ret = PCG_E_BREAKDOWN;
@@ -465,15 +493,94 @@ pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, 
         info->status = ret;
         info->rel_res_recursive = fin.rr0 > 0 ? std::sqrt(fin.rr / fin.rr0) : 0.0;
         info->rel_res_true_fp64 = fin.rr0 > 0 ? std::sqrt(c->hres[0] / fin.rr0) : 0.0;
-        info->k1_ms = k1;
-        info->k2_ms = k2;
-        info->k1_launches = nk;
-        info->k2_launches = nk;
+        info->k1_ms = res.k1_ms;
+        info->k2_ms = res.k2_ms;
+        info->k1_launches = res.nk;
+        info->k2_launches = res.nk;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     if (ret == PCG_E_BREAKDOWN) fail(ret, "pcg_solve: breakdown (p.Ap <= 0 or a non-finite value) at iteration %d", fin.iters + 1);
     else if (ret == PCG_E_NOCONV) fail(ret, "pcg_solve: no convergence in %d iterations", maxit);
     return ret;
+}
+
+pcg_status pcg_solve_refined(pcg_ctx c, const double* b64, double* x64, double rtol_outer, double rtol_inner,
+                             int max_outer, int maxit_inner, pcg_info* info) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!c) return fail(PCG_E_ARG, "pcg_solve_refined: null context");
+    if (!b64 || !x64) return fail(PCG_E_ARG, "pcg_solve_refined: null pointer");
+    if (!aligned16(b64) || !aligned16(x64)) return fail(PCG_E_ARG, "pcg_solve_refined: pointers must be 16-byte aligned");
+    if (!(rtol_outer >= 0.0) || !(rtol_inner > 0.0) || max_outer < 0 || maxit_inner < 1)
+        return fail(PCG_E_ARG, "pcg_solve_refined: bad tolerance or iteration limit");
+    if (c->dt == DT_F64) return fail(PCG_E_UNSUPPORTED, "pcg_solve_refined: the inner storage must be F32, BF16 or F16");
+    if (overlap(b64, x64, (size_t)c->n * 8)) return fail(PCG_E_ARG, "pcg_solve_refined: b and x overlap");
+    hipStream_t st = c->stream;
+    if (!c->rhat) HIPCHK(hipMalloc(&c->rhat, dt_size(c->dt) * c->n));
+    const int xacc_dt = c->opt.x_accum_f64 ? DT_F64 : c->dt;
+    c->ref_relres.clear();
+    c->ref_inner.clear();
+
+    HIPCHK(launch_zero(DT_F64, c->n, x64, st));
+    double nb = 0.0, t1e6 = -1.0, t1e10 = -1.0;
+    int outer = 0, inner_total = 0;
+    pcg_status ret = PCG_E_NOCONV;
+    for (;;) {
+        HIPCHK(launch_residual64(DT_F64, DT_F64, c->plan_res, c->geo_res, b64, x64, c->res2, red_of(c), st));
+        HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const double rn = std::sqrt(c->hres[0]), amax = c->hres[1];
+        if (outer == 0) nb = rn;  // x = 0: the residual is b
+        const double t = nb > 0.0 ? rn / nb : 0.0;
+        const double now = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        c->ref_relres.push_back(t);
+        if (!std::isfinite(t)) {
+            ret = PCG_E_BREAKDOWN;
+            break;
+        }
+        if (t <= 1e-6 && t1e6 < 0) t1e6 = now;
+        if (t <= 1e-10 && t1e10 < 0) t1e10 = now;
+        if (t <= rtol_outer) {
+            ret = PCG_OK;
+            break;
+        }
+        if (outer >= max_outer) break;
+        // rhat = lp(s (b - A x)), s = 1 / max|r|; inner Jacobi-PCG A d = rhat.
+        const double scale = 1.0 / amax;
+        HIPCHK(launch_cast_scaled(c->dt, c->plan_res, c->geo_res, b64, x64, scale, c->rhat, st));
+        IterResult res;
+        pcg_status s = run_iterations(c, c->rhat, nullptr, c->dt, rtol_inner, maxit_inner, 20, &res);
+        if (s != PCG_OK) return s;
+        c->ref_inner.push_back(res.fin.iters);
+        inner_total += res.fin.iters;
+        HIPCHK(launch_correct(xacc_dt, c->n, c->xacc, scale, x64, st));
+        ++outer;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->iters = inner_total;
+        info->outer_iters = outer;
+        info->status = ret;
+        info->rel_res_true_fp64 = c->ref_relres.empty() ? 0.0 : c->ref_relres.back();
+        info->rel_res_recursive = info->rel_res_true_fp64;
+        info->t_1e6 = t1e6;
+        info->t_1e10 = t1e10;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (ret == PCG_E_NOCONV) fail(ret, "pcg_solve_refined: not converged after %d refinement steps", outer);
+    else if (ret == PCG_E_BREAKDOWN) fail(ret, "pcg_solve_refined: non-finite residual");
+    return ret;
+}
+
+pcg_status pcg_refine_history(pcg_ctx c, double* relres, int* inner_iters, int n, int* count) {
+    if (!c || !count || n < 0) return fail(PCG_E_ARG, "pcg_refine_history: bad argument");
+    int m = std::min<int>(n, (int)c->ref_relres.size());
+    for (int i = 0; i < m; ++i) {
+        if (relres) relres[i] = c->ref_relres[i];
+        if (inner_iters) inner_iters[i] = i < (int)c->ref_inner.size() ? c->ref_inner[i] : 0;
+    }
+    *count = m;
+    return PCG_OK;
 }
 
 pcg_status pcg_get_history(pcg_ctx c, double* hist, int n, int* count) {

@@ -77,7 +77,10 @@ template <typename C, int BX, int BY, int VX> struct ZTile {
     static_assert(2 * BX + 2 * TY <= NT, "not enough threads for the halo ring");
 };
 
-constexpr int ZM_DEPTH = 2;  // planes of look-ahead of every load
+#ifndef PCGMI_ZM_DEPTH
+#define PCGMI_ZM_DEPTH 2
+#endif
+constexpr int ZM_DEPTH = PCGMI_ZM_DEPTH;  // planes of look-ahead of every load
 
 // Runs the z-march for logical tile `tile`. Returns the op's accumulators in acc.
 template <typename C, int BX, int BY, int VX, int NC, class Loader, class Op>
@@ -157,20 +160,19 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
     };
     auto fetch_op = [&](int k, ORaw& r) { op.fetch((fvalid(k) && k < z1) ? col + k * sz : 0, r); };
 
-    // Pipeline (two slots, D = 2 planes of look-ahead). At the top of step k:
+    // Pipeline with D slots (D planes of look-ahead). At the top of step k,
+    // with s = (k - z0) mod D:
     //   zm, zcur, zp : values of planes k-1, k, k+1
-    //   f[s]         : raw loads of plane k+2   (s = (k - z0) & 1; the other
-    //                  slot holds plane k+3)
+    //   f[s]         : raw loads of plane k+2 (slot s+j holds plane k+2+j)
     //   hv           : halo values of plane k;  h[s]: raw halo of plane k+1
     //   o[s]         : raw op loads of plane k
-    // A slot is consumed first and then refilled with the plane two steps on,
+    // A slot is consumed first and then refilled with the plane D steps on,
     // so no register of an in-flight load is ever copied (a copy would make
-    // the compiler wait for the load). The loop is unrolled by two so slot
+    // the compiler wait for the load). The loop is unrolled by D so slot
     // roles are static.
-    static_assert(ZM_DEPTH == 2, "the slot rotation below assumes two planes of look-ahead");
     Pts<C, VX> zm, zcur, zp, hv;
-    FRaw f0, f1, h0, h1;
-    ORaw o0, o1;
+    FRaw f[D], h[D];
+    ORaw o[D];
     {
         FRaw t;
         fetch_plane(z0 - 1, t);
@@ -182,18 +184,19 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
         fetch_halo(z0, t);
         finish_halo(z0, t, hv);
     }
-    fetch_plane(z0 + 2, f0);
-    fetch_plane(z0 + 3, f1);
-    fetch_halo(z0 + 1, h0);
-    fetch_halo(z0 + 2, h1);
-    fetch_op(z0, o0);
-    fetch_op(z0 + 1, o1);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        fetch_plane(z0 + 2 + j, f[j]);
+        fetch_halo(z0 + 1 + j, h[j]);
+        fetch_op(z0 + j, o[j]);
+    }
 
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = C(0);
 
     const int lrow = (ty + 1) * ZT::PITCH + ZT::PAD + tx * VX;
-    auto step = [&](int k, C* buf, FRaw& f, FRaw& h, ORaw& o) {
+    auto step = [&](int k, FRaw& fs, FRaw& hs, ORaw& os) {
+        C* buf = lds + ((k - z0) & 1) * ZT::PLANE;
         // Stage plane k: own points and halo.
 #pragma unroll
         for (int i = 0; i < VX; ++i) buf[lrow + i] = zcur.v[i];
@@ -203,12 +206,12 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
         } else if (hkind == 2) {
             buf[lds_off] = hv.v[0];
         }
-        // Consume this slot's field and halo loads, refill it two planes on.
+        // Consume this slot's field and halo loads, refill it D planes on.
         Pts<C, VX> znext, hnext;
-        finish_plane(k + 2, f, znext);
-        fetch_plane(k + 4, f);
-        finish_halo(k + 1, h, hnext);
-        fetch_halo(k + 3, h);
+        finish_plane(k + 2, fs, znext);
+        fetch_plane(k + 2 + D, fs);
+        finish_halo(k + 1, hs, hnext);
+        fetch_halo(k + 1 + D, hs);
         __syncthreads();
         Pts<C, VX> ax;
         const C* up = buf + lrow + ZT::PITCH;
@@ -220,16 +223,17 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
             C r = i == VX - 1 ? right : zcur.v[i + 1];
             ax.v[i] = C(6) * zcur.v[i] - l - r - dn[i] - up[i] - zm.v[i] - zp.v[i];
         }
-        if (own) op.apply(col + k * sz, o, zcur.v, ax.v, acc);
-        fetch_op(k + 2, o);
+        if (own) op.apply(col + k * sz, os, zcur.v, ax.v, acc);
+        fetch_op(k + D, os);
         zm = zcur;
         zcur = zp;
         zp = znext;
         hv = hnext;
     };
-    for (int k = z0; k < z1; k += 2) {
-        step(k, lds, f0, h0, o0);
-        if (k + 1 < z1) step(k + 1, lds + ZT::PLANE, f1, h1, o1);
+    for (int k = z0; k < z1; k += D) {
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            if (k + j < z1) step(k + j, f[j], h[j], o[j]);
     }
 }
 
