@@ -256,6 +256,7 @@ pcg_status run_iterations(pcg_ctx c, const void* b, const void* x0, int x0_dt, d
         if (s != PCG_OK) return s;
     }
     hipEvent_t* evs = nullptr;
+    std::vector<float> k1_each, k2_each;  // per-iteration kernel times (timing mode)
     if (timing) {
         evs = new hipEvent_t[3 * C];
         for (int i = 0; i < 3 * C; ++i) (void)hipEventCreate(&evs[i]);
@@ -297,10 +298,9 @@ pcg_status run_iterations(pcg_ctx c, const void* b, const void* x0, int x0_dt, d
                     float a = 0.f, b2 = 0.f;
                     (void)hipEventElapsedTime(&a, evs[3 * i], evs[3 * i + 1]);
                     (void)hipEventElapsedTime(&b2, evs[3 * i + 1], evs[3 * i + 2]);
-                    out->k1_ms += a;
-                    out->k2_ms += b2;
+                    k1_each.push_back(a);
+                    k2_each.push_back(b2);
                 }
-                out->nk += C;
             }
             HIPCHK(hipMemcpyAsync(&c->hst[slot], c->st, sizeof(SolveState), hipMemcpyDeviceToHost, st));
             HIPCHK(hipEventRecord(c->ev_chunk[slot], st));
@@ -323,6 +323,14 @@ pcg_status run_iterations(pcg_ctx c, const void* b, const void* x0, int x0_dt, d
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipMemcpy(&fin, c->st, sizeof(SolveState), hipMemcpyDeviceToHost));
     c->last_iters = fin.iters;
+    // Only iterations that did work count (later launches of the last chunk
+    // return at once).
+    const int nwork = std::min<int>(fin.iters, (int)k1_each.size());
+    for (int i = 0; i < nwork; ++i) {
+        out->k1_ms += k1_each[i];
+        out->k2_ms += k2_each[i];
+    }
+    out->nk = nwork;
     return PCG_OK;
 }
 
