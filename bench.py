@@ -201,7 +201,7 @@ def main():
     refined = {}
     if not args.no_refined:
         for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
-            rctx = P.pcg_create(n, n, n, dt, x_accum_f64=0)
+            rctx = P.pcg_create(n, n, n, dt, x_accum=torch.float32)
             x64 = torch.empty(N, dtype=torch.float64, device="cuda")
             P.pcg_solve_refined(rctx, b64, x64, rtol_outer=1e-10)
             torch.cuda.synchronize()

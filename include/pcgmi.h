@@ -49,7 +49,8 @@ typedef enum { PCG_F32 = 0, PCG_BF16 = 1, PCG_F16 = 2, PCG_F64 = 3 } pcg_dtype;
 
 typedef struct {
     int chunk_iters;   /* iterations per captured HIP graph chunk (default 16, even) */
-    int x_accum_f64;   /* 1 (default): x accumulated in FP64 workspace; 0: in storage type */
+    int x_accum;       /* type of the x accumulator in the workspace: PCG_F64 (default,
+                          -1 selects it), PCG_F32, or the storage type */
     int x_dtype;       /* type of the caller's x in pcg_solve: PCG_F32 (default for F32
                           storage) or PCG_F64; for BF16/F16 storage x is that type or F64 */
     int use_x0;        /* 0 (default): x0 = 0; 1: x holds the initial guess on entry */
@@ -80,8 +81,8 @@ pcg_status pcg_options_default(pcg_options *opt);
 
 /* Create a context for an nx*ny*nz grid whose vectors are stored as
  * `storage`. hip_stream is a hipStream_t (NULL = default stream). opt may be
- * NULL (defaults). Allocates the workspace: for F32 storage 3 vectors of
- * the storage type (r, p twice) plus an FP64 x accumulator, plus reduction
+ * NULL (defaults). Allocates the workspace: 3 vectors of the storage type
+ * (r, p twice) plus the x accumulator (opt->x_accum), plus reduction
  * partials and a small scalar block. Errors: PCG_E_ARG (dims < 1 or
  * nx*ny*nz > 2^33), PCG_E_NOMEM, PCG_E_HIP. */
 pcg_status pcg_create(pcg_ctx *out, int nx, int ny, int nz, pcg_dtype storage, void *hip_stream,
@@ -127,8 +128,10 @@ pcg_status pcg_solve(pcg_ctx ctx, const void *b, void *x, double rtol, int maxit
  *         nearest even); inner Jacobi-PCG A d = rhat in the storage type with
  *         FP32 arithmetic, stopped at ||r_in|| <= rtol_inner ||rhat||, at
  *         maxit_inner, or when ||r_in|| fell by less than 10% over 20
- *         iterations; d accumulates in FP64 when the context's x_accum_f64
- *         is set, else in the storage type; x += d / s in FP64.
+ *         iterations; d accumulates in the context's x_accum type (FP32
+ *         keeps the correction accurate at large grids, where rounding d to
+ *         16 bits costs about kappa(A) times its unit roundoff); x += d / s
+ *         in FP64.
  * info: iters = total inner iterations, outer_iters, rel_res_true_fp64 (the
  * last FP64 residual), t_1e6 / t_1e10 = seconds until the FP64 residual
  * first reached 1e-6 / 1e-10 (-1 if never). Returns PCG_OK when the

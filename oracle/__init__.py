@@ -261,16 +261,18 @@ def _stencil_f32(v, shape) -> np.ndarray:
 
 
 def inner_pcg_lp(shape, rhat, fmt: str, rtol: float, maxit: int,
-                 stag_window: int = 20, stag_drop: float = 0.9):
+                 stag_window: int = 20, stag_drop: float = 0.9, d_fmt: str | None = None):
     """Jacobi-PCG on A d = rhat with every vector (d, r, p) stored in `fmt`
     and FP32 element arithmetic (FP64 for fmt "f64"); scalars and dot sums in
     FP64.
 
     Stops at ||r|| <= rtol ||rhat|| (recursive), at maxit, on breakdown, or when
     ||r_k|| > stag_drop * ||r_{k - stag_window}|| (stagnation).
+    d_fmt: format the correction d accumulates in (default: fmt).
     Returns (d as FP64 values of the stored format, iterations).
     """
     rnd = _ROUND[fmt]
+    rnd_d = _ROUND[d_fmt or fmt]
     f32 = np.float64 if fmt == "f64" else np.float32   # element arithmetic type
     dinv = f32(1.0 / 6.0)
     r = rnd(rhat)
@@ -291,7 +293,7 @@ def inner_pcg_lp(shape, rhat, fmt: str, rtol: float, maxit: int,
         if not (sigma > 0.0) or not math.isfinite(sigma):
             break
         alpha = f32(rho / sigma)
-        d = rnd(d.astype(f32) + alpha * p.astype(f32))
+        d = rnd_d(d.astype(f32) + alpha * p.astype(f32))
         r = rnd(r.astype(f32) - alpha * q)
         rr = float(np.dot(r, r))
         nr = math.sqrt(rr)
@@ -307,7 +309,7 @@ def inner_pcg_lp(shape, rhat, fmt: str, rtol: float, maxit: int,
 
 
 def ir_emulate(shape, b, fmt: str = "bf16", rtol_outer: float = 1e-10, rtol_in: float | None = None,
-               max_outer: int = 30, maxit_in: int = 2000):
+               max_outer: int = 30, maxit_in: int = 2000, d_fmt: str | None = None):
     """FP64 iterative refinement with an emulated low-precision inner PCG.
 
     x = 0; loop: r = b - A x (FP64); stop when ||r||/||b|| <= rtol_outer;
@@ -328,7 +330,7 @@ def ir_emulate(shape, b, fmt: str = "bf16", rtol_outer: float = 1e-10, rtol_in: 
         if t <= rtol_outer or outer >= max_outer:
             break
         s = 1.0 / amax
-        d, it = inner_pcg_lp(shape, s * r, fmt, rtol_in, maxit_in)
+        d, it = inner_pcg_lp(shape, s * r, fmt, rtol_in, maxit_in, d_fmt=d_fmt)
         inner.append(it)
         x = x + d / s
         outer += 1

@@ -26,7 +26,7 @@ DT_TORCH = {v: k for k, v in _TORCH_DT.items()}
 
 
 class PcgOptions(ctypes.Structure):
-    _fields_ = [("chunk_iters", ctypes.c_int), ("x_accum_f64", ctypes.c_int), ("x_dtype", ctypes.c_int),
+    _fields_ = [("chunk_iters", ctypes.c_int), ("x_accum", ctypes.c_int), ("x_dtype", ctypes.c_int),
                 ("use_x0", ctypes.c_int), ("use_graph", ctypes.c_int), ("kernel_timing", ctypes.c_int),
                 ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int), ("zchunk", ctypes.c_int)]
 
@@ -110,7 +110,7 @@ def pcg_options_default(**overrides) -> PcgOptions:
     o = PcgOptions()
     _check(lib.pcg_options_default(ctypes.byref(o)))
     for k, v in overrides.items():
-        if k == "x_dtype":
+        if k in ("x_dtype", "x_accum"):
             v = dtype_code(v)
         setattr(o, k, int(v))
     return o

@@ -183,21 +183,23 @@ hipError_t launch_dot(int dt, int64_t n, const void* x, const void* y, float* ou
     });
 }
 
-hipError_t launch_pcg_start_zero(int dt, int64_t n, const void* b, void* r, void* x, bool x64, void* p0, void* p1,
+hipError_t launch_pcg_start_zero(int dt, int64_t n, const void* b, void* r, void* x, int xdt, void* p0, void* p1,
                                  SolveState* st, double* hist, Red red, hipStream_t s) {
     return dispatch_dt(dt, [&](auto tag) {
         using T = decltype(tag);
         const int64_t nvec = n / Traits<T>::W;
         const unsigned nb = stream_blocks(nvec, (int64_t)NT * 4, DOT_MAX_BLOCKS);
-        if (x64)
-            hipLaunchKernelGGL((k_start_zero<T, double>), dim3(nb), dim3(NT), 0, s, n, static_cast<const T*>(b),
-                               static_cast<T*>(r), static_cast<double*>(x), static_cast<T*>(p0),
-                               static_cast<T*>(p1), st, hist, red);
-        else
-            hipLaunchKernelGGL((k_start_zero<T, T>), dim3(nb), dim3(NT), 0, s, n, static_cast<const T*>(b),
-                               static_cast<T*>(r), static_cast<T*>(x), static_cast<T*>(p0), static_cast<T*>(p1),
-                               st, hist, red);
-        return hipGetLastError();
+        auto go = [&](auto xtag) {
+            using X = decltype(xtag);
+            hipLaunchKernelGGL((k_start_zero<T, X>), dim3(nb), dim3(NT), 0, s, n, static_cast<const T*>(b),
+                               static_cast<T*>(r), static_cast<X*>(x), static_cast<T*>(p0), static_cast<T*>(p1), st,
+                               hist, red);
+            return hipGetLastError();
+        };
+        if (xdt == DT_F64) return go(double{});
+        if (xdt == DT_F32) return go(float{});
+        if (xdt == dt) return go(T{});
+        return hipErrorInvalidValue;
     });
 }
 

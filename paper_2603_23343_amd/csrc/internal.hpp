@@ -55,14 +55,14 @@ hipError_t launch_stencil(int dt, const Plan& p, const Geometry& g, const void* 
 hipError_t launch_pcg_direction(int dt, const Plan& p, const Geometry& g, const void* r, const void* pold,
                                 void* pnew, SolveState* st, Red red, hipStream_t s);
 // Iteration kernel 2: q = A p, x += alpha p, r -= alpha q, r.r -> convergence, beta.
-// x is FP64 when x64 is true, else of the storage type.
-hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, const void* pdir, void* x, bool x64,
+// x (the accumulator) is of type xdt: FP64, FP32 or the storage type.
+hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, const void* pdir, void* x, int xdt,
                              void* r, SolveState* st, double* hist, Red red, hipStream_t s);
 // r = stored(b - A x0) computed in FP64 (x0 of type xdt), totals {r.r, b.b}
 // -> solve start. Uses the FP64 residual shape (pres, gres).
 hipError_t launch_pcg_start_x0(int dt, int xdt, const Plan& pres, const Geometry& gres, const void* b,
                                const void* x0, void* r, SolveState* st, double* hist, Red red, hipStream_t s);
-// FP64 residual of b (type bdt) and x (FP64 if x64 else type xdt): out = {||r||^2, max|r|}.
+// FP64 residual of b (type bdt) and x (type xdt): out = {||r||^2, max|r|}.
 hipError_t launch_residual64(int bdt, int xdt, const Plan& p, const Geometry& g, const void* b, const void* x,
                              double* out, Red red, hipStream_t s);
 
@@ -78,7 +78,7 @@ hipError_t launch_axpy(int dt, int64_t n, float alpha, const void* x, const void
 hipError_t launch_dot(int dt, int64_t n, const void* x, const void* y, float* out_f32, double* out_f64, Red red,
                       hipStream_t s);
 // r = b, x = 0, p0 = p1 = 0; totals {b.b, b.b} -> solve start.
-hipError_t launch_pcg_start_zero(int dt, int64_t n, const void* b, void* r, void* x, bool x64, void* p0, void* p1,
+hipError_t launch_pcg_start_zero(int dt, int64_t n, const void* b, void* r, void* x, int xdt, void* p0, void* p1,
                                  SolveState* st, double* hist, Red red, hipStream_t s);
 // Fill n elements of type dt (or FP64 when dt == DT_F64) with zero.
 hipError_t launch_zero(int dt, int64_t n, void* p, hipStream_t s);

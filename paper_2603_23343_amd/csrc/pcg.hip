@@ -29,19 +29,23 @@ hipError_t launch_pcg_direction(int dt, const Plan& p, const Geometry& g, const 
     });
 }
 
-hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, const void* pdir, void* x, bool x64,
+hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, const void* pdir, void* x, int xdt,
                              void* r, SolveState* st, double* hist, Red red, hipStream_t s) {
     return dispatch_dt(dt, [&](auto tag) {
         using T = decltype(tag);
         using C = typename Traits<T>::C;
         return dispatch_cfg<Traits<T>::W>(p.cfg, [&]<int BX, int BY, int VX>() {
             LoadField<T> ld{static_cast<const T*>(pdir)};
-            if (x64) {
-                OpUpdate<T, double, VX> op{static_cast<double*>(x), static_cast<T*>(r), st, C(0), 0.0};
-                return run_zmarch<ZF_UPDATE, C, BX, BY, VX, 1, 0u, true>(g, ld, op, FinBeta{st, hist}, red, &st->done, s);
-            }
-            OpUpdate<T, T, VX> op{static_cast<T*>(x), static_cast<T*>(r), st, C(0), 0.0};
-            return run_zmarch<ZF_UPDATE, C, BX, BY, VX, 1, 0u, true>(g, ld, op, FinBeta{st, hist}, red, &st->done, s);
+            auto go = [&](auto xtag) {
+                using X = decltype(xtag);
+                OpUpdate<T, X, VX> op{static_cast<X*>(x), static_cast<T*>(r), st, C(0), 0.0};
+                return run_zmarch<ZF_UPDATE, C, BX, BY, VX, 1, 0u, true>(g, ld, op, FinBeta{st, hist}, red,
+                                                                         &st->done, s);
+            };
+            if (xdt == DT_F64) return go(double{});
+            if (xdt == DT_F32) return go(float{});
+            if (xdt == dt) return go(T{});
+            return hipErrorInvalidValue;
         });
     });
 }

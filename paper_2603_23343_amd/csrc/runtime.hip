@@ -90,7 +90,7 @@ struct pcg_ctx_s {
     // workspace
     void* r = nullptr;
     void* p[2] = {nullptr, nullptr};
-    void* xacc = nullptr;  // FP64 or storage type (opt.x_accum_f64)
+    void* xacc = nullptr;  // x accumulator, type opt.x_accum
     double* partials = nullptr;
     size_t partials_cap = 0;  // doubles
     unsigned* ticket = nullptr;
@@ -174,7 +174,6 @@ pcg_status ensure_hist(pcg_ctx c, int maxit) {
 // Enqueue iterations [first, first + count) on stream s. Iteration i reads
 // the direction buffer p[(i - 1) & 1] and writes p[i & 1].
 hipError_t enqueue_iters(pcg_ctx c, int first, int count, hipStream_t s, hipEvent_t* evs) {
-    const bool x64 = c->opt.x_accum_f64 != 0;
     for (int i = first; i < first + count; ++i) {
         void* pold = c->p[(i - 1) & 1];
         void* pnew = c->p[i & 1];
@@ -182,7 +181,8 @@ hipError_t enqueue_iters(pcg_ctx c, int first, int count, hipStream_t s, hipEven
         hipError_t e = launch_pcg_direction(c->dt, c->plan, c->geo, c->r, pold, pnew, c->st, red_of(c), s);
         if (e != hipSuccess) return e;
         if (evs) (void)hipEventRecord(evs[3 * (i - first) + 1], s);
-        e = launch_pcg_update(c->dt, c->plan, c->geo, pnew, c->xacc, x64, c->r, c->st, c->hist, red_of(c), s);
+        e = launch_pcg_update(c->dt, c->plan, c->geo, pnew, c->xacc, c->opt.x_accum, c->r, c->st, c->hist,
+                              red_of(c), s);
         if (e != hipSuccess) return e;
         if (evs) (void)hipEventRecord(evs[3 * (i - first) + 2], s);
     }
@@ -226,8 +226,7 @@ pcg_status run_iterations(pcg_ctx c, const void* b, const void* x0, int x0_dt, d
     pcg_status s = ensure_hist(c, maxit);
     if (s != PCG_OK) return s;
     hipStream_t st = c->stream;
-    const bool x64 = c->opt.x_accum_f64 != 0;
-    const int xacc_dt = x64 ? DT_F64 : c->dt;
+    const int xacc_dt = c->opt.x_accum;
 
     // Host-side initial state: rtol^2 (scaled by ||b||^2 on the device), 1/6, maxit.
     SolveState init{};
@@ -244,7 +243,7 @@ pcg_status run_iterations(pcg_ctx c, const void* b, const void* x0, int x0_dt, d
         HIPCHK(launch_pcg_start_x0(c->dt, xacc_dt, c->plan_res, c->geo_res, b, c->xacc, c->r, c->st, c->hist,
                                    red_of(c), st));
     } else {
-        HIPCHK(launch_pcg_start_zero(c->dt, c->n, b, c->r, c->xacc, x64, c->p[0], c->p[1], c->st, c->hist,
+        HIPCHK(launch_pcg_start_zero(c->dt, c->n, b, c->r, c->xacc, xacc_dt, c->p[0], c->p[1], c->st, c->hist,
                                      red_of(c), st));
     }
 
@@ -344,7 +343,7 @@ pcg_status pcg_options_default(pcg_options* o) {
     if (!o) return fail(PCG_E_ARG, "pcg_options_default: null options");
     std::memset(o, 0, sizeof *o);
     o->chunk_iters = 16;
-    o->x_accum_f64 = 1;
+    o->x_accum = -1;  // resolved at pcg_create: FP64
     o->x_dtype = -1;  // resolved at pcg_create: F32 storage -> F32, otherwise storage type
     o->use_graph = 1;
     return PCG_OK;
@@ -366,7 +365,10 @@ pcg_status pcg_create(pcg_ctx* out, int nx, int ny, int nz, pcg_dtype storage, v
     if (o.x_dtype < 0) o.x_dtype = storage;
     if (o.x_dtype != storage && o.x_dtype != PCG_F64)
         return fail(PCG_E_ARG, "pcg_create: x_dtype must be the storage type or PCG_F64");
-    if (storage == PCG_F64) o.x_accum_f64 = 1;
+    if (o.x_accum < 0) o.x_accum = PCG_F64;
+    if (o.x_accum != PCG_F64 && o.x_accum != PCG_F32 && o.x_accum != storage)
+        return fail(PCG_E_ARG, "pcg_create: x_accum must be PCG_F64, PCG_F32 or the storage type");
+    if (storage == PCG_F64) o.x_accum = PCG_F64;
 
     pcg_ctx c = new (std::nothrow) pcg_ctx_s();
     if (!c) return fail(PCG_E_NOMEM, "pcg_create: out of host memory");
@@ -384,7 +386,7 @@ pcg_status pcg_create(pcg_ctx* out, int nx, int ny, int nz, pcg_dtype storage, v
     c->chunk_iters = o.chunk_iters;
 
     const size_t es = dt_size(storage);
-    const size_t xs = o.x_accum_f64 ? 8 : es;
+    const size_t xs = dt_size(o.x_accum);
     size_t maxblk = std::max<size_t>({(size_t)c->geo.nblocks, (size_t)c->geo_res.nblocks, (size_t)DOT_MAX_BLOCKS});
     c->partials_cap = 2 * maxblk;
     hipError_t e = hipSuccess;
@@ -478,7 +480,7 @@ pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, 
     if (overlap2(b, (size_t)c->n * dt_size(c->dt), x, xbytes))
         return fail(PCG_E_ARG, "pcg_solve: b and x overlap");
     hipStream_t st = c->stream;
-    const int xacc_dt = c->opt.x_accum_f64 ? DT_F64 : c->dt;
+    const int xacc_dt = c->opt.x_accum;
     IterResult res;
     pcg_status s = run_iterations(c, b, c->opt.use_x0 ? x : nullptr, c->opt.x_dtype, rtol, maxit, 0, &res);
     if (s != PCG_OK) return s;
@@ -524,7 +526,7 @@ pcg_status pcg_solve_refined(pcg_ctx c, const double* b64, double* x64, double r
     if (overlap(b64, x64, (size_t)c->n * 8)) return fail(PCG_E_ARG, "pcg_solve_refined: b and x overlap");
     hipStream_t st = c->stream;
     if (!c->rhat) HIPCHK(hipMalloc(&c->rhat, dt_size(c->dt) * c->n));
-    const int xacc_dt = c->opt.x_accum_f64 ? DT_F64 : c->dt;
+    const int xacc_dt = c->opt.x_accum;
     c->ref_relres.clear();
     c->ref_inner.clear();
 

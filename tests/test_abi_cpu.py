@@ -68,7 +68,7 @@ def test_options_default(lib):
     import paper_2603_23343_amd as P
 
     o = P.pcg_options_default()
-    assert o.chunk_iters == 16 and o.x_accum_f64 == 1 and o.use_graph == 1 and o.use_x0 == 0
+    assert o.chunk_iters == 16 and o.x_accum == -1 and o.use_graph == 1 and o.use_x0 == 0
     assert o.kernel_timing == 0 and o.x_dtype == -1
 
 

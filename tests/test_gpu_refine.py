@@ -28,10 +28,12 @@ def _system(orc, n):
 
 @pytest.mark.parametrize("n", [16, 32])
 @pytest.mark.parametrize("dtype,fmt", [(torch.bfloat16, "bf16"), (torch.float16, "f16")])
-def test_refined_matches_emulation(P, orc, n, dtype, fmt):
+@pytest.mark.parametrize("acc", ["f32", "lp"])
+def test_refined_matches_emulation(P, orc, n, dtype, fmt, acc):
+    """Inner correction accumulated in FP32 (default) or in the storage type."""
     shape, xs, b = _system(orc, n)
-    ref = orc.ir_emulate(shape, b, fmt=fmt, rtol_outer=1e-10)
-    ctx = P.pcg_create(n, n, n, dtype, x_accum_f64=0)
+    ref = orc.ir_emulate(shape, b, fmt=fmt, rtol_outer=1e-10, d_fmt="f32" if acc == "f32" else None)
+    ctx = P.pcg_create(n, n, n, dtype, x_accum=torch.float32 if acc == "f32" else dtype)
     b64 = torch.from_numpy(b).cuda()
     x64 = torch.empty_like(b64)
     info = P.pcg_solve_refined(ctx, b64, x64, rtol_outer=1e-10)
@@ -51,7 +53,7 @@ def test_refined_fp64_accumulator(P, orc, dtype):
     """The inner solution accumulated in FP64 also reaches 1e-10."""
     n = 24
     shape, _, b = _system(orc, n)
-    ctx = P.pcg_create(n, n, n, dtype, x_accum_f64=1)
+    ctx = P.pcg_create(n, n, n, dtype, x_accum=torch.float64)
     b64 = torch.from_numpy(b).cuda()
     x64 = torch.empty_like(b64)
     info = P.pcg_solve_refined(ctx, b64, x64, rtol_outer=1e-10)
@@ -61,7 +63,7 @@ def test_refined_fp64_accumulator(P, orc, dtype):
 
 def test_refined_zero_rhs_and_limits(P):
     n = 8
-    ctx = P.pcg_create(n, n, n, torch.bfloat16, x_accum_f64=0)
+    ctx = P.pcg_create(n, n, n, torch.bfloat16, x_accum=torch.float32)
     b64 = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
     x64 = torch.ones_like(b64)
     info = P.pcg_solve_refined(ctx, b64, x64)
@@ -83,7 +85,7 @@ def test_refined_256(P, orc, dtype):
     is <= 1e-10; the solution error is at the level the residual implies."""
     n = 256
     shape, xs, b = _system(orc, n)
-    ctx = P.pcg_create(n, n, n, dtype, x_accum_f64=0)
+    ctx = P.pcg_create(n, n, n, dtype, x_accum=torch.float32)
     b64 = torch.from_numpy(b).cuda()
     x64 = torch.empty_like(b64)
     info = P.pcg_solve_refined(ctx, b64, x64, rtol_outer=1e-10)
