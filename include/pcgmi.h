@@ -60,6 +60,9 @@ typedef struct {
     int tile_x;        /* stencil tile in x (points); 0 = autotuned default */
     int tile_y;        /* stencil tile in y (rows); 0 = default */
     int zchunk;        /* z planes per work-group; 0 = default */
+    int stag_window;   /* refinement's inner solves stop when the best ||r|| so far has
+                          not improved by 10% for this many iterations; 0 = never;
+                          -1 = default (100) */
 } pcg_options;
 
 typedef struct {
@@ -127,8 +130,8 @@ pcg_status pcg_solve(pcg_ctx ctx, const void *b, void *x, double rtol, int maxit
  *         s = 1 / max|r|; rhat = storage(s r) (FP64 -> FP32 -> storage,
  *         nearest even); inner Jacobi-PCG A d = rhat in the storage type with
  *         FP32 arithmetic, stopped at ||r_in|| <= rtol_inner ||rhat||, at
- *         maxit_inner, or when ||r_in|| fell by less than 10% over 20
- *         iterations; d accumulates in the context's x_accum type (FP32
+ *         maxit_inner, or when the best ||r_in|| has not improved by 10%
+ *         for the context's stag_window iterations; d accumulates in the context's x_accum type (FP32
  *         keeps the correction accurate at large grids, where rounding d to
  *         16 bits costs about kappa(A) times its unit roundoff); x += d / s
  *         in FP64.

@@ -261,13 +261,14 @@ def _stencil_f32(v, shape) -> np.ndarray:
 
 
 def inner_pcg_lp(shape, rhat, fmt: str, rtol: float, maxit: int,
-                 stag_window: int = 20, stag_drop: float = 0.9, d_fmt: str | None = None):
+                 stag_window: int = 100, stag_drop: float = 0.9, d_fmt: str | None = None):
     """Jacobi-PCG on A d = rhat with every vector (d, r, p) stored in `fmt`
     and FP32 element arithmetic (FP64 for fmt "f64"); scalars and dot sums in
     FP64.
 
-    Stops at ||r|| <= rtol ||rhat|| (recursive), at maxit, on breakdown, or when
-    ||r_k|| > stag_drop * ||r_{k - stag_window}|| (stagnation).
+    Stops at ||r|| <= rtol ||rhat|| (recursive), at maxit, on breakdown, or on
+    stagnation: the best residual so far has not dropped below stag_drop
+    times the previous best mark for stag_window iterations.
     d_fmt: format the correction d accumulates in (default: fmt).
     Returns (d as FP64 values of the stored format, iterations).
     """
@@ -284,7 +285,7 @@ def inner_pcg_lp(shape, rhat, fmt: str, rtol: float, maxit: int,
         return d, 0
     rho = float(dinv) * rr
     beta = 0.0
-    norms = [nr0]
+    best, best_at = nr0, 0
     it = 0
     for it in range(1, maxit + 1):
         p = rnd(dinv * r.astype(f32) + f32(beta) * p.astype(f32))
@@ -297,11 +298,13 @@ def inner_pcg_lp(shape, rhat, fmt: str, rtol: float, maxit: int,
         r = rnd(r.astype(f32) - alpha * q)
         rr = float(np.dot(r, r))
         nr = math.sqrt(rr)
-        norms.append(nr)
         if not math.isfinite(nr) or nr <= rtol * nr0:
             break
-        if it >= stag_window and nr > stag_drop * norms[it - stag_window]:
-            break
+        if stag_window > 0:
+            if nr < stag_drop * best:
+                best, best_at = nr, it
+            elif it - best_at >= stag_window:
+                break
         rho_new = float(dinv) * rr
         beta = rho_new / rho
         rho = rho_new

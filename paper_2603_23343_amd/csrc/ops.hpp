@@ -22,7 +22,9 @@ struct SolveState {
     int iters;     // completed iterations
     int done;      // 0 running, 1 converged, 2 breakdown, 3 maxit reached, 4 stagnated
     int maxit;
-    int stag;      // > 0: stop when ||r|| fell by less than 10% over stag iterations
+    int stag;      // > 0: stop when the best ||r|| has not improved by 10% for stag iterations
+    int stag_at;   // iteration of the last 10% improvement of the best residual
+    double stag_best;  // best relative residual at that iteration
 };
 
 // ---------------------------------------------------------------- loaders
@@ -293,9 +295,15 @@ struct FinBeta {
             st->done = 3;
             return;
         }
-        if (st->stag > 0 && hist && it >= st->stag && sqrt(rr / st->rr0) > 0.9 * hist[it - st->stag]) {
-            st->done = 4;
-            return;
+        if (st->stag > 0) {
+            const double rel = sqrt(rr / st->rr0);
+            if (rel < 0.9 * st->stag_best) {
+                st->stag_best = rel;
+                st->stag_at = it;
+            } else if (it - st->stag_at >= st->stag) {
+                st->done = 4;
+                return;
+            }
         }
         double rho_new = st->dinv * rr;
         st->beta = rho_new / st->rho;
@@ -314,6 +322,8 @@ struct FinStart {
         st->tol2 = st->tol2 * bb;  // host stores rtol^2 here before the launch
         st->iters = 0;
         st->beta = 0.0;
+        st->stag_at = 0;
+        st->stag_best = bb > 0.0 ? sqrt(rr / bb) : 0.0;
         st->rho = st->dinv * rr;
         if (hist) hist[0] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
         if (!isfinite(rr) || !isfinite(bb)) st->done = 2;

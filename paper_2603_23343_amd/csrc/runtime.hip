@@ -137,6 +137,9 @@ void free_ctx(pcg_ctx c) {
 // of the 16-byte vector width. Measured on MI355X at 256^3 and 512^3.
 Plan default_plan(int nx, int ny, int nz, int dt, const pcg_options& o) {
     Plan p{2, 16};
+    // widest vector shape whose footprint fits in nx (64, 32 or 16 threads wide)
+    if (plan_tx(p, dt) > nx) p.cfg = 1;
+    if (plan_tx(p, dt) > nx) p.cfg = 0;
     if (nx % dt_width(dt) != 0) p.cfg = 5;
     if (o.tile_x > 0 || o.tile_y > 0) {
         for (int c = 0; c < NUM_TILE_CFG; ++c) {
@@ -219,8 +222,8 @@ struct IterResult {
 
 // Start a solve of A x = b on the workspace (x0 = 0, or x0 given in x0 of
 // type x0_dt) and run PCG iterations until the device state says done:
-// converged, breakdown, maxit, or (stag > 0) a residual that fell by less
-// than 10% over the last stag iterations. The iterate is left in c->xacc.
+// converged, breakdown, maxit, or (stag > 0) no 10% improvement of the best
+// residual for stag iterations. The iterate is left in c->xacc.
 pcg_status run_iterations(pcg_ctx c, const void* b, const void* x0, int x0_dt, double rtol, int maxit, int stag,
                           IterResult* out) {
     pcg_status s = ensure_hist(c, maxit);
@@ -346,6 +349,7 @@ pcg_status pcg_options_default(pcg_options* o) {
     o->x_accum = -1;  // resolved at pcg_create: FP64
     o->x_dtype = -1;  // resolved at pcg_create: F32 storage -> F32, otherwise storage type
     o->use_graph = 1;
+    o->stag_window = -1;
     return PCG_OK;
 }
 
@@ -366,6 +370,7 @@ pcg_status pcg_create(pcg_ctx* out, int nx, int ny, int nz, pcg_dtype storage, v
     if (o.x_dtype != storage && o.x_dtype != PCG_F64)
         return fail(PCG_E_ARG, "pcg_create: x_dtype must be the storage type or PCG_F64");
     if (o.x_accum < 0) o.x_accum = PCG_F64;
+    if (o.stag_window < 0) o.stag_window = 100;
     if (o.x_accum != PCG_F64 && o.x_accum != PCG_F32 && o.x_accum != storage)
         return fail(PCG_E_ARG, "pcg_create: x_accum must be PCG_F64, PCG_F32 or the storage type");
     if (storage == PCG_F64) o.x_accum = PCG_F64;
@@ -558,7 +563,7 @@ pcg_status pcg_solve_refined(pcg_ctx c, const double* b64, double* x64, double r
         const double scale = 1.0 / amax;
         HIPCHK(launch_cast_scaled(c->dt, c->plan_res, c->geo_res, b64, x64, scale, c->rhat, st));
         IterResult res;
-        pcg_status s = run_iterations(c, c->rhat, nullptr, c->dt, rtol_inner, maxit_inner, 20, &res);
+        pcg_status s = run_iterations(c, c->rhat, nullptr, c->dt, rtol_inner, maxit_inner, c->opt.stag_window, &res);
         if (s != PCG_OK) return s;
         c->ref_inner.push_back(res.fin.iters);
         inner_total += res.fin.iters;
