@@ -39,10 +39,15 @@ BYTES_DIRECTION = 12
 BYTES_UPDATE = 28
 
 
+# Sources that define the PCG iteration kernels; counter-measured traffic in
+# profiles/traffic.json is used only while these files are unchanged.
+ITER_KERNEL_SOURCES = ["common.hpp", "zmarch.hpp", "ops.hpp", "zkernel.hpp", "pcg.hip", "internal.hpp"]
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_23343_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in ITER_KERNEL_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -149,6 +154,8 @@ def main():
     ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--maxit", type=int, default=5000)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="also copy a buffer of this many MiB 5 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver is single-GPU.",
@@ -158,6 +165,16 @@ def main():
     import torch
 
     import paper_2603_23343_amd as P
+
+    if args.copy_probe > 0:
+        # A plain device copy of known size: its FETCH_SIZE / WRITE_SIZE
+        # counters calibrate the counter bytes of the solver's kernels.
+        src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     n = args.n
     N = n ** 3
@@ -200,8 +217,8 @@ def main():
     # FP16 inner Jacobi-PCG; time to FP64 true residual 1e-6 and 1e-10.
     refined = {}
     if not args.no_refined:
-        for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
-            rctx = P.pcg_create(n, n, n, dt, x_accum=torch.float32)
+        for name, rdt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+            rctx = P.pcg_create(n, n, n, rdt, x_accum=torch.float32)
             x64 = torch.empty(N, dtype=torch.float64, device="cuda")
             P.pcg_solve_refined(rctx, b64, x64, rtol_outer=1e-10)
             torch.cuda.synchronize()
