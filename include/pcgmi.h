@@ -148,6 +148,20 @@ pcg_status pcg_solve_refined(pcg_ctx ctx, const double *b64, double *x64, double
  * (inner_iters, may be NULL), n entries at most; *count = entries written. */
 pcg_status pcg_refine_history(pcg_ctx ctx, double *relres, int *inner_iters, int n, int *count);
 
+/* Switch the context's operator to the variable-coefficient form
+ * (A_k u)_p = sum over the six faces f of k_f (u_p - u_nb), with the face
+ * coefficient k_f = 2 k_p k_q / (k_p + k_q) (harmonic mean of the two cell
+ * values), k_f = k_p on a boundary face and u = 0 outside the grid; the
+ * Jacobi preconditioner becomes D^-1 with D_p = sum_f k_f. This is the
+ * paper's operator (Sec. VII) with k = 1 and the learned-preconditioner
+ * workload's operator in general. k_cell: DEVICE array of nx*ny*nz FP32
+ * cell values > 0, owned by the caller and read by later calls (keep it
+ * alive and unchanged); NULL restores constant coefficients. Computes and
+ * stores D^-1 in the workspace. Needs F32 or F64 storage
+ * (PCG_E_UNSUPPORTED otherwise). Affects stencil_apply, pcg_solve and
+ * pcg_solve_refined on this context. */
+pcg_status pcg_set_coefficients(pcg_ctx ctx, const float *k_cell);
+
 /* Copy the recursive relative residuals ||r_k||/||b||, k = 0..iters of the
  * last pcg_solve on this context, to the host array hist (n entries at most).
  * *count receives the number written. */

@@ -67,6 +67,7 @@ def _load():
         "pcg_solve_refined": ([vp, vp, vp, d, d, i, i, ctypes.POINTER(PcgInfo)], i),
         "pcg_refine_history": ([vp, ctypes.POINTER(d), ctypes.POINTER(i), i, ctypes.POINTER(i)], i),
         "pcg_last_error": ([], ctypes.c_char_p),
+        "pcg_set_coefficients": ([vp, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -221,3 +222,10 @@ def pcg_refine_history(ctx: Context, n=256):
     _check(lib.pcg_refine_history(ctx.handle, rel.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                   inner.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), n, ctypes.byref(cnt)))
     return rel[: cnt.value].copy(), inner[: max(cnt.value - 1, 0)].copy()
+
+
+def pcg_set_coefficients(ctx: Context, k_cell):
+    """Variable-coefficient operator with FP32 cell values k_cell (device,
+    kept alive by the context object); None restores constant coefficients."""
+    ctx._kcell = k_cell
+    _check(lib.pcg_set_coefficients(ctx.handle, _ptr(k_cell)))

@@ -83,30 +83,39 @@ __global__ void __launch_bounds__(NT) k_dot(int64_t n, const T* __restrict__ x, 
     }
 }
 
-// r = b, x = 0, p0 = p1 = 0 and the totals {b.b, b.b} for the solve start.
+// Start of a solve from x0 = 0: r = b, x = 0, p0 = 0 (the first direction
+// kernel reads p0 as p_old with beta = 0; p1 is written before it is read)
+// and the totals {b.b, b.b, sum dinv b^2} for the solve state.
 template <typename T, typename X>
 __global__ void __launch_bounds__(NT) k_start_zero(int64_t n, const T* __restrict__ b, T* __restrict__ r,
-                                                   X* __restrict__ x, T* __restrict__ p0, T* __restrict__ p1,
-                                                   SolveState* st, double* hist, Red red) {
+                                                   X* __restrict__ x, T* __restrict__ p0,
+                                                   const T* __restrict__ dinv, SolveState* st, double* hist,
+                                                   Red red) {
     using C = typename Traits<T>::C;
     constexpr int W = Traits<T>::W;
-    __shared__ double scratch[32];
+    __shared__ double scratch[48];
     const int64_t nvec = n / W;
     const int64_t stride = (int64_t)gridDim.x * NT;
-    C acc = C(0);
+    const C dconst = (C)st->dinv;
+    C acc = C(0), accz = C(0);
     C zero[W];
+    double xz[W];
 #pragma unroll
-    for (int e = 0; e < W; ++e) zero[e] = C(0);
+    for (int e = 0; e < W; ++e) {
+        zero[e] = C(0);
+        xz[e] = 0.0;
+    }
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nvec; i += stride) {
-        C a[W];
+        C a[W], d[W];
         load_vec<T>(b + i * W, a);
+        if (dinv) load_vec<T>(dinv + i * W, d);
         store_vec<T>(r + i * W, a);
         store_vec<T>(p0 + i * W, zero);
-        store_vec<T>(p1 + i * W, zero);
+        st_any<X, W>(x, i * W, xz);
 #pragma unroll
         for (int e = 0; e < W; ++e) {
-            x[i * W + e] = from_c<X>((typename Traits<X>::C)0);
             acc += a[e] * a[e];
+            accz += (dinv ? d[e] : dconst) * a[e] * a[e];
         }
     }
     if (blockIdx.x == 0) {
@@ -115,13 +124,13 @@ __global__ void __launch_bounds__(NT) k_start_zero(int64_t n, const T* __restric
             C a = to_c(b[t]);
             r[t] = b[t];
             p0[t] = from_c<T>(C(0));
-            p1[t] = from_c<T>(C(0));
             x[t] = from_c<X>((typename Traits<X>::C)0);
             acc += a * a;
+            accz += (dinv ? to_c(dinv[t]) : dconst) * a * a;
         }
     }
-    double v[2] = {(double)acc, (double)acc}, tot[2];
-    if (grid_reduce<2, 0u>(v, red.partials, red.ticket, gridDim.x, blockIdx.x, scratch, tot) &&
+    double v[3] = {(double)acc, (double)acc, (double)accz}, tot[3];
+    if (grid_reduce<3, 0u>(v, red.partials, red.ticket, gridDim.x, blockIdx.x, scratch, tot) &&
         threadIdx.x == 0)
         FinStart{st, hist}(tot);
 }
@@ -183,8 +192,8 @@ hipError_t launch_dot(int dt, int64_t n, const void* x, const void* y, float* ou
     });
 }
 
-hipError_t launch_pcg_start_zero(int dt, int64_t n, const void* b, void* r, void* x, int xdt, void* p0, void* p1,
-                                 SolveState* st, double* hist, Red red, hipStream_t s) {
+hipError_t launch_pcg_start_zero(int dt, int64_t n, const void* b, void* r, void* x, int xdt, void* p0,
+                                 const void* dinv, SolveState* st, double* hist, Red red, hipStream_t s) {
     return dispatch_dt(dt, [&](auto tag) {
         using T = decltype(tag);
         const int64_t nvec = n / Traits<T>::W;
@@ -192,8 +201,8 @@ hipError_t launch_pcg_start_zero(int dt, int64_t n, const void* b, void* r, void
         auto go = [&](auto xtag) {
             using X = decltype(xtag);
             hipLaunchKernelGGL((k_start_zero<T, X>), dim3(nb), dim3(NT), 0, s, n, static_cast<const T*>(b),
-                               static_cast<T*>(r), static_cast<X*>(x), static_cast<T*>(p0), static_cast<T*>(p1), st,
-                               hist, red);
+                               static_cast<T*>(r), static_cast<X*>(x), static_cast<T*>(p0),
+                               static_cast<const T*>(dinv), st, hist, red);
             return hipGetLastError();
         };
         if (xdt == DT_F64) return go(double{});

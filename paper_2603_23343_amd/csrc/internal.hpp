@@ -48,27 +48,37 @@ struct Red {
     unsigned* ticket;
 };
 
+// The operator of a context: constant coefficients (kc == null) or the
+// variable-coefficient operator with cell coefficients kc (FP32) and the
+// inverse Jacobi diagonal dinv (storage type).
+struct OpDesc {
+    const float* kc;
+    const void* dinv;
+};
+
 // ---- z-march kernels (stencil family) ----
-hipError_t launch_stencil(int dt, const Plan& p, const Geometry& g, const void* x, void* y, hipStream_t s);
+hipError_t launch_stencil(int dt, const Plan& p, const Geometry& g, OpDesc od, const void* x, void* y, hipStream_t s);
+// dinv = 1 / diag(A_k) for cell coefficients kc.
+hipError_t launch_var_dinv(int dt, const Plan& p, const Geometry& g, const float* kc, void* dinv, hipStream_t s);
 
 // Iteration kernel 1: p_new = D^-1 r + beta p_old (rounded to storage), p.Ap -> alpha.
-hipError_t launch_pcg_direction(int dt, const Plan& p, const Geometry& g, const void* r, const void* pold,
-                                void* pnew, SolveState* st, Red red, hipStream_t s);
+hipError_t launch_pcg_direction(int dt, const Plan& p, const Geometry& g, OpDesc od, const void* r,
+                                const void* pold, void* pnew, SolveState* st, Red red, hipStream_t s);
 // Iteration kernel 2: q = A p, x += alpha p, r -= alpha q, r.r -> convergence, beta.
 // x (the accumulator) is of type xdt: FP64, FP32 or the storage type.
-hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, const void* pdir, void* x, int xdt,
-                             void* r, SolveState* st, double* hist, Red red, hipStream_t s);
+hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, OpDesc od, const void* pdir, void* x,
+                             int xdt, void* r, SolveState* st, double* hist, Red red, hipStream_t s);
 // r = stored(b - A x0) computed in FP64 (x0 of type xdt), totals {r.r, b.b}
 // -> solve start. Uses the FP64 residual shape (pres, gres).
-hipError_t launch_pcg_start_x0(int dt, int xdt, const Plan& pres, const Geometry& gres, const void* b,
+hipError_t launch_pcg_start_x0(int dt, int xdt, const Plan& pres, const Geometry& gres, OpDesc od, const void* b,
                                const void* x0, void* r, SolveState* st, double* hist, Red red, hipStream_t s);
 // FP64 residual of b (type bdt) and x (type xdt): out = {||r||^2, max|r|}.
-hipError_t launch_residual64(int bdt, int xdt, const Plan& p, const Geometry& g, const void* b, const void* x,
-                             double* out, Red red, hipStream_t s);
+hipError_t launch_residual64(int bdt, int xdt, const Plan& p, const Geometry& g, OpDesc od, const void* b,
+                             const void* x, double* out, Red red, hipStream_t s);
 
 // Refinement: rhat (storage type dt) = stored(scale (b - A x)), FP64 b and x.
-hipError_t launch_cast_scaled(int dt, const Plan& pres, const Geometry& gres, const double* b, const double* x,
-                              double scale, void* rhat, hipStream_t s);
+hipError_t launch_cast_scaled(int dt, const Plan& pres, const Geometry& gres, OpDesc od, const double* b,
+                              const double* x, double scale, void* rhat, hipStream_t s);
 // Refinement: x += d / scale, d of type ddt.
 hipError_t launch_correct(int ddt, int64_t n, const void* d, double scale, double* x, hipStream_t s);
 
@@ -77,9 +87,10 @@ hipError_t launch_axpy(int dt, int64_t n, float alpha, const void* x, const void
 // out_f32 and/or out_f64 (device) receive the dot; either may be null.
 hipError_t launch_dot(int dt, int64_t n, const void* x, const void* y, float* out_f32, double* out_f64, Red red,
                       hipStream_t s);
-// r = b, x = 0, p0 = p1 = 0; totals {b.b, b.b} -> solve start.
-hipError_t launch_pcg_start_zero(int dt, int64_t n, const void* b, void* r, void* x, int xdt, void* p0, void* p1,
-                                 SolveState* st, double* hist, Red red, hipStream_t s);
+// r = b, x = 0, p0 = 0; totals {b.b, b.b, sum dinv b^2} -> solve start (dinv
+// from the array when given, else the solve state's constant).
+hipError_t launch_pcg_start_zero(int dt, int64_t n, const void* b, void* r, void* x, int xdt, void* p0,
+                                 const void* dinv, SolveState* st, double* hist, Red red, hipStream_t s);
 // Fill n elements of type dt (or FP64 when dt == DT_F64) with zero.
 hipError_t launch_zero(int dt, int64_t n, void* p, hipStream_t s);
 // Convert n elements: dst (type ddt) = src (type sdt), rounding to nearest even.

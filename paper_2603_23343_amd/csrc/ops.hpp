@@ -83,6 +83,85 @@ template <typename T> struct LoadDirection {
     }
 };
 
+// Variable coefficients: the field x (type T) together with the cell
+// coefficient k (FP32) of each point.
+template <typename T> struct LoadUK {
+    using C = typename Traits<T>::C;
+    template <int N> struct Raw {
+        RawN<T, N> u;
+        RawN<float, N> k;
+    };
+    const T* __restrict__ x;
+    const float* __restrict__ kc;
+    __device__ void init() {}
+    template <int N> __device__ __forceinline__ void fetch(int64_t i, Raw<N>& r) const {
+        r.u.load(x + i);
+        r.k.load(kc + i);
+    }
+    template <int N> __device__ __forceinline__ void finish(const Raw<N>& r, UK<C>* out) const {
+#pragma unroll
+        for (int v = 0; v < N; ++v) out[v] = UK<C>{r.u.get(v), (C)r.k.get(v)};
+    }
+};
+
+// Field of type S widened to C, with k (variable-coefficient FP64 kernels).
+template <typename S, typename C> struct LoadWidenUK {
+    template <int N> struct Raw {
+        RawN<S, N> u;
+        RawN<float, N> k;
+    };
+    const S* __restrict__ x;
+    const float* __restrict__ kc;
+    __device__ void init() {}
+    template <int N> __device__ __forceinline__ void fetch(int64_t i, Raw<N>& r) const {
+        r.u.load(x + i);
+        r.k.load(kc + i);
+    }
+    template <int N> __device__ __forceinline__ void finish(const Raw<N>& r, UK<C>* out) const {
+#pragma unroll
+        for (int v = 0; v < N; ++v) out[v] = UK<C>{(C)r.u.get(v), (C)r.k.get(v)};
+    }
+};
+
+// The cell coefficient alone (for the diagonal of the variable operator).
+template <typename C> struct LoadK {
+    template <int N> using Raw = RawN<float, N>;
+    const float* __restrict__ kc;
+    __device__ void init() {}
+    template <int N> __device__ __forceinline__ void fetch(int64_t i, Raw<N>& r) const { r.load(kc + i); }
+    template <int N> __device__ __forceinline__ void finish(const Raw<N>& r, C* out) const {
+#pragma unroll
+        for (int v = 0; v < N; ++v) out[v] = (C)r.get(v);
+    }
+};
+
+// Direction with a variable Jacobi scale: p = stored(dinv_p r + beta p_old), with k.
+template <typename T> struct LoadDirectionVar {
+    using C = typename Traits<T>::C;
+    template <int N> struct Raw {
+        RawN<T, N> r, p, d;
+        RawN<float, N> k;
+    };
+    const T* __restrict__ r;
+    const T* __restrict__ pold;
+    const T* __restrict__ dinv;
+    const float* __restrict__ kc;
+    const SolveState* st;
+    C beta;
+    __device__ void init() { beta = (C)st->beta; }
+    template <int N> __device__ __forceinline__ void fetch(int64_t i, Raw<N>& raw) const {
+        raw.r.load(r + i);
+        raw.p.load(pold + i);
+        raw.d.load(dinv + i);
+        raw.k.load(kc + i);
+    }
+    template <int N> __device__ __forceinline__ void finish(const Raw<N>& raw, UK<C>* out) const {
+#pragma unroll
+        for (int v = 0; v < N; ++v)
+            out[v] = UK<C>{stored<T>(raw.d.get(v) * raw.r.get(v) + beta * raw.p.get(v)), (C)raw.k.get(v)};
+    }
+};
+
 // ---------------------------------------------------------------- store helpers
 
 template <typename T, int VX>
@@ -125,8 +204,8 @@ template <typename T, int VX> struct OpStore {
     T* __restrict__ y;
     __device__ void init() {}
     __device__ __forceinline__ void fetch(int64_t, Raw&) const {}
-    template <int NC>
-    __device__ __forceinline__ void apply(int64_t i, const Raw&, const C* c, const C* ax, C (&acc)[NC]) const {
+    template <int NC, class Cell>
+    __device__ __forceinline__ void apply(int64_t i, const Raw&, const Cell* c, const C* ax, C (&acc)[NC]) const {
         st_pts<T, VX>(y, i, ax);
     }
 };
@@ -139,25 +218,32 @@ template <typename T, int VX> struct OpDirection {
     T* __restrict__ pnew;
     __device__ void init() {}
     __device__ __forceinline__ void fetch(int64_t, Raw&) const {}
-    template <int NC>
-    __device__ __forceinline__ void apply(int64_t i, const Raw&, const C* c, const C* ax, C (&acc)[NC]) const {
-        st_pts<T, VX>(pnew, i, c);
+    template <int NC, class Cell>
+    __device__ __forceinline__ void apply(int64_t i, const Raw&, const Cell* c, const C* ax, C (&acc)[NC]) const {
+        C u[VX];
 #pragma unroll
-        for (int v = 0; v < VX; ++v) acc[0] += c[v] * ax[v];
+        for (int v = 0; v < VX; ++v) {
+            u[v] = cell_u(c[v]);
+            acc[0] += u[v] * ax[v];
+        }
+        st_pts<T, VX>(pnew, i, u);
     }
 };
 
 // Iteration kernel 2: with q = A p recomputed from p, x += alpha p and
-// r = stored(r - alpha q); accumulate r.r of the stored residual.
-template <typename T, typename X, int VX> struct OpUpdate {
+// r = stored(r - alpha q); accumulate r.r of the stored residual and, with a
+// variable Jacobi scale (dinv != null), r.z = sum dinv r^2 as component 1.
+template <typename T, typename X, int VX, bool VAR = false> struct OpUpdate {
     using C = typename Traits<T>::C;
     struct Raw {
         RawN<T, VX> r;
         RawN<X, VX> x;
+        RawN<T, VAR ? VX : 1> d;
     };
     X* __restrict__ x;
     T* __restrict__ r;
     const SolveState* st;
+    const T* __restrict__ dinv;
     C alpha;
     double alpha_d;
     __device__ void init() {
@@ -167,19 +253,37 @@ template <typename T, typename X, int VX> struct OpUpdate {
     __device__ __forceinline__ void fetch(int64_t i, Raw& raw) const {
         raw.r.load(r + i);
         raw.x.load(x + i);
+        if constexpr (VAR) raw.d.load(dinv + i);
     }
-    template <int NC>
-    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const C* c, const C* ax, C (&acc)[NC]) const {
+    template <int NC, class Cell>
+    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const Cell* c, const C* ax, C (&acc)[NC]) const {
         C rv[VX];
         double xv[VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
-            xv[v] = (double)raw.x.get(v) + alpha_d * (double)c[v];
+            xv[v] = (double)raw.x.get(v) + alpha_d * (double)cell_u(c[v]);
             rv[v] = stored<T>(raw.r.get(v) - alpha * ax[v]);
             acc[0] += rv[v] * rv[v];
+            if constexpr (VAR) acc[NC - 1] += raw.d.get(v) * rv[v] * rv[v];
         }
         st_any<X, VX>(x, i, xv);
         st_pts<T, VX>(r, i, rv);
+    }
+};
+
+// dinv = 1 / D with D the variable operator's diagonal (from StencilVarDiag).
+template <typename T, int VX> struct OpStoreInverse {
+    using C = typename Traits<T>::C;
+    using Raw = NoRaw;
+    T* __restrict__ dinv;
+    __device__ void init() {}
+    __device__ __forceinline__ void fetch(int64_t, Raw&) const {}
+    template <int NC, class Cell>
+    __device__ __forceinline__ void apply(int64_t i, const Raw&, const Cell* c, const C* ax, C (&acc)[NC]) const {
+        C out[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) out[v] = C(1) / ax[v];
+        st_pts<T, VX>(dinv, i, out);
     }
 };
 
@@ -191,8 +295,8 @@ template <typename B, int VX> struct OpResidual64 {
     const B* __restrict__ b;
     __device__ void init() {}
     __device__ __forceinline__ void fetch(int64_t i, Raw& raw) const { raw.b.load(b + i); }
-    template <int NC>
-    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const double* c, const double* ax,
+    template <int NC, class Cell>
+    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const Cell* c, const double* ax,
                                           double (&acc)[NC]) const {
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
@@ -215,8 +319,8 @@ template <typename T, int VX> struct OpCastScaled {
     double scale;
     __device__ void init() {}
     __device__ __forceinline__ void fetch(int64_t i, Raw& raw) const { raw.b.load(b + i); }
-    template <int NC>
-    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const double* c, const double* ax,
+    template <int NC, class Cell>
+    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const Cell* c, const double* ax,
                                           double (&acc)[NC]) const {
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
@@ -228,17 +332,21 @@ template <typename T, int VX> struct OpCastScaled {
 
 // Residual of an initial guess, computed in FP64 and rounded to the storage
 // type (through FP32 for 16-bit types): r = stored(b - A x0); accumulates
-// r.r of the stored residual and b.b.
+// r.r of the stored residual, b.b and r.z = sum dinv r^2 (dinv from the array
+// when given, else the constant of the solve state).
 template <typename T, int VX> struct OpInitResidual {
     struct Raw {
         RawN<T, VX> b;
     };
     const T* __restrict__ b;
     T* __restrict__ r;
-    __device__ void init() {}
+    const T* __restrict__ dinv;
+    const SolveState* st;
+    double dconst;
+    __device__ void init() { dconst = st->dinv; }
     __device__ __forceinline__ void fetch(int64_t i, Raw& raw) const { raw.b.load(b + i); }
-    template <int NC>
-    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const double* c, const double* ax,
+    template <int NC, class Cell>
+    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const Cell* c, const double* ax,
                                           double (&acc)[NC]) const {
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
@@ -246,8 +354,10 @@ template <typename T, int VX> struct OpInitResidual {
             const T rs = from_c<T>((typename Traits<T>::C)(bv - ax[v]));
             r[i + v] = rs;
             const double rv = (double)to_c(rs);
+            const double dv = dinv ? (double)to_c(dinv[i + v]) : dconst;
             acc[0] += rv * rv;
             acc[1] += bv * bv;
+            acc[2] += dv * rv * rv;
         }
     }
 };
@@ -273,10 +383,12 @@ struct FinAlpha {
     }
 };
 
-// After r.r: count the iteration, test convergence, form beta.
+// After r.r: count the iteration, test convergence, form beta. With a
+// variable Jacobi scale (var), rho_new = r.z is the second total.
 struct FinBeta {
     SolveState* st;
     double* hist;  // relres per iteration (maxit + 1 entries) or null
+    bool var;
     __device__ void operator()(const double* tot) const {
         double rr = tot[0];
         int it = st->iters + 1;
@@ -305,13 +417,13 @@ struct FinBeta {
                 return;
             }
         }
-        double rho_new = st->dinv * rr;
+        double rho_new = var ? tot[1] : st->dinv * rr;
         st->beta = rho_new / st->rho;
         st->rho = rho_new;
     }
 };
 
-// Start of a solve from r and ||b||^2: tot = {r.r, b.b}.
+// Start of a solve: tot = {r.r, b.b, r.z}.
 struct FinStart {
     SolveState* st;
     double* hist;
@@ -324,7 +436,7 @@ struct FinStart {
         st->beta = 0.0;
         st->stag_at = 0;
         st->stag_best = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-        st->rho = st->dinv * rr;
+        st->rho = tot[2];
         if (hist) hist[0] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
         if (!isfinite(rr) || !isfinite(bb)) st->done = 2;
         else if (bb == 0.0 || rr <= st->tol2) st->done = 1;

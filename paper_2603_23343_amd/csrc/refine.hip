@@ -20,16 +20,21 @@ __global__ void __launch_bounds__(STREAM_THREADS) k_correct(int64_t n, const D* 
 
 }  // namespace
 
-hipError_t launch_cast_scaled(int dt, const Plan& pres, const Geometry& gres, const double* b, const double* x,
-                              double scale, void* rhat, hipStream_t s) {
+hipError_t launch_cast_scaled(int dt, const Plan& pres, const Geometry& gres, OpDesc od, const double* b,
+                              const double* x, double scale, void* rhat, hipStream_t s) {
     const int cfg = TILE_CFGS[pres.cfg].vec ? 2 : 5;
     return dispatch_dt(dt, [&](auto tag) {
         using T = decltype(tag);
         return dispatch_cfg<2>(cfg, [&]<int BX, int BY, int VX>() {
-            LoadWiden<double, double> ld{x};
             OpCastScaled<T, VX> op{b, static_cast<T*>(rhat), scale};
-            return run_zmarch<ZF_GENERIC, double, BX, BY, VX, 1, 0u, false>(gres, ld, op, FinNone{},
-                                                                           Red{nullptr, nullptr}, nullptr, s);
+            if (od.kc) {
+                LoadWidenUK<double, double> ld{x, od.kc};
+                return run_zmarch<ZF_GENERIC, double, StencilVar<double>, BX, BY, VX, 1, 0u, false>(
+                    gres, ld, op, FinNone{}, Red{nullptr, nullptr}, nullptr, s);
+            }
+            LoadWiden<double, double> ld{x};
+            return run_zmarch<ZF_GENERIC, double, StencilConst<double>, BX, BY, VX, 1, 0u, false>(
+                gres, ld, op, FinNone{}, Red{nullptr, nullptr}, nullptr, s);
         });
     });
 }

@@ -106,6 +106,9 @@ struct pcg_ctx_s {
     int chunk_iters = 0;
     hipEvent_t ev_chunk[2] = {nullptr, nullptr};
     int last_iters = 0;
+    // operator: constant coefficients unless pcg_set_coefficients gave k
+    const float* kc = nullptr;  // caller's cell coefficients (device, FP32)
+    void* dinv = nullptr;       // inverse Jacobi diagonal (storage type), owned
     // iterative refinement
     void* rhat = nullptr;  // scaled residual in the storage type
     std::vector<double> ref_relres;
@@ -115,13 +118,15 @@ struct pcg_ctx_s {
 namespace {
 
 Red red_of(pcg_ctx c) { return Red{c->partials, c->ticket}; }
+OpDesc op_of(pcg_ctx c) { return OpDesc{c->kc, c->kc ? c->dinv : nullptr}; }
 
 void free_ctx(pcg_ctx c) {
     if (!c) return;
     if (c->chunk) (void)hipGraphExecDestroy(c->chunk);
     for (auto& e : c->ev_chunk)
         if (e) (void)hipEventDestroy(e);
-    void* dev[] = {c->r, c->p[0], c->p[1], c->xacc, c->partials, c->ticket, c->st, c->hist, c->res2, c->rhat};
+    void* dev[] = {c->r, c->p[0], c->p[1], c->xacc, c->partials, c->ticket, c->st, c->hist, c->res2, c->rhat,
+                   c->dinv};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     if (c->hst) (void)hipHostFree(c->hst);
@@ -181,11 +186,12 @@ hipError_t enqueue_iters(pcg_ctx c, int first, int count, hipStream_t s, hipEven
         void* pold = c->p[(i - 1) & 1];
         void* pnew = c->p[i & 1];
         if (evs) (void)hipEventRecord(evs[3 * (i - first)], s);
-        hipError_t e = launch_pcg_direction(c->dt, c->plan, c->geo, c->r, pold, pnew, c->st, red_of(c), s);
+        hipError_t e =
+            launch_pcg_direction(c->dt, c->plan, c->geo, op_of(c), c->r, pold, pnew, c->st, red_of(c), s);
         if (e != hipSuccess) return e;
         if (evs) (void)hipEventRecord(evs[3 * (i - first) + 1], s);
-        e = launch_pcg_update(c->dt, c->plan, c->geo, pnew, c->xacc, c->opt.x_accum, c->r, c->st, c->hist,
-                              red_of(c), s);
+        e = launch_pcg_update(c->dt, c->plan, c->geo, op_of(c), pnew, c->xacc, c->opt.x_accum, c->r, c->st,
+                              c->hist, red_of(c), s);
         if (e != hipSuccess) return e;
         if (evs) (void)hipEventRecord(evs[3 * (i - first) + 2], s);
     }
@@ -243,11 +249,11 @@ pcg_status run_iterations(pcg_ctx c, const void* b, const void* x0, int x0_dt, d
         HIPCHK(launch_convert(x0_dt, xacc_dt, c->n, x0, c->xacc, st));
         HIPCHK(launch_zero(c->dt, c->n, c->p[0], st));
         HIPCHK(launch_zero(c->dt, c->n, c->p[1], st));
-        HIPCHK(launch_pcg_start_x0(c->dt, xacc_dt, c->plan_res, c->geo_res, b, c->xacc, c->r, c->st, c->hist,
-                                   red_of(c), st));
+        HIPCHK(launch_pcg_start_x0(c->dt, xacc_dt, c->plan_res, c->geo_res, op_of(c), b, c->xacc, c->r, c->st,
+                                   c->hist, red_of(c), st));
     } else {
-        HIPCHK(launch_pcg_start_zero(c->dt, c->n, b, c->r, c->xacc, xacc_dt, c->p[0], c->p[1], c->st, c->hist,
-                                     red_of(c), st));
+        HIPCHK(launch_pcg_start_zero(c->dt, c->n, b, c->r, c->xacc, xacc_dt, c->p[0], op_of(c).dinv, c->st,
+                                     c->hist, red_of(c), st));
     }
 
     const int C = c->chunk_iters;
@@ -438,7 +444,7 @@ pcg_status stencil_apply(pcg_ctx c, const void* x, void* y) {
     if (!x || !y) return fail(PCG_E_ARG, "stencil_apply: null pointer");
     if (!aligned16(x) || !aligned16(y)) return fail(PCG_E_ARG, "stencil_apply: pointers must be 16-byte aligned");
     if (overlap(x, y, (size_t)c->n * dt_size(c->dt))) return fail(PCG_E_ARG, "stencil_apply: x and y overlap");
-    HIPCHK(launch_stencil(c->dt, c->plan, c->geo, x, y, c->stream));
+    HIPCHK(launch_stencil(c->dt, c->plan, c->geo, op_of(c), x, y, c->stream));
     return PCG_OK;
 }
 
@@ -494,7 +500,8 @@ pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, 
     if (c->opt.x_dtype == xacc_dt) HIPCHK(hipMemcpyAsync(x, c->xacc, xbytes, hipMemcpyDeviceToDevice, st));
     else HIPCHK(launch_convert(xacc_dt, c->opt.x_dtype, c->n, c->xacc, x, st));
     if (res.fin.rr0 == 0.0) HIPCHK(launch_zero(c->opt.x_dtype, c->n, x, st));
-    HIPCHK(launch_residual64(c->dt, c->opt.x_dtype, c->plan_res, c->geo_res, b, x, c->res2, red_of(c), st));
+    HIPCHK(launch_residual64(c->dt, c->opt.x_dtype, c->plan_res, c->geo_res, op_of(c), b, x, c->res2, red_of(c),
+                             st));
     HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const SolveState& fin = res.fin;
@@ -540,7 +547,8 @@ pcg_status pcg_solve_refined(pcg_ctx c, const double* b64, double* x64, double r
     int outer = 0, inner_total = 0;
     pcg_status ret = PCG_E_NOCONV;
     for (;;) {
-        HIPCHK(launch_residual64(DT_F64, DT_F64, c->plan_res, c->geo_res, b64, x64, c->res2, red_of(c), st));
+        HIPCHK(launch_residual64(DT_F64, DT_F64, c->plan_res, c->geo_res, op_of(c), b64, x64, c->res2, red_of(c),
+                                 st));
         HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         const double rn = std::sqrt(c->hres[0]), amax = c->hres[1];
@@ -561,7 +569,7 @@ pcg_status pcg_solve_refined(pcg_ctx c, const double* b64, double* x64, double r
         if (outer >= max_outer) break;
         // rhat = lp(s (b - A x)), s = 1 / max|r|; inner Jacobi-PCG A d = rhat.
         const double scale = 1.0 / amax;
-        HIPCHK(launch_cast_scaled(c->dt, c->plan_res, c->geo_res, b64, x64, scale, c->rhat, st));
+        HIPCHK(launch_cast_scaled(c->dt, c->plan_res, c->geo_res, op_of(c), b64, x64, scale, c->rhat, st));
         IterResult res;
         pcg_status s = run_iterations(c, c->rhat, nullptr, c->dt, rtol_inner, maxit_inner, c->opt.stag_window, &res);
         if (s != PCG_OK) return s;
@@ -595,6 +603,25 @@ pcg_status pcg_refine_history(pcg_ctx c, double* relres, int* inner_iters, int n
         if (inner_iters) inner_iters[i] = i < (int)c->ref_inner.size() ? c->ref_inner[i] : 0;
     }
     *count = m;
+    return PCG_OK;
+}
+
+pcg_status pcg_set_coefficients(pcg_ctx c, const float* k_cell) {
+    if (!c) return fail(PCG_E_ARG, "pcg_set_coefficients: null context");
+    if (!k_cell) {
+        c->kc = nullptr;
+        return PCG_OK;
+    }
+    if (!aligned16(k_cell)) return fail(PCG_E_ARG, "pcg_set_coefficients: k must be 16-byte aligned");
+    if (c->dt != DT_F32 && c->dt != DT_F64)
+        return fail(PCG_E_UNSUPPORTED, "pcg_set_coefficients: variable coefficients need F32 or F64 storage");
+    if (!c->dinv) HIPCHK(hipMalloc(&c->dinv, dt_size(c->dt) * c->n));
+    HIPCHK(launch_var_dinv(c->dt, c->plan, c->geo, k_cell, c->dinv, c->stream));
+    c->kc = k_cell;
+    if (c->chunk) {  // captured kernels use the old operator
+        HIPCHK(hipGraphExecDestroy(c->chunk));
+        c->chunk = nullptr;
+    }
     return PCG_OK;
 }
 

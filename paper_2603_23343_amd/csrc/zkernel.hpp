@@ -2,6 +2,8 @@
 // types and compiled work-group shapes.
 #pragma once
 
+#include <type_traits>
+
 #include "ops.hpp"
 
 namespace pcgmi {
@@ -10,12 +12,13 @@ namespace pcgmi {
 // combined over the grid (component c maxed when bit c of MM is set) and
 // handed to fin by the last work-group. A set *done skips the launch's work:
 // captured PCG iterations after convergence cost only the launch.
-template <typename C, int BX, int BY, int VX, int NC, unsigned MM, bool RED, class L, class O, class F>
+template <typename C, class SP, int BX, int BY, int VX, int NC, unsigned MM, bool RED, class L, class O, class F>
 __device__ __forceinline__ void zmarch_body(const Grid3& g, const L& ld, const O& op, const F& fin, Red red,
                                             const int* done) {
     if (done != nullptr && *done != 0) return;
-    using ZT = ZTile<C, BX, BY, VX>;
-    __shared__ __attribute__((aligned(16))) C lds[2 * ZT::PLANE];
+    using Cell = typename SP::Cell;
+    using ZT = ZTile<Cell, BX, BY, VX>;
+    __shared__ __attribute__((aligned(16))) Cell lds[2 * ZT::PLANE];
     __shared__ double rscratch[NC * 16];
     L l = ld;
     O o = op;
@@ -23,7 +26,7 @@ __device__ __forceinline__ void zmarch_body(const Grid3& g, const L& ld, const O
     o.init();
     const unsigned tile = xcd_remap(blockIdx.x, g.nblocks);
     C acc[NC];
-    zmarch<C, BX, BY, VX, NC>(g, tile, l, o, acc, lds);
+    zmarch<C, SP, BX, BY, VX, NC>(g, tile, l, o, acc, lds);
     if constexpr (RED) {
         double v[NC], tot[NC];
 #pragma unroll
@@ -36,10 +39,11 @@ __device__ __forceinline__ void zmarch_body(const Grid3& g, const L& ld, const O
 
 // One __global__ name per kernel family (so profiles tell them apart), all
 // running the same body.
-#define PCGMI_ZKERNEL(NAME)                                                                                 \
-    template <typename C, int BX, int BY, int VX, int NC, unsigned MM, bool RED, class L, class O, class F> \
-    __global__ void __launch_bounds__(BX* BY) NAME(Grid3 g, L ld, O op, F fin, Red red, const int* done) {  \
-        zmarch_body<C, BX, BY, VX, NC, MM, RED>(g, ld, op, fin, red, done);                                 \
+#define PCGMI_ZKERNEL(NAME)                                                                               \
+    template <typename C, class SP, int BX, int BY, int VX, int NC, unsigned MM, bool RED, class L, class O, \
+              class F>                                                                                    \
+    __global__ void __launch_bounds__(BX* BY) NAME(Grid3 g, L ld, O op, F fin, Red red, const int* done) { \
+        zmarch_body<C, SP, BX, BY, VX, NC, MM, RED>(g, ld, op, fin, red, done);                           \
     }
 PCGMI_ZKERNEL(k_stencil)
 PCGMI_ZKERNEL(k_pcg_direction)
@@ -50,23 +54,24 @@ PCGMI_ZKERNEL(k_zgeneric)
 
 enum ZFamily { ZF_STENCIL, ZF_DIRECTION, ZF_UPDATE, ZF_RESIDUAL64, ZF_START_X0, ZF_GENERIC };
 
-template <int FAM, typename C, int BX, int BY, int VX, int NC, unsigned MM, bool RED, class L, class O, class F>
+template <int FAM, typename C, class SP, int BX, int BY, int VX, int NC, unsigned MM, bool RED, class L, class O,
+          class F>
 hipError_t run_zmarch(const Grid3& g, const L& ld, const O& op, const F& fin, Red red, const int* done,
                       hipStream_t s) {
     if (g.nblocks == 0) return hipSuccess;
     const dim3 grid(g.nblocks), block(BX * BY);
     if constexpr (FAM == ZF_STENCIL)
-        hipLaunchKernelGGL((k_stencil<C, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+        hipLaunchKernelGGL((k_stencil<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
     else if constexpr (FAM == ZF_DIRECTION)
-        hipLaunchKernelGGL((k_pcg_direction<C, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+        hipLaunchKernelGGL((k_pcg_direction<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
     else if constexpr (FAM == ZF_UPDATE)
-        hipLaunchKernelGGL((k_pcg_update<C, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+        hipLaunchKernelGGL((k_pcg_update<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
     else if constexpr (FAM == ZF_RESIDUAL64)
-        hipLaunchKernelGGL((k_residual64<C, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+        hipLaunchKernelGGL((k_residual64<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
     else if constexpr (FAM == ZF_START_X0)
-        hipLaunchKernelGGL((k_start_x0<C, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+        hipLaunchKernelGGL((k_start_x0<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
     else
-        hipLaunchKernelGGL((k_zgeneric<C, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+        hipLaunchKernelGGL((k_zgeneric<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
     return hipGetLastError();
 }
 
@@ -83,6 +88,9 @@ template <int W, class F> hipError_t dispatch_cfg(int cfg, F&& f) {
         default: return hipErrorInvalidValue;
     }
 }
+
+// Storage types with variable-coefficient kernels compiled.
+template <typename T> constexpr bool VAR_TYPE = std::is_same_v<T, float> || std::is_same_v<T, double>;
 
 // Calls f(T{}) with T the storage type of dt.
 template <class F> hipError_t dispatch_dt(int dt, F&& f) {

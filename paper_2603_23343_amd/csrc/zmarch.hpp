@@ -63,15 +63,68 @@ template <typename T, int N> struct RawN<T, N, false> {
     __device__ __forceinline__ typename Traits<T>::C get(int i) const { return to_c(e[i]); }
 };
 
-// LDS row pitch: interior starts at column PAD (16-byte aligned), left halo at
-// PAD-1, right halo at PAD+TX.
-template <typename C> struct LdsPad {
-    static constexpr int PAD = 16 / (int)sizeof(C);
+// ---------------------------------------------------------------------------
+// Stencil policies. A policy names the per-point "cell" the skeleton stages in
+// registers and LDS and the seven-point combination of a cell with its six
+// face neighbours. Cells outside the grid are zero().
+// ---------------------------------------------------------------------------
+
+// Constant coefficients (paper Sec. VI/VII): (Ax)_p = 6 x_p - sum of the six neighbours.
+template <typename C> struct StencilConst {
+    using Cell = C;
+    __device__ __forceinline__ static Cell zero() { return C(0); }
+    __device__ __forceinline__ static C apply(const Cell& c, const Cell& l, const Cell& r, const Cell& d,
+                                              const Cell& u, const Cell& b, const Cell& f) {
+        return C(6) * c - l - r - d - u - b - f;
+    }
 };
 
-template <typename C, int BX, int BY, int VX> struct ZTile {
+// A field value with the cell coefficient k of its point.
+template <typename C> struct UK {
+    C u, k;
+};
+
+// Variable coefficients: (A_k u)_p = sum over faces of k_f (u_p - u_nb),
+// k_f = 2 k_p k_q / (k_p + k_q) between cells p and q; on a boundary face
+// (neighbour outside the grid, staged as k = 0) k_f = k_p and u_nb = 0.
+template <typename C> struct StencilVar {
+    using Cell = UK<C>;
+    __device__ __forceinline__ static Cell zero() { return Cell{C(0), C(0)}; }
+    __device__ __forceinline__ static C face(const Cell& c, const Cell& n) {
+        const C kf = n.k == C(0) ? c.k : C(2) * c.k * n.k / (c.k + n.k);
+        return kf * (c.u - n.u);
+    }
+    __device__ __forceinline__ static C apply(const Cell& c, const Cell& l, const Cell& r, const Cell& d,
+                                              const Cell& u, const Cell& b, const Cell& f) {
+        return face(c, l) + face(c, r) + face(c, d) + face(c, u) + face(c, b) + face(c, f);
+    }
+};
+
+// Diagonal of the variable-coefficient operator: the sum of the six face
+// coefficients (cells carry k only).
+template <typename C> struct StencilVarDiag {
+    using Cell = C;
+    __device__ __forceinline__ static Cell zero() { return C(0); }
+    __device__ __forceinline__ static C kf(C kc, C kn) { return kn == C(0) ? kc : C(2) * kc * kn / (kc + kn); }
+    __device__ __forceinline__ static C apply(const Cell& c, const Cell& l, const Cell& r, const Cell& d,
+                                              const Cell& u, const Cell& b, const Cell& f) {
+        return kf(c, l) + kf(c, r) + kf(c, d) + kf(c, u) + kf(c, b) + kf(c, f);
+    }
+};
+
+// The field value of a cell.
+template <typename C> __device__ __forceinline__ C cell_u(const C& c) { return c; }
+template <typename C> __device__ __forceinline__ C cell_u(const UK<C>& c) { return c.u; }
+
+// LDS row pitch: interior starts at column PAD (16-byte aligned), left halo at
+// PAD-1, right halo at PAD+TX.
+template <typename Cell> struct LdsPad {
+    static constexpr int PAD = sizeof(Cell) >= 16 ? 1 : 16 / (int)sizeof(Cell);
+};
+
+template <typename Cell, int BX, int BY, int VX> struct ZTile {
     static constexpr int TX = BX * VX, TY = BY, NT = BX * BY;
-    static constexpr int PAD = LdsPad<C>::PAD;
+    static constexpr int PAD = LdsPad<Cell>::PAD;
     static constexpr int PITCH = TX + 2 * PAD;
     static constexpr int PLANE = (TY + 2) * PITCH;
     static_assert(2 * BX + 2 * TY <= NT, "not enough threads for the halo ring");
@@ -82,11 +135,13 @@ template <typename C, int BX, int BY, int VX> struct ZTile {
 #endif
 constexpr int ZM_DEPTH = PCGMI_ZM_DEPTH;  // planes of look-ahead of every load
 
-// Runs the z-march for logical tile `tile`. Returns the op's accumulators in acc.
-template <typename C, int BX, int BY, int VX, int NC, class Loader, class Op>
+// Runs the z-march for logical tile `tile` with stencil policy SP. Returns the
+// op's accumulators in acc.
+template <typename C, class SP, int BX, int BY, int VX, int NC, class Loader, class Op>
 __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Loader& ld, const Op& op,
-                                       C (&acc)[NC], C* lds /* 2 * ZTile::PLANE elements */) {
-    using ZT = ZTile<C, BX, BY, VX>;
+                                       C (&acc)[NC], typename SP::Cell* lds /* 2 * ZTile::PLANE cells */) {
+    using Cell = typename SP::Cell;
+    using ZT = ZTile<Cell, BX, BY, VX>;
     using FRaw = typename Loader::template Raw<VX>;
     using ORaw = typename Op::Raw;
     constexpr int D = ZM_DEPTH;
@@ -145,18 +200,18 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
     auto fetch_halo = [&](int k, FRaw& r) {
         ld.template fetch<VX>((hval_ok(k) && k < z1) ? hcol + k * sz : 0, r);
     };
-    auto finish_plane = [&](int k, const FRaw& r, Pts<C, VX>& out) {
+    auto finish_plane = [&](int k, const FRaw& r, Pts<Cell, VX>& out) {
         ld.template finish<VX>(r, out.v);
         const bool ok = fvalid(k);
 #pragma unroll
-        for (int i = 0; i < VX; ++i) out.v[i] = ok ? out.v[i] : C(0);
+        for (int i = 0; i < VX; ++i) out.v[i] = ok ? out.v[i] : SP::zero();
     };
-    auto finish_halo = [&](int k, const FRaw& r, Pts<C, VX>& out) {
+    auto finish_halo = [&](int k, const FRaw& r, Pts<Cell, VX>& out) {
         ld.template finish<VX>(r, out.v);
         const bool ok = hval_ok(k);
         if (hkind == 2) out.v[0] = hsel == 0 ? out.v[0] : out.v[VX - 1];
 #pragma unroll
-        for (int i = 0; i < VX; ++i) out.v[i] = ok ? out.v[i] : C(0);
+        for (int i = 0; i < VX; ++i) out.v[i] = ok ? out.v[i] : SP::zero();
     };
     auto fetch_op = [&](int k, ORaw& r) { op.fetch((fvalid(k) && k < z1) ? col + k * sz : 0, r); };
 
@@ -170,7 +225,7 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
     // so no register of an in-flight load is ever copied (a copy would make
     // the compiler wait for the load). The loop is unrolled by D so slot
     // roles are static.
-    Pts<C, VX> zm, zcur, zp, hv;
+    Pts<Cell, VX> zm, zcur, zp, hv;
     FRaw f[D], h[D];
     ORaw o[D];
     {
@@ -196,7 +251,7 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
 
     const int lrow = (ty + 1) * ZT::PITCH + ZT::PAD + tx * VX;
     auto step = [&](int k, FRaw& fs, FRaw& hs, ORaw& os) {
-        C* buf = lds + ((k - z0) & 1) * ZT::PLANE;
+        Cell* buf = lds + ((k - z0) & 1) * ZT::PLANE;
         // Stage plane k: own points and halo.
 #pragma unroll
         for (int i = 0; i < VX; ++i) buf[lrow + i] = zcur.v[i];
@@ -207,21 +262,21 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
             buf[lds_off] = hv.v[0];
         }
         // Consume this slot's field and halo loads, refill it D planes on.
-        Pts<C, VX> znext, hnext;
+        Pts<Cell, VX> znext, hnext;
         finish_plane(k + 2, fs, znext);
         fetch_plane(k + 2 + D, fs);
         finish_halo(k + 1, hs, hnext);
         fetch_halo(k + 1 + D, hs);
         __syncthreads();
         Pts<C, VX> ax;
-        const C* up = buf + lrow + ZT::PITCH;
-        const C* dn = buf + lrow - ZT::PITCH;
-        const C left = buf[lrow - 1], right = buf[lrow + VX];
+        const Cell* up = buf + lrow + ZT::PITCH;
+        const Cell* dn = buf + lrow - ZT::PITCH;
+        const Cell left = buf[lrow - 1], right = buf[lrow + VX];
 #pragma unroll
         for (int i = 0; i < VX; ++i) {
-            C l = i == 0 ? left : zcur.v[i - 1];
-            C r = i == VX - 1 ? right : zcur.v[i + 1];
-            ax.v[i] = C(6) * zcur.v[i] - l - r - dn[i] - up[i] - zm.v[i] - zp.v[i];
+            const Cell l = i == 0 ? left : zcur.v[i - 1];
+            const Cell r = i == VX - 1 ? right : zcur.v[i + 1];
+            ax.v[i] = SP::apply(zcur.v[i], l, r, dn[i], up[i], zm.v[i], zp.v[i]);
         }
         if (own) op.apply(col + k * sz, os, zcur.v, ax.v, acc);
         fetch_op(k + D, os);
