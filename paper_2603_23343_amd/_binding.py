@@ -96,6 +96,18 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _need(t, n, name, dtype=None):
+    """A device tensor with at least n contiguous elements (of dtype)."""
+    if t is None or isinstance(t, int):
+        return
+    if not t.is_cuda or not t.is_contiguous():
+        raise PcgError(PCG_E_ARG, f"{name}: expected a contiguous device tensor")
+    if t.numel() < n:
+        raise PcgError(PCG_E_ARG, f"{name}: {t.numel()} elements, need {n}")
+    if dtype is not None and t.dtype != dtype:
+        raise PcgError(PCG_E_ARG, f"{name}: dtype {t.dtype}, need {dtype}")
+
+
 def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -163,22 +175,34 @@ def pcg_destroy(ctx: Context):
 
 
 def stencil_apply(ctx: Context, x, y):
+    _need(x, ctx.n, "x", ctx.dtype)
+    _need(y, ctx.n, "y", ctx.dtype)
     _check(lib.stencil_apply(ctx.handle, _ptr(x), _ptr(y)))
 
 
 def axpy(ctx: Context, n, alpha, x, y, z):
+    for t, nm in ((x, "x"), (y, "y"), (z, "z")):
+        _need(t, n, nm, ctx.dtype)
     _check(lib.axpy(ctx.handle, int(n), float(alpha), _ptr(x), _ptr(y), _ptr(z)))
 
 
 def dot(ctx: Context, n, x, y, out):
+    _need(x, n, "x", ctx.dtype)
+    _need(y, n, "y", ctx.dtype)
+    _need(out, 1, "out", torch.float32)
     _check(lib.dot(ctx.handle, int(n), _ptr(x), _ptr(y), _ptr(out)))
 
 
 def dot_f64(ctx: Context, n, x, y, out):
+    _need(x, n, "x", ctx.dtype)
+    _need(y, n, "y", ctx.dtype)
+    _need(out, 1, "out", torch.float64)
     _check(lib.dot_f64(ctx.handle, int(n), _ptr(x), _ptr(y), _ptr(out)))
 
 
 def pcg_solve(ctx: Context, b, x, rtol=1e-6, maxit=500, raise_on_error=True) -> dict:
+    _need(b, ctx.n, "b", ctx.dtype)
+    _need(x, ctx.n, "x")
     info = PcgInfo()
     st = lib.pcg_solve(ctx.handle, _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(info))
     out = info.as_dict()
@@ -203,6 +227,8 @@ def pcg_solve_refined(ctx: Context, b64, x64, rtol_outer=1e-10, rtol_inner=None,
     """FP64 iterative refinement around the context's reduced-precision PCG."""
     if rtol_inner is None:
         rtol_inner = 1e-2 if ctx.dtype == torch.bfloat16 else 1e-3
+    _need(b64, ctx.n, "b64", torch.float64)
+    _need(x64, ctx.n, "x64", torch.float64)
     info = PcgInfo()
     st = lib.pcg_solve_refined(ctx.handle, _ptr(b64), _ptr(x64), float(rtol_outer), float(rtol_inner),
                                int(max_outer), int(maxit_inner), ctypes.byref(info))
@@ -227,5 +253,6 @@ def pcg_refine_history(ctx: Context, n=256):
 def pcg_set_coefficients(ctx: Context, k_cell):
     """Variable-coefficient operator with FP32 cell values k_cell (device,
     kept alive by the context object); None restores constant coefficients."""
+    _need(k_cell, ctx.n, "k_cell", torch.float32)
     ctx._kcell = k_cell
     _check(lib.pcg_set_coefficients(ctx.handle, _ptr(k_cell)))

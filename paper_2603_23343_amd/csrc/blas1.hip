@@ -186,6 +186,7 @@ hipError_t launch_dot(int dt, int64_t n, const void* x, const void* y, float* ou
         using T = decltype(tag);
         const int64_t nvec = n / Traits<T>::W;
         const unsigned nb = stream_blocks(nvec, (int64_t)NT * 4, DOT_MAX_BLOCKS);
+        if ((size_t)nb > red.cap) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_dot<T>, dim3(nb), dim3(NT), 0, s, n, static_cast<const T*>(x),
                            static_cast<const T*>(y), out_f32, out_f64, red);
         return hipGetLastError();
@@ -198,6 +199,7 @@ hipError_t launch_pcg_start_zero(int dt, int64_t n, const void* b, void* r, void
         using T = decltype(tag);
         const int64_t nvec = n / Traits<T>::W;
         const unsigned nb = stream_blocks(nvec, (int64_t)NT * 4, DOT_MAX_BLOCKS);
+        if ((size_t)3 * nb > red.cap) return hipErrorInvalidValue;
         auto go = [&](auto xtag) {
             using X = decltype(xtag);
             hipLaunchKernelGGL((k_start_zero<T, X>), dim3(nb), dim3(NT), 0, s, n, static_cast<const T*>(b),

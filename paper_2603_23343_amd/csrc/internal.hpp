@@ -43,10 +43,15 @@ struct Geometry {
 };
 Geometry make_geometry(int nx, int ny, int nz, const Plan& p, int dt);
 
+// Grid-reduction workspace: `cap` doubles of per-work-group partials and the
+// ticket counter. Every reducing launch checks NC * work-groups <= cap on the
+// host and fails with hipErrorInvalidValue otherwise.
 struct Red {
     double* partials;
     unsigned* ticket;
+    size_t cap;
 };
+constexpr int MAX_RED_COMPONENTS = 4;
 
 // The operator of a context: constant coefficients (kc == null) or the
 // variable-coefficient operator with cell coefficients kc (FP32) and the

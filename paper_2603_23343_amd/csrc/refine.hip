@@ -30,11 +30,11 @@ hipError_t launch_cast_scaled(int dt, const Plan& pres, const Geometry& gres, Op
             if (od.kc) {
                 LoadWidenUK<double, double> ld{x, od.kc};
                 return run_zmarch<ZF_GENERIC, double, StencilVar<double>, BX, BY, VX, 1, 0u, false>(
-                    gres, ld, op, FinNone{}, Red{nullptr, nullptr}, nullptr, s);
+                    gres, ld, op, FinNone{}, Red{nullptr, nullptr, 0}, nullptr, s);
             }
             LoadWiden<double, double> ld{x};
             return run_zmarch<ZF_GENERIC, double, StencilConst<double>, BX, BY, VX, 1, 0u, false>(
-                gres, ld, op, FinNone{}, Red{nullptr, nullptr}, nullptr, s);
+                gres, ld, op, FinNone{}, Red{nullptr, nullptr, 0}, nullptr, s);
         });
     });
 }

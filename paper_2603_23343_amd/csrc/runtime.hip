@@ -117,7 +117,7 @@ struct pcg_ctx_s {
 
 namespace {
 
-Red red_of(pcg_ctx c) { return Red{c->partials, c->ticket}; }
+Red red_of(pcg_ctx c) { return Red{c->partials, c->ticket, c->partials_cap}; }
 OpDesc op_of(pcg_ctx c) { return OpDesc{c->kc, c->kc ? c->dinv : nullptr}; }
 
 void free_ctx(pcg_ctx c) {
@@ -399,7 +399,7 @@ pcg_status pcg_create(pcg_ctx* out, int nx, int ny, int nz, pcg_dtype storage, v
     const size_t es = dt_size(storage);
     const size_t xs = dt_size(o.x_accum);
     size_t maxblk = std::max<size_t>({(size_t)c->geo.nblocks, (size_t)c->geo_res.nblocks, (size_t)DOT_MAX_BLOCKS});
-    c->partials_cap = 2 * maxblk;
+    c->partials_cap = (size_t)MAX_RED_COMPONENTS * maxblk;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMalloc(&c->r, es * n);
     if (e == hipSuccess) e = hipMalloc(&c->p[0], es * n);

@@ -17,13 +17,13 @@ hipError_t launch_stencil(int dt, const Plan& p, const Geometry& g, OpDesc od, c
                 if constexpr (VAR_TYPE<T>) {
                     LoadUK<T> ld{static_cast<const T*>(x), od.kc};
                     return run_zmarch<ZF_STENCIL, C, StencilVar<C>, BX, BY, VX, 1, 0u, false>(
-                        g, ld, op, FinNone{}, Red{nullptr, nullptr}, nullptr, s);
+                        g, ld, op, FinNone{}, Red{nullptr, nullptr, 0}, nullptr, s);
                 }
                 return hipErrorInvalidValue;
             }
             LoadField<T> ld{static_cast<const T*>(x)};
             return run_zmarch<ZF_STENCIL, C, StencilConst<C>, BX, BY, VX, 1, 0u, false>(
-                g, ld, op, FinNone{}, Red{nullptr, nullptr}, nullptr, s);
+                g, ld, op, FinNone{}, Red{nullptr, nullptr, 0}, nullptr, s);
         });
     });
 }
@@ -62,7 +62,7 @@ hipError_t launch_var_dinv(int dt, const Plan& p, const Geometry& g, const float
                 LoadK<C> ld{kc};
                 OpStoreInverse<T, VX> op{static_cast<T*>(dinv)};
                 return run_zmarch<ZF_GENERIC, C, StencilVarDiag<C>, BX, BY, VX, 1, 0u, false>(
-                    g, ld, op, FinNone{}, Red{nullptr, nullptr}, nullptr, s);
+                    g, ld, op, FinNone{}, Red{nullptr, nullptr, 0}, nullptr, s);
             });
         }
         return hipErrorInvalidValue;

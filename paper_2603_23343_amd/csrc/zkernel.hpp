@@ -59,6 +59,7 @@ template <int FAM, typename C, class SP, int BX, int BY, int VX, int NC, unsigne
 hipError_t run_zmarch(const Grid3& g, const L& ld, const O& op, const F& fin, Red red, const int* done,
                       hipStream_t s) {
     if (g.nblocks == 0) return hipSuccess;
+    if (RED && (red.partials == nullptr || (size_t)NC * g.nblocks > red.cap)) return hipErrorInvalidValue;
     const dim3 grid(g.nblocks), block(BX * BY);
     if constexpr (FAM == ZF_STENCIL)
         hipLaunchKernelGGL((k_stencil<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
