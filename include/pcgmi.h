@@ -167,6 +167,49 @@ pcg_status pcg_set_coefficients(pcg_ctx ctx, const float *k_cell);
  * *count receives the number written. */
 pcg_status pcg_get_history(pcg_ctx ctx, double *hist, int n, int *count);
 
+/* ------------------------------------------------------------------------
+ * Learned preconditioner (not in the paper): a 3D CNN z = rms(r) N(r / rms(r), g)
+ * with four 3x3x3 convolution layers 2 -> 16 -> 16 -> 16 -> 1, zero
+ * padding, ReLU after the first three, no bias. Input channels: the scaled
+ * residual and g (the standardised log-coefficient field). Weights: FP32
+ * master copy, packed as W1[27][2][16], W2[27][16][16], W3[27][16][16],
+ * W4[27][16][1] (tap t = 9 dz + 3 dy + dx, offsets -1..1), 15120 floats;
+ * computed with BF16 weights and activations and FP32 accumulation on the
+ * matrix cores. Activations live in the network object, sized for the last
+ * grid used.
+ * ------------------------------------------------------------------------ */
+typedef struct cnn_s *cnn_net;
+
+/* Create a network (weights zero) whose work is enqueued on hip_stream. */
+pcg_status cnn_create(cnn_net *out, void *hip_stream);
+pcg_status cnn_destroy(cnn_net net);
+/* Number of weights (15120). */
+int cnn_num_weights(void);
+/* Copy the 15120 FP32 master weights from / to a DEVICE buffer. Setting
+ * weights resets the Adam moments and step count. */
+pcg_status cnn_set_weights(cnn_net net, const float *w_dev);
+pcg_status cnn_get_weights(cnn_net net, float *w_dev);
+/* z = s N(r / s, g) on an nx*ny*nz grid: r of type rdt (F32, F64 or BF16),
+ * g FP32 (NULL: zero channel), z FP32, all DEVICE arrays of nx*ny*nz
+ * values. rr_dev: DEVICE pointer to ||r||^2 (FP64) giving s = rms(r) =
+ * sqrt(rr / (nx ny nz)); NULL means s = 1 (the raw network). */
+pcg_status cnn_forward(cnn_net net, int nx, int ny, int nz, pcg_dtype rdt, const void *r, const float *g,
+                       const double *rr_dev, float *z);
+/* Mean relative-MSE loss over a batch of training pairs and its gradient
+ * with respect to the master weights. pairs: DEVICE BF16 array
+ * [batch][2][nx*ny*nz] holding, per pair, the network input channel (the
+ * scaled residual) and the target (the scaled error); g as in cnn_forward.
+ * Loss per pair: ||N - e||^2 / ||e||^2. grad_dev: DEVICE FP32[15120] (NULL:
+ * the network's own gradient buffer); loss_dev: DEVICE double (may be NULL). */
+pcg_status cnn_loss_grad(cnn_net net, int nx, int ny, int nz, const void *pairs, const float *g, int batch,
+                         float *grad_dev, double *loss_dev);
+/* One Adam step (lr, beta = (0.9, 0.999), eps = 1e-8, bias-corrected) on the
+ * master weights with gradient grad_dev (NULL: the network's own). */
+pcg_status cnn_adam_step(cnn_net net, const float *grad_dev, float lr);
+/* cnn_loss_grad followed by cnn_adam_step. */
+pcg_status cnn_train_step(cnn_net net, int nx, int ny, int nz, const void *pairs, const float *g, int batch,
+                          float lr, double *loss_dev);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *pcg_last_error(void);
 

@@ -5,6 +5,8 @@ include/pcgmi.h); this package is its thin Python binding. Importing it
 requires the built library and raises otherwise.
 """
 from ._binding import (  # noqa: F401
+    Cnn, cnn_adam_step, cnn_create, cnn_forward, cnn_get_weights, cnn_loss_grad, cnn_num_weights, cnn_set_weights,
+    cnn_train_step,
     DT_TORCH, LIBPATH, PCG_BF16, PCG_E_ARG, PCG_E_BREAKDOWN, PCG_E_HIP, PCG_E_NOCONV, PCG_E_NOMEM,
     PCG_E_UNSUPPORTED, PCG_F16, PCG_F32, PCG_F64, PCG_OK, Context, PcgError, PcgInfo, PcgOptions, axpy,
     dot, dot_f64, dtype_code, lib, pcg_create, pcg_destroy, pcg_get_history, pcg_last_error,

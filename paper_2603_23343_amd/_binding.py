@@ -68,6 +68,15 @@ def _load():
         "pcg_refine_history": ([vp, ctypes.POINTER(d), ctypes.POINTER(i), i, ctypes.POINTER(i)], i),
         "pcg_last_error": ([], ctypes.c_char_p),
         "pcg_set_coefficients": ([vp, vp], i),
+        "cnn_create": ([ctypes.POINTER(vp), vp], i),
+        "cnn_destroy": ([vp], i),
+        "cnn_num_weights": ([], i),
+        "cnn_set_weights": ([vp, vp], i),
+        "cnn_get_weights": ([vp, vp], i),
+        "cnn_forward": ([vp, i, i, i, i, vp, vp, vp, vp], i),
+        "cnn_loss_grad": ([vp, i, i, i, vp, vp, i, vp, vp], i),
+        "cnn_adam_step": ([vp, vp, ctypes.c_float], i),
+        "cnn_train_step": ([vp, i, i, i, vp, vp, i, ctypes.c_float, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -256,3 +265,80 @@ def pcg_set_coefficients(ctx: Context, k_cell):
     _need(k_cell, ctx.n, "k_cell", torch.float32)
     ctx._kcell = k_cell
     _check(lib.pcg_set_coefficients(ctx.handle, _ptr(k_cell)))
+
+
+class Cnn:
+    """Owns a cnn_net handle (the learned preconditioner's network)."""
+
+    def __init__(self, handle, stream):
+        self.handle = handle
+        self.stream = stream
+
+    def close(self):
+        if self.handle:
+            lib.cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cnn_create(stream=None) -> Cnn:
+    h = ctypes.c_void_p()
+    s = _stream(stream)
+    _check(lib.cnn_create(ctypes.byref(h), s))
+    return Cnn(h, s)
+
+
+def cnn_num_weights() -> int:
+    return int(lib.cnn_num_weights())
+
+
+def cnn_set_weights(net: Cnn, w):
+    _need(w, cnn_num_weights(), "w", torch.float32)
+    _check(lib.cnn_set_weights(net.handle, _ptr(w)))
+
+
+def cnn_get_weights(net: Cnn, w=None):
+    if w is None:
+        w = torch.empty(cnn_num_weights(), dtype=torch.float32, device="cuda")
+    _need(w, cnn_num_weights(), "w", torch.float32)
+    _check(lib.cnn_get_weights(net.handle, _ptr(w)))
+    return w
+
+
+def cnn_forward(net: Cnn, shape, r, g, z, rr=None):
+    nz, ny, nx = shape
+    n = nx * ny * nz
+    _need(r, n, "r")
+    _need(g, n, "g", torch.float32)
+    _need(z, n, "z", torch.float32)
+    _need(rr, 1, "rr", torch.float64)
+    _check(lib.cnn_forward(net.handle, nx, ny, nz, dtype_code(r.dtype), _ptr(r), _ptr(g), _ptr(rr), _ptr(z)))
+
+
+def cnn_loss_grad(net: Cnn, shape, pairs, g, batch, grad=None, loss=None):
+    nz, ny, nx = shape
+    n = nx * ny * nz
+    _need(pairs, 2 * batch * n, "pairs", torch.bfloat16)
+    _need(g, n, "g", torch.float32)
+    _need(grad, cnn_num_weights(), "grad", torch.float32)
+    _need(loss, 1, "loss", torch.float64)
+    _check(lib.cnn_loss_grad(net.handle, nx, ny, nz, _ptr(pairs), _ptr(g), int(batch), _ptr(grad), _ptr(loss)))
+
+
+def cnn_adam_step(net: Cnn, grad=None, lr=1e-3):
+    _need(grad, cnn_num_weights(), "grad", torch.float32)
+    _check(lib.cnn_adam_step(net.handle, _ptr(grad), float(lr)))
+
+
+def cnn_train_step(net: Cnn, shape, pairs, g, batch, lr=1e-3, loss=None):
+    nz, ny, nx = shape
+    n = nx * ny * nz
+    _need(pairs, 2 * batch * n, "pairs", torch.bfloat16)
+    _need(g, n, "g", torch.float32)
+    _need(loss, 1, "loss", torch.float64)
+    _check(lib.cnn_train_step(net.handle, nx, ny, nz, _ptr(pairs), _ptr(g), int(batch), float(lr), _ptr(loss)))

@@ -60,6 +60,13 @@ bool overlap(const void* a, const void* b, size_t bytes) { return overlap2(a, by
 
 namespace pcgmi {
 
+// Record an error message for pcg_last_error() from other translation units.
+const char* set_error(pcg_status st, const char* msg) {
+    (void)st;
+    g_err = msg;
+    return g_err.c_str();
+}
+
 Geometry make_geometry(int nx, int ny, int nz, const Plan& p, int dt) {
     Geometry g{};
     g.nx = nx;
