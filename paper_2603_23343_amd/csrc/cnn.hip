@@ -264,6 +264,8 @@ hipError_t launch_pack_input(int dt, int64_t n, const void* r, const float* g, c
         hipLaunchKernelGGL(k_pack_input<float>, dim3((unsigned)nb), dim3(256), 0, s, n, static_cast<const float*>(r), g, rr, o);
     else if (dt == DT_F64)
         hipLaunchKernelGGL(k_pack_input<double>, dim3((unsigned)nb), dim3(256), 0, s, n, static_cast<const double*>(r), g, rr, o);
+    else if (dt == DT_BF16)
+        hipLaunchKernelGGL(k_pack_input<bf16>, dim3((unsigned)nb), dim3(256), 0, s, n, static_cast<const bf16*>(r), g, rr, o);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
