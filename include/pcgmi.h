@@ -210,6 +210,37 @@ pcg_status cnn_adam_step(cnn_net net, const float *grad_dev, float lr);
 pcg_status cnn_train_step(cnn_net net, int nx, int ny, int nz, const void *pairs, const float *g, int batch,
                           float lr, double *loss_dev);
 
+/* Flexible CG (Notay 2000, one stored direction) with preconditioner
+ * M(r) = cnn_forward(net, r, g, ||r||^2) -- z = rms(r) N(r / rms(r), g) --
+ * or, when net is NULL, M = D^-1 (then FCG reproduces Jacobi-PCG):
+ *   q = A p; sigma = p.q; alpha = (p.r)/sigma; x += alpha p; r -= alpha q;
+ *   stop on ||r|| <= rtol ||b||; z = M(r); beta = -(z.q)/sigma; p = z + beta p.
+ * Fallback: M switches to D^-1 for the rest of the solve (restarting the
+ * direction recurrence) when z.r <= 0, a value is not finite, or the best
+ * residual has not improved by 10% for 20 iterations. When the recursion has
+ * converged, the FP64 true residual judges: above rtol, Jacobi-PCG continues
+ * from the current x. The context needs F32 storage and an FP64 x
+ * accumulator; the network must use the context's stream; g: DEVICE FP32
+ * network channel (may be NULL). info: fallback_used = 0 (none), 1 (switched
+ * to Jacobi; outer_iters = the iteration), 2 (Jacobi-PCG continuation). */
+pcg_status pcg_solve_flexible(pcg_ctx ctx, cnn_net net, const float *g, const void *b, void *x, double rtol,
+                              int maxit, pcg_info *info);
+
+/* Jacobi-PCG from x0 = 0 that also records (r_k, x_k) after the iterations
+ * listed in snap_iters (host array, increasing, nsnap entries): r_snaps
+ * receives nsnap vectors of the storage type, x_snaps nsnap vectors of the
+ * accumulator type (= x_dtype, which must equal x_accum). Snapshots past
+ * convergence hold the final state. Used to generate (residual, error)
+ * training pairs from the FP64 solver. */
+pcg_status pcg_solve_snapshots(pcg_ctx ctx, const void *b, void *x, double rtol, int maxit, const int *snap_iters,
+                               int nsnap, void *r_snaps, void *x_snaps, pcg_info *info);
+
+/* Training pairs from FP64 snapshots (F64 context): for each j, rho =
+ * rms(r_j), pairs[j] = (bf16(r_j / rho), bf16((x_star - x_j) / rho)), laid
+ * out as DEVICE BF16 [npairs][2][nx*ny*nz] (the layout cnn_loss_grad reads). */
+pcg_status pcg_make_pairs(pcg_ctx ctx, int npairs, const double *r_snaps, const double *x_snaps,
+                          const double *x_star, void *pairs);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *pcg_last_error(void);
 

@@ -68,6 +68,9 @@ def _load():
         "pcg_refine_history": ([vp, ctypes.POINTER(d), ctypes.POINTER(i), i, ctypes.POINTER(i)], i),
         "pcg_last_error": ([], ctypes.c_char_p),
         "pcg_set_coefficients": ([vp, vp], i),
+        "pcg_solve_flexible": ([vp, vp, vp, vp, vp, d, i, ctypes.POINTER(PcgInfo)], i),
+        "pcg_solve_snapshots": ([vp, vp, vp, d, i, ctypes.POINTER(i), i, vp, vp, ctypes.POINTER(PcgInfo)], i),
+        "pcg_make_pairs": ([vp, i, vp, vp, vp, vp], i),
         "cnn_create": ([ctypes.POINTER(vp), vp], i),
         "cnn_destroy": ([vp], i),
         "cnn_num_weights": ([], i),
@@ -342,3 +345,38 @@ def cnn_train_step(net: Cnn, shape, pairs, g, batch, lr=1e-3, loss=None):
     _need(g, n, "g", torch.float32)
     _need(loss, 1, "loss", torch.float64)
     _check(lib.cnn_train_step(net.handle, nx, ny, nz, _ptr(pairs), _ptr(g), int(batch), float(lr), _ptr(loss)))
+
+
+def pcg_solve_flexible(ctx: Context, net, g, b, x, rtol=1e-6, maxit=2000, raise_on_error=True) -> dict:
+    """Flexible CG with the network preconditioner (net=None: Jacobi)."""
+    _need(b, ctx.n, "b", torch.float32)
+    _need(x, ctx.n, "x")
+    _need(g, ctx.n, "g", torch.float32)
+    info = PcgInfo()
+    st = lib.pcg_solve_flexible(ctx.handle, None if net is None else net.handle, _ptr(g), _ptr(b), _ptr(x),
+                                float(rtol), int(maxit), ctypes.byref(info))
+    out = info.as_dict()
+    out["status"] = st
+    if st != PCG_OK and (raise_on_error or st not in (PCG_E_NOCONV, PCG_E_BREAKDOWN)):
+        raise PcgError(st, pcg_last_error())
+    return out
+
+
+def pcg_solve_snapshots(ctx: Context, b, x, snap_iters, r_snaps, x_snaps, rtol=1e-12, maxit=10000) -> dict:
+    its = (ctypes.c_int * len(snap_iters))(*[int(v) for v in snap_iters])
+    _need(b, ctx.n, "b", ctx.dtype)
+    _need(x, ctx.n, "x")
+    _need(r_snaps, ctx.n * len(snap_iters), "r_snaps", ctx.dtype)
+    _need(x_snaps, ctx.n * len(snap_iters), "x_snaps")
+    info = PcgInfo()
+    _check(lib.pcg_solve_snapshots(ctx.handle, _ptr(b), _ptr(x), float(rtol), int(maxit), its, len(snap_iters),
+                                   _ptr(r_snaps), _ptr(x_snaps), ctypes.byref(info)))
+    return info.as_dict()
+
+
+def pcg_make_pairs(ctx: Context, npairs, r_snaps, x_snaps, x_star, pairs):
+    _need(r_snaps, ctx.n * npairs, "r_snaps", torch.float64)
+    _need(x_snaps, ctx.n * npairs, "x_snaps", torch.float64)
+    _need(x_star, ctx.n, "x_star", torch.float64)
+    _need(pairs, 2 * ctx.n * npairs, "pairs", torch.bfloat16)
+    _check(lib.pcg_make_pairs(ctx.handle, int(npairs), _ptr(r_snaps), _ptr(x_snaps), _ptr(x_star), _ptr(pairs)))

@@ -145,6 +145,10 @@ pcg_status forward(cnn_net n, float* out, const double* rr, double mul) {
 
 }  // namespace
 
+namespace pcgmi {
+hipStream_t cnn_stream_of(cnn_net n) { return n->stream; }
+}  // namespace pcgmi
+
 extern "C" {
 
 pcg_status cnn_create(cnn_net* out, void* hip_stream) {

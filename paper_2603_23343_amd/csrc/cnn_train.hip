@@ -121,7 +121,28 @@ __global__ void k_adam(int n, float* __restrict__ w, const float* __restrict__ g
     w[i] -= lr * mh / (sqrtf(vh) + eps);
 }
 
+// One training pair from a solver snapshot: rho = rms(r) from the device
+// scalar rr; out[0..n) = bf16(r / rho), out[n..2n) = bf16((x* - x) / rho).
+__global__ void __launch_bounds__(256) k_make_pair(int64_t n, const double* __restrict__ r, const double* __restrict__ x,
+                                                   const double* __restrict__ xs, const double* rr,
+                                                   uint16_t* __restrict__ out) {
+    const double inv = 1.0 / sqrt(*rr / (double)n);
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        out[i] = f32_to_bf16_bits((float)(r[i] * inv));
+        out[n + i] = f32_to_bf16_bits((float)((xs[i] - x[i]) * inv));
+    }
+}
+
 }  // namespace
+
+hipError_t launch_make_pair(int64_t n, const double* r, const double* x, const double* xs, const double* rr,
+                            void* out, hipStream_t s) {
+    int64_t nb = (n + 1023) / 1024;
+    nb = nb < 1 ? 1 : (nb > 8192 ? 8192 : nb);
+    hipLaunchKernelGGL(k_make_pair, dim3((unsigned)nb), dim3(256), 0, s, n, r, x, xs, rr, static_cast<uint16_t*>(out));
+    return hipGetLastError();
+}
 
 int wgrad_groups(int64_t nvox) {
     int64_t g = (nvox + 4095) / 4096;

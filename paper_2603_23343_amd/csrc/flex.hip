@@ -1,0 +1,261 @@
+// flex.hip -- flexible conjugate gradients with one stored direction (Notay,
+// SIAM J. Sci. Comput. 22(4), 2000), for a preconditioner that changes from
+// one application to the next (the learned network), with the Jacobi
+// preconditioner as fallback:
+//
+//   q = A p; sigma = p.q; alpha = (p.r) / sigma; x += alpha p; r -= alpha q
+//   z = M(r); beta = -(z.q) / sigma; p = z + beta p
+//
+// Kernels per iteration (all skip their work once the solve state is done):
+//   direction: p = z + beta p_old on the fly for the tile and its halo,
+//              q = A p stored, sigma = p.q and p.r -> alpha;
+//   update:    x += alpha p, r -= alpha q, ||r||^2 -> convergence, and the
+//              stagnation test that switches to Jacobi;
+//   M:         the network (cnn_forward, scaled by rms(r) from the state) or
+//              nothing when Jacobi is selected;
+//   select:    z = D^-1 r when Jacobi is selected, then z.q and z.r ->
+//              beta, or a switch to Jacobi when z.r <= 0 or a value is not
+//              finite (the second, "redo" launch then recomputes z with
+//              D^-1 and restarts the direction recurrence).
+#include "zkernel.hpp"
+
+namespace pcgmi {
+
+namespace {
+
+// p = stored(z + beta p_old); beta = 0 on a restart.
+template <typename T> struct LoadFlexDir {
+    using C = typename Traits<T>::C;
+    template <int N> struct Raw {
+        RawN<T, N> z, p;
+    };
+    const T* __restrict__ z;
+    const T* __restrict__ pold;
+    const SolveState* st;
+    C beta;
+    __device__ void init() { beta = (st->flags & FLEX_RESTART) ? C(0) : (C)st->beta; }
+    template <int N> __device__ __forceinline__ void fetch(int64_t i, Raw<N>& raw) const {
+        raw.z.load(z + i);
+        raw.p.load(pold + i);
+    }
+    template <int N> __device__ __forceinline__ void finish(const Raw<N>& raw, C* out) const {
+#pragma unroll
+        for (int v = 0; v < N; ++v) out[v] = stored<T>(raw.z.get(v) + beta * raw.p.get(v));
+    }
+};
+
+template <typename T> struct LoadFlexDirVar {
+    using C = typename Traits<T>::C;
+    template <int N> struct Raw {
+        RawN<T, N> z, p;
+        RawN<float, N> k;
+    };
+    const T* __restrict__ z;
+    const T* __restrict__ pold;
+    const float* __restrict__ kc;
+    const SolveState* st;
+    C beta;
+    __device__ void init() { beta = (st->flags & FLEX_RESTART) ? C(0) : (C)st->beta; }
+    template <int N> __device__ __forceinline__ void fetch(int64_t i, Raw<N>& raw) const {
+        raw.z.load(z + i);
+        raw.p.load(pold + i);
+        raw.k.load(kc + i);
+    }
+    template <int N> __device__ __forceinline__ void finish(const Raw<N>& raw, UK<C>* out) const {
+#pragma unroll
+        for (int v = 0; v < N; ++v)
+            out[v] = UK<C>{stored<T>(raw.z.get(v) + beta * raw.p.get(v)), (C)raw.k.get(v)};
+    }
+};
+
+// Stores p and q = A p; accumulates p.q and p.r.
+template <typename T, int VX> struct OpFlexDir {
+    using C = typename Traits<T>::C;
+    struct Raw {
+        RawN<T, VX> r;
+    };
+    T* __restrict__ pnew;
+    T* __restrict__ q;
+    const T* __restrict__ r;
+    __device__ void init() {}
+    __device__ __forceinline__ void fetch(int64_t i, Raw& raw) const { raw.r.load(r + i); }
+    template <int NC, class Cell>
+    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const Cell* c, const C* ax, C (&acc)[NC]) const {
+        C u[VX], qv[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            u[v] = cell_u(c[v]);
+            qv[v] = stored<T>(ax[v]);
+            acc[0] += u[v] * qv[v];
+            acc[1] += u[v] * raw.r.get(v);
+        }
+        st_pts<T, VX>(pnew, i, u);
+        st_pts<T, VX>(q, i, qv);
+    }
+};
+
+struct FinFlexAlpha {
+    SolveState* st;
+    __device__ void operator()(const double* tot) const {
+        const double sigma = tot[0], pr = tot[1];
+        st->sigma = sigma;
+        st->flags &= ~FLEX_RESTART;
+        if (!(sigma > 0.0) || !isfinite(sigma) || !isfinite(pr)) {
+            st->done = 2;
+            return;
+        }
+        st->alpha = pr / sigma;
+    }
+};
+
+// After ||r||^2: count, test convergence; switch to Jacobi (with a restart)
+// when the best residual has not improved by 10% for `stag` iterations.
+struct FinFlexRes {
+    SolveState* st;
+    double* hist;
+    __device__ void operator()(const double* tot) const {
+        const double rr = tot[0];
+        const int it = st->iters + 1;
+        st->iters = it;
+        st->rr = rr;
+        const double rel = sqrt(rr / st->rr0);
+        if (hist) hist[it] = rel;
+        if (!isfinite(rr)) {
+            st->done = 2;
+            return;
+        }
+        if (rr <= st->tol2) {
+            st->done = 1;
+            return;
+        }
+        if (it >= st->maxit) {
+            st->done = 3;
+            return;
+        }
+        if (rel < 0.9 * st->stag_best) {
+            st->stag_best = rel;
+            st->stag_at = it;
+        } else if (!(st->flags & FLEX_JACOBI) && st->stag > 0 && it - st->stag_at >= st->stag) {
+            st->flags |= FLEX_JACOBI | FLEX_RESTART;
+            st->fallback_at = it;
+            st->stag_at = it;
+        }
+    }
+};
+
+// After z.q and z.r: beta, or a switch to Jacobi when z is not a descent
+// preconditioner (z.r <= 0) or not finite.
+struct FinFlexBeta {
+    SolveState* st;
+    bool redo_pass;
+    __device__ void operator()(const double* tot) const {
+        const double zq = tot[0], zr = tot[1];
+        st->zr = zr;
+        if (redo_pass) st->flags &= ~FLEX_REDO;
+        const bool jac = st->flags & FLEX_JACOBI;
+        if (!jac && (!(zr > 0.0) || !isfinite(zr) || !isfinite(zq))) {
+            st->flags |= FLEX_JACOBI | FLEX_RESTART | FLEX_REDO;
+            st->fallback_at = st->iters;
+            return;
+        }
+        st->beta = (st->flags & FLEX_RESTART) ? 0.0 : -zq / st->sigma;
+    }
+};
+
+constexpr int NT = STREAM_THREADS;
+
+// x += alpha p; r = stored(r - alpha q); ||r||^2.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_flex_update(int64_t n, const T* __restrict__ p, const T* __restrict__ q,
+                                                    T* __restrict__ r, double* __restrict__ x, SolveState* st,
+                                                    double* hist, Red red) {
+    if (st->done) return;
+    __shared__ double scratch[16];
+    using C = typename Traits<T>::C;
+    const C a = (C)st->alpha;
+    const double ad = (double)a;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    C acc = C(0);
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
+        const C pv = to_c(p[i]);
+        x[i] += ad * (double)pv;
+        const C rv = stored<T>(to_c(r[i]) - a * to_c(q[i]));
+        r[i] = from_c<T>(rv);
+        acc += rv * rv;
+    }
+    double v[1] = {(double)acc}, tot[1];
+    if (grid_reduce<1, 0u>(v, red.partials, red.ticket, gridDim.x, blockIdx.x, scratch, tot) && threadIdx.x == 0)
+        FinFlexRes{st, hist}(tot);
+}
+
+// z = D^-1 r when Jacobi is selected (or on the redo pass); z.q, z.r -> beta.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_flex_select(int64_t n, T* __restrict__ z, const T* __restrict__ r,
+                                                    const T* __restrict__ q, const T* __restrict__ dinv,
+                                                    SolveState* st, int redo_pass, Red red) {
+    if (st->done) return;
+    if (redo_pass && !(st->flags & FLEX_REDO)) return;
+    __shared__ double scratch[32];
+    using C = typename Traits<T>::C;
+    const bool jac = (st->flags & FLEX_JACOBI) != 0;
+    const C dc = (C)st->dinv;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    C zq = C(0), zr = C(0);
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
+        const C rv = to_c(r[i]);
+        C zv;
+        if (jac) {
+            zv = stored<T>((dinv ? to_c(dinv[i]) : dc) * rv);
+            z[i] = from_c<T>(zv);
+        } else {
+            zv = to_c(z[i]);
+        }
+        zq += zv * to_c(q[i]);
+        zr += zv * rv;
+    }
+    double v[2] = {(double)zq, (double)zr}, tot[2];
+    if (grid_reduce<2, 0u>(v, red.partials, red.ticket, gridDim.x, blockIdx.x, scratch, tot) && threadIdx.x == 0)
+        FinFlexBeta{st, redo_pass != 0}(tot);
+}
+
+inline unsigned nblk(int64_t n) {
+    int64_t b = (n + NT * 4 - 1) / (NT * 4);
+    return (unsigned)(b < 1 ? 1 : (b > DOT_MAX_BLOCKS ? DOT_MAX_BLOCKS : b));
+}
+
+}  // namespace
+
+hipError_t launch_flex_direction(const Plan& p, const Geometry& g, OpDesc od, const float* z, const float* pold,
+                                 float* pnew, float* q, const float* r, SolveState* st, Red red, hipStream_t s) {
+    using T = float;
+    using C = float;
+    return dispatch_cfg<Traits<T>::W>(p.cfg, [&]<int BX, int BY, int VX>() {
+        OpFlexDir<T, VX> op{pnew, q, r};
+        if (od.kc) {
+            LoadFlexDirVar<T> ld{z, pold, od.kc, st, C(0)};
+            return run_zmarch<ZF_DIRECTION, C, StencilVar<C>, BX, BY, VX, 2, 0u, true>(g, ld, op, FinFlexAlpha{st},
+                                                                                      red, &st->done, s);
+        }
+        LoadFlexDir<T> ld{z, pold, st, C(0)};
+        return run_zmarch<ZF_DIRECTION, C, StencilConst<C>, BX, BY, VX, 2, 0u, true>(g, ld, op, FinFlexAlpha{st},
+                                                                                    red, &st->done, s);
+    });
+}
+
+hipError_t launch_flex_update(int64_t n, const float* p, const float* q, float* r, double* x, SolveState* st,
+                              double* hist, Red red, hipStream_t s) {
+    const unsigned nb = nblk(n);
+    if ((size_t)nb > red.cap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_flex_update<float>, dim3(nb), dim3(NT), 0, s, n, p, q, r, x, st, hist, red);
+    return hipGetLastError();
+}
+
+hipError_t launch_flex_select(int64_t n, float* z, const float* r, const float* q, const float* dinv, SolveState* st,
+                              bool redo_pass, Red red, hipStream_t s) {
+    const unsigned nb = nblk(n);
+    if ((size_t)2 * nb > red.cap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_flex_select<float>, dim3(nb), dim3(NT), 0, s, n, z, r, q, dinv, st, redo_pass ? 1 : 0, red);
+    return hipGetLastError();
+}
+
+}  // namespace pcgmi

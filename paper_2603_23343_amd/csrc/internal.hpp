@@ -101,6 +101,18 @@ hipError_t launch_zero(int dt, int64_t n, void* p, hipStream_t s);
 // Convert n elements: dst (type ddt) = src (type sdt), rounding to nearest even.
 hipError_t launch_convert(int sdt, int ddt, int64_t n, const void* src, void* dst, hipStream_t s);
 
+// flexible CG (FP32 storage)
+hipError_t launch_flex_direction(const Plan& p, const Geometry& g, OpDesc od, const float* z, const float* pold,
+                                 float* pnew, float* q, const float* r, SolveState* st, Red red, hipStream_t s);
+hipError_t launch_flex_update(int64_t n, const float* p, const float* q, float* r, double* x, SolveState* st,
+                              double* hist, Red red, hipStream_t s);
+hipError_t launch_flex_select(int64_t n, float* z, const float* r, const float* q, const float* dinv, SolveState* st,
+                              bool redo_pass, Red red, hipStream_t s);
+// training pairs from solver snapshots
+hipError_t launch_make_pair(int64_t n, const double* r, const double* x, const double* xs, const double* rr,
+                            void* out, hipStream_t s);
+hipStream_t cnn_stream_of(cnn_net n);
+
 constexpr int DOT_MAX_BLOCKS = 2048;
 constexpr int STREAM_THREADS = 256;
 

@@ -25,7 +25,12 @@ struct SolveState {
     int stag;      // > 0: stop when the best ||r|| has not improved by 10% for stag iterations
     int stag_at;   // iteration of the last 10% improvement of the best residual
     double stag_best;  // best relative residual at that iteration
+    // flexible CG
+    int flags;        // FLEX_JACOBI: preconditioner is D^-1; FLEX_RESTART: next beta = 0; FLEX_REDO
+    int fallback_at;  // iteration of the switch to Jacobi (-1: none)
+    double zr;        // z.r of the last preconditioned residual
 };
+constexpr int FLEX_JACOBI = 1, FLEX_RESTART = 2, FLEX_REDO = 4;
 
 // ---------------------------------------------------------------- loaders
 // A loader provides Raw<N> (registers of one fetch of N consecutive points),

@@ -116,6 +116,9 @@ struct pcg_ctx_s {
     // operator: constant coefficients unless pcg_set_coefficients gave k
     const float* kc = nullptr;  // caller's cell coefficients (device, FP32)
     void* dinv = nullptr;       // inverse Jacobi diagonal (storage type), owned
+    // flexible CG
+    void* q = nullptr;  // A p (storage type)
+    void* z = nullptr;  // preconditioned residual (storage type)
     // iterative refinement
     void* rhat = nullptr;  // scaled residual in the storage type
     std::vector<double> ref_relres;
@@ -133,7 +136,7 @@ void free_ctx(pcg_ctx c) {
     for (auto& e : c->ev_chunk)
         if (e) (void)hipEventDestroy(e);
     void* dev[] = {c->r, c->p[0], c->p[1], c->xacc, c->partials, c->ticket, c->st, c->hist, c->res2, c->rhat,
-                   c->dinv};
+                   c->dinv, c->q, c->z};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     if (c->hst) (void)hipHostFree(c->hst);
@@ -610,6 +613,191 @@ pcg_status pcg_refine_history(pcg_ctx c, double* relres, int* inner_iters, int n
         if (inner_iters) inner_iters[i] = i < (int)c->ref_inner.size() ? c->ref_inner[i] : 0;
     }
     *count = m;
+    return PCG_OK;
+}
+
+pcg_status pcg_solve_flexible(pcg_ctx c, cnn_net net, const float* g, const void* b, void* x, double rtol,
+                              int maxit, pcg_info* info) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!c) return fail(PCG_E_ARG, "pcg_solve_flexible: null context");
+    if (!b || !x) return fail(PCG_E_ARG, "pcg_solve_flexible: null pointer");
+    if (!aligned16(b) || !aligned16(x)) return fail(PCG_E_ARG, "pcg_solve_flexible: pointers must be 16-byte aligned");
+    if (!(rtol >= 0.0) || maxit < 0) return fail(PCG_E_ARG, "pcg_solve_flexible: rtol must be >= 0 and maxit >= 0");
+    if (c->dt != DT_F32 || c->opt.x_accum != DT_F64)
+        return fail(PCG_E_UNSUPPORTED, "pcg_solve_flexible: needs F32 storage with an FP64 x accumulator");
+    if (net && cnn_stream_of(net) != c->stream)
+        return fail(PCG_E_ARG, "pcg_solve_flexible: the network and the context must use the same stream");
+    const size_t xbytes = (size_t)c->n * dt_size(c->opt.x_dtype);
+    if (overlap2(b, (size_t)c->n * 4, x, xbytes)) return fail(PCG_E_ARG, "pcg_solve_flexible: b and x overlap");
+    pcg_status s = ensure_hist(c, maxit);
+    if (s != PCG_OK) return s;
+    hipStream_t st = c->stream;
+    if (!c->q) HIPCHK(hipMalloc(&c->q, 4 * c->n));
+    if (!c->z) HIPCHK(hipMalloc(&c->z, 4 * c->n));
+    const OpDesc od = op_of(c);
+    const float* dinv = static_cast<const float*>(od.dinv);
+    float* r = static_cast<float*>(c->r);
+    float* q = static_cast<float*>(c->q);
+    float* z = static_cast<float*>(c->z);
+    double* xacc = static_cast<double*>(c->xacc);
+
+    SolveState init{};
+    init.tol2 = rtol * rtol;
+    init.dinv = 1.0 / 6.0;
+    init.maxit = maxit;
+    init.stag = 20;
+    init.flags = FLEX_RESTART | (net ? 0 : FLEX_JACOBI);
+    init.fallback_at = -1;
+    c->hst[0] = init;
+    HIPCHK(hipMemcpyAsync(c->st, &c->hst[0], sizeof(SolveState), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_pcg_start_zero(DT_F32, c->n, b, r, xacc, DT_F64, c->p[0], od.dinv, c->st, c->hist, red_of(c), st));
+    HIPCHK(launch_zero(DT_F32, c->n, q, st));
+    auto precond = [&](bool use_net) -> pcg_status {
+        if (use_net) {
+            pcg_status ps = cnn_forward(net, c->nx, c->ny, c->nz, PCG_F32, r, g, &c->st->rr, z);
+            if (ps != PCG_OK) return ps;
+        }
+        HIPCHK(launch_flex_select(c->n, z, r, q, dinv, c->st, false, red_of(c), st));
+        HIPCHK(launch_flex_select(c->n, z, r, q, dinv, c->st, true, red_of(c), st));
+        return PCG_OK;
+    };
+    bool net_on = net != nullptr;
+    s = precond(net_on);
+    if (s != PCG_OK) return s;
+
+    SolveState fin{};
+    int it = 0;
+    const int C = c->chunk_iters;
+    for (;;) {
+        HIPCHK(hipMemcpyAsync(&c->hst[1], c->st, sizeof(SolveState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        fin = c->hst[1];
+        if (fin.done != 0 || it >= maxit) break;
+        if (fin.flags & FLEX_JACOBI) net_on = false;
+        for (int k = 0; k < C && it < maxit; ++k) {
+            ++it;
+            void* pold = c->p[(it - 1) & 1];
+            void* pnew = c->p[it & 1];
+            HIPCHK(launch_flex_direction(c->plan, c->geo, od, z, static_cast<const float*>(pold),
+                                         static_cast<float*>(pnew), q, r, c->st, red_of(c), st));
+            HIPCHK(launch_flex_update(c->n, static_cast<const float*>(pnew), q, r, xacc, c->st, c->hist, red_of(c),
+                                      st));
+            s = precond(net_on);
+            if (s != PCG_OK) return s;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(&fin, c->st, sizeof(SolveState), hipMemcpyDeviceToHost));
+    int iters = fin.iters;
+    int fallback = fin.fallback_at >= 0 ? 1 : 0;
+
+    // The FP64 true residual judges the result; if the recursion converged
+    // but the true residual did not, continue with Jacobi-PCG from this x.
+    HIPCHK(launch_residual64(DT_F32, DT_F64, c->plan_res, c->geo_res, od, b, xacc, c->res2, red_of(c), st));
+    HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double true_rel = fin.rr0 > 0 ? std::sqrt(c->hres[0] / fin.rr0) : 0.0;
+    int status = fin.done;
+    if (fin.done == 1 && true_rel > rtol && iters < maxit) {
+        IterResult res;
+        s = run_iterations(c, b, xacc, DT_F64, rtol, maxit - iters, 0, &res);
+        if (s != PCG_OK) return s;
+        iters += res.fin.iters;
+        status = res.fin.done;
+        fallback = 2;
+        HIPCHK(launch_residual64(DT_F32, DT_F64, c->plan_res, c->geo_res, od, b, xacc, c->res2, red_of(c), st));
+        HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        true_rel = fin.rr0 > 0 ? std::sqrt(c->hres[0] / fin.rr0) : 0.0;
+        fin.rr = res.fin.rr;
+    }
+    if (c->opt.x_dtype == DT_F64) HIPCHK(hipMemcpyAsync(x, xacc, xbytes, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(launch_convert(DT_F64, c->opt.x_dtype, c->n, xacc, x, st));
+    HIPCHK(hipStreamSynchronize(st));
+    c->last_iters = fin.iters;
+    pcg_status ret = status == 1 ? PCG_OK : status == 2 ? PCG_E_BREAKDOWN : PCG_E_NOCONV;
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->iters = iters;
+        info->status = ret;
+        info->fallback_used = fallback;
+        info->outer_iters = fin.fallback_at;
+        info->rel_res_recursive = fin.rr0 > 0 ? std::sqrt(fin.rr / fin.rr0) : 0.0;
+        info->rel_res_true_fp64 = true_rel;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (ret == PCG_E_BREAKDOWN) fail(ret, "pcg_solve_flexible: breakdown");
+    else if (ret == PCG_E_NOCONV) fail(ret, "pcg_solve_flexible: no convergence in %d iterations", maxit);
+    return ret;
+}
+
+pcg_status pcg_solve_snapshots(pcg_ctx c, const void* b, void* x, double rtol, int maxit, const int* snap_iters,
+                               int nsnap, void* r_snaps, void* x_snaps, pcg_info* info) {
+    if (!c || !b || !x || (nsnap > 0 && (!snap_iters || !r_snaps || !x_snaps)))
+        return fail(PCG_E_ARG, "pcg_solve_snapshots: null argument");
+    if (nsnap < 0 || maxit < 0 || !(rtol >= 0.0)) return fail(PCG_E_ARG, "pcg_solve_snapshots: bad count");
+    for (int j = 1; j < nsnap; ++j)
+        if (snap_iters[j] <= snap_iters[j - 1]) return fail(PCG_E_ARG, "pcg_solve_snapshots: iterations must increase");
+    if (c->opt.x_dtype != c->opt.x_accum)
+        return fail(PCG_E_ARG, "pcg_solve_snapshots: x_dtype must equal the accumulator type");
+    pcg_status s = ensure_hist(c, maxit);
+    if (s != PCG_OK) return s;
+    hipStream_t st = c->stream;
+    const size_t es = dt_size(c->dt), xs = dt_size(c->opt.x_accum);
+    SolveState init{};
+    init.tol2 = rtol * rtol;
+    init.dinv = 1.0 / 6.0;
+    init.maxit = maxit;
+    c->hst[0] = init;
+    HIPCHK(hipMemcpyAsync(c->st, &c->hst[0], sizeof(SolveState), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_pcg_start_zero(c->dt, c->n, b, c->r, c->xacc, c->opt.x_accum, c->p[0], op_of(c).dinv, c->st,
+                                 c->hist, red_of(c), st));
+    int j = 0;
+    SolveState fin{};
+    for (int it = 1; it <= maxit; ++it) {
+        hipError_t e = enqueue_iters(c, it, 1, st, nullptr);
+        if (e != hipSuccess) return fail(PCG_E_HIP, "pcg_solve_snapshots: %s", hipGetErrorString(e));
+        while (j < nsnap && snap_iters[j] == it) {
+            HIPCHK(hipMemcpyAsync(static_cast<char*>(r_snaps) + (size_t)j * c->n * es, c->r, c->n * es,
+                                  hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(static_cast<char*>(x_snaps) + (size_t)j * c->n * xs, c->xacc, c->n * xs,
+                                  hipMemcpyDeviceToDevice, st));
+            ++j;
+        }
+        if (it % 32 == 0 || it == maxit) {
+            HIPCHK(hipMemcpyAsync(&c->hst[1], c->st, sizeof(SolveState), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (c->hst[1].done != 0 && j >= nsnap) break;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(&fin, c->st, sizeof(SolveState), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(x, c->xacc, c->n * xs, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    c->last_iters = fin.iters;
+    const pcg_status ret = fin.done == 1 ? PCG_OK : fin.done == 2 ? PCG_E_BREAKDOWN : PCG_E_NOCONV;
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->iters = fin.iters;
+        info->status = ret;
+        info->rel_res_recursive = fin.rr0 > 0 ? std::sqrt(fin.rr / fin.rr0) : 0.0;
+    }
+    if (ret != PCG_OK) fail(ret, "pcg_solve_snapshots: solve did not converge (status %d)", (int)ret);
+    return ret;
+}
+
+pcg_status pcg_make_pairs(pcg_ctx c, int npairs, const double* r_snaps, const double* x_snaps, const double* x_star,
+                          void* pairs) {
+    if (!c || npairs < 0 || (npairs > 0 && (!r_snaps || !x_snaps || !x_star || !pairs)))
+        return fail(PCG_E_ARG, "pcg_make_pairs: bad argument");
+    hipStream_t st = c->stream;
+    for (int j = 0; j < npairs; ++j) {
+        const double* rj = r_snaps + (size_t)j * c->n;
+        HIPCHK(launch_dot(DT_F64, c->n, rj, rj, nullptr, c->res2, red_of(c), st));
+        HIPCHK(launch_make_pair(c->n, rj, x_snaps + (size_t)j * c->n, x_star, c->res2,
+                                static_cast<uint16_t*>(pairs) + (size_t)2 * j * c->n, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
     return PCG_OK;
 }
 

@@ -1,0 +1,137 @@
+"""GPU parity of flexible CG with the network / Jacobi preconditioner and its
+fallback rule, and of the FP64 snapshot solve that generates training pairs,
+against the FP64 oracle (oracle.fcg, oracle.pcg) through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from gpu_helpers import make_vec
+
+pytestmark = pytest.mark.gpu
+
+CHANS = [2, 16, 16, 16, 1]
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2603_23343_amd as P
+
+    return P
+
+
+def _flat(ws):
+    return np.concatenate([w.reshape(-1) for w in ws]).astype(np.float32)
+
+
+def _scaled_identity_net(c):
+    """Weights computing N(u, g) = c u through the ReLU layers."""
+    ws = [np.zeros((27, CHANS[i], CHANS[i + 1])) for i in range(4)]
+    ws[0][13, 0, 0], ws[0][13, 0, 1] = 1.0, -1.0
+    for li in (1, 2):
+        ws[li][13, 0, 0] = ws[li][13, 1, 1] = 1.0
+    ws[3][13, 0, 0], ws[3][13, 1, 0] = c, -c
+    return ws
+
+
+def _ctx(P, n, kc=None):
+    ctx = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64)
+    if kc is not None:
+        P.pcg_set_coefficients(ctx, kc)
+    return ctx
+
+
+@pytest.mark.parametrize("var", [False, True])
+def test_fcg_jacobi_matches_oracle(P, orc, var):
+    n = 24
+    shape = (n, n, n)
+    k32 = synthetic.coefficient_field(n) if var else None
+    k64 = None if k32 is None else k32.astype(np.float64)
+    b, b64 = make_vec(41, n ** 3, torch.float32)
+    ref = orc.fcg(shape, b64, precond=None, rtol=1e-6, maxit=3000, kcell=k64)
+    refp = orc.pcg(shape, b64, rtol=1e-6, maxit=3000, kcell=k64)
+    kd = None if k32 is None else torch.from_numpy(k32).cuda()
+    ctx = _ctx(P, n, kd)
+    x = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+    info = P.pcg_solve_flexible(ctx, None, None, b, x, rtol=1e-6, maxit=3000)
+    print(var, info["iters"], ref["iters"], refp["iters"], flush=True)
+    assert info["status"] == P.PCG_OK and info["fallback_used"] == 0
+    assert abs(info["iters"] - ref["iters"]) <= 2 and abs(info["iters"] - refp["iters"]) <= 2
+    assert orc.true_relres(shape, b64, x.cpu().numpy(), kcell=k64) <= 1e-6
+
+
+def test_fcg_identity_network(P, orc):
+    """A network computing z = r / 6 makes FCG the constant-coefficient
+    Jacobi-PCG (up to the BF16 rounding of the network input)."""
+    n = 24
+    shape = (n, n, n)
+    b, b64 = make_vec(42, n ** 3, torch.float32)
+    net = P.cnn_create()
+    P.cnn_set_weights(net, torch.from_numpy(_flat(_scaled_identity_net(1.0 / 6.0))).cuda())
+    ctx = _ctx(P, n)
+    x = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+    g = torch.zeros(n ** 3, dtype=torch.float32, device="cuda")
+    info = P.pcg_solve_flexible(ctx, net, g, b, x, rtol=1e-6, maxit=2000)
+
+    def emulated(r):
+        rho = np.sqrt(np.dot(r, r) / r.size)
+        return rho * orc.round_bf16(orc.round_f32(r / rho)) / 6.0
+
+    ref = orc.fcg(shape, b64, precond=emulated, rtol=1e-6, maxit=2000)
+    print("identity-net fcg", info["iters"], ref["iters"], info["fallback_used"], flush=True)
+    assert info["status"] == P.PCG_OK and info["fallback_used"] == 0
+    assert abs(info["iters"] - ref["iters"]) <= 3
+    assert orc.true_relres(shape, b64, x.cpu().numpy()) <= 1e-6
+
+
+@pytest.mark.parametrize("c", [0.0, -1.0])
+def test_fcg_fallback_on_bad_network(P, orc, c):
+    """z = 0 (z.r = 0) or z = -r (z.r < 0): the solve switches to Jacobi at
+    once and then runs like Jacobi-PCG."""
+    n = 20
+    shape = (n, n, n)
+    b, b64 = make_vec(43, n ** 3, torch.float32)
+    net = P.cnn_create()
+    P.cnn_set_weights(net, torch.from_numpy(_flat(_scaled_identity_net(c))).cuda())
+    ctx = _ctx(P, n)
+    x = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+    g = torch.zeros(n ** 3, dtype=torch.float32, device="cuda")
+    info = P.pcg_solve_flexible(ctx, net, g, b, x, rtol=1e-6, maxit=2000)
+    refp = orc.pcg(shape, b64, rtol=1e-6, maxit=2000)
+    assert info["status"] == P.PCG_OK
+    assert info["fallback_used"] == 1 and info["outer_iters"] == 0
+    assert abs(info["iters"] - refp["iters"]) <= 2
+    assert orc.true_relres(shape, b64, x.cpu().numpy()) <= 1e-6
+
+
+def test_snapshots_and_pairs(P, orc):
+    n = 20
+    shape = (n, n, n)
+    k32 = synthetic.coefficient_field(n)
+    k64 = k32.astype(np.float64)
+    b, b64 = make_vec(44, n ** 3, torch.float64)
+    ctx = P.pcg_create(n, n, n, torch.float64)
+    P.pcg_set_coefficients(ctx, torch.from_numpy(k32).cuda())
+    snaps = [1, 4, 9, 30]
+    N = n ** 3
+    rs = torch.empty(len(snaps) * N, dtype=torch.float64, device="cuda")
+    xs = torch.empty_like(rs)
+    x = torch.empty(N, dtype=torch.float64, device="cuda")
+    P.pcg_solve_snapshots(ctx, b, x, snaps, rs, xs, rtol=1e-12, maxit=5000)
+    for j, k in enumerate(snaps):
+        ref = orc.pcg(shape, b64, rtol=0.0, maxit=k, kcell=k64)
+        xk = xs[j * N:(j + 1) * N].cpu().numpy()
+        assert np.max(np.abs(xk - ref["x"])) <= 1e-9 * np.max(np.abs(ref["x"]))
+        rk = rs[j * N:(j + 1) * N].cpu().numpy()
+        r_true, _, _ = orc.residual(shape, b64, xk, kcell=k64)
+        assert np.max(np.abs(rk - r_true)) <= 1e-9 * np.max(np.abs(b64))
+    pairs = torch.empty(2 * len(snaps) * N, dtype=torch.bfloat16, device="cuda")
+    P.pcg_make_pairs(ctx, len(snaps), rs, xs, x, pairs)
+    pf = pairs.float().cpu().numpy().astype(np.float64)
+    xst = x.cpu().numpy()
+    for j in range(len(snaps)):
+        rk = rs[j * N:(j + 1) * N].cpu().numpy()
+        xk = xs[j * N:(j + 1) * N].cpu().numpy()
+        rho = np.sqrt(np.dot(rk, rk) / N)
+        assert np.array_equal(pf[2 * j * N:(2 * j + 1) * N], orc.round_bf16(rk / rho))
+        assert np.array_equal(pf[(2 * j + 1) * N:(2 * j + 2) * N], orc.round_bf16((xst - xk) / rho))
