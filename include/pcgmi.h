@@ -63,6 +63,10 @@ typedef struct {
     int stag_window;   /* refinement's inner solves stop when the best ||r|| so far has
                           not improved by 10% for this many iterations; 0 = never;
                           -1 = default (100) */
+    int max_restarts;  /* pcg_solve: when the recursion has converged but the FP64 true
+                          residual ||b - A x|| > rtol ||b||, restart from x with r = b - A x
+                          (computed in FP64, stored in the storage type) and beta = 0, at
+                          most this many times; 0 = never; -1 = default (3) */
 } pcg_options;
 
 typedef struct {
@@ -77,6 +81,7 @@ typedef struct {
     double t_1e10;           /* refinement: seconds until the true residual <= 1e-10 */
     double k1_ms, k2_ms;     /* kernel_timing: summed event time of the two iteration kernels */
     int k1_launches, k2_launches;
+    int restarts;            /* pcg_solve: FP64 residual restarts taken (max_restarts) */
 } pcg_info;
 
 /* Fill *opt with the defaults listed above. */
@@ -115,8 +120,10 @@ pcg_status dot_f64(pcg_ctx ctx, int64_t n, const void *x, const void *y, double 
 
 /* Solve A x = b with Jacobi-PCG (paper Sec. VII): b of the storage type, x
  * of opt->x_dtype. Stops when the recursive residual satisfies
- * ||r|| <= rtol ||b|| or after maxit iterations; then recomputes the true
- * residual ||b - A x|| / ||b|| in FP64. b = 0 gives x = 0, iters = 0.
+ * ||r|| <= rtol ||b|| or after maxit iterations (in total, restarts
+ * included); then recomputes the true residual ||b - A x|| / ||b|| in FP64
+ * and, while it exceeds rtol, restarts from x (opt->max_restarts).
+ * b = 0 gives x = 0, iters = 0.
  * Returns PCG_OK, PCG_E_NOCONV (last iterate left in x) or PCG_E_BREAKDOWN.
  * info may be NULL. Blocks until the solve is finished. */
 pcg_status pcg_solve(pcg_ctx ctx, const void *b, void *x, double rtol, int maxit, pcg_info *info);
@@ -240,6 +247,69 @@ pcg_status pcg_solve_snapshots(pcg_ctx ctx, const void *b, void *x, double rtol,
  * out as DEVICE BF16 [npairs][2][nx*ny*nz] (the layout cnn_loss_grad reads). */
 pcg_status pcg_make_pairs(pcg_ctx ctx, int npairs, const double *r_snaps, const double *x_snaps,
                           const double *x_star, void *pairs);
+
+/* ------------------------------------------------------------------------
+ * Batched solves: many independent constant-coefficient problems (the
+ * Jacobi-PCG of Sec. VII on grids of different sizes, FP32 vectors, FP64 x,
+ * x0 = 0) in ONE persistent kernel launch. Batching is not part of the
+ * paper's method; the per-problem iteration is the single-problem solver's.
+ *
+ * Every work-group of the launch belongs to one problem; a problem's
+ * work-groups form a group on one XCD that meets at group barriers twice per
+ * iteration. The grid is the device's resident capacity (occupancy query), so
+ * all groups run concurrently. Each problem is laid out contiguously, C-order
+ * [nz][ny][nx], at its offset in two caller-owned DEVICE arenas: b (FP32) and
+ * x (FP64), each of `total` elements (pcg_batch_layout).
+ *
+ * Internally every problem's r, p and x live in arenas whose rows are padded
+ * to a multiple of 4 points (padding held at 0), so 4-wide vector tiles work
+ * for any nx; b is read from and x written to the caller's layout.
+ *
+ * Tile plans: per problem a work-group tile shape (cfg 0: 64x16 points,
+ * 1: 128x8, 2: 256x4, all 4-wide FP32 vectors; 5: 64x4 scalar) and a
+ * z-chunk. The z-chunk follows from the shape and the
+ * group size (fewest planes for the busiest work-group). The shape is given
+ * by the caller, read from the JSON tile cache, or measured: the autotuner
+ * runs `tune_iters` iterations of every problem still without a shape under
+ * each candidate shape (all problems in one launch, twice), keeps for each
+ * problem the shape with the shortest wall-clock time, and records it in the
+ * cache keyed by device, problem shape and group size.
+ * ------------------------------------------------------------------------ */
+typedef struct pcg_batch_s *pcg_batch;
+
+/* Create a batch of nprob problems; dims = host int[nprob][3] {nx, ny, nz}
+ * (each >= 1, at most 2^31 points). cfgs = host int[nprob] tile shapes (0, 1,
+ * 2 or 5), or NULL to use the cache / the
+ * autotuner. cache_path: JSON file read and rewritten by the autotuner (NULL:
+ * no cache). tune_iters: iterations per tuning launch (<= 0: 20). Allocates
+ * the workspace (3 FP32 and 1 FP64 row-padded arenas, per-problem scalars). PCG_E_UNSUPPORTED if
+ * more problems than resident work-groups fall on one XCD. */
+pcg_status pcg_batch_create(pcg_batch *out, int nprob, const int *dims, const int *cfgs,
+                            const char *cache_path, int tune_iters, void *hip_stream);
+pcg_status pcg_batch_destroy(pcg_batch batch);
+
+/* Host outputs, each optional (NULL): offsets int64[nprob] (element offset of
+ * each problem in the arenas, a multiple of 64), total (arena length),
+ * plans int[nprob][4] {cfg, zc, work-groups, tiles}, grid int[2]
+ * {work-groups of the launch, problems whose shape was measured}. */
+pcg_status pcg_batch_layout(pcg_batch batch, int64_t *offsets, int64_t *total, int *plans, int *grid);
+
+/* Solve all problems from x0 = 0 with Jacobi-PCG until ||r_i|| <= rtol ||b_i||
+ * (recursive residual) or maxit iterations in total. When a problem's
+ * recursion stops, its FP64 true residual b - A x is computed; if that is
+ * still above rtol ||b_i||, the problem restarts from x with r = fl32(b - A x)
+ * and beta = 0 (at most 3 times), as pcg_solve does. b: DEVICE FP32 arena
+ * (read only); x: DEVICE FP64 arena (written). use_graph = 1 captures
+ * [barrier reset, persistent kernel] in a HIP graph on the first call and
+ * replays it while (b, x, rtol, maxit) stay the same. Host outputs (NULL to
+ * skip): iters int[nprob] (restarts included), relres double[nprob] (FP64
+ * ||b - A x|| / ||b||), latency_s double[nprob] (device wall clock from the
+ * earliest problem's start to this problem's end), restarts int[nprob],
+ * seconds (host wall time of the call). Returns after the launch has ended;
+ * PCG_E_NOCONV / PCG_E_BREAKDOWN if any problem did not converge (outputs
+ * still written); PCG_E_HIP if a group barrier wait exceeded its bound. */
+pcg_status pcg_batch_solve(pcg_batch batch, const float *b, double *x, double rtol, int maxit, int use_graph,
+                           int *iters, double *relres, double *latency_s, int *restarts, double *seconds);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *pcg_last_error(void);

@@ -29,7 +29,7 @@ class PcgOptions(ctypes.Structure):
     _fields_ = [("chunk_iters", ctypes.c_int), ("x_accum", ctypes.c_int), ("x_dtype", ctypes.c_int),
                 ("use_x0", ctypes.c_int), ("use_graph", ctypes.c_int), ("kernel_timing", ctypes.c_int),
                 ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int), ("zchunk", ctypes.c_int),
-                ("stag_window", ctypes.c_int)]
+                ("stag_window", ctypes.c_int), ("max_restarts", ctypes.c_int)]
 
 
 class PcgInfo(ctypes.Structure):
@@ -37,7 +37,8 @@ class PcgInfo(ctypes.Structure):
                 ("status", ctypes.c_int), ("rel_res_recursive", ctypes.c_double),
                 ("rel_res_true_fp64", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("t_1e6", ctypes.c_double), ("t_1e10", ctypes.c_double), ("k1_ms", ctypes.c_double),
-                ("k2_ms", ctypes.c_double), ("k1_launches", ctypes.c_int), ("k2_launches", ctypes.c_int)]
+                ("k2_ms", ctypes.c_double), ("k1_launches", ctypes.c_int), ("k2_launches", ctypes.c_int),
+                ("restarts", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -80,6 +81,11 @@ def _load():
         "cnn_loss_grad": ([vp, i, i, i, vp, vp, i, vp, vp], i),
         "cnn_adam_step": ([vp, vp, ctypes.c_float], i),
         "cnn_train_step": ([vp, i, i, i, vp, vp, i, ctypes.c_float, vp], i),
+        "pcg_batch_create": ([ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.c_char_p, i, vp], i),
+        "pcg_batch_destroy": ([vp], i),
+        "pcg_batch_layout": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i), ctypes.POINTER(i)], i),
+        "pcg_batch_solve": ([vp, vp, vp, d, i, i, ctypes.POINTER(i), ctypes.POINTER(d), ctypes.POINTER(d),
+                             ctypes.POINTER(i), ctypes.POINTER(d)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -380,3 +386,80 @@ def pcg_make_pairs(ctx: Context, npairs, r_snaps, x_snaps, x_star, pairs):
     _need(x_star, ctx.n, "x_star", torch.float64)
     _need(pairs, 2 * ctx.n * npairs, "pairs", torch.bfloat16)
     _check(lib.pcg_make_pairs(ctx.handle, int(npairs), _ptr(r_snaps), _ptr(x_snaps), _ptr(x_star), _ptr(pairs)))
+
+
+class Batch:
+    """Owns a pcg_batch handle: many constant-coefficient problems solved in
+    one persistent launch. offsets[i] is problem i's element offset in the
+    FP32 b arena and the FP64 x arena (both `total` elements long)."""
+
+    def __init__(self, handle, dims, stream):
+        self.handle = handle
+        self.dims = [tuple(d) for d in dims]
+        self.stream = stream
+        n = len(self.dims)
+        offs = (ctypes.c_int64 * n)()
+        total = ctypes.c_int64()
+        plans = (ctypes.c_int * (4 * n))()
+        grid = (ctypes.c_int * 2)()
+        _check(lib.pcg_batch_layout(handle, offs, ctypes.byref(total), plans, grid))
+        self.offsets = list(offs)
+        self.total = int(total.value)
+        self.plans = [tuple(plans[4 * i:4 * i + 4]) for i in range(n)]  # (cfg, zc, work-groups, tiles)
+        self.grid = int(grid[0])
+        self.tuned = int(grid[1])
+
+    def __len__(self):
+        return len(self.dims)
+
+    def view(self, arena, i):
+        nx, ny, nz = self.dims[i]
+        return arena[self.offsets[i]:self.offsets[i] + nx * ny * nz]
+
+    def close(self):
+        if self.handle:
+            lib.pcg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pcg_batch_create(dims, cfgs=None, cache_path=None, tune_iters=20, stream=None) -> Batch:
+    """dims: [(nx, ny, nz)] per problem; cfgs: per-problem tile shapes or None
+    (cache / autotuner)."""
+    n = len(dims)
+    flat = (ctypes.c_int * (3 * n))(*[int(v) for d in dims for v in d])
+    cf = None if cfgs is None else (ctypes.c_int * n)(*[int(c) for c in cfgs])
+    h = ctypes.c_void_p()
+    s = _stream(stream)
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib.pcg_batch_create(ctypes.byref(h), n, flat, cf, path, int(tune_iters), s))
+    return Batch(h, dims, s)
+
+
+def pcg_batch_destroy(batch: Batch):
+    batch.close()
+
+
+def pcg_batch_solve(batch: Batch, b, x, rtol=1e-6, maxit=500, use_graph=True, raise_on_error=True) -> dict:
+    """Solve every problem of the batch; b FP32 and x FP64 device arenas.
+    Returns per-problem iters, relres (FP64 true), latency_s, restarts, plus seconds
+    (host wall time) and status."""
+    _need(b, batch.total, "b", torch.float32)
+    _need(x, batch.total, "x", torch.float64)
+    n = len(batch)
+    its = (ctypes.c_int * n)()
+    rel = (ctypes.c_double * n)()
+    lat = (ctypes.c_double * n)()
+    rst = (ctypes.c_int * n)()
+    secs = ctypes.c_double()
+    st = lib.pcg_batch_solve(batch.handle, _ptr(b), _ptr(x), float(rtol), int(maxit), 1 if use_graph else 0, its, rel,
+                             lat, rst, ctypes.byref(secs))
+    if raise_on_error and st != PCG_OK:
+        _check(st)
+    return {"status": st, "iters": list(its), "relres": list(rel), "latency_s": list(lat), "restarts": list(rst),
+            "seconds": secs.value}

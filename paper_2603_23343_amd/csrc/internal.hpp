@@ -40,6 +40,7 @@ struct Geometry {
     int nx, ny, nz;
     int ntx, nty, nzc, zc;
     unsigned nblocks;
+    int pitch;  // row stride in elements (nx, or nx padded to the vector width)
 };
 Geometry make_geometry(int nx, int ny, int nz, const Plan& p, int dt);
 

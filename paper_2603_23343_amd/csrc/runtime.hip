@@ -78,6 +78,7 @@ Geometry make_geometry(int nx, int ny, int nz, const Plan& p, int dt) {
     g.zc = std::max(1, std::min(p.zc, nz));
     g.nzc = (nz + g.zc - 1) / g.zc;
     g.nblocks = (unsigned)g.ntx * (unsigned)g.nty * (unsigned)g.nzc;
+    g.pitch = nx;
     return g;
 }
 
@@ -256,7 +257,7 @@ pcg_status run_iterations(pcg_ctx c, const void* b, const void* x0, int x0_dt, d
     c->hst[0] = init;
     HIPCHK(hipMemcpyAsync(c->st, &c->hst[0], sizeof(SolveState), hipMemcpyHostToDevice, st));
     if (x0) {
-        HIPCHK(launch_convert(x0_dt, xacc_dt, c->n, x0, c->xacc, st));
+        if (x0 != c->xacc) HIPCHK(launch_convert(x0_dt, xacc_dt, c->n, x0, c->xacc, st));
         HIPCHK(launch_zero(c->dt, c->n, c->p[0], st));
         HIPCHK(launch_zero(c->dt, c->n, c->p[1], st));
         HIPCHK(launch_pcg_start_x0(c->dt, xacc_dt, c->plan_res, c->geo_res, op_of(c), b, c->xacc, c->r, c->st,
@@ -366,6 +367,7 @@ pcg_status pcg_options_default(pcg_options* o) {
     o->x_dtype = -1;  // resolved at pcg_create: F32 storage -> F32, otherwise storage type
     o->use_graph = 1;
     o->stag_window = -1;
+    o->max_restarts = -1;
     return PCG_OK;
 }
 
@@ -387,6 +389,7 @@ pcg_status pcg_create(pcg_ctx* out, int nx, int ny, int nz, pcg_dtype storage, v
         return fail(PCG_E_ARG, "pcg_create: x_dtype must be the storage type or PCG_F64");
     if (o.x_accum < 0) o.x_accum = PCG_F64;
     if (o.stag_window < 0) o.stag_window = 100;
+    if (o.max_restarts < 0) o.max_restarts = 3;
     if (o.x_accum != PCG_F64 && o.x_accum != PCG_F32 && o.x_accum != storage)
         return fail(PCG_E_ARG, "pcg_create: x_accum must be PCG_F64, PCG_F32 or the storage type");
     if (storage == PCG_F64) o.x_accum = PCG_F64;
@@ -502,18 +505,36 @@ pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, 
         return fail(PCG_E_ARG, "pcg_solve: b and x overlap");
     hipStream_t st = c->stream;
     const int xacc_dt = c->opt.x_accum;
-    IterResult res;
-    pcg_status s = run_iterations(c, b, c->opt.use_x0 ? x : nullptr, c->opt.x_dtype, rtol, maxit, 0, &res);
-    if (s != PCG_OK) return s;
+    IterResult res, seg;
+    int restarts = 0, total_iters = 0;
+    const void* x0 = c->opt.use_x0 ? x : nullptr;
+    int x0_dt = c->opt.x_dtype;
+    for (;;) {
+        pcg_status s = run_iterations(c, b, x0, x0_dt, rtol, maxit - total_iters, 0, &seg);
+        if (s != PCG_OK) return s;
+        total_iters += seg.fin.iters;
+        res.k1_ms += seg.k1_ms;
+        res.k2_ms += seg.k2_ms;
+        res.nk += seg.nk;
+        res.fin = seg.fin;
 
-    // Result to the caller's x, then the FP64 true residual of what is returned.
-    if (c->opt.x_dtype == xacc_dt) HIPCHK(hipMemcpyAsync(x, c->xacc, xbytes, hipMemcpyDeviceToDevice, st));
-    else HIPCHK(launch_convert(xacc_dt, c->opt.x_dtype, c->n, c->xacc, x, st));
-    if (res.fin.rr0 == 0.0) HIPCHK(launch_zero(c->opt.x_dtype, c->n, x, st));
-    HIPCHK(launch_residual64(c->dt, c->opt.x_dtype, c->plan_res, c->geo_res, op_of(c), b, x, c->res2, red_of(c),
-                             st));
-    HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+        // Result to the caller's x, then the FP64 true residual of what is returned.
+        if (c->opt.x_dtype == xacc_dt) HIPCHK(hipMemcpyAsync(x, c->xacc, xbytes, hipMemcpyDeviceToDevice, st));
+        else HIPCHK(launch_convert(xacc_dt, c->opt.x_dtype, c->n, c->xacc, x, st));
+        if (res.fin.rr0 == 0.0) HIPCHK(launch_zero(c->opt.x_dtype, c->n, x, st));
+        HIPCHK(launch_residual64(c->dt, c->opt.x_dtype, c->plan_res, c->geo_res, op_of(c), b, x, c->res2, red_of(c),
+                                 st));
+        HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        // Converged on the recursion but not in FP64: restart from the
+        // accumulator with the FP64 residual (the start kernel recomputes it).
+        const bool true_ok = c->hres[0] <= rtol * rtol * res.fin.rr0;
+        if (res.fin.done != 1 || true_ok || restarts >= c->opt.max_restarts || total_iters >= maxit) break;
+        ++restarts;
+        x0 = c->xacc;
+        x0_dt = xacc_dt;
+    }
+    res.fin.iters = total_iters;
     const SolveState& fin = res.fin;
 
     pcg_status ret = PCG_OK;
@@ -529,6 +550,7 @@ pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, 
         info->k2_ms = res.k2_ms;
         info->k1_launches = res.nk;
         info->k2_launches = res.nk;
+        info->restarts = restarts;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     if (ret == PCG_E_BREAKDOWN) fail(ret, "pcg_solve: breakdown (p.Ap <= 0 or a non-finite value) at iteration %d", fin.iters + 1);

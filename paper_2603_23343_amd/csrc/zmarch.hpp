@@ -136,8 +136,11 @@ template <typename Cell, int BX, int BY, int VX> struct ZTile {
 constexpr int ZM_DEPTH = PCGMI_ZM_DEPTH;  // planes of look-ahead of every load
 
 // Runs the z-march for logical tile `tile` with stencil policy SP. Returns the
-// op's accumulators in acc.
-template <typename C, class SP, int BX, int BY, int VX, int NC, class Loader, class Op>
+// op's accumulators in acc. Rows are g.pitch elements apart. With LM (lane
+// mask), vector lanes at x >= nx (row padding up to the pitch) read as 0 and
+// their stencil result is 0, so padding that starts at 0 stays 0 under every
+// op; without it the vector path needs nx % VX == 0.
+template <typename C, class SP, int BX, int BY, int VX, int NC, bool LM = false, class Loader, class Op>
 __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Loader& ld, const Op& op,
                                        C (&acc)[NC], typename SP::Cell* lds /* 2 * ZTile::PLANE cells */) {
     using Cell = typename SP::Cell;
@@ -154,11 +157,14 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
     const int x0 = bx * ZT::TX, y0 = by * ZT::TY;
     const int z0 = bz * g.zc;
     const int z1 = min(z0 + g.zc, g.nz);
-    const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+    const int64_t sy = g.pitch, sz = (int64_t)g.pitch * g.ny;
 
     const int xs = x0 + tx * VX, ys = y0 + ty;
-    const bool own = (xs < g.nx) && (ys < g.ny);  // nx % VX == 0 on the vector path
+    const bool own = (xs < g.nx) && (ys < g.ny);  // nx % VX == 0 on the vector path unless LM
     const int64_t col = (int64_t)ys * sy + xs;
+    bool lane_ok[VX];
+#pragma unroll
+    for (int i = 0; i < VX; ++i) lane_ok[i] = !LM || xs + i < g.nx;
 
     // Halo duty: threads [0, 2BX) load one vector of the y-halo rows,
     // threads [2BX, 2BX + 2TY) the aligned vector holding one point of the
@@ -204,7 +210,7 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
         ld.template finish<VX>(r, out.v);
         const bool ok = fvalid(k);
 #pragma unroll
-        for (int i = 0; i < VX; ++i) out.v[i] = ok ? out.v[i] : SP::zero();
+        for (int i = 0; i < VX; ++i) out.v[i] = (ok && lane_ok[i]) ? out.v[i] : SP::zero();
     };
     auto finish_halo = [&](int k, const FRaw& r, Pts<Cell, VX>& out) {
         ld.template finish<VX>(r, out.v);
@@ -277,6 +283,7 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
             const Cell l = i == 0 ? left : zcur.v[i - 1];
             const Cell r = i == VX - 1 ? right : zcur.v[i + 1];
             ax.v[i] = SP::apply(zcur.v[i], l, r, dn[i], up[i], zm.v[i], zp.v[i]);
+            if constexpr (LM) ax.v[i] = lane_ok[i] ? ax.v[i] : C(0);
         }
         if (own) op.apply(col + k * sz, os, zcur.v, ax.v, acc);
         fetch_op(k + D, os);

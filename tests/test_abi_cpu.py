@@ -69,7 +69,7 @@ def test_options_default(lib):
 
     o = P.pcg_options_default()
     assert o.chunk_iters == 16 and o.x_accum == -1 and o.use_graph == 1 and o.use_x0 == 0
-    assert o.kernel_timing == 0 and o.x_dtype == -1 and o.stag_window == -1
+    assert o.kernel_timing == 0 and o.x_dtype == -1 and o.stag_window == -1 and o.max_restarts == -1
 
 
 def test_product_path_does_not_import_oracle():
@@ -80,3 +80,24 @@ def test_product_path_does_not_import_oracle():
             txt = open(path).read()
             assert "import oracle" not in txt and "from oracle" not in txt, path
             assert "liboracle" not in txt, path
+
+
+def test_batch_argument_validation_without_gpu(lib):
+    vp, i = ctypes.c_void_p, ctypes.c_int
+    lib.pcg_batch_create.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.c_char_p,
+                                     i, vp]
+    lib.pcg_last_error.restype = ctypes.c_char_p
+    h = vp()
+    dims = (i * 6)(16, 16, 16, 17, 8, 8)
+    assert lib.pcg_batch_create(ctypes.byref(h), 0, dims, None, None, 0, None) == 1
+    bad = (i * 3)(16, 0, 16)
+    assert lib.pcg_batch_create(ctypes.byref(h), 1, bad, None, None, 0, None) == 1
+    assert b"dimension" in lib.pcg_last_error()
+    # tile shapes are 0, 1, 2 or 5
+    assert lib.pcg_batch_create(ctypes.byref(h), 2, dims, (i * 2)(2, 3), None, 0, None) == 1
+    assert b"tile shape 3" in lib.pcg_last_error()
+    assert lib.pcg_batch_create(ctypes.byref(h), 2, dims, (i * 2)(-1, 0), None, 0, None) == 1
+    lib.pcg_batch_solve.argtypes = [vp, vp, vp, ctypes.c_double, i, i, vp, vp, vp, vp, vp]
+    assert lib.pcg_batch_solve(None, None, None, 1e-6, 10, 1, None, None, None, None, None) == 1
+    lib.pcg_batch_destroy.argtypes = [vp]
+    assert lib.pcg_batch_destroy(None) == 0

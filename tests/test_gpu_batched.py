@@ -1,0 +1,166 @@
+"""GPU parity of the batched persistent solve (many constant-coefficient
+Jacobi-PCG problems of different sizes in one launch) through the C ABI.
+
+Each problem is an ordinary single-problem solve: its iteration count is
+within 2 of the FP64 oracle's (oracle.pcg), its FP64 true relative residual
+is <= 1e-6, and it agrees with the library's single-problem pcg_solve (same
+iteration count up to 1, normwise x difference <= 1e-5: both stop at
+||r|| <= 1e-6 ||b||, so they differ by at most the solve error, and the
+batched reductions sum in a different order than the single solve's).
+"""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2603_23343_amd as P
+
+    return P
+
+
+def _arena(P, bt, seeds):
+    """FP32 b arena with b_i ~ U[-1, 1] (seed per problem); host FP64 copies."""
+    b = torch.zeros(bt.total, dtype=torch.float32, device="cuda")
+    host = []
+    for i, (nx, ny, nz) in enumerate(bt.dims):
+        v = synthetic.uniform_f32(seeds[i], nx * ny * nz)
+        bt.view(b, i).copy_(torch.from_numpy(v))
+        host.append(v.astype(np.float64))
+    return b, host
+
+
+DIMS_SMALL = [(16, 16, 16), (17, 9, 23), (24, 20, 12), (33, 33, 33), (20, 13, 7), (5, 6, 7), (1, 1, 1), (64, 8, 40)]
+
+
+@pytest.mark.parametrize("cfgs", [None, [5] * len(DIMS_SMALL), "vector"])
+def test_batch_matches_oracle(P, orc, cfgs, tmp_path):
+    dims = DIMS_SMALL
+    if cfgs == "vector":  # 4-wide vector tiles, on padded rows where nx % 4 != 0
+        cfgs = [i % 3 for i in range(len(dims))]
+    print("batch", dims, cfgs, flush=True)
+    bt = P.pcg_batch_create(dims, cfgs=cfgs, cache_path=str(tmp_path / "tiles.json") if cfgs is None else None)
+    print("plans", bt.plans, "grid", bt.grid, flush=True)
+    seeds = [1000 + i for i in range(len(dims))]
+    b, bh = _arena(P, bt, seeds)
+    x = torch.full((bt.total,), np.nan, dtype=torch.float64, device="cuda")
+    res = P.pcg_batch_solve(bt, b, x, rtol=1e-6, maxit=2000)
+    xh = x.cpu().numpy()
+    for i, d in enumerate(dims):
+        shape = (d[2], d[1], d[0])
+        ref = orc.pcg(shape, bh[i], rtol=1e-6, maxit=2000)
+        xi = xh[bt.offsets[i]:bt.offsets[i] + int(np.prod(d))]
+        tr = orc.true_relres(shape, bh[i], xi)
+        print(d, "iters", res["iters"][i], "oracle", ref["iters"], "true relres", tr, flush=True)
+        assert abs(res["iters"][i] - ref["iters"]) <= 2
+        assert tr <= 1e-6
+        # the kernel's own FP64 judge agrees with the oracle's recomputation
+        # (up to FP64 rounding of b - A x: ~1e-16 ||A|| ||x|| / ||b||)
+        assert abs(res["relres"][i] - tr) <= 1e-9 * tr + 1e-13
+    assert all(l > 0 for l in res["latency_s"])
+
+
+def test_batch_matches_single_solve_and_replays(P, orc):
+    dims = [(32, 32, 32), (20, 20, 20), (48, 24, 16), (19, 23, 29)]
+    bt = P.pcg_batch_create(dims, cfgs=[2, 0, 1, 0])
+    b, bh = _arena(P, bt, [2000 + i for i in range(len(dims))])
+    x = torch.zeros(bt.total, dtype=torch.float64, device="cuda")
+    r1 = P.pcg_batch_solve(bt, b, x, rtol=1e-6, maxit=2000, use_graph=True)
+    x1 = x.clone()
+    # graph replays and an eager launch give the same bits
+    for use_graph in (True, True, False):
+        x.fill_(7.0)
+        r2 = P.pcg_batch_solve(bt, b, x, rtol=1e-6, maxit=2000, use_graph=use_graph)
+        assert r2["iters"] == r1["iters"]
+        for i in range(len(dims)):
+            assert torch.equal(bt.view(x, i), bt.view(x1, i))
+    for i, (nx, ny, nz) in enumerate(dims):
+        ctx = P.pcg_create(nx, ny, nz, torch.float32, x_dtype=torch.float64)
+        xs = torch.empty(nx * ny * nz, dtype=torch.float64, device="cuda")
+        info = P.pcg_solve(ctx, bt.view(b, i), xs, rtol=1e-6, maxit=2000)
+        xb = bt.view(x1, i)
+        rel = (torch.linalg.norm(xb - xs) / torch.linalg.norm(xs)).item()
+        print((nx, ny, nz), "batched", r1["iters"][i], "single", info["iters"], "x rel diff", rel, flush=True)
+        assert abs(r1["iters"][i] - info["iters"]) <= 1
+        assert rel <= 1e-5
+        ctx.close()
+
+
+def test_batch_maxit_and_zero_rhs(P):
+    dims = [(16, 16, 16), (12, 12, 12)]
+    bt = P.pcg_batch_create(dims, cfgs=[0, 5])
+    b = torch.zeros(bt.total, dtype=torch.float32, device="cuda")
+    bt.view(b, 0).copy_(torch.from_numpy(synthetic.uniform_f32(3000, 16 ** 3)))
+    x = torch.full((bt.total,), 5.0, dtype=torch.float64, device="cuda")
+    res = P.pcg_batch_solve(bt, b, x, rtol=1e-6, maxit=3, raise_on_error=False)
+    assert res["status"] == P.PCG_E_NOCONV
+    assert res["iters"] == [3, 0]
+    # the zero right-hand side converges at once with x = 0
+    assert torch.count_nonzero(bt.view(x, 1)).item() == 0
+
+
+def test_batch_restart_from_fp64_residual(P, orc):
+    """At rtol = 1e-7 the FP32 recursion drifts away from the FP64 residual;
+    restarts from r = b - A x bring the true residual down, and every problem
+    ends with relres == its FP64 true residual."""
+    dims = [(40, 40, 40), (48, 32, 24)]
+    bt = P.pcg_batch_create(dims, cfgs=[2, 1])
+    b, bh = _arena(P, bt, [4000, 4001])
+    x = torch.zeros(bt.total, dtype=torch.float64, device="cuda")
+    res = P.pcg_batch_solve(bt, b, x, rtol=1e-7, maxit=3000, raise_on_error=False)
+    xh = x.cpu().numpy()
+    print("restart test", res, flush=True)
+    for i, d in enumerate(dims):
+        shape = (d[2], d[1], d[0])
+        xi = xh[bt.offsets[i]:bt.offsets[i] + int(np.prod(d))]
+        tr = orc.true_relres(shape, bh[i], xi)
+        assert abs(res["relres"][i] - tr) <= 1e-9 * tr + 1e-13
+        assert 0 <= res["restarts"][i] <= 3
+        assert res["restarts"][i] == 3 or tr <= 1e-7
+        ctx = P.pcg_create(d[0], d[1], d[2], torch.float32, x_dtype=torch.float64, max_restarts=0)
+        xs = torch.empty(int(np.prod(d)), dtype=torch.float64, device="cuda")
+        info = P.pcg_solve(ctx, bt.view(b, i), xs, rtol=1e-7, maxit=3000)
+        assert tr <= info["rel_res_true_fp64"] * (1 + 1e-9)
+        ctx.close()
+
+
+def test_autotuner_cache(P, tmp_path):
+    dims = [(32, 32, 32), (24, 24, 24), (17, 17, 17)]
+    path = tmp_path / "tiles.json"
+    bt = P.pcg_batch_create(dims, cache_path=str(path), tune_iters=10)
+    assert bt.tuned == 3
+    entries = json.load(open(path))["entries"]
+    assert len(entries) == 3
+    for e, p in zip(sorted(entries, key=lambda e: -e["nx"]), bt.plans):
+        assert e["cfg"] == p[0]
+    bt2 = P.pcg_batch_create(dims, cache_path=str(path))
+    assert bt2.tuned == 0 and bt2.plans == bt.plans
+
+
+def test_batch_64_uneven(P, orc):
+    """The 64-problem workload (edges log-uniform in [16, 128], b_i seeds
+    1000 + i): every problem's FP64 true residual <= 1e-6; iteration counts
+    against the oracle on the problems with n <= 40."""
+    sizes = synthetic.batch_sizes()
+    dims = [(n, n, n) for n in sizes]
+    bt = P.pcg_batch_create(dims)
+    b, bh = _arena(P, bt, [synthetic.SEED_C4_B_BASE + i for i in range(len(dims))])
+    x = torch.zeros(bt.total, dtype=torch.float64, device="cuda")
+    res = P.pcg_batch_solve(bt, b, x, rtol=1e-6, maxit=5000)
+    xh = x.cpu().numpy()
+    print("64 problems", sum(n ** 3 for n in sizes), "points", res["seconds"], "s; max latency",
+          max(res["latency_s"]), "plans", bt.plans, flush=True)
+    for i, n in enumerate(sizes):
+        xi = xh[bt.offsets[i]:bt.offsets[i] + n ** 3]
+        tr = orc.true_relres((n, n, n), bh[i], xi)
+        assert tr <= 1e-6, (n, tr)
+        if n <= 40:
+            ref = orc.pcg((n, n, n), bh[i], rtol=1e-6, maxit=5000)
+            assert abs(res["iters"][i] - ref["iters"]) <= 2, (n, res["iters"][i], ref["iters"])

@@ -167,3 +167,22 @@ def test_deterministic_repeat(P):
     i1 = P.pcg_solve(ctx, b, x1, 1e-6, 1000)
     i2 = P.pcg_solve(ctx, b, x2, 1e-6, 1000)
     assert i1["iters"] == i2["iters"] and torch.equal(x1, x2)
+
+
+def test_fp64_residual_restart(P, orc):
+    """rtol = 1e-7 is below what the FP32 recursion tracks faithfully at 40^3:
+    with restarts from the FP64 residual the returned x has a true residual
+    no worse than without them, and <= rtol unless all restarts were used."""
+    shape = (40, 40, 40)
+    n = 40 ** 3
+    b, b64 = make_vec(23, n, torch.float32)
+    _, x0, i0, _ = _solve(P, shape, b, rtol=1e-7, maxit=3000, x_dtype=torch.float64, max_restarts=0)
+    _, x1, i1, _ = _solve(P, shape, b, rtol=1e-7, maxit=3000, x_dtype=torch.float64)
+    t0 = orc.true_relres(shape, b64, host64(x0))
+    t1 = orc.true_relres(shape, b64, host64(x1))
+    print("no restart", i0["iters"], t0, "restarts", i1["restarts"], i1["iters"], t1, flush=True)
+    assert i0["restarts"] == 0 and 0 <= i1["restarts"] <= 3
+    assert t1 <= t0 * (1 + 1e-9)
+    assert i1["restarts"] == 3 or t1 <= 1e-7
+    assert abs(i1["rel_res_true_fp64"] - t1) <= 1e-6 * t1
+    assert i1["iters"] >= i0["iters"]
