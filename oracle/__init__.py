@@ -353,8 +353,8 @@ def fcg(shape, b, precond, rtol=1e-6, maxit=2000, kcell=None, stag_window=20, st
             z = M(r); beta = -(z.q)/sigma; p = z + beta p
 
     M falls back to D^-1 for the rest of the solve when z.r <= 0, a value is
-    not finite, or ||r|| drops by less than 10% over 20 iterations; the
-    direction recurrence restarts from p = z at the switch.
+    not finite, or the best ||r|| so far has not improved by 10% for 20
+    iterations; the direction recurrence restarts from p = z at the switch.
     precond(r) -> z. Returns dict(x, iters, status, relres, fallback_at).
     """
     op = (lambda v: stencil(v, shape)) if kcell is None else (lambda v: vstencil(kcell, v, shape))
@@ -377,6 +377,7 @@ def fcg(shape, b, precond, rtol=1e-6, maxit=2000, kcell=None, stag_window=20, st
         z = dinv * r
     p = z.copy()
     norms = [nb]
+    best, best_at = 1.0, 0
     status = NOCONV
     k = 0
     for k in range(1, maxit + 1):
@@ -393,11 +394,15 @@ def fcg(shape, b, precond, rtol=1e-6, maxit=2000, kcell=None, stag_window=20, st
         if nr <= rtol * nb:
             status = OK
             break
+        stag = False
+        if nr / nb < stag_drop * best:
+            best, best_at = nr / nb, k
+        elif use_m and k - best_at >= stag_window:
+            stag, best_at = True, k
         z = apply_m(r)
         restart = False
         if use_m:
             bad = (not np.all(np.isfinite(z))) or dot(z, r) <= 0.0
-            stag = k >= stag_window and nr > stag_drop * norms[k - stag_window]
             if bad or stag:
                 use_m, fallback_at, restart = False, k, True
                 z = dinv * r
@@ -507,6 +512,27 @@ def rel_mse(pred, target):
         diff = p - t
         loss += float(np.sum(diff * diff)) / den
         grads.append(2.0 * diff / den)
+    return loss, grads
+
+
+def anorm_loss(pred, rh, eh, shape, kcell=None):
+    """A-norm error of the preconditioner z = D^-1 rh + pred as an
+    approximation of eh (the error belonging to the residual rh), per sample
+    normalised by rh.D^-1 rh:
+        u = pred + D^-1 rh - eh,  L = u.A u / (rh.D^-1 rh),  dL/dpred = 2 A u / (rh.D^-1 rh)
+    (A symmetric). Returns (sum over samples of L, list of gradients)."""
+    op = (lambda v: stencil(v, shape)) if kcell is None else (lambda v: vstencil(kcell, v, shape))
+    n = int(np.prod(shape))
+    dinv = 1.0 / (np.full(n, 6.0) if kcell is None else vdiag(kcell, shape))
+    loss = 0.0
+    grads = []
+    for p, r, e in zip(pred, rh, eh):
+        p, r, e = (np.asarray(a, dtype=np.float64).reshape(-1) for a in (p, r, e))
+        u = p + dinv * r - e
+        au = op(u)
+        den = float(np.sum(dinv * r * r))
+        loss += float(np.dot(u, au)) / den
+        grads.append(2.0 * au / den)
     return loss, grads
 
 

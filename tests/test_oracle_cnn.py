@@ -153,3 +153,43 @@ def test_cnn_apply_scale_equivariance(orc):
     z1 = orc.cnn_apply(ws, r, g, shape)
     z2 = orc.cnn_apply(ws, 4.0 * r, g, shape)
     assert np.max(np.abs(z2 - 4.0 * z1)) < 1e-12 * max(1.0, np.max(np.abs(z2)))
+
+
+def test_anorm_loss_zero_at_optimum(orc):
+    """The A-norm loss of z = D^-1 rh + pred vanishes at pred = eh - D^-1 rh."""
+    shape = (5, 6, 7)
+    n = 210
+    k = synthetic.coefficient_field(7)[:n].astype(np.float64)  # any positive field
+    rh, eh = synthetic.uniform(11, n), synthetic.uniform(12, n)
+    dinv = 1.0 / orc.vdiag(k, shape)
+    loss, grads = orc.anorm_loss([eh - dinv * rh], [rh], [eh], shape, kcell=k)
+    assert abs(loss) < 1e-24 and np.max(np.abs(grads[0])) < 1e-12
+    loss, _ = orc.anorm_loss([np.zeros(n)], [rh], [eh], shape, kcell=k)
+    assert loss > 0.0
+
+
+@pytest.mark.parametrize("mode", [(1, 1, 1), (2, 3, 1), (4, 5, 6)])
+def test_anorm_loss_eigenvector_closed_form(orc, mode):
+    """Constant coefficients, rh = lambda v and eh = v for a sine eigenvector v
+    of A, pred = 0: u = (lambda/6 - 1) v, so L = (lambda - 6)^2 / (6 lambda)."""
+    nz, ny, nx = 6, 7, 8
+    a, b, c = mode
+    v = synthetic.sine_mode(nx, ny, nz, a, b, c)
+    lam = 6.0 - 2 * np.cos(a * np.pi / (nx + 1)) - 2 * np.cos(b * np.pi / (ny + 1)) - 2 * np.cos(c * np.pi / (nz + 1))
+    loss, _ = orc.anorm_loss([np.zeros(v.size)], [lam * v], [v], (nz, ny, nx))
+    assert abs(loss - (lam - 6.0) ** 2 / (6.0 * lam)) <= 1e-12 * max(1.0, loss)
+
+
+def test_anorm_loss_gradient_finite_differences(orc):
+    shape = (3, 4, 5)
+    n = 60
+    k = np.exp(synthetic.uniform(21, n))
+    rh, eh, p = synthetic.uniform(22, n), synthetic.uniform(23, n), synthetic.uniform(24, n)
+    _, g = orc.anorm_loss([p], [rh], [eh], shape, kcell=k)
+    h = 1e-6
+    for j in (0, 7, 31, 59):
+        dp = np.zeros(n)
+        dp[j] = h
+        lp, _ = orc.anorm_loss([p + dp], [rh], [eh], shape, kcell=k)
+        lm, _ = orc.anorm_loss([p - dp], [rh], [eh], shape, kcell=k)
+        assert abs((lp - lm) / (2 * h) - g[0][j]) <= 1e-6 * max(1.0, abs(g[0][j]))
