@@ -202,14 +202,24 @@ pcg_status cnn_get_weights(cnn_net net, float *w_dev);
  * sqrt(rr / (nx ny nz)); NULL means s = 1 (the raw network). */
 pcg_status cnn_forward(cnn_net net, int nx, int ny, int nz, pcg_dtype rdt, const void *r, const float *g,
                        const double *rr_dev, float *z);
-/* Mean relative-MSE loss over a batch of training pairs and its gradient
- * with respect to the master weights. pairs: DEVICE BF16 array
- * [batch][2][nx*ny*nz] holding, per pair, the network input channel (the
- * scaled residual) and the target (the scaled error); g as in cnn_forward.
- * Loss per pair: ||N - e||^2 / ||e||^2. grad_dev: DEVICE FP32[15120] (NULL:
- * the network's own gradient buffer); loss_dev: DEVICE double (may be NULL). */
+/* Mean loss over a batch of training pairs and its gradient with respect to
+ * the master weights. pairs: DEVICE BF16 array [batch][2][nx*ny*nz] holding,
+ * per pair, the network input channel (the scaled residual rh) and the
+ * target (the scaled error eh); g as in cnn_forward. Loss per pair:
+ *  - no operator set (cnn_set_operator): relative MSE ||N - eh||^2 / ||eh||^2;
+ *  - operator A with Jacobi scale D^-1 set: the A-norm error of the
+ *    preconditioner D^-1 rh + N (the form pcg_solve_flexible applies),
+ *    u = N + D^-1 rh - eh, loss u.A u / (rh.D^-1 rh); the normaliser makes
+ *    every residual count alike, whatever its smoothness.
+ * grad_dev: DEVICE FP32[15120] (NULL: the network's own gradient buffer);
+ * loss_dev: DEVICE double (may be NULL). */
 pcg_status cnn_loss_grad(cnn_net net, int nx, int ny, int nz, const void *pairs, const float *g, int batch,
                          float *grad_dev, double *loss_dev);
+/* Use the A-norm loss with ctx's operator (an F32 context on the training
+ * grid, on the network's stream, with the coefficients of the problem the
+ * pairs come from); NULL restores the relative-MSE loss. The context must
+ * outlive its use here. */
+pcg_status cnn_set_operator(cnn_net net, pcg_ctx ctx);
 /* One Adam step (lr, beta = (0.9, 0.999), eps = 1e-8, bias-corrected) on the
  * master weights with gradient grad_dev (NULL: the network's own). */
 pcg_status cnn_adam_step(cnn_net net, const float *grad_dev, float lr);
@@ -218,8 +228,9 @@ pcg_status cnn_train_step(cnn_net net, int nx, int ny, int nz, const void *pairs
                           float lr, double *loss_dev);
 
 /* Flexible CG (Notay 2000, one stored direction) with preconditioner
- * M(r) = cnn_forward(net, r, g, ||r||^2) -- z = rms(r) N(r / rms(r), g) --
- * or, when net is NULL, M = D^-1 (then FCG reproduces Jacobi-PCG):
+ * M(r) = D^-1 r + rms(r) N(r / rms(r), g): Jacobi plus the network's
+ * correction (cnn_forward with ||r||^2), so a network with zero output is
+ * Jacobi; when net is NULL, M = D^-1 (then FCG reproduces Jacobi-PCG):
  *   q = A p; sigma = p.q; alpha = (p.r)/sigma; x += alpha p; r -= alpha q;
  *   stop on ||r|| <= rtol ||b||; z = M(r); beta = -(z.q)/sigma; p = z + beta p.
  * Fallback: M switches to D^-1 for the rest of the solve (restarting the

@@ -81,6 +81,7 @@ def _load():
         "cnn_loss_grad": ([vp, i, i, i, vp, vp, i, vp, vp], i),
         "cnn_adam_step": ([vp, vp, ctypes.c_float], i),
         "cnn_train_step": ([vp, i, i, i, vp, vp, i, ctypes.c_float, vp], i),
+        "cnn_set_operator": ([vp, vp], i),
         "pcg_batch_create": ([ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.c_char_p, i, vp], i),
         "pcg_batch_destroy": ([vp], i),
         "pcg_batch_layout": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i), ctypes.POINTER(i)], i),
@@ -337,6 +338,13 @@ def cnn_loss_grad(net: Cnn, shape, pairs, g, batch, grad=None, loss=None):
     _need(grad, cnn_num_weights(), "grad", torch.float32)
     _need(loss, 1, "loss", torch.float64)
     _check(lib.cnn_loss_grad(net.handle, nx, ny, nz, _ptr(pairs), _ptr(g), int(batch), _ptr(grad), _ptr(loss)))
+
+
+def cnn_set_operator(net: Cnn, ctx):
+    """A-norm loss with ctx's operator (ctx None: relative MSE). The network
+    keeps a reference to ctx so that it outlives its use."""
+    _check(lib.cnn_set_operator(net.handle, None if ctx is None else ctx.handle))
+    net.op_ctx = ctx
 
 
 def cnn_adam_step(net: Cnn, grad=None, lr=1e-3):

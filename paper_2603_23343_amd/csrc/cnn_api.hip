@@ -22,7 +22,7 @@ hipError_t launch_pack_input(int dt, int64_t n, const void* r, const float* g, c
                              hipStream_t s);
 hipError_t launch_swizzle_weights(const float* w, int cin, int cout, int CIN, int mirror, void* out, hipStream_t s);
 int conv_swizzle_elems(int CIN);
-int wgrad_groups(int64_t nvox);
+int wgrad_groups(int nx, int ny, int nz);
 hipError_t launch_wgrad(int nx, int ny, int nz, int cx, int cy, const void* X, const void* dY, bool dy_f32,
                         float* partials, int groups, hipStream_t s);
 hipError_t launch_reduce_partials(const float* partials, int groups, int len, float scale, bool accumulate,
@@ -30,6 +30,13 @@ hipError_t launch_reduce_partials(const float* partials, int groups, int len, fl
 hipError_t launch_loss(int64_t n, const float* out, const void* tgt, double* loss_acc, double* coef, float* dout,
                        void* dpack, Red red, hipStream_t s);
 hipError_t launch_adam(int n, float* w, const float* g, float* m, float* v, float lr, int step, hipStream_t s);
+hipError_t launch_anorm_u(int64_t n, const float* out, const void* pair, const float* dinv, float* u, hipStream_t s);
+hipError_t launch_anorm_loss(int64_t n, const float* u, const float* au, const void* rh, const float* dinv,
+                             double* loss_acc, double* coef, float* dout, void* dpack, Red red, hipStream_t s);
+hipError_t ctx_apply_f32(pcg_ctx c, const float* u, float* y);
+const float* ctx_dinv_f32(pcg_ctx c);
+bool ctx_is_f32_grid(pcg_ctx c, int nx, int ny, int nz);
+hipStream_t ctx_stream(pcg_ctx c);
 const char* set_error(pcg_status st, const char* msg);
 }  // namespace pcgmi
 
@@ -78,16 +85,20 @@ struct cnn_s {
     double* scal = nullptr;  // {loss accumulator, gradient coefficient}
     double* rpart = nullptr;
     unsigned* ticket = nullptr;
+    // A-norm loss: the operator's context (null: relative-MSE loss) and
+    // the vectors u = N + D^-1 rh - eh and A u
+    pcg_ctx op = nullptr;
+    float *u = nullptr, *au = nullptr;
 };
 
 namespace {
 
 void free_grid(cnn_net n) {
-    void* p[] = {n->in0, n->h1, n->h2, n->h3, n->da, n->db, n->out, n->dout, n->partials, n->dpack};
+    void* p[] = {n->in0, n->h1, n->h2, n->h3, n->da, n->db, n->out, n->dout, n->partials, n->dpack, n->u, n->au};
     for (void* q : p)
         if (q) (void)hipFree(q);
     n->in0 = n->h1 = n->h2 = n->h3 = n->da = n->db = n->dpack = nullptr;
-    n->out = n->dout = n->partials = nullptr;
+    n->out = n->dout = n->partials = n->u = n->au = nullptr;
     n->nvox = 0;
 }
 
@@ -96,7 +107,7 @@ pcg_status ensure_grid(cnn_net n, int nx, int ny, int nz) {
     CHK(hipStreamSynchronize(n->stream));
     free_grid(n);
     const int64_t nv = (int64_t)nx * ny * nz;
-    n->groups = wgrad_groups(nv);
+    n->groups = wgrad_groups(nx, ny, nz);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMalloc(&n->in0, 4 * nv);
     if (e == hipSuccess) e = hipMalloc(&n->h1, 32 * nv);
@@ -108,6 +119,8 @@ pcg_status ensure_grid(cnn_net n, int nx, int ny, int nz) {
     if (e == hipSuccess) e = hipMalloc(&n->dout, 4 * nv);
     if (e == hipSuccess) e = hipMalloc(&n->dpack, 4 * nv);
     if (e == hipSuccess) e = hipMalloc(&n->partials, sizeof(float) * (size_t)n->groups * 27 * 256);
+    if (e == hipSuccess) e = hipMalloc(&n->u, 4 * nv);
+    if (e == hipSuccess) e = hipMalloc(&n->au, 4 * nv);
     if (e != hipSuccess) {
         free_grid(n);
         return err(e == hipErrorOutOfMemory ? PCG_E_NOMEM : PCG_E_HIP, "cnn: workspace: %s", hipGetErrorString(e));
@@ -232,6 +245,8 @@ pcg_status cnn_forward(cnn_net n, int nx, int ny, int nz, pcg_dtype rdt, const v
 pcg_status cnn_loss_grad(cnn_net n, int nx, int ny, int nz, const void* pairs, const float* g, int batch,
                          float* grad_dev, double* loss_dev) {
     if (!n || !pairs || batch < 1) return err(PCG_E_ARG, "cnn_loss_grad: bad argument");
+    if (n->op && !ctx_is_f32_grid(n->op, nx, ny, nz))
+        return err(PCG_E_ARG, "cnn_loss_grad: the operator's context is not an F32 context on this grid");
     pcg_status st = ensure_grid(n, nx, ny, nz);
     if (st != PCG_OK) return st;
     st = ensure_swizzled(n);
@@ -248,7 +263,14 @@ pcg_status cnn_loss_grad(cnn_net n, int nx, int ny, int nz, const void* pairs, c
         CHK(launch_pack_input(PCG_BF16, nv, rh, g, nullptr, n->in0, s));
         st = forward(n, n->out, nullptr, 1.0);
         if (st != PCG_OK) return st;
-        CHK(launch_loss(nv, n->out, eh, &n->scal[0], &n->scal[1], n->dout, n->dpack, red, s));
+        if (n->op) {
+            const float* dinv = ctx_dinv_f32(n->op);
+            CHK(launch_anorm_u(nv, n->out, rh, dinv, n->u, s));
+            CHK(ctx_apply_f32(n->op, n->u, n->au));
+            CHK(launch_anorm_loss(nv, n->u, n->au, rh, dinv, &n->scal[0], &n->scal[1], n->dout, n->dpack, red, s));
+        } else {
+            CHK(launch_loss(nv, n->out, eh, &n->scal[0], &n->scal[1], n->dout, n->dpack, red, s));
+        }
         const bool acc = b > 0;
         const int X = nx, Y = ny, Z = nz;
         // layer 4: dW4 from (h3, dOut); dh3 = conv(dOut, mirrored W4) * (h3 > 0)
@@ -276,6 +298,14 @@ pcg_status cnn_loss_grad(cnn_net n, int nx, int ny, int nz, const void* pairs, c
         CHK(hipMemcpyAsync(loss_dev, &mean, sizeof(double), hipMemcpyHostToDevice, s));
         CHK(hipStreamSynchronize(s));
     }
+    return PCG_OK;
+}
+
+pcg_status cnn_set_operator(cnn_net n, pcg_ctx ctx) {
+    if (!n) return err(PCG_E_ARG, "cnn_set_operator: null network");
+    if (ctx && ctx_stream(ctx) != n->stream)
+        return err(PCG_E_ARG, "cnn_set_operator: the network and the context must use the same stream");
+    n->op = ctx;
     return PCG_OK;
 }
 

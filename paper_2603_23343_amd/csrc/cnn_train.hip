@@ -1,7 +1,8 @@
 // cnn_train.hip -- training-step kernels of the learned preconditioner:
-// relative-MSE loss and its gradient, the weight gradient of a 3x3x3
-// convolution (split over voxels with a fixed-order reduction, so the result
-// is deterministic), and Adam (Kingma & Ba 2015) on FP32 master weights.
+// relative-MSE and A-norm losses and their gradients, the weight gradient of a 3x3x3
+// convolution on the matrix cores (rows split over work-groups, partials
+// reduced in a fixed order, so the result is deterministic), and Adam
+// (Kingma & Ba 2015) on FP32 master weights.
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
@@ -13,51 +14,129 @@ namespace {
 
 __device__ __forceinline__ float bf16v(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
-template <typename Y> __device__ __forceinline__ float ld_val(const Y* p, int64_t i);
-template <> __device__ __forceinline__ float ld_val<uint16_t>(const uint16_t* p, int64_t i) { return bf16v(p[i]); }
-template <> __device__ __forceinline__ float ld_val<float>(const float* p, int64_t i) { return p[i]; }
 
-// Weight gradient dW[t][cx][cy] = sum_v X[v + off_t][cx] dY[v][cy] over a
-// contiguous chunk of voxels per work-group; partials[g][27][CX][CY].
-// Thread layout: pair = tid % (CX*CY), voxel lane = tid / (CX*CY).
+// Weight gradient on the matrix cores. For tap t = (dz, dy, dx) and an
+// output x-row (z, y):
+//   dW[t][ci][co] += sum_x X[z+dz-1, y+dy-1, x+dx-1][ci] dY[z, y, x][co]
+//                 = sum_x' X[z+dz-1, y+dy-1, x'][ci] dY[z, y, x'-(dx-1)][co],
+// a 16 x 16 x K product (K = the row, 32 points per v_mfma_f32_16x16x32_bf16)
+// with A = the neighbour row of X and B = the output row of dY shifted by
+// the tap's x offset. A work-group stages, per chunk of up to WGM_K points
+// of a row, the 9 neighbour rows of X and the 3 shifted copies of dY in LDS,
+// transposed to [channel][x] (channels beyond CX / CY are zero); wave w
+// accumulates taps w, w + 4, ... over all its rows in registers. Rows are
+// dealt to work-groups round-robin; partials[g][27][CX][CY] feed the
+// fixed-order reduction, so the result is deterministic.
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+
+constexpr int WGM_K = 128;           // points of a row per staged chunk
+constexpr int WGM_SP = WGM_K + 8;    // LDS row pitch (bf16), padded against bank conflicts
+
+template <int CX> __device__ __forceinline__ void load_x16(const uint16_t* __restrict__ X, int64_t v, uint16_t (&c)[16]) {
+    if constexpr (CX == 16) {
+        uint4 a = make_uint4(0, 0, 0, 0), b = make_uint4(0, 0, 0, 0);
+        if (v >= 0) {
+            a = *reinterpret_cast<const uint4*>(X + v * 16);
+            b = *reinterpret_cast<const uint4*>(X + v * 16 + 8);
+        }
+        const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            c[2 * i] = (uint16_t)(w[i] & 0xffffu);
+            c[2 * i + 1] = (uint16_t)(w[i] >> 16);
+        }
+    } else {
+        const uint32_t w = v >= 0 ? *reinterpret_cast<const uint32_t*>(X + v * 2) : 0u;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) c[i] = 0;
+        c[0] = (uint16_t)(w & 0xffffu);
+        c[1] = (uint16_t)(w >> 16);
+    }
+}
+
+template <int CY, typename Y>
+__device__ __forceinline__ void load_dy16(const Y* __restrict__ dY, int64_t v, uint16_t (&c)[16]) {
+    if constexpr (CY == 16) {
+        load_x16<16>(reinterpret_cast<const uint16_t*>(dY), v, c);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) c[i] = 0;
+        c[0] = v >= 0 ? f32_to_bf16_bits(dY[v]) : (uint16_t)0;
+    }
+}
+
 template <int CX, int CY, typename Y>
-__global__ void __launch_bounds__(256) k_wgrad(int nx, int ny, int nz, const uint16_t* __restrict__ X,
-                                               const Y* __restrict__ dY, float* __restrict__ partials,
-                                               int64_t chunk) {
-    constexpr int NP = CX * CY, NV = 256 / NP;
-    static_assert(256 % NP == 0, "pairs must divide the work-group");
-    __shared__ float red[256];
-    const int tid = threadIdx.x, pair = tid % NP, vl = tid / NP;
-    const int cx = pair / CY, cy = pair % CY;
-    const int64_t nvox = (int64_t)nx * ny * nz;
-    const int64_t v0 = (int64_t)blockIdx.x * chunk, v1 = v0 + chunk < nvox ? v0 + chunk : nvox;
-    float acc[27];
+__global__ void __launch_bounds__(256) k_wgrad_mfma(int nx, int ny, int nz, const uint16_t* __restrict__ X,
+                                                    const Y* __restrict__ dY, float* __restrict__ partials) {
+    __shared__ __attribute__((aligned(16))) uint16_t xs[9 * 16 * WGM_SP];
+    __shared__ __attribute__((aligned(16))) uint16_t ys[3 * 16 * WGM_SP];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int m = lane & 15, kg = lane >> 4;
+    f32x4_t acc[7];
 #pragma unroll
-    for (int t = 0; t < 27; ++t) acc[t] = 0.f;
-    for (int64_t v = v0 + vl; v < v1; v += NV) {
-        const float dy = ld_val<Y>(dY, v * CY + cy);
-        const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((int64_t)nx * ny));
+    for (int j = 0; j < 7; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    const int nch = (nx + WGM_K - 1) / WGM_K;
+    const int nitems = ny * nz * nch;
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int ch = item % nch, row = item / nch;
+        const int y = row % ny, z = row / ny;
+        const int x0 = ch * WGM_K;
+        const int len = min(WGM_K, nx - x0);
+        const int kp = (len + 31) & ~31;  // K of this chunk, zero-padded to 32
+        const int npairs = kp / 2;
+        __syncthreads();  // the previous chunk's fragments have been read
+        for (int idx = tid; idx < 9 * npairs; idx += 256) {
+            const int r = idx / npairs, xp = (idx - r * npairs) * 2;
+            const int zz = z + r / 3 - 1, yy = y + r % 3 - 1;
+            const bool rok = zz >= 0 && zz < nz && yy >= 0 && yy < ny;
+            const int64_t base = ((int64_t)zz * ny + yy) * nx + x0;
+            uint16_t a[16], b[16];
+            load_x16<CX>(X, rok && xp < len ? base + xp : -1, a);
+            load_x16<CX>(X, rok && xp + 1 < len ? base + xp + 1 : -1, b);
 #pragma unroll
-        for (int t = 0; t < 27; ++t) {
-            const int xx = x + (t % 3) - 1, yy = y + (t / 3) % 3 - 1, zz = z + t / 9 - 1;
-            const bool in = xx >= 0 && xx < nx && yy >= 0 && yy < ny && zz >= 0 && zz < nz;
-            const int64_t nb = in ? ((int64_t)zz * ny + yy) * nx + xx : 0;
-            const float xv = bf16v(X[nb * CX + cx]);
-            acc[t] += in ? xv * dy : 0.f;
+            for (int c = 0; c < 16; ++c)
+                *reinterpret_cast<uint32_t*>(&xs[(r * 16 + c) * WGM_SP + xp]) = (uint32_t)a[c] | ((uint32_t)b[c] << 16);
+        }
+        for (int idx = tid; idx < 3 * npairs; idx += 256) {
+            const int sft = idx / npairs, xp = (idx - sft * npairs) * 2;
+            const int64_t base = (int64_t)row * nx;
+            const int xa = x0 + xp - (sft - 1), xb = xa + 1;  // dY column feeding x' = x0 + xp (+1)
+            uint16_t a[16], b[16];
+            load_dy16<CY, Y>(dY, (xp < len && xa >= 0 && xa < nx) ? base + xa : -1, a);
+            load_dy16<CY, Y>(dY, (xp + 1 < len && xb >= 0 && xb < nx) ? base + xb : -1, b);
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                *reinterpret_cast<uint32_t*>(&ys[(sft * 16 + c) * WGM_SP + xp]) = (uint32_t)a[c] | ((uint32_t)b[c] << 16);
+        }
+        __syncthreads();
+        for (int kb = 0; kb < kp; kb += 32) {
+            const int ko = kb + 8 * kg;
+            bf16x8_t bq[3];
+#pragma unroll
+            for (int sft = 0; sft < 3; ++sft) bq[sft] = *reinterpret_cast<const bf16x8_t*>(&ys[(sft * 16 + m) * WGM_SP + ko]);
+#pragma unroll
+            for (int j = 0; j < 7; ++j) {
+                const int t = wid + 4 * j;
+                if (t < 27) {
+                    const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&xs[((t / 3) * 16 + m) * WGM_SP + ko]);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[t % 3], acc[j], 0, 0, 0);
+                }
+            }
         }
     }
-    // Sum the NV voxel lanes of each pair in a fixed order.
-    float* out = partials + (size_t)blockIdx.x * 27 * NP;
-#pragma unroll 1
-    for (int t = 0; t < 27; ++t) {
-        red[tid] = acc[t];
-        __syncthreads();
-        if (vl == 0) {
-            float s = 0.f;
-            for (int q = 0; q < NV; ++q) s += red[q * NP + pair];
-            out[t * NP + pair] = s;
+    // lane holds C[ci = 4 kg + i][co = m] of each of its taps
+    float* out = partials + (size_t)blockIdx.x * 27 * CX * CY;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        const int t = wid + 4 * j;
+        if (t < 27) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ci = 4 * kg + i;
+                if (ci < CX && m < CY) out[(t * CX + ci) * CY + m] = acc[j][i];
+            }
         }
-        __syncthreads();
     }
 }
 
@@ -108,6 +187,53 @@ __global__ void __launch_bounds__(256) k_loss_grad(int64_t n, const float* __res
     }
 }
 
+// A-norm loss of one sample in the Jacobi-plus-correction form. With the
+// network output N (FP32), the pair (rh, eh) (bf16) and the Jacobi scale
+// dinv (null: the constant 1/6):
+//   u = N + dinv rh - eh                          (k_anorm_u)
+//   L = u.Au / (rh.dinv rh),  dL/dN = 2 Au / (rh.dinv rh)
+// k_anorm_sums reduces u.Au and rh.dinv rh (given Au) into loss_acc and coef.
+__global__ void __launch_bounds__(256) k_anorm_u(int64_t n, const float* __restrict__ out,
+                                                 const uint16_t* __restrict__ rh, const uint16_t* __restrict__ eh,
+                                                 const float* __restrict__ dinv, float* __restrict__ u) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        const float d = dinv ? dinv[i] : (1.f / 6.f);
+        u[i] = out[i] + d * bf16v(rh[i]) - bf16v(eh[i]);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_anorm_sums(int64_t n, const float* __restrict__ u,
+                                                    const float* __restrict__ au, const uint16_t* __restrict__ rh,
+                                                    const float* __restrict__ dinv, double* loss_acc, double* coef,
+                                                    Red red) {
+    __shared__ double scratch[32];
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        const double r = (double)bf16v(rh[i]);
+        a += (double)u[i] * (double)au[i];
+        b += (dinv ? (double)dinv[i] : 1.0 / 6.0) * r * r;
+    }
+    double v[2] = {a, b}, tot[2];
+    if (grid_reduce<2, 0u>(v, red.partials, red.ticket, gridDim.x, blockIdx.x, scratch, tot) && threadIdx.x == 0) {
+        *loss_acc += tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
+        *coef = tot[1] > 0.0 ? 2.0 / tot[1] : 0.0;
+    }
+}
+
+// dOut = coef Au: FP32 for the weight gradient, packed (bf16, 0) for dgrad.
+__global__ void __launch_bounds__(256) k_scale_grad(int64_t n, const float* __restrict__ au, const double* coef,
+                                                    float* __restrict__ dout, uint32_t* __restrict__ dpack) {
+    const float c = (float)*coef;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        const float g = c * au[i];
+        dout[i] = g;
+        dpack[i] = (uint32_t)f32_to_bf16_bits(g);
+    }
+}
+
 __global__ void k_adam(int n, float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -144,25 +270,25 @@ hipError_t launch_make_pair(int64_t n, const double* r, const double* x, const d
     return hipGetLastError();
 }
 
-int wgrad_groups(int64_t nvox) {
-    int64_t g = (nvox + 4095) / 4096;
-    return (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
+// Work-groups of the weight-gradient launch (and partial sets to reduce):
+// one per staged row chunk up to 1024.
+int wgrad_groups(int nx, int ny, int nz) {
+    const int64_t items = (int64_t)ny * nz * ((nx + WGM_K - 1) / WGM_K);
+    return (int)(items < 1 ? 1 : (items > 1024 ? 1024 : items));
 }
 
 hipError_t launch_wgrad(int nx, int ny, int nz, int cx, int cy, const void* X, const void* dY, bool dy_f32,
                         float* partials, int groups, hipStream_t s) {
-    const int64_t nvox = (int64_t)nx * ny * nz;
-    const int64_t chunk = (nvox + groups - 1) / groups;
     auto x16 = static_cast<const uint16_t*>(X);
     if (cx == 16 && cy == 16 && !dy_f32)
-        hipLaunchKernelGGL((k_wgrad<16, 16, uint16_t>), dim3(groups), dim3(256), 0, s, nx, ny, nz, x16,
-                           static_cast<const uint16_t*>(dY), partials, chunk);
+        hipLaunchKernelGGL((k_wgrad_mfma<16, 16, uint16_t>), dim3(groups), dim3(256), 0, s, nx, ny, nz, x16,
+                           static_cast<const uint16_t*>(dY), partials);
     else if (cx == 2 && cy == 16 && !dy_f32)
-        hipLaunchKernelGGL((k_wgrad<2, 16, uint16_t>), dim3(groups), dim3(256), 0, s, nx, ny, nz, x16,
-                           static_cast<const uint16_t*>(dY), partials, chunk);
+        hipLaunchKernelGGL((k_wgrad_mfma<2, 16, uint16_t>), dim3(groups), dim3(256), 0, s, nx, ny, nz, x16,
+                           static_cast<const uint16_t*>(dY), partials);
     else if (cx == 16 && cy == 1 && dy_f32)
-        hipLaunchKernelGGL((k_wgrad<16, 1, float>), dim3(groups), dim3(256), 0, s, nx, ny, nz, x16,
-                           static_cast<const float*>(dY), partials, chunk);
+        hipLaunchKernelGGL((k_wgrad_mfma<16, 1, float>), dim3(groups), dim3(256), 0, s, nx, ny, nz, x16,
+                           static_cast<const float*>(dY), partials);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -183,6 +309,27 @@ hipError_t launch_loss(int64_t n, const float* out, const void* tgt, double* los
     auto t16 = static_cast<const uint16_t*>(tgt);
     hipLaunchKernelGGL(k_loss_sums, dim3((unsigned)nb), dim3(256), 0, s, n, out, t16, loss_acc, coef, red);
     hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)nb), dim3(256), 0, s, n, out, t16, coef, dout,
+                       static_cast<uint32_t*>(dpack));
+    return hipGetLastError();
+}
+
+hipError_t launch_anorm_u(int64_t n, const float* out, const void* pair, const float* dinv, float* u,
+                          hipStream_t s) {
+    int64_t nb = (n + 1023) / 1024;
+    nb = nb < 1 ? 1 : (nb > 8192 ? 8192 : nb);
+    auto rh = static_cast<const uint16_t*>(pair);
+    hipLaunchKernelGGL(k_anorm_u, dim3((unsigned)nb), dim3(256), 0, s, n, out, rh, rh + n, dinv, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_anorm_loss(int64_t n, const float* u, const float* au, const void* rh, const float* dinv,
+                             double* loss_acc, double* coef, float* dout, void* dpack, Red red, hipStream_t s) {
+    int64_t nb = (n + 1023) / 1024;
+    nb = nb < 1 ? 1 : (nb > DOT_MAX_BLOCKS ? DOT_MAX_BLOCKS : nb);
+    if ((size_t)2 * nb > red.cap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_anorm_sums, dim3((unsigned)nb), dim3(256), 0, s, n, u, au,
+                       static_cast<const uint16_t*>(rh), dinv, loss_acc, coef, red);
+    hipLaunchKernelGGL(k_scale_grad, dim3((unsigned)nb), dim3(256), 0, s, n, au, coef, dout,
                        static_cast<uint32_t*>(dpack));
     return hipGetLastError();
 }

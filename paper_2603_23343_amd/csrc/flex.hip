@@ -11,9 +11,10 @@
 //              q = A p stored, sigma = p.q and p.r -> alpha;
 //   update:    x += alpha p, r -= alpha q, ||r||^2 -> convergence, and the
 //              stagnation test that switches to Jacobi;
-//   M:         the network (cnn_forward, scaled by rms(r) from the state) or
-//              nothing when Jacobi is selected;
-//   select:    z = D^-1 r when Jacobi is selected, then z.q and z.r ->
+//   M:         the network's correction (cnn_forward, scaled by rms(r)
+//              from the state) or nothing when Jacobi is selected;
+//   select:    z = D^-1 r, plus the correction while the network is in use,
+//              then z.q and z.r ->
 //              beta, or a switch to Jacobi when z.r <= 0 or a value is not
 //              finite (the second, "redo" launch then recomputes z with
 //              D^-1 and restarts the direction recurrence).
@@ -188,7 +189,8 @@ __global__ void __launch_bounds__(NT) k_flex_update(int64_t n, const T* __restri
         FinFlexRes{st, hist}(tot);
 }
 
-// z = D^-1 r when Jacobi is selected (or on the redo pass); z.q, z.r -> beta.
+// z = D^-1 r (+ the network's correction in z unless Jacobi is selected or
+// this is the redo pass); z.q, z.r -> beta.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_flex_select(int64_t n, T* __restrict__ z, const T* __restrict__ r,
                                                     const T* __restrict__ q, const T* __restrict__ dinv,
@@ -204,12 +206,10 @@ __global__ void __launch_bounds__(NT) k_flex_select(int64_t n, T* __restrict__ z
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
         const C rv = to_c(r[i]);
         C zv;
-        if (jac) {
-            zv = stored<T>((dinv ? to_c(dinv[i]) : dc) * rv);
-            z[i] = from_c<T>(zv);
-        } else {
-            zv = to_c(z[i]);
-        }
+        const C jv = (dinv ? to_c(dinv[i]) : dc) * rv;
+        // Jacobi, or Jacobi plus the network's correction held in z
+        zv = stored<T>(jac ? jv : jv + to_c(z[i]));
+        z[i] = from_c<T>(zv);
         zq += zv * to_c(q[i]);
         zr += zv * rv;
     }

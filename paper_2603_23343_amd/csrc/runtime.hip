@@ -131,6 +131,23 @@ namespace {
 Red red_of(pcg_ctx c) { return Red{c->partials, c->ticket, c->partials_cap}; }
 OpDesc op_of(pcg_ctx c) { return OpDesc{c->kc, c->kc ? c->dinv : nullptr}; }
 
+}  // namespace
+
+// Access for the network's A-norm loss (same library): the context's
+// operator on FP32 vectors, its Jacobi scale, dims and stream.
+namespace pcgmi {
+hipError_t ctx_apply_f32(pcg_ctx c, const float* u, float* y) {
+    return launch_stencil(DT_F32, c->plan, c->geo, op_of(c), u, y, c->stream);
+}
+const float* ctx_dinv_f32(pcg_ctx c) { return static_cast<const float*>(op_of(c).dinv); }
+bool ctx_is_f32_grid(pcg_ctx c, int nx, int ny, int nz) {
+    return c->dt == DT_F32 && c->nx == nx && c->ny == ny && c->nz == nz;
+}
+hipStream_t ctx_stream(pcg_ctx c) { return c->stream; }
+}  // namespace pcgmi
+
+namespace {
+
 void free_ctx(pcg_ctx c) {
     if (!c) return;
     if (c->chunk) (void)hipGraphExecDestroy(c->chunk);
@@ -505,11 +522,12 @@ pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, 
         return fail(PCG_E_ARG, "pcg_solve: b and x overlap");
     hipStream_t st = c->stream;
     const int xacc_dt = c->opt.x_accum;
-    IterResult res, seg;
+    IterResult res;
     int restarts = 0, total_iters = 0;
     const void* x0 = c->opt.use_x0 ? x : nullptr;
     int x0_dt = c->opt.x_dtype;
     for (;;) {
+        IterResult seg;  // run_iterations accumulates its kernel times into a fresh result
         pcg_status s = run_iterations(c, b, x0, x0_dt, rtol, maxit - total_iters, 0, &seg);
         if (s != PCG_OK) return s;
         total_iters += seg.fin.iters;

@@ -2,6 +2,13 @@
 error) training pairs with the FP64 solver, train the network, and solve
 with flexible CG. Orchestration only: every arithmetic step runs in the
 library's kernels (snapshot solve, pair scaling, forward/backward, Adam).
+
+Two sources of pairs, both from the solver itself:
+  - generate_pairs: snapshots (r_k, x* - x_k) of FP64 Jacobi-PCG solves;
+  - onpolicy_pairs: iterates x_k of the flexible solve with the current
+    network, r_k = b - A x_k in FP64 and e_k = x* - x_k with x* from an
+    FP64 solve -- the residuals the preconditioner meets inside the flexible
+    solve, on which a network trained only on Jacobi-PCG residuals degrades.
 """
 from __future__ import annotations
 
@@ -96,3 +103,91 @@ def he_init(seed: int) -> np.ndarray:
         std = (2.0 / (27 * chans[i])) ** 0.5
         out.append(np.random.default_rng(seed + i).standard_normal(27 * chans[i] * chans[i + 1]) * std)
     return np.concatenate(out).astype(np.float32)
+
+
+def onpolicy_pairs(net, n: int, kcell: torch.Tensor, g: torch.Tensor, rhs_seeds, snap_iters, rtol: float = 1e-12,
+                   maxit: int = 20000, stream=None):
+    """Pairs from flexible-CG trajectories with the current network.
+
+    For each seed, b ~ U[-1, 1] (FP64); x* from FP64 Jacobi-PCG to rtol; for
+    every k in snap_iters, x_k = the flexible solve's iterate after k
+    iterations (FP32 vectors, FP64 x, b rounded to FP32), r_k = b - A x_k in
+    FP64, and the pair (r_k, x* - x_k) scaled by rms(r_k).
+    Returns (pairs BF16 [npairs * 2 * n^3], seconds).
+    """
+    import synthetic
+
+    t0 = time.perf_counter()
+    N = n ** 3
+    ctx64 = B.pcg_create(n, n, n, torch.float64, stream=stream)
+    B.pcg_set_coefficients(ctx64, kcell)
+    ctx32 = B.pcg_create(n, n, n, torch.float32, stream=stream, x_dtype=torch.float64)
+    B.pcg_set_coefficients(ctx32, kcell)
+    seeds = list(rhs_seeds)
+    its = list(snap_iters)
+    pairs = torch.empty(2 * len(seeds) * len(its) * N, dtype=torch.bfloat16, device="cuda")
+    xs = torch.empty(N, dtype=torch.float64, device="cuda")
+    xk = torch.empty(N, dtype=torch.float64, device="cuda")
+    ax = torch.empty(N, dtype=torch.float64, device="cuda")
+    rk = torch.empty(N, dtype=torch.float64, device="cuda")
+    slot = 0
+    for seed in seeds:
+        b64 = torch.from_numpy(synthetic.uniform(seed, N)).cuda()
+        b32 = b64.float()
+        B.pcg_solve(ctx64, b64, xs, rtol, maxit)
+        for k in its:
+            B.pcg_solve_flexible(ctx32, net, g, b32, xk, rtol=0.0, maxit=int(k), raise_on_error=False)
+            B.stencil_apply(ctx64, xk, ax)
+            B.axpy(ctx64, N, -1.0, ax, b64, rk)
+            B.pcg_make_pairs(ctx64, 1, rk, xk, xs, pairs[2 * slot * N:2 * (slot + 1) * N])
+            slot += 1
+    torch.cuda.synchronize()
+    ctx64.close()
+    ctx32.close()
+    return pairs, time.perf_counter() - t0
+
+
+def train_onpolicy(net, n: int, kcell: torch.Tensor, g: torch.Tensor, train_seeds, rounds: int = 4,
+                   epochs: int = 3, batch: int = 8, lr: float = 1e-3, snaps_per_rhs: int = 16,
+                   onpolicy_seeds: int = 4, onpolicy_iters=None, seed: int = 0, stream=None):
+    """A-norm training (cnn_set_operator) of the Jacobi-plus-correction
+    network: FP64 Jacobi-PCG snapshot pairs, then `rounds` rounds of
+    `epochs` epochs, each followed by on-policy pairs from flexible-CG
+    trajectories of `onpolicy_seeds` training right-hand sides (cycled).
+    Returns a log dict (losses per round, pair counts, seconds)."""
+    ctx = B.pcg_create(n, n, n, torch.float32, stream=stream)
+    B.pcg_set_coefficients(ctx, kcell)
+    B.cnn_set_operator(net, ctx)
+    seeds = list(train_seeds)
+    its = list(onpolicy_iters) if onpolicy_iters is not None else list(range(2, 25, 2))
+    t0 = time.perf_counter()
+    pairs, t_gen = generate_pairs(n, kcell, seeds, snaps_per_rhs=snaps_per_rhs, perm_seed=seed, stream=stream)
+    log = {"losses": [], "pairs": [], "gen_s": t_gen, "train_s": 0.0, "onpolicy_s": 0.0}
+    N = n ** 3
+    for rnd in range(rounds):
+        hist, tt = train(net, n, pairs, g, epochs, batch, lr, seed=seed + rnd)
+        log["losses"].append(hist[-1])
+        log["pairs"].append(pairs.numel() // (2 * N))
+        log["train_s"] += tt
+        if rnd + 1 == rounds:
+            break
+        pick = [seeds[(rnd * onpolicy_seeds + j) % len(seeds)] for j in range(onpolicy_seeds)]
+        extra, to = onpolicy_pairs(net, n, kcell, g, pick, its, stream=stream)
+        log["onpolicy_s"] += to
+        pairs = torch.cat([pairs, extra])
+        # keep contiguous batches mixed: shuffle whole pairs
+        npairs = pairs.numel() // (2 * N)
+        perm = torch.from_numpy(np.random.default_rng(seed + 100 + rnd).permutation(npairs)).cuda()
+        pairs = pairs.view(npairs, 2 * N)[perm].reshape(-1).contiguous()
+    B.cnn_set_operator(net, None)
+    ctx.close()
+    log["total_s"] = time.perf_counter() - t0
+    return log
+
+
+def he_init_correction(seed: int) -> np.ndarray:
+    """He-normal layers 1-3 and a zero last layer: the correction starts at 0,
+    so the preconditioner D^-1 r + N starts as Jacobi."""
+    w = he_init(seed)
+    w[14688:] = 0.0
+    return w

@@ -58,13 +58,13 @@ def _fwd_emulated(orc, ws, inp, relu=True):
 
 def _bwd_emulated(orc, wb, acts, dout):
     """Oracle back-propagation with the GPU's BF16 roundings of the
-    propagated gradients (the last layer's gradient enters the input-gradient
-    convolution as BF16 and stays FP32 for its weight gradient)."""
+    propagated gradients (the last layer's gradient enters both its weight
+    gradient and the input-gradient convolution as BF16)."""
     rb = orc.round_bf16
     grads = [None] * 4
     g = dout
     for li in range(3, -1, -1):
-        _, dw = orc.conv3d_bwd(acts[li], wb[li], g)
+        _, dw = orc.conv3d_bwd(acts[li], wb[li], rb(g) if li == 3 else g)
         grads[li] = dw
         if li > 0:
             gin = rb(g) if li == 3 else g
@@ -172,6 +172,58 @@ def test_loss_and_gradients(P, orc, shape, batch):
         rel = np.linalg.norm(got - ref_grads[i]) / np.linalg.norm(ref_grads[i])
         print(shape, "layer", i + 1, "grad rel err", rel, flush=True)
         assert rel <= 1e-2
+
+
+@pytest.mark.parametrize("var", [False, True])
+def test_anorm_loss_and_gradients(P, orc, var):
+    """A-norm loss of the Jacobi-plus-correction preconditioner (operator from
+    an F32 context) against the oracle's anorm_loss with the GPU's BF16
+    roundings emulated; same bars as the relative-MSE test."""
+    shape = (10, 9, 12)
+    nz, ny, nx = shape
+    n = int(np.prod(shape))
+    batch = 2
+    ws = _init_weights(13)
+    g = synthetic.uniform_f32(41, n)
+    k32 = synthetic.coefficient_field(12)[:n].copy() if var else None
+    pairs = []
+    for b in range(batch):
+        pairs += [synthetic.f32_to_bf16_bits(synthetic.uniform_f32(52 + b, n)),
+                  synthetic.f32_to_bf16_bits(synthetic.uniform_f32(62 + b, n))]
+    from gpu_helpers import bf16_tensor
+
+    ctx = P.pcg_create(nx, ny, nz, torch.float32)
+    if var:
+        P.pcg_set_coefficients(ctx, torch.from_numpy(k32).cuda())
+    net = P.cnn_create()
+    P.cnn_set_weights(net, torch.from_numpy(_flat(ws)).cuda())
+    P.cnn_set_operator(net, ctx)
+    grad = torch.zeros(P.cnn_num_weights(), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    P.cnn_loss_grad(net, shape, bf16_tensor(np.concatenate(pairs)).cuda(), torch.from_numpy(g).cuda(), batch,
+                    grad=grad, loss=loss)
+    k64 = None if k32 is None else k32.astype(np.float64)
+    ref_loss, ref_grads = 0.0, [np.zeros((27, CHANS[i], CHANS[i + 1])) for i in range(4)]
+    for b in range(batch):
+        rh = synthetic.bf16_bits_to_f32(pairs[2 * b]).astype(np.float64)
+        eh = synthetic.bf16_bits_to_f32(pairs[2 * b + 1]).astype(np.float64)
+        inp = np.stack([rh.reshape(shape), g.astype(np.float64).reshape(shape)], axis=-1)
+        out, acts, wb = _fwd_emulated(orc, ws, inp)
+        l, dl = orc.anorm_loss([out.reshape(-1)], [rh], [eh], shape, kcell=k64)
+        ref_loss += l / batch
+        gr = _bwd_emulated(orc, wb, acts, dl[0].reshape(*shape, 1))
+        for i in range(4):
+            ref_grads[i] += gr[i] / batch
+    print("anorm loss", loss.item(), ref_loss, flush=True)
+    assert abs(loss.item() - ref_loss) <= 1e-3 * ref_loss
+    gg = grad.cpu().numpy().astype(np.float64)
+    for i in range(4):
+        got = gg[OFF[i]:OFF[i + 1]].reshape(ref_grads[i].shape)
+        rel = np.linalg.norm(got - ref_grads[i]) / np.linalg.norm(ref_grads[i])
+        print("anorm layer", i + 1, "grad rel err", rel, flush=True)
+        assert rel <= 1e-2
+    # the operator can be unset again (relative MSE)
+    P.cnn_set_operator(net, None)
 
 
 def test_adam_step(P, orc):

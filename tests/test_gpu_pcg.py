@@ -186,3 +186,13 @@ def test_fp64_residual_restart(P, orc):
     assert i1["restarts"] == 3 or t1 <= 1e-7
     assert abs(i1["rel_res_true_fp64"] - t1) <= 1e-6 * t1
     assert i1["iters"] >= i0["iters"]
+
+
+def test_kernel_timing_counts_each_iteration_once(P, orc):
+    """With a restart the per-kernel event sums still cover each iteration
+    once: their total stays below the solve's wall time."""
+    shape = (40, 40, 40)
+    b, _ = make_vec(23, 40 ** 3, torch.float32)
+    _, _, info, _ = _solve(P, shape, b, rtol=1e-7, maxit=3000, x_dtype=torch.float64, kernel_timing=1)
+    assert info["k1_launches"] == info["iters"] == info["k2_launches"]
+    assert info["k1_ms"] + info["k2_ms"] <= info["seconds"] * 1e3
