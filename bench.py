@@ -1,7 +1,8 @@
 """Benchmark of the Jacobi-PCG hot path on one MI355X.
 
-Step = one full FP32 Jacobi-PCG solve (x0 = 0, recursive relative residual
-1e-6) of the 256^3 seven-point Poisson system b = A x*, x* = lowest sine mode
+Step = one full FP32 Jacobi-PCG solve (x0 = 0, relative residual 1e-6 judged
+in FP64, with restarts from the FP64 residual when the FP32 recursion drifts)
+of the 256^3 seven-point Poisson system b = A x*, x* = lowest sine mode
 + 1e-3 U[-1,1] noise (seed 4). `value` = seconds per solve (lower is better).
 
 Also reported on the same JSON line:
@@ -11,8 +12,19 @@ Also reported on the same JSON line:
   roofline      -- the dominant kernel (the PCG update kernel) measured with
                    HIP events on the library's stream in an event-timed solve
                    of the same workload, against 8 TB/s;
+  learned       -- the learned preconditioner on the variable-coefficient
+                   operator (k = exp(GRF), harmonic-mean faces): the
+                   network's forward and training step at 128^3 (MFMA
+                   TFLOP/s against the dense BF16 peak), and the whole
+                   workflow (FP64 pair generation, on-policy rounds, A-norm
+                   training, flexible CG on a held-out right-hand side)
+                   against Jacobi-PCG at --learned-n;
   kernels_512   -- standalone stencil / axpy / dot at 512^3 (FP32 and BF16),
                    achieved GB/s of algorithmic bytes;
+  batched       -- 64 uneven problems (edges log-uniform in [16, 128], seed 5;
+                   b_i ~ U[-1,1], seeds 1000 + i) in one persistent
+                   hipGraph-captured launch: solves/s, per-problem latency,
+                   against 64 sequential pcg_solve calls;
   cpu_baseline  -- the FP64 CPU oracle's Jacobi-PCG on the same system,
                    timed on a bounded number of iterations and scaled.
 """
@@ -142,6 +154,141 @@ def cpu_baseline(b64_host, n, gpu_iters, budget_s=15.0):
                           f"first {its} iterations timed ({tm:.1f} s), scaled to the GPU's {gpu_iters} iterations"))}
 
 
+def bench_batched(P, torch, reps):
+    """The 64-problem batch: graph replays timed with torch events on the
+    stream the batch was created on (the current stream)."""
+    import synthetic
+
+    sizes = synthetic.batch_sizes()
+    dims = [(m, m, m) for m in sizes]
+    t0 = time.perf_counter()
+    bt = P.pcg_batch_create(dims)
+    t_create = time.perf_counter() - t0
+    b = torch.zeros(bt.total, dtype=torch.float32, device="cuda")
+    for i, m in enumerate(sizes):
+        bt.view(b, i).copy_(torch.from_numpy(synthetic.uniform_f32(synthetic.SEED_C4_B_BASE + i, m ** 3)))
+    x = torch.zeros(bt.total, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        r = P.pcg_batch_solve(bt, b, x, rtol=1e-6, maxit=5000)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        r = P.pcg_batch_solve(bt, b, x, rtol=1e-6, maxit=5000)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    lat = sorted(r["latency_s"])
+    traffic = sum(44.0 * m ** 3 * it for m, it in zip(sizes, r["iters"]))
+    # the same 64 problems one after another through pcg_solve
+    ctxs = []
+    for i, m in enumerate(sizes):
+        ctx = P.pcg_create(m, m, m, torch.float32, x_dtype=torch.float64)
+        ctxs.append((ctx, torch.empty(m ** 3, dtype=torch.float64, device="cuda")))
+    for i, (ctx, xi) in enumerate(ctxs):
+        P.pcg_solve(ctx, bt.view(b, i), xi, 1e-6, 5000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_iters = []
+    for i, (ctx, xi) in enumerate(ctxs):
+        seq_iters.append(P.pcg_solve(ctx, bt.view(b, i), xi, 1e-6, 5000)["iters"])
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    for ctx, _ in ctxs:
+        ctx.close()
+    out = {"problems": len(sizes), "points": int(sum(m ** 3 for m in sizes)), "ms_per_batch": round(ms, 3),
+           "solves_per_s": round(len(sizes) / (ms * 1e-3), 1),
+           "latency_ms": {"min": round(lat[0] * 1e3, 3), "median": round(lat[len(lat) // 2] * 1e3, 3),
+                          "max": round(lat[-1] * 1e3, 3)},
+           "effective_GB/s": round(traffic / (ms * 1e-3) / 1e9, 1),
+           "iters_total": int(sum(r["iters"])), "restarts_total": int(sum(r["restarts"])),
+           "max_true_relres": max(r["relres"]), "sequential_ms": round(seq * 1e3, 2),
+           "speedup_vs_sequential": round(seq * 1e3 / ms, 3),
+           "iters_equal_sequential": int(sum(1 for a, c in zip(r["iters"], seq_iters) if a == c)),
+           "work_groups": bt.grid, "create_and_tune_s": round(t_create, 3)}
+    bt.close()
+    return out
+
+
+BF16_PEAK_TFLOPS = 2500.0
+# FLOP per voxel of one forward pass: 2 x 27 taps x (2*16 + 16*16 + 16*16 + 16*1)
+CNN_FLOP_PER_VOXEL = 2 * 27 * (2 * 16 + 16 * 16 + 16 * 16 + 16)
+
+
+def bench_learned(P, torch, n_work, rounds, n_kernel=128):
+    import numpy as np
+
+    import synthetic
+    from paper_2603_23343_amd import learned as L
+
+    out = {}
+    # network kernels at n_kernel^3
+    nk = n_kernel
+    N = nk ** 3
+    net = P.cnn_create()
+    P.cnn_set_weights(net, torch.from_numpy(L.he_init(7)).cuda())
+    r = torch.from_numpy(synthetic.uniform_f32(1, N)).cuda()
+    g = torch.from_numpy(synthetic.gaussian_random_field(nk).astype(np.float32)).cuda()
+    z = torch.empty(N, device="cuda")
+    for _ in range(3):
+        P.cnn_forward(net, (nk, nk, nk), r, g, z)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(20):
+        P.cnn_forward(net, (nk, nk, nk), r, g, z)
+    ev1.record()
+    torch.cuda.synchronize()
+    fwd_ms = ev0.elapsed_time(ev1) / 20
+    pairs = torch.from_numpy(synthetic.f32_to_bf16_bits(synthetic.uniform_f32(3, 2 * 4 * N)).view(np.int16)).view(
+        torch.bfloat16).cuda()
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    P.cnn_train_step(net, (nk, nk, nk), pairs, g, 4, lr=1e-5, loss=loss)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(3):
+        P.cnn_train_step(net, (nk, nk, nk), pairs, g, 4, lr=1e-5, loss=loss)
+    ev1.record()
+    torch.cuda.synchronize()
+    train_ms = ev0.elapsed_time(ev1) / 12
+    fl = CNN_FLOP_PER_VOXEL * N
+    out["network"] = {"grid": nk, "forward_ms": round(fwd_ms, 4),
+                      "forward_TFLOP/s": round(fl / (fwd_ms * 1e-3) / 1e12, 1),
+                      "forward_frac_of_bf16_peak": round(fl / (fwd_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4),
+                      "train_ms_per_sample": round(train_ms, 3),
+                      "train_TFLOP/s": round(3 * fl / (train_ms * 1e-3) / 1e12, 1)}
+    net.close()
+    # workflow at n_work^3
+    n = n_work
+    N = n ** 3
+    kd = torch.from_numpy(synthetic.coefficient_field(n)).cuda()
+    gd = torch.from_numpy(synthetic.gaussian_random_field(n).astype(np.float32)).cuda()
+    net = P.cnn_create()
+    P.cnn_set_weights(net, torch.from_numpy(L.he_init_correction(7)).cuda())
+    log = L.train_onpolicy(net, n, kd, gd, range(synthetic.SEED_C5_TRAIN_BASE, synthetic.SEED_C5_TRAIN_BASE + 8),
+                           rounds=rounds, epochs=3)
+    ctx = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64)
+    P.pcg_set_coefficients(ctx, kd)
+    x = torch.empty(N, dtype=torch.float64, device="cuda")
+    b = torch.from_numpy(synthetic.uniform_f32(synthetic.SEED_C5_HELDOUT_BASE, N)).cuda()
+    P.pcg_solve(ctx, b, x, 1e-6, 20000)
+    jac = P.pcg_solve(ctx, b, x, 1e-6, 20000)
+    P.pcg_solve_flexible(ctx, net, gd, b, x, 1e-6, 20000, raise_on_error=False)
+    fcg = P.pcg_solve_flexible(ctx, net, gd, b, x, 1e-6, 20000, raise_on_error=False)
+    out["workflow"] = {"grid": n, "rounds": rounds, "pairs": log["pairs"][-1],
+                       "final_loss": round(log["losses"][-1], 4), "pair_gen_s": round(log["gen_s"], 3),
+                       "onpolicy_s": round(log["onpolicy_s"], 3), "train_s": round(log["train_s"], 3),
+                       "jacobi_pcg": {"iters": jac["iters"], "ms": round(jac["seconds"] * 1e3, 3),
+                                      "true_relres": jac["rel_res_true_fp64"]},
+                       "flexible_cg_learned": {"iters": fcg["iters"], "ms": round(fcg["seconds"] * 1e3, 3),
+                                               "fallback_used": fcg["fallback_used"],
+                                               "true_relres": fcg["rel_res_true_fp64"]},
+                       "iteration_ratio": round(fcg["iters"] / max(jac["iters"], 1), 3)}
+    net.close()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +300,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernels", action="store_true")
     ap.add_argument("--no-refined", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-n", type=int, default=64)
+    ap.add_argument("--learned-rounds", type=int, default=12)
+    ap.add_argument("--batched-reps", type=int, default=10)
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also copy a buffer of this many MiB 5 times (counter calibration)")
@@ -231,6 +383,16 @@ def main():
             del x64
         print(f"# refined: {refined}", file=sys.stderr, flush=True)
 
+    batched = None
+    if not args.no_batched:
+        batched = bench_batched(P, torch, args.batched_reps)
+        print(f"# batched: {batched}", file=sys.stderr, flush=True)
+
+    learned = None
+    if not args.no_learned:
+        learned = bench_learned(P, torch, args.learned_n, args.learned_rounds)
+        print(f"# learned: {learned}", file=sys.stderr, flush=True)
+
     kern = None
     if not args.no_kernels:
         del ctx
@@ -246,12 +408,15 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": (f"{n}^3 seven-point Poisson, b = A x*, x* = sin*sin*sin + 1e-3 U[-1,1] "
-                                "(seed 4); FP32 Jacobi-PCG from x0 = 0 to recursive 1e-6, FP64 x accumulator"),
+                                "(seed 4); FP32 Jacobi-PCG from x0 = 0 to 1e-6, judged by the FP64 true residual "
+                                "(restarts from r = b - A x when the recursion drifts), FP64 x accumulator"),
                    "grid": [n, n, n], "iters": iters, "rel_res_recursive": info["rel_res_recursive"],
-                   "rel_res_true_fp64": info["rel_res_true_fp64"],
+                   "rel_res_true_fp64": info["rel_res_true_fp64"], "restarts": info["restarts"],
                    "per_iteration_us": round(dt * 1e6 / max(iters, 1), 2)},
         "roofline": roofline,
         "refined": refined or None,
+        "batched": batched,
+        "learned": learned,
         "kernels_512": kern,
         "cpu_baseline": cpu,
     }

@@ -24,7 +24,7 @@ __device__ __forceinline__ float bf16v(uint16_t b) { return __uint_as_float(((ui
 // the tap's x offset. A work-group stages, per chunk of up to WGM_K points
 // of a row, the 9 neighbour rows of X and the 3 shifted copies of dY in LDS,
 // transposed to [channel][x] (channels beyond CX / CY are zero); wave w
-// accumulates taps w, w + 4, ... over all its rows in registers. Rows are
+// accumulates taps w, w + 4, ... (acc[t / 4]) over all its rows in registers. Rows are
 // dealt to work-groups round-robin; partials[g][27][CX][CY] feed the
 // fixed-order reduction, so the result is deterministic.
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
@@ -112,20 +112,24 @@ __global__ void __launch_bounds__(256) k_wgrad_mfma(int nx, int ny, int nz, cons
         __syncthreads();
         for (int kb = 0; kb < kp; kb += 32) {
             const int ko = kb + 8 * kg;
-            bf16x8_t bq[3];
+            // tap t = 3 r + sft (r = 3 dz + dy): both loops unrolled, so the
+            // accumulator acc[t / 4] of the wave owning t (t % 4 == wid) is
+            // a fixed register block
 #pragma unroll
-            for (int sft = 0; sft < 3; ++sft) bq[sft] = *reinterpret_cast<const bf16x8_t*>(&ys[(sft * 16 + m) * WGM_SP + ko]);
+            for (int sft = 0; sft < 3; ++sft) {
+                const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&ys[(sft * 16 + m) * WGM_SP + ko]);
 #pragma unroll
-            for (int j = 0; j < 7; ++j) {
-                const int t = wid + 4 * j;
-                if (t < 27) {
-                    const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&xs[((t / 3) * 16 + m) * WGM_SP + ko]);
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[t % 3], acc[j], 0, 0, 0);
+                for (int r = 0; r < 9; ++r) {
+                    const int t = 3 * r + sft;
+                    if ((t & 3) == wid) {
+                        const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&xs[(r * 16 + m) * WGM_SP + ko]);
+                        acc[t >> 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t >> 2], 0, 0, 0);
+                    }
                 }
             }
         }
     }
-    // lane holds C[ci = 4 kg + i][co = m] of each of its taps
+    // lane holds C[ci = 4 kg + i][co = m] of each of its taps t = wid + 4 j
     float* out = partials + (size_t)blockIdx.x * 27 * CX * CY;
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
@@ -140,15 +144,25 @@ __global__ void __launch_bounds__(256) k_wgrad_mfma(int nx, int ny, int nz, cons
     }
 }
 
-// grad[j] (+)= scale * sum_g partials[g][j], g in index order.
-__global__ void k_reduce_partials(const float* __restrict__ partials, int ngroups, int len, float scale,
-                                  int accumulate, float* __restrict__ grad) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= len) return;
+// grad[j] (+)= scale * sum_g partials[g][j]. A work-group owns 64 outputs;
+// thread (q, j) with q = tid / 64 sums
+// groups q, q + 4, q + 8, ... for output j in FP64, and the 4 sums are added
+// in q order, so the result does not depend on timing.
+__global__ void __launch_bounds__(256) k_reduce_partials(const float* __restrict__ partials, int ngroups, int len,
+                                                         float scale, int accumulate, float* __restrict__ grad) {
+    __shared__ double part[4][64];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (int g = 0; g < ngroups; ++g) s += (double)partials[(size_t)g * len + j];
-    const float v = (float)(s * (double)scale);
-    grad[j] = accumulate ? grad[j] + v : v;
+    if (j < len)
+        for (int g = q; g < ngroups; g += 4) s += (double)partials[(size_t)g * len + j];
+    part[q][lane] = s;
+    __syncthreads();
+    if (q == 0 && j < len) {
+        const double t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        const float v = (float)(t * (double)scale);
+        grad[j] = accumulate ? grad[j] + v : v;
+    }
 }
 
 // Loss of one sample: out (FP32 network output) against the target channel of
@@ -271,10 +285,10 @@ hipError_t launch_make_pair(int64_t n, const double* r, const double* x, const d
 }
 
 // Work-groups of the weight-gradient launch (and partial sets to reduce):
-// one per staged row chunk up to 1024.
+// one per staged row chunk up to 512 (two per CU).
 int wgrad_groups(int nx, int ny, int nz) {
     const int64_t items = (int64_t)ny * nz * ((nx + WGM_K - 1) / WGM_K);
-    return (int)(items < 1 ? 1 : (items > 1024 ? 1024 : items));
+    return (int)(items < 1 ? 1 : (items > 512 ? 512 : items));
 }
 
 hipError_t launch_wgrad(int nx, int ny, int nz, int cx, int cy, const void* X, const void* dY, bool dy_f32,
@@ -296,7 +310,7 @@ hipError_t launch_wgrad(int nx, int ny, int nz, int cx, int cy, const void* X, c
 
 hipError_t launch_reduce_partials(const float* partials, int groups, int len, float scale, bool accumulate,
                                   float* grad, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3((len + 255) / 256), dim3(256), 0, s, partials, groups, len, scale,
+    hipLaunchKernelGGL(k_reduce_partials, dim3((len + 63) / 64), dim3(256), 0, s, partials, groups, len, scale,
                        accumulate ? 1 : 0, grad);
     return hipGetLastError();
 }

@@ -1,0 +1,58 @@
+"""What the trained network gains: flexible CG with the learned
+Jacobi-plus-correction preconditioner against Jacobi-PCG (the method without
+the network) and against an untrained network, on the variable-coefficient
+operator (k = exp(Gaussian random field), harmonic-mean faces), held-out
+right-hand sides. Training: FP64 Jacobi-PCG snapshot pairs plus on-policy
+pairs from the flexible solve, A-norm loss, Adam -- all on the GPU through
+the C ABI. The FP64 true residual of every solve is checked with the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2603_23343_amd as P
+
+    return P
+
+
+def test_trained_network_gains(P, orc):
+    from paper_2603_23343_amd import learned
+
+    n = 32
+    N = n ** 3
+    shape = (n, n, n)
+    k32 = synthetic.coefficient_field(n)
+    k64 = k32.astype(np.float64)
+    kd = torch.from_numpy(k32).cuda()
+    gd = torch.from_numpy(synthetic.gaussian_random_field(n).astype(np.float32)).cuda()
+    ctx = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64)
+    P.pcg_set_coefficients(ctx, kd)
+    x = torch.empty(N, dtype=torch.float64, device="cuda")
+
+    net_u = P.cnn_create()
+    P.cnn_set_weights(net_u, torch.from_numpy(learned.he_init(7)).cuda())
+    net = P.cnn_create()
+    P.cnn_set_weights(net, torch.from_numpy(learned.he_init_correction(7)).cuda())
+    log = learned.train_onpolicy(net, n, kd, gd, range(synthetic.SEED_C5_TRAIN_BASE, synthetic.SEED_C5_TRAIN_BASE + 8),
+                                 rounds=6, epochs=3)
+    print("training", log, flush=True)
+    for j in range(2):
+        b64 = synthetic.uniform(synthetic.SEED_C5_HELDOUT_BASE + j, N)
+        b = torch.from_numpy(b64.astype(np.float32)).cuda()
+        bb = b.double().cpu().numpy()
+        jac = P.pcg_solve(ctx, b, x, 1e-6, 5000)
+        unt = P.pcg_solve_flexible(ctx, net_u, gd, b, x, 1e-6, 5000)
+        tr = P.pcg_solve_flexible(ctx, net, gd, b, x, 1e-6, 5000)
+        print("held-out", j, "jacobi", jac["iters"], "untrained", unt["iters"], unt["fallback_used"],
+              "trained", tr["iters"], tr["fallback_used"], flush=True)
+        assert tr["status"] == P.PCG_OK and tr["fallback_used"] == 0
+        assert orc.true_relres(shape, bb, x.cpu().numpy(), kcell=k64) <= 1e-6
+        assert tr["iters"] <= 0.7 * jac["iters"]
+        assert tr["iters"] < unt["iters"]
