@@ -1,0 +1,105 @@
+"""Parity at the full sizes and in the launch configuration the benchmark
+uses (default plans, default options), where the oracle cannot recompute
+everything: sampled outputs computed one by one by the FP64 oracle's
+definition, whole-vector properties, and the FP64 true residual.
+
+- 512^3 stencil / axpy (alpha = 0.5) / dot, FP32 and BF16, x and y from the
+  benchmark's seeds; 65536 sampled points per output; tolerances as in the
+  small-size kernel tests.
+- 256^3 FP32 Jacobi-PCG on b = A x* (b from the oracle's FP64 stencil):
+  without restarts the iteration count is within 2 of the oracle's FP64
+  Jacobi-PCG; with the default restarts the FP64 true residual (oracle) is
+  <= 1e-6.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+from gpu_helpers import host64, make_vec, ulp
+
+pytestmark = pytest.mark.gpu
+
+N5 = 512
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2603_23343_amd as P
+
+    return P
+
+
+def _sample(n_total, k, seed):
+    return np.sort(np.random.default_rng(seed).choice(n_total, size=k, replace=False))
+
+
+def _stencil_at(x64, shape, idx):
+    """(A x)[idx] from the definition: 6 x_p minus the in-grid face neighbours,
+    and the absolute-value bound 6|x_p| + sum |x_nb|."""
+    nz, ny, nx = shape
+    k, rem = np.divmod(idx, ny * nx)
+    j, i = np.divmod(rem, nx)
+    val = 6.0 * x64[idx]
+    bound = 6.0 * np.abs(x64[idx])
+    for ok, off in ((i > 0, -1), (i < nx - 1, 1), (j > 0, -nx), (j < ny - 1, nx), (k > 0, -nx * ny),
+                    (k < nz - 1, nx * ny)):
+        nb = np.where(ok, x64[np.where(ok, idx + off, 0)], 0.0)
+        val -= nb
+        bound += np.abs(nb)
+    return val, bound
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_kernels_512(P, orc, dtype):
+    n = N5
+    N = n ** 3
+    shape = (n, n, n)
+    print("512^3 kernels", dtype, flush=True)
+    x, x64 = make_vec(synthetic.SEED_C2_X, N, dtype)
+    y, y64 = make_vec(synthetic.SEED_C2_Y, N, dtype)
+    ctx = P.pcg_create(n, n, n, dtype)
+    z = torch.empty_like(x)
+    idx = _sample(N, 65536, 7)
+    # stencil
+    P.stencil_apply(ctx, x, z)
+    got = host64(z)[idx]
+    ref, bound = _stencil_at(x64, shape, idx)
+    tol = 1e-6 * bound + (ulp(ref, dtype) if dtype != torch.float32 else 0.0)
+    assert np.all(np.abs(got - ref) <= tol)
+    # axpy, alpha = 0.5
+    P.axpy(ctx, N, 0.5, x, y, z)
+    got = host64(z)[idx]
+    ref = 0.5 * x64[idx] + y64[idx]
+    tol = 1e-6 * (0.5 * np.abs(x64[idx]) + np.abs(y64[idx])) + (ulp(ref, dtype) if dtype != torch.float32 else 0.0)
+    assert np.all(np.abs(got - ref) <= tol)
+    # dot over the whole vectors
+    d = torch.zeros(1, dtype=torch.float32, device="cuda")
+    P.dot(ctx, N, x, y, d)
+    ref = orc.dot(x64, y64)
+    assert abs(d.item() - ref) <= 1e-5 * float(np.sum(np.abs(x64 * y64)))
+    ctx.close()
+
+
+def test_pcg_256_bench_configuration(P, orc):
+    n = 256
+    N = n ** 3
+    shape = (n, n, n)
+    print("256^3 PCG", flush=True)
+    b64 = orc.stencil(synthetic.smooth_plus_noise(n), shape)
+    b32 = b64.astype(np.float32)
+    bb = b32.astype(np.float64)
+    b = torch.from_numpy(b32).cuda()
+    x = torch.empty(N, dtype=torch.float64, device="cuda")
+    ctx0 = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64, max_restarts=0)
+    i0 = P.pcg_solve(ctx0, b, x, 1e-6, 5000)
+    ctx0.close()
+    ref = orc.pcg(shape, bb, rtol=1e-6, maxit=5000)
+    print("iterations", i0["iters"], "oracle", ref["iters"], flush=True)
+    assert abs(i0["iters"] - ref["iters"]) <= 2
+    ctx = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64)
+    info = P.pcg_solve(ctx, b, x, 1e-6, 5000)
+    tr = orc.true_relres(shape, bb, x.cpu().numpy())
+    print("restarts", info["restarts"], "iters", info["iters"], "true relres", tr, flush=True)
+    assert tr <= 1e-6
+    assert abs(info["rel_res_true_fp64"] - tr) <= 1e-6 * tr
