@@ -179,7 +179,7 @@ def bench_batched(P, torch, reps):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / reps
     lat = sorted(r["latency_s"])
-    traffic = sum(44.0 * m ** 3 * it for m, it in zip(sizes, r["iters"]))
+    traffic = sum(float(BYTES_DIRECTION + BYTES_UPDATE) * m ** 3 * it for m, it in zip(sizes, r["iters"]))
     # the same 64 problems one after another through pcg_solve
     ctxs = []
     for i, m in enumerate(sizes):
