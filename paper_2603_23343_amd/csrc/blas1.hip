@@ -62,7 +62,22 @@ __global__ void __launch_bounds__(NT) k_dot(int64_t n, const T* __restrict__ x, 
     C acc[W];
 #pragma unroll
     for (int e = 0; e < W; ++e) acc[e] = C(0);
-    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nvec; i += stride) {
+    // four independent vector pairs in flight per thread, then the tail
+    constexpr int U = 4;
+    int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    for (; i + (U - 1) * stride < nvec; i += U * stride) {
+        C a[U][W], b[U][W];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            load_vec<T>(x + (i + u * stride) * W, a[u]);
+            load_vec<T>(y + (i + u * stride) * W, b[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < W; ++e) acc[e] += a[u][e] * b[u][e];
+    }
+    for (; i < nvec; i += stride) {
         C a[W], b[W];
         load_vec<T>(x + i * W, a);
         load_vec<T>(y + i * W, b);
@@ -73,13 +88,24 @@ __global__ void __launch_bounds__(NT) k_dot(int64_t n, const T* __restrict__ x, 
         const int64_t t = nvec * W + threadIdx.x;
         if (t < n) acc[0] += to_c(x[t]) * to_c(y[t]);
     }
-    double v[1] = {0.0}, tot[1];
+    double v[1] = {0.0};
 #pragma unroll
     for (int e = 0; e < W; ++e) v[0] += (double)acc[e];
-    if (grid_reduce<1, 0u>(v, red.partials, red.ticket, gridDim.x, blockIdx.x, scratch, tot) &&
-        threadIdx.x == 0) {
-        if (out_f32) *out_f32 = (float)tot[0];
-        if (out_f64) *out_f64 = tot[0];
+    // partial per work-group; k_dot_finish sums them in index order (a
+    // kernel boundary instead of a release fence per work-group)
+    block_reduce<1, 0u>(v, scratch);
+    if (threadIdx.x == 0) red.partials[blockIdx.x] = v[0];
+}
+
+__global__ void __launch_bounds__(NT) k_dot_finish(const double* __restrict__ partials, unsigned nblocks,
+                                                   float* out_f32, double* out_f64) {
+    __shared__ double scratch[16];
+    double v[1] = {0.0};
+    for (unsigned i = threadIdx.x; i < nblocks; i += NT) v[0] += partials[i];
+    block_reduce<1, 0u>(v, scratch);
+    if (threadIdx.x == 0) {
+        if (out_f32) *out_f32 = (float)v[0];
+        if (out_f64) *out_f64 = v[0];
     }
 }
 
@@ -185,10 +211,12 @@ hipError_t launch_dot(int dt, int64_t n, const void* x, const void* y, float* ou
     return dispatch_dt(dt, [&](auto tag) {
         using T = decltype(tag);
         const int64_t nvec = n / Traits<T>::W;
-        const unsigned nb = stream_blocks(nvec, (int64_t)NT * 4, DOT_MAX_BLOCKS);
+        // 1024 work-groups (4 per CU) streamed best in a sweep of 1024..16384
+        const unsigned nb = stream_blocks(nvec, (int64_t)NT * 4, 1024);
         if ((size_t)nb > red.cap) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_dot<T>, dim3(nb), dim3(NT), 0, s, n, static_cast<const T*>(x),
                            static_cast<const T*>(y), out_f32, out_f64, red);
+        hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(NT), 0, s, red.partials, nb, out_f32, out_f64);
         return hipGetLastError();
     });
 }

@@ -17,10 +17,13 @@
 // input) a chunk covers 16 taps and a lane gathers four (tap, 2-channel)
 // pairs. Taps beyond 27 and neighbours outside the grid contribute zero.
 // Weights are pre-swizzled into exactly the B lane layout, so each lane
-// reads its 16 bytes per chunk with one load. A wavefront computes 4 tiles
-// (64 consecutive voxels) and keeps all weight chunks in registers; the
-// 16 x 16 FP32 results go through LDS so each voxel's 16 channels leave as
-// two 16-byte stores.
+// reads its 16 bytes per chunk with one load and keeps all chunks in
+// registers. A work-group owns a 16 x 8 x 4 block of output voxels: it
+// stages the block's input with its one-voxel halo (18 x 10 x 6 voxels) in
+// LDS once, so every input voxel crosses L2 about twice instead of 27 times,
+// and each wavefront computes 8 tiles of 16 voxels (x-rows of the block)
+// from LDS. The 16 x 16 FP32 results go through LDS so each voxel's 16
+// channels leave as two 16-byte stores.
 //
 // The transposed convolution of the backward pass (input gradient) is the
 // same kernel with the taps mirrored and Cin/Cout swapped in the swizzle.
@@ -37,7 +40,6 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 
 constexpr int CONV_WAVES = 4;     // wavefronts per work-group
-constexpr int CONV_TILES = 4;     // 16-voxel tiles per wavefront
 constexpr int CONV_NT = 64 * CONV_WAVES;
 
 __device__ __forceinline__ __bf16 bits_to_bf16(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
@@ -49,14 +51,6 @@ struct Dims {
     int64_t nvox;
 };
 
-// Linear index of the neighbour of voxel v at tap t, or -1 outside the grid.
-__device__ __forceinline__ int64_t nb_index(const Dims& d, int x, int y, int z, int t) {
-    const int xx = x + (t % 3) - 1, yy = y + (t / 3) % 3 - 1, zz = z + t / 9 - 1;
-    if (xx < 0 || xx >= d.nx || yy < 0 || yy >= d.ny || zz < 0 || zz >= d.nz) return -1;
-    return ((int64_t)zz * d.ny + yy) * d.nx + xx;
-}
-
-// Output modes of the conv kernel.
 enum ConvOut : int {
     OUT_RELU_BF16 = 0,   // hidden layer: bf16(relu(D)), 16 channels
     OUT_SCALED_F32 = 1,  // last layer: out[v] = scale * D[v][0] (FP32, one channel)
@@ -68,18 +62,48 @@ template <int CIN> struct ConvK {
     static constexpr int CHUNKS = CIN == 16 ? 14 : 2;  // 32-wide K chunks (27 taps padded)
 };
 
+// Output block per work-group and its input halo block.
+constexpr int CB_X = 16, CB_Y = 8, CB_Z = 4;
+constexpr int CH_X = CB_X + 2, CH_Y = CB_Y + 2, CH_Z = CB_Z + 2;
+constexpr int CH_VOX = CH_X * CH_Y * CH_Z;
+constexpr int CB_ROWS = CB_Y * CB_Z;                 // 16-voxel x-rows (tiles) per block
+constexpr int CB_TILES = CB_ROWS / CONV_WAVES;       // tiles per wavefront
+
 // in: [nvox][CIN] bf16 bits. wsw: [CHUNKS][64 lanes][8] bf16 bits (B operand).
 template <int CIN, int MODE>
-__global__ void __launch_bounds__(CONV_NT) k_conv3d(Dims d, const uint16_t* __restrict__ in,
+__global__ void __launch_bounds__(CONV_NT) k_conv3d(Dims d, int nbx, int nby, const uint16_t* __restrict__ in,
                                                     const uint16_t* __restrict__ wsw, void* __restrict__ out,
                                                     const uint16_t* __restrict__ mask, const double* scale_rms2,
                                                     double scale_mul) {
     constexpr int NCH = ConvK<CIN>::CHUNKS;
+    constexpr int VB = CIN * 2;  // bytes per staged voxel (32 or 4)
+    __shared__ __attribute__((aligned(16))) unsigned char halo[CH_VOX * VB];
     __shared__ float lds_d[CONV_WAVES][16][17];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t wave_gid = (int64_t)blockIdx.x * CONV_WAVES + wid;
-    const int64_t vbase = wave_gid * (16 * CONV_TILES);
-    if (vbase >= d.nvox) return;  // whole wavefront past the end (no barrier below is block-wide)
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, bz = blockIdx.x / (nbx * nby);
+    const int x0 = bx * CB_X, y0 = by * CB_Y, z0 = bz * CB_Z;
+
+    // Stage the halo block (zero outside the grid).
+    if constexpr (CIN == 16) {
+        for (int it = tid; it < CH_VOX * 2; it += CONV_NT) {
+            const int h = it >> 1, half = it & 1;
+            const int hx = h % CH_X, hy = (h / CH_X) % CH_Y, hz = h / (CH_X * CH_Y);
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz)
+                v = *reinterpret_cast<const uint4*>(in + (((int64_t)gz * d.ny + gy) * d.nx + gx) * 16 + 8 * half);
+            *reinterpret_cast<uint4*>(halo + (size_t)it * 16) = v;
+        }
+    } else {
+        for (int h = tid; h < CH_VOX; h += CONV_NT) {
+            const int hx = h % CH_X, hy = (h / CH_X) % CH_Y, hz = h / (CH_X * CH_Y);
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            uint32_t v = 0u;
+            if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz)
+                v = *reinterpret_cast<const uint32_t*>(in + (((int64_t)gz * d.ny + gy) * d.nx + gx) * 2);
+            *reinterpret_cast<uint32_t*>(halo + (size_t)h * 4) = v;
+        }
+    }
 
     // B operands: all weight chunks in registers.
     bf16x8_t bw[NCH];
@@ -90,52 +114,63 @@ __global__ void __launch_bounds__(CONV_NT) k_conv3d(Dims d, const uint16_t* __re
 #pragma unroll
         for (int j = 0; j < 8; ++j) bw[c][j] = bits_to_bf16(raw.e[j].bits);
     }
-    const int row = lane & 15, kgrp = lane >> 4;  // A: voxel row, K group of 8
-    f32x4_t acc[CONV_TILES];
+    __syncthreads();
+
+    const int row = lane & 15, kgrp = lane >> 4;  // A: voxel row (x within the tile), K group of 8
+    f32x4_t acc[CB_TILES];
 #pragma unroll
-    for (int tt = 0; tt < CONV_TILES; ++tt) {
-        acc[tt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-        const int64_t v = vbase + tt * 16 + row;
-        const bool vok = v < d.nvox;
-        const int64_t vv = vok ? v : 0;
-        const int x = (int)(vv % d.nx), y = (int)((vv / d.nx) % d.ny), z = (int)(vv / ((int64_t)d.nx * d.ny));
+    for (int tt = 0; tt < CB_TILES; ++tt) acc[tt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
+    for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+        for (int tt = 0; tt < CB_TILES; ++tt) {
+            const int q = wid + CONV_WAVES * tt;  // tile row in the block
+            const int yl = q % CB_Y, zl = q / CB_Y;
             bf16x8_t a;
             if constexpr (CIN == 16) {
                 const int tap = 2 * c + (kgrp >> 1);
-                const int ci0 = 8 * (kgrp & 1);
-                const int64_t nb = (vok && tap < 27) ? nb_index(d, x, y, z, tap) : -1;
-                Vec16<bf16> raw = *reinterpret_cast<const Vec16<bf16>*>(in + (nb >= 0 ? nb : 0) * 16 + ci0);
+                const int tq = tap < 27 ? tap : 0;
+                const int h = ((zl + tq / 9) * CH_Y + (yl + (tq / 3) % 3)) * CH_X + row + tq % 3;
+                const uint4 raw = *reinterpret_cast<const uint4*>(halo + (size_t)h * 32 + 16 * (kgrp & 1));
+                const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
-                for (int j = 0; j < 8; ++j) a[j] = bits_to_bf16(nb >= 0 ? raw.e[j].bits : (uint16_t)0);
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t v = tap < 27 ? w[j] : 0u;
+                    a[2 * j] = bits_to_bf16((uint16_t)(v & 0xffffu));
+                    a[2 * j + 1] = bits_to_bf16((uint16_t)(v >> 16));
+                }
             } else {
                 // k = 2 tap + channel; lane's 8 values: taps 16 c + 4 kgrp + (0..3), 2 channels each
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int tap = 16 * c + 4 * kgrp + q;
-                    const int64_t nb = (vok && tap < 27) ? nb_index(d, x, y, z, tap) : -1;
-                    const uint32_t w2 = *reinterpret_cast<const uint32_t*>(in + (nb >= 0 ? nb : 0) * 2);
-                    const uint32_t w = nb >= 0 ? w2 : 0u;
-                    a[2 * q] = bits_to_bf16((uint16_t)(w & 0xffffu));
-                    a[2 * q + 1] = bits_to_bf16((uint16_t)(w >> 16));
+                for (int qq = 0; qq < 4; ++qq) {
+                    const int tap = 16 * c + 4 * kgrp + qq;
+                    const int tq = tap < 27 ? tap : 0;
+                    const int h = ((zl + tq / 9) * CH_Y + (yl + (tq / 3) % 3)) * CH_X + row + tq % 3;
+                    const uint32_t w2 = *reinterpret_cast<const uint32_t*>(halo + (size_t)h * 4);
+                    const uint32_t v = tap < 27 ? w2 : 0u;
+                    a[2 * qq] = bits_to_bf16((uint16_t)(v & 0xffffu));
+                    a[2 * qq + 1] = bits_to_bf16((uint16_t)(v >> 16));
                 }
             }
             acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[c], acc[tt], 0, 0, 0);
         }
     }
-    // Results: lane holds D[4 kgrp + i][row] (voxel 4 kgrp + i, channel row).
+
+    // Results: lane holds D[4 kgrp + i][row] (voxel 4 kgrp + i of the tile, channel row).
     float scale = 0.f;
     if constexpr (MODE == OUT_SCALED_F32) scale = (float)(scale_rms2 ? sqrt(*scale_rms2) * scale_mul : scale_mul);
 #pragma unroll
-    for (int tt = 0; tt < CONV_TILES; ++tt) {
-        const int64_t v0 = vbase + tt * 16;
+    for (int tt = 0; tt < CB_TILES; ++tt) {
+        const int q = wid + CONV_WAVES * tt;
+        const int gy = y0 + q % CB_Y, gz = z0 + q / CB_Y;
+        const bool rok = gy < d.ny && gz < d.nz;
+        const int64_t vrow = ((int64_t)gz * d.ny + gy) * d.nx;
         if constexpr (MODE == OUT_SCALED_F32) {
-            if (row == 0) {
+            if (row == 0 && rok) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int64_t v = v0 + 4 * kgrp + i;
-                    if (v < d.nvox) static_cast<float*>(out)[v] = scale * acc[tt][i];
+                    const int gx = x0 + 4 * kgrp + i;
+                    if (gx < d.nx) static_cast<float*>(out)[vrow + gx] = scale * acc[tt][i];
                 }
             }
         } else {
@@ -148,8 +183,9 @@ __global__ void __launch_bounds__(CONV_NT) k_conv3d(Dims d, const uint16_t* __re
             // lanes 0..31 write the tile's 16 voxels x 16 channels as 8-channel (16-byte) pieces.
             if (lane < 32) {
                 const int vi = lane >> 1, c0 = 8 * (lane & 1);
-                const int64_t v = v0 + vi;
-                if (v < d.nvox) {
+                const int gx = x0 + vi;
+                if (rok && gx < d.nx) {
+                    const int64_t v = vrow + gx;
                     Vec16<bf16> o;
                     Vec16<bf16> m;
                     if constexpr (MODE == OUT_MASK_BF16) m = *reinterpret_cast<const Vec16<bf16>*>(mask + v * 16 + c0);
@@ -223,14 +259,16 @@ __global__ void k_swizzle_weights(const float* __restrict__ w, int cin, int cout
 hipError_t launch_conv3d(int nx, int ny, int nz, int cin, int mode, const void* in, const void* wsw, void* out,
                          const void* mask, const double* scale_rms2, double scale_mul, hipStream_t s) {
     Dims d{nx, ny, nz, (int64_t)nx * ny * nz};
-    const int64_t waves = (d.nvox + 16 * CONV_TILES - 1) / (16 * CONV_TILES);
-    const unsigned nb = (unsigned)((waves + CONV_WAVES - 1) / CONV_WAVES);
-    if (nb == 0) return hipSuccess;
+    if (d.nvox == 0) return hipSuccess;
+    const int nbx = (nx + CB_X - 1) / CB_X, nby = (ny + CB_Y - 1) / CB_Y, nbz = (nz + CB_Z - 1) / CB_Z;
+    const int64_t nb = (int64_t)nbx * nby * nbz;
+    if (nb > INT32_MAX) return hipErrorInvalidValue;
     auto in16 = static_cast<const uint16_t*>(in);
     auto w16 = static_cast<const uint16_t*>(wsw);
     auto m16 = static_cast<const uint16_t*>(mask);
 #define PCGMI_CONV(CI, MO) \
-    hipLaunchKernelGGL((k_conv3d<CI, MO>), dim3(nb), dim3(CONV_NT), 0, s, d, in16, w16, out, m16, scale_rms2, scale_mul)
+    hipLaunchKernelGGL((k_conv3d<CI, MO>), dim3((unsigned)nb), dim3(CONV_NT), 0, s, d, nbx, nby, in16, w16, out, m16, \
+                       scale_rms2, scale_mul)
     if (cin == 16) {
         switch (mode) {
             case OUT_RELU_BF16: PCGMI_CONV(16, OUT_RELU_BF16); break;

@@ -78,7 +78,17 @@ __global__ void __launch_bounds__(256) k_wgrad_mfma(int nx, int ny, int nz, cons
     for (int j = 0; j < 7; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     const int nch = (nx + WGM_K - 1) / WGM_K;
     const int nitems = ny * nz * nch;
-    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    // XCD-aware dealing: work-group b runs on XCD b mod 8; with a grid that is
+    // a multiple of 8, each XCD takes a contiguous slab of rows, so the
+    // neighbour rows a work-group stages are mostly in its XCD's L2.
+    int first = blockIdx.x, last = nitems, step = gridDim.x;
+    if (gridDim.x % 8 == 0) {
+        const int xcd = blockIdx.x % 8, per = gridDim.x / 8;
+        first = (int)((int64_t)nitems * xcd / 8) + (int)(blockIdx.x / 8);
+        last = (int)((int64_t)nitems * (xcd + 1) / 8);
+        step = per;
+    }
+    for (int item = first; item < last; item += step) {
         const int ch = item % nch, row = item / nch;
         const int y = row % ny, z = row / ny;
         const int x0 = ch * WGM_K;
@@ -285,10 +295,13 @@ hipError_t launch_make_pair(int64_t n, const double* r, const double* x, const d
 }
 
 // Work-groups of the weight-gradient launch (and partial sets to reduce):
-// one per staged row chunk up to 512 (two per CU).
+// one per staged row chunk up to 512 (two per CU); a multiple of 8 from 64
+// rows on, for the XCD slabs.
 int wgrad_groups(int nx, int ny, int nz) {
     const int64_t items = (int64_t)ny * nz * ((nx + WGM_K - 1) / WGM_K);
-    return (int)(items < 1 ? 1 : (items > 512 ? 512 : items));
+    if (items < 64) return (int)(items < 1 ? 1 : items);
+    const int64_t g = items > 512 ? 512 : items;
+    return (int)(g / 8 * 8);
 }
 
 hipError_t launch_wgrad(int nx, int ny, int nz, int cx, int cy, const void* X, const void* dY, bool dy_f32,

@@ -163,17 +163,24 @@ void free_ctx(pcg_ctx c) {
     delete c;
 }
 
-// Default plan: 64 x 4 threads (a 256 x 4 FP32 footprint: every wavefront
-// streams one contiguous 1 KiB row segment), long z chunks (64 planes) when
-// the x-y plane is small enough that the launch still has one work-group
-// per CU or more, else 16 planes; the scalar shape when nx is not a multiple
-// of the 16-byte vector width. Measured on MI355X at 256^3 and 512^3.
+// Default plan (measured on MI355X with the split reductions): when the x-y
+// plane is small (<= 65536 points, e.g. 256^3) a footprint 128 points wide
+// (FP32 128 x 8, 16-bit 128 x 16, FP64 128 x 4) with 32-plane chunks (8 for
+// 16-bit storage); on
+// larger planes 256 x 4 FP32 / 128 x 16 16-bit / 128 x 4 FP64 footprints
+// with 16-plane chunks; chunks halved while the launch has fewer than 256
+// work-groups; the scalar shape when nx is not a multiple of the 16-byte
+// vector width.
 Plan default_plan(int nx, int ny, int nz, int dt, const pcg_options& o) {
-    Plan p{2, 16};
-    // widest vector shape whose footprint fits in nx (64, 32 or 16 threads wide)
-    if (plan_tx(p, dt) > nx) p.cfg = 1;
-    if (plan_tx(p, dt) > nx) p.cfg = 0;
-    if (nx % dt_width(dt) != 0) p.cfg = 5;
+    const bool small_plane = (int64_t)nx * ny <= 65536;
+    const int w = dt_width(dt);  // 4 FP32, 8 16-bit, 2 FP64
+    Plan p{2, small_plane ? (w == 8 ? 8 : 32) : 16};
+    if (w == 8) p.cfg = 0;                       // 16 x 16 threads: 128 x 16 points
+    else if (w == 4 && small_plane) p.cfg = 1;   // 32 x 8 threads: 128 x 8 points
+    // narrower vector shapes while the footprint is wider than nx
+    if (plan_tx(p, dt) > nx && p.cfg == 2) p.cfg = 1;
+    if (plan_tx(p, dt) > nx && p.cfg == 1) p.cfg = 0;
+    if (nx % w != 0) p.cfg = 5;
     if (o.tile_x > 0 || o.tile_y > 0) {
         for (int c = 0; c < NUM_TILE_CFG; ++c) {
             Plan q{c, 1};
@@ -186,7 +193,7 @@ Plan default_plan(int nx, int ny, int nz, int dt, const pcg_options& o) {
     }
     const int64_t tiles = (int64_t)((nx + plan_tx(p, dt) - 1) / plan_tx(p, dt)) *
                           ((ny + plan_ty(p) - 1) / plan_ty(p));
-    int64_t zc = (int64_t)nx * ny <= 65536 ? 64 : 16;
+    int64_t zc = p.zc;
     // keep at least ~256 work-groups when the grid allows it
     while (zc > 4 && tiles * ((nz + zc - 1) / zc) < 256) zc /= 2;
     p.zc = o.zchunk > 0 ? o.zchunk : (int)zc;

@@ -10,11 +10,15 @@ namespace pcgmi {
 
 // One work-group per (x-y tile, z chunk). NC reduction components are
 // combined over the grid (component c maxed when bit c of MM is set) and
-// handed to fin by the last work-group. A set *done skips the launch's work:
+// handed to fin, either by the last work-group (atomic ticket) or, with
+// split, by a one-work-group finishing kernel launched next: every
+// work-group's agent-scope release fence costs ~40 ns of serialized time on
+// this multi-XCD part (measured), which a kernel boundary replaces. Both ways
+// sum the partials in the same order. A set *done skips the launch's work:
 // captured PCG iterations after convergence cost only the launch.
 template <typename C, class SP, int BX, int BY, int VX, int NC, unsigned MM, bool RED, class L, class O, class F>
 __device__ __forceinline__ void zmarch_body(const Grid3& g, const L& ld, const O& op, const F& fin, Red red,
-                                            const int* done) {
+                                            const int* done, int split) {
     if (done != nullptr && *done != 0) return;
     using Cell = typename SP::Cell;
     using ZT = ZTile<Cell, BX, BY, VX>;
@@ -31,19 +35,51 @@ __device__ __forceinline__ void zmarch_body(const Grid3& g, const L& ld, const O
         double v[NC], tot[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) v[c] = (double)acc[c];
+        if (split) {
+            block_reduce<NC, MM>(v, rscratch);
+            if (threadIdx.x == 0)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) red.partials[NC * blockIdx.x + c] = v[c];
+            return;
+        }
         if (grid_reduce<NC, MM>(v, red.partials, red.ticket, g.nblocks, blockIdx.x, rscratch, tot) &&
             threadIdx.x == 0)
             fin(tot);
     }
 }
 
+// The finishing kernel of the split reduction: one work-group of the z-march
+// kernel's size sums the partials as the last work-group would, then fin.
+template <int NC, unsigned MM, class F>
+__global__ void __launch_bounds__(256) k_zfinish(const double* __restrict__ partials, unsigned nblocks, F fin,
+                                                 const int* done) {
+    if (done != nullptr && *done != 0) return;
+    __shared__ double lds[NC * 16];
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    for (unsigned i = threadIdx.x; i < nblocks; i += blockDim.x)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double t = partials[NC * i + c];
+            if ((MM >> c) & 1u) acc[c] = t > acc[c] ? t : acc[c];
+            else acc[c] += t;
+        }
+    block_reduce<NC, MM>(acc, lds);
+    if (threadIdx.x == 0) fin(acc);
+}
+
+// Work-groups from which a reducing z-march splits off its finishing kernel.
+constexpr unsigned SPLIT_MIN_BLOCKS = 64;
+
 // One __global__ name per kernel family (so profiles tell them apart), all
 // running the same body.
 #define PCGMI_ZKERNEL(NAME)                                                                               \
     template <typename C, class SP, int BX, int BY, int VX, int NC, unsigned MM, bool RED, class L, class O, \
               class F>                                                                                    \
-    __global__ void __launch_bounds__(BX* BY) NAME(Grid3 g, L ld, O op, F fin, Red red, const int* done) { \
-        zmarch_body<C, SP, BX, BY, VX, NC, MM, RED>(g, ld, op, fin, red, done);                           \
+    __global__ void __launch_bounds__(BX* BY) NAME(Grid3 g, L ld, O op, F fin, Red red, const int* done,   \
+                                                   int split) {                                           \
+        zmarch_body<C, SP, BX, BY, VX, NC, MM, RED>(g, ld, op, fin, red, done, split);                    \
     }
 PCGMI_ZKERNEL(k_stencil)
 PCGMI_ZKERNEL(k_pcg_direction)
@@ -61,18 +97,20 @@ hipError_t run_zmarch(const Grid3& g, const L& ld, const O& op, const F& fin, Re
     if (g.nblocks == 0) return hipSuccess;
     if (RED && (red.partials == nullptr || (size_t)NC * g.nblocks > red.cap)) return hipErrorInvalidValue;
     const dim3 grid(g.nblocks), block(BX * BY);
+    const int split = (RED && g.nblocks >= SPLIT_MIN_BLOCKS) ? 1 : 0;
     if constexpr (FAM == ZF_STENCIL)
-        hipLaunchKernelGGL((k_stencil<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+        hipLaunchKernelGGL((k_stencil<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
     else if constexpr (FAM == ZF_DIRECTION)
-        hipLaunchKernelGGL((k_pcg_direction<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+        hipLaunchKernelGGL((k_pcg_direction<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
     else if constexpr (FAM == ZF_UPDATE)
-        hipLaunchKernelGGL((k_pcg_update<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+        hipLaunchKernelGGL((k_pcg_update<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
     else if constexpr (FAM == ZF_RESIDUAL64)
-        hipLaunchKernelGGL((k_residual64<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+        hipLaunchKernelGGL((k_residual64<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
     else if constexpr (FAM == ZF_START_X0)
-        hipLaunchKernelGGL((k_start_x0<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+        hipLaunchKernelGGL((k_start_x0<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
     else
-        hipLaunchKernelGGL((k_zgeneric<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done);
+        hipLaunchKernelGGL((k_zgeneric<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
+    if (split) hipLaunchKernelGGL((k_zfinish<NC, MM, F>), dim3(1), block, 0, s, red.partials, g.nblocks, fin, done);
     return hipGetLastError();
 }
 
