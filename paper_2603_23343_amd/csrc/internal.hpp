@@ -21,7 +21,7 @@ inline int dt_width(int dt) { return (int)(16 / dt_size(dt)); }  // elements per
 // or 1 for the scalar shape used when nx is not a multiple of that width).
 struct TileCfg {
     int bx, by;
-    bool vec;
+    bool vec;  // one 16-byte vector per thread and plane (else one element)
 };
 constexpr int NUM_TILE_CFG = 6;
 constexpr TileCfg TILE_CFGS[NUM_TILE_CFG] = {

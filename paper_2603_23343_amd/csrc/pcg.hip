@@ -80,7 +80,7 @@ hipError_t launch_pcg_start_x0(int dt, int xdt, const Plan& pres, const Geometry
         using T = decltype(tag);
         return dispatch_dt(xdt, [&](auto xtag) {
             using X = decltype(xtag);
-            return dispatch_cfg<2>(cfg, [&]<int BX, int BY, int VX>() {
+            return dispatch_cfg_f64(cfg, [&]<int BX, int BY, int VX>() {
                 OpInitResidual<T, VX> op{static_cast<const T*>(b), static_cast<T*>(r),
                                          static_cast<const T*>(od.dinv), st, 0.0};
                 if (od.kc) {

@@ -25,7 +25,7 @@ hipError_t launch_cast_scaled(int dt, const Plan& pres, const Geometry& gres, Op
     const int cfg = TILE_CFGS[pres.cfg].vec ? 2 : 5;
     return dispatch_dt(dt, [&](auto tag) {
         using T = decltype(tag);
-        return dispatch_cfg<2>(cfg, [&]<int BX, int BY, int VX>() {
+        return dispatch_cfg_f64(cfg, [&]<int BX, int BY, int VX>() {
             OpCastScaled<T, VX> op{b, static_cast<T*>(rhat), scale};
             if (od.kc) {
                 LoadWidenUK<double, double> ld{x, od.kc};

@@ -38,7 +38,7 @@ hipError_t launch_residual64(int bdt, int xdt, const Plan& p, const Geometry& g,
         using B = decltype(btag);
         return dispatch_dt(xdt, [&](auto xtag) {
             using X = decltype(xtag);
-            return dispatch_cfg<2>(cfg, [&]<int BX, int BY, int VX>() {
+            return dispatch_cfg_f64(cfg, [&]<int BX, int BY, int VX>() {
                 OpResidual64<B, VX> op{static_cast<const B*>(b)};
                 if (od.kc) {
                     LoadWidenUK<X, double> ld{static_cast<const X*>(x), od.kc};

@@ -128,6 +128,16 @@ template <int W, class F> hipError_t dispatch_cfg(int cfg, F&& f) {
     }
 }
 
+// The FP64 residual and start kernels compile only the 64 x 4 shapes
+// (cfg 2: two doubles per thread, cfg 5: one).
+template <class F> hipError_t dispatch_cfg_f64(int cfg, F&& f) {
+    switch (cfg) {
+        case 2: return f.template operator()<64, 4, 2>();
+        case 5: return f.template operator()<64, 4, 1>();
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // Storage types with variable-coefficient kernels compiled.
 template <typename T> constexpr bool VAR_TYPE = std::is_same_v<T, float> || std::is_same_v<T, double>;
 
