@@ -154,7 +154,7 @@ def cpu_baseline(b64_host, n, gpu_iters, budget_s=15.0):
                           f"first {its} iterations timed ({tm:.1f} s), scaled to the GPU's {gpu_iters} iterations"))}
 
 
-def bench_batched(P, torch, reps):
+def bench_batched(P, torch, reps, oracle_budget_s=0.0):
     """The 64-problem batch: graph replays timed with torch events on the
     stream the batch was created on (the current stream)."""
     import synthetic
@@ -207,7 +207,35 @@ def bench_batched(P, torch, reps):
            "iters_equal_sequential": int(sum(1 for a, c in zip(r["iters"], seq_iters) if a == c)),
            "work_groups": bt.grid, "create_and_tune_s": round(t_create, 3)}
     bt.close()
+    if oracle_budget_s > 0:
+        out["oracle"] = batched_oracle(sizes, r["iters"], oracle_budget_s)
     return out
+
+
+def batched_oracle(sizes, gpu_iters, budget_s):
+    """The FP64 oracle's Jacobi-PCG on the batch's problems, smallest first,
+    until the budget is spent; scaled to all of them by point-iterations."""
+    import oracle
+    import synthetic
+
+    order = sorted(range(len(sizes)), key=lambda i: sizes[i])
+    t_done, work_done, solved = 0.0, 0.0, 0
+    for i in order:
+        m = sizes[i]
+        b64 = synthetic.uniform_f32(synthetic.SEED_C4_B_BASE + i, m ** 3).astype("float64")
+        t0 = time.perf_counter()
+        ref = oracle.pcg((m, m, m), b64, rtol=1e-6, maxit=5000)
+        t_done += time.perf_counter() - t0
+        work_done += m ** 3 * ref["iters"]
+        solved += 1
+        if t_done > budget_s:
+            break
+    total = sum(m ** 3 * it for m, it in zip(sizes, gpu_iters))
+    est = t_done * total / max(work_done, 1.0)
+    return {"value": round(est, 3), "unit": "s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": (f"FP64 oracle Jacobi-PCG on the {solved} smallest of the {len(sizes)} problems "
+                       f"({t_done:.1f} s), scaled to all by point-iterations"),
+            "solves_per_s": round(len(sizes) / est, 3)}
 
 
 BF16_PEAK_TFLOPS = 2500.0
@@ -215,7 +243,7 @@ BF16_PEAK_TFLOPS = 2500.0
 CNN_FLOP_PER_VOXEL = 2 * 27 * (2 * 16 + 16 * 16 + 16 * 16 + 16)
 
 
-def bench_learned(P, torch, n_work, rounds, n_kernel=128):
+def bench_learned(P, torch, n_work, rounds, n_kernel=128, oracle_cpu=False):
     import numpy as np
 
     import synthetic
@@ -275,7 +303,17 @@ def bench_learned(P, torch, n_work, rounds, n_kernel=128):
     jac = P.pcg_solve(ctx, b, x, 1e-6, 20000)
     P.pcg_solve_flexible(ctx, net, gd, b, x, 1e-6, 20000, raise_on_error=False)
     fcg = P.pcg_solve_flexible(ctx, net, gd, b, x, 1e-6, 20000, raise_on_error=False)
-    out["workflow"] = {"grid": n, "rounds": rounds, "pairs": log["pairs"][-1],
+    oracle_out = None
+    if oracle_cpu:
+        import oracle
+
+        t0 = time.perf_counter()
+        ref = oracle.pcg((n, n, n), b.double().cpu().numpy(), rtol=1e-6, maxit=20000,
+                         kcell=kd.double().cpu().numpy())
+        oracle_out = {"value": round(time.perf_counter() - t0, 3), "unit": "s", "cores": oracle.threads(),
+                      "kind": "oracle", "iters": ref["iters"],
+                      "sample": f"FP64 oracle Jacobi-PCG on the same {n}^3 variable-coefficient system, full solve"}
+    out["workflow"] = {"grid": n, "rounds": rounds, "pairs": log["pairs"][-1], "jacobi_pcg_oracle": oracle_out,
                        "final_loss": round(log["losses"][-1], 4), "pair_gen_s": round(log["gen_s"], 3),
                        "onpolicy_s": round(log["onpolicy_s"], 3), "train_s": round(log["train_s"], 3),
                        "jacobi_pcg": {"iters": jac["iters"], "ms": round(jac["seconds"] * 1e3, 3),
@@ -385,12 +423,12 @@ def main():
 
     batched = None
     if not args.no_batched:
-        batched = bench_batched(P, torch, args.batched_reps)
+        batched = bench_batched(P, torch, args.batched_reps, 0.0 if args.no_cpu_baseline else 3.0)
         print(f"# batched: {batched}", file=sys.stderr, flush=True)
 
     learned = None
     if not args.no_learned:
-        learned = bench_learned(P, torch, args.learned_n, args.learned_rounds)
+        learned = bench_learned(P, torch, args.learned_n, args.learned_rounds, oracle_cpu=not args.no_cpu_baseline)
         print(f"# learned: {learned}", file=sys.stderr, flush=True)
 
     kern = None
