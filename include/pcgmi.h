@@ -267,7 +267,9 @@ pcg_status pcg_make_pairs(pcg_ctx ctx, int npairs, const double *r_snaps, const 
  *
  * Every work-group of the launch belongs to one problem; a problem's
  * work-groups form a group on one XCD that meets at group barriers twice per
- * iteration. The grid is the device's resident capacity (occupancy query), so
+ * iteration. The kernel reads each work-group's XCD from the hardware and,
+ * when a group is really on one XCD, synchronises it through that XCD's L2
+ * without agent-scope fences. The grid is the device's resident capacity (occupancy query), so
  * all groups run concurrently. Each problem is laid out contiguously, C-order
  * [nz][ny][nx], at its offset in two caller-owned DEVICE arenas: b (FP32) and
  * x (FP64), each of `total` elements (pcg_batch_layout).
@@ -301,8 +303,11 @@ pcg_status pcg_batch_destroy(pcg_batch batch);
 
 /* Host outputs, each optional (NULL): offsets int64[nprob] (element offset of
  * each problem in the arenas, a multiple of 64), total (arena length),
- * plans int[nprob][4] {cfg, zc, work-groups, tiles}, grid int[2]
- * {work-groups of the launch, problems whose shape was measured}. */
+ * plans int[nprob][4] {cfg, zc, work-groups, tiles}, grid int[3]
+ * {work-groups of the launch, problems whose shape was measured, problems
+ * whose group barriers ran in the XCD-local form in the last solve (all of
+ * them when every work-group ran on the XCD the layout assigns it; otherwise
+ * those groups use agent-scope fences)}. */
 pcg_status pcg_batch_layout(pcg_batch batch, int64_t *offsets, int64_t *total, int *plans, int *grid);
 
 /* Solve all problems from x0 = 0 with Jacobi-PCG until ||r_i|| <= rtol ||b_i||

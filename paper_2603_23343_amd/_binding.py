@@ -409,7 +409,7 @@ class Batch:
         offs = (ctypes.c_int64 * n)()
         total = ctypes.c_int64()
         plans = (ctypes.c_int * (4 * n))()
-        grid = (ctypes.c_int * 2)()
+        grid = (ctypes.c_int * 3)()
         _check(lib.pcg_batch_layout(handle, offs, ctypes.byref(total), plans, grid))
         self.offsets = list(offs)
         self.total = int(total.value)
@@ -469,5 +469,7 @@ def pcg_batch_solve(batch: Batch, b, x, rtol=1e-6, maxit=500, use_graph=True, ra
                              lat, rst, ctypes.byref(secs))
     if raise_on_error and st != PCG_OK:
         _check(st)
+    grid = (ctypes.c_int * 3)()
+    _check(lib.pcg_batch_layout(batch.handle, None, None, None, grid))
     return {"status": st, "iters": list(its), "relres": list(rel), "latency_s": list(lat), "restarts": list(rst),
-            "seconds": secs.value}
+            "seconds": secs.value, "xcd_local": int(grid[2])}

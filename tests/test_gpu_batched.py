@@ -156,7 +156,10 @@ def test_batch_64_uneven(P, orc):
     res = P.pcg_batch_solve(bt, b, x, rtol=1e-6, maxit=5000)
     xh = x.cpu().numpy()
     print("64 problems", sum(n ** 3 for n in sizes), "points", res["seconds"], "s; max latency",
-          max(res["latency_s"]), "plans", bt.plans, flush=True)
+          max(res["latency_s"]), "XCD-local groups", res["xcd_local"], "plans", bt.plans, flush=True)
+    # on MI355X every work-group runs on the XCD the layout assigns it, so all
+    # groups take the XCD-local barriers (the results below check that form)
+    assert res["xcd_local"] == len(sizes)
     for i, n in enumerate(sizes):
         xi = xh[bt.offsets[i]:bt.offsets[i] + n ** 3]
         tr = orc.true_relres((n, n, n), bh[i], xi)
