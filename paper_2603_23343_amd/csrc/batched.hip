@@ -435,16 +435,19 @@ void set_plan(BatchProb& p, int cfg) {
 // XCDs by longest-processing-time-first on their HBM traffic (points x
 // estimated iterations), then each XCD's resident work-groups are dealt out
 // greedily to the problem with the longest estimated solve time, which
-// balances finish times. The estimate is a model, used only for this split:
+// balances finish times. The estimate is a model, used only for this split,
+// with constants fitted (least squares) to the measured per-problem times of
+// the 64-problem batch on MI355X:
 //   iterations ~ 2.8 max(nx, ny, nz)  (Jacobi-PCG iterations grow with the
 //                                      square root of the condition number)
-//   one plane step of a work-group ~ 0.6 us + 2.5 ns per point of its tile
+//   one plane step of a work-group ~ 0.81 us + 1.06 ns per point of its tile
 //   a phase = (busiest work-group's tiles) x (zc + 3 start-up planes) steps
-//   an iteration = 2 phases + 2 group barriers of ~3 us.
+//   an iteration = 2 phases + ~45 us of latency (2 group barriers, the
+//   partial sums, pipeline start-up), whatever the group size.
 namespace {
 
 struct CostModel {
-    double step0 = 0.6, step_pt = 0.0025, barrier = 3.0;
+    double step0 = 0.81, step_pt = 0.00106, barrier = 22.7;
 };
 
 int model_cfg(const BatchProb& p) { return p.nx > 128 ? 2 : (p.nx > 64 ? 1 : 0); }
