@@ -18,7 +18,8 @@ Also reported on the same JSON line:
                    TFLOP/s against the dense BF16 peak), and the whole
                    workflow (FP64 pair generation, on-policy rounds, A-norm
                    training, flexible CG on a held-out right-hand side)
-                   against Jacobi-PCG at --learned-n;
+                   against Jacobi-PCG at each grid of --learned-n (64 and 128
+                   by default);
   kernels_512   -- standalone stencil / axpy / dot at 512^3 (FP32 and BF16),
                    achieved GB/s of algorithmic bytes;
   batched       -- 64 uneven problems (edges log-uniform in [16, 128], seed 5;
@@ -243,7 +244,7 @@ BF16_PEAK_TFLOPS = 2500.0
 CNN_FLOP_PER_VOXEL = 2 * 27 * (2 * 16 + 16 * 16 + 16 * 16 + 16)
 
 
-def bench_learned(P, torch, n_work, rounds, n_kernel=128, oracle_cpu=False):
+def bench_learned(P, torch, n_works, rounds, n_kernel=128, oracle_cpu=False):
     import numpy as np
 
     import synthetic
@@ -286,8 +287,19 @@ def bench_learned(P, torch, n_work, rounds, n_kernel=128, oracle_cpu=False):
                       "train_ms_per_sample": round(train_ms, 3),
                       "train_TFLOP/s": round(3 * fl / (train_ms * 1e-3) / 1e12, 1)}
     net.close()
-    # workflow at n_work^3
-    n = n_work
+    out["workflow"] = [learned_workflow(P, torch, n, rounds, oracle_cpu) for n in n_works]
+    return out
+
+
+def learned_workflow(P, torch, n, rounds, oracle_cpu):
+    """On-policy training of the correction network on one n^3 variable-coefficient
+    problem, then Jacobi-PCG against flexible CG with the learned preconditioner on a
+    held-out right-hand side (both judged by the FP64 true residual)."""
+    import numpy as np
+
+    import synthetic
+    from paper_2603_23343_amd import learned as L
+
     N = n ** 3
     kd = torch.from_numpy(synthetic.coefficient_field(n)).cuda()
     gd = torch.from_numpy(synthetic.gaussian_random_field(n).astype(np.float32)).cuda()
@@ -313,15 +325,15 @@ def bench_learned(P, torch, n_work, rounds, n_kernel=128, oracle_cpu=False):
         oracle_out = {"value": round(time.perf_counter() - t0, 3), "unit": "s", "cores": oracle.threads(),
                       "kind": "oracle", "iters": ref["iters"],
                       "sample": f"FP64 oracle Jacobi-PCG on the same {n}^3 variable-coefficient system, full solve"}
-    out["workflow"] = {"grid": n, "rounds": rounds, "pairs": log["pairs"][-1], "jacobi_pcg_oracle": oracle_out,
-                       "final_loss": round(log["losses"][-1], 4), "pair_gen_s": round(log["gen_s"], 3),
-                       "onpolicy_s": round(log["onpolicy_s"], 3), "train_s": round(log["train_s"], 3),
-                       "jacobi_pcg": {"iters": jac["iters"], "ms": round(jac["seconds"] * 1e3, 3),
-                                      "true_relres": jac["rel_res_true_fp64"]},
-                       "flexible_cg_learned": {"iters": fcg["iters"], "ms": round(fcg["seconds"] * 1e3, 3),
-                                               "fallback_used": fcg["fallback_used"],
-                                               "true_relres": fcg["rel_res_true_fp64"]},
-                       "iteration_ratio": round(fcg["iters"] / max(jac["iters"], 1), 3)}
+    out = {"grid": n, "rounds": rounds, "pairs": log["pairs"][-1], "jacobi_pcg_oracle": oracle_out,
+           "final_loss": round(log["losses"][-1], 4), "pair_gen_s": round(log["gen_s"], 3),
+           "onpolicy_s": round(log["onpolicy_s"], 3), "train_s": round(log["train_s"], 3),
+           "jacobi_pcg": {"iters": jac["iters"], "ms": round(jac["seconds"] * 1e3, 3),
+                          "true_relres": jac["rel_res_true_fp64"]},
+           "flexible_cg_learned": {"iters": fcg["iters"], "ms": round(fcg["seconds"] * 1e3, 3),
+                                   "fallback_used": fcg["fallback_used"],
+                                   "true_relres": fcg["rel_res_true_fp64"]},
+           "iteration_ratio": round(fcg["iters"] / max(jac["iters"], 1), 3)}
     net.close()
     ctx.close()
     return out
@@ -340,7 +352,8 @@ def main():
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--learned-n", type=int, default=64)
+    ap.add_argument("--learned-n", default="64,128",
+                    help="comma-separated grid sizes of the learned-preconditioner workflow")
     ap.add_argument("--learned-rounds", type=int, default=12)
     ap.add_argument("--batched-reps", type=int, default=10)
     ap.add_argument("--maxit", type=int, default=5000)
@@ -428,7 +441,8 @@ def main():
 
     learned = None
     if not args.no_learned:
-        learned = bench_learned(P, torch, args.learned_n, args.learned_rounds, oracle_cpu=not args.no_cpu_baseline)
+        sizes = [int(v) for v in args.learned_n.split(",")]
+        learned = bench_learned(P, torch, sizes, args.learned_rounds, oracle_cpu=not args.no_cpu_baseline)
         print(f"# learned: {learned}", file=sys.stderr, flush=True)
 
     kern = None

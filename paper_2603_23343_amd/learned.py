@@ -74,8 +74,10 @@ def generate_pairs(n: int, kcell: torch.Tensor, rhs_seeds, snaps_per_rhs: int = 
 
 def train(net, n: int, pairs: torch.Tensor, g: torch.Tensor, epochs: int, batch: int, lr: float,
           seed: int = 0, lr_decay: float = 1.0):
-    """Adam on mean relative-MSE over contiguous batches (visited in a random
-    order each epoch). Returns (per-epoch mean losses, seconds)."""
+    """Adam over contiguous batches of pairs (visited in a random order each
+    epoch) on the network's loss: the A-norm loss once cnn_set_operator has
+    given it the operator, the relative MSE otherwise. Returns (per-epoch
+    mean losses, seconds)."""
     N = n ** 3
     npairs = pairs.numel() // (2 * N)
     nb = npairs // batch
