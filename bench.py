@@ -409,7 +409,7 @@ def main():
     traffic = load_traffic("pcg_update")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "pcg_update (k_zmarch<..., OpUpdate, FinBeta>)",
+                "kernel": "pcg_update (k_pcg_update<..., OpUpdate, FinAlpha>: finishes p.Ap, then the update)",
                 "bytes_per_launch": BYTES_UPDATE * N, "avg_us": round(k2_us, 2),
                 "direction_kernel_avg_us": round(k1_us, 2),
                 "direction_kernel_GB/s": round(BYTES_DIRECTION * N / (k1_us * 1e-6) / 1e9, 1),

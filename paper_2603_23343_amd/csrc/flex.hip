@@ -233,11 +233,11 @@ hipError_t launch_flex_direction(const Plan& p, const Geometry& g, OpDesc od, co
         OpFlexDir<T, VX> op{pnew, q, r};
         if (od.kc) {
             LoadFlexDirVar<T> ld{z, pold, od.kc, st, C(0)};
-            return run_zmarch<ZF_DIRECTION, C, StencilVar<C>, BX, BY, VX, 2, 0u, true>(g, ld, op, FinFlexAlpha{st},
+            return run_zmarch<ZF_FLEX_DIRECTION, C, StencilVar<C>, BX, BY, VX, 2, 0u, true>(g, ld, op, FinFlexAlpha{st},
                                                                                       red, &st->done, s);
         }
         LoadFlexDir<T> ld{z, pold, st, C(0)};
-        return run_zmarch<ZF_DIRECTION, C, StencilConst<C>, BX, BY, VX, 2, 0u, true>(g, ld, op, FinFlexAlpha{st},
+        return run_zmarch<ZF_FLEX_DIRECTION, C, StencilConst<C>, BX, BY, VX, 2, 0u, true>(g, ld, op, FinFlexAlpha{st},
                                                                                     red, &st->done, s);
     });
 }

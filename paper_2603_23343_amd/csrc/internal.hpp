@@ -67,13 +67,31 @@ hipError_t launch_stencil(int dt, const Plan& p, const Geometry& g, OpDesc od, c
 // dinv = 1 / diag(A_k) for cell coefficients kc.
 hipError_t launch_var_dinv(int dt, const Plan& p, const Geometry& g, const float* kc, void* dinv, hipStream_t s);
 
-// Iteration kernel 1: p_new = D^-1 r + beta p_old (rounded to storage), p.Ap -> alpha.
+// Links of a chain of PCG iteration kernels: each kernel finishes the
+// previous kernel's reduction (pin, nin partials per component) on a copy of
+// the solve state read from sin, stores the new state in sout (work-group 0)
+// and leaves its own partials in pout. pin == null: sin is current.
+struct Chain {
+    const double* pin;
+    unsigned nin;
+    const SolveState* sin;
+    SolveState* sout;
+    double* hist;  // relative residual per iteration (maxit + 1 entries) or null
+    double* pout;
+};
+
+// Iteration kernel 1: finishes the previous update's r.r (and r.z) into beta,
+// the iteration count and the convergence test; then p_new = D^-1 r + beta
+// p_old (rounded to storage) and partials of p.Ap.
 hipError_t launch_pcg_direction(int dt, const Plan& p, const Geometry& g, OpDesc od, const void* r,
-                                const void* pold, void* pnew, SolveState* st, Red red, hipStream_t s);
-// Iteration kernel 2: q = A p, x += alpha p, r -= alpha q, r.r -> convergence, beta.
-// x (the accumulator) is of type xdt: FP64, FP32 or the storage type.
+                                const void* pold, void* pnew, const Chain& ch, hipStream_t s);
+// Iteration kernel 2: finishes p.Ap into alpha; then q = A p, x += alpha p,
+// r -= alpha q and partials of r.r (and r.z). x (the accumulator) is of type
+// xdt: FP64, FP32 or the storage type.
 hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, OpDesc od, const void* pdir, void* x,
-                             int xdt, void* r, SolveState* st, double* hist, Red red, hipStream_t s);
+                             int xdt, void* r, const Chain& ch, hipStream_t s);
+// Finishes the last update's partials of a chain (beta, count, convergence).
+hipError_t launch_pcg_close(bool var, const Chain& ch, hipStream_t s);
 // r = stored(b - A x0) computed in FP64 (x0 of type xdt), totals {r.r, b.b}
 // -> solve start. Uses the FP64 residual shape (pres, gres).
 hipError_t launch_pcg_start_x0(int dt, int xdt, const Plan& pres, const Geometry& gres, OpDesc od, const void* b,

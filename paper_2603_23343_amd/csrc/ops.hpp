@@ -7,9 +7,10 @@
 
 namespace pcgmi {
 
-// Device-resident scalars of one solve. Written only by the last work-group
-// of a kernel (or by the init kernel) and read by the next kernel, so kernel
-// boundaries order every access.
+// Device-resident scalars of one solve. Written by one work-group of a
+// kernel (the last to finish a grid reduction, work-group 0 of a chained PCG
+// kernel into the other of the two state buffers, or the init kernel) and
+// read by later kernels, so kernel boundaries order every access.
 struct SolveState {
     double rho;    // r.z of the current residual
     double alpha;  // rho / (p.Ap) of the current iteration

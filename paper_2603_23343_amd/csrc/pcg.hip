@@ -2,14 +2,18 @@
 // Sec. VII composes PCG from the stencil, the dot reduction and element-wise
 // updates; here they are fused so each iteration makes two passes over HBM):
 //
-//   kernel 1 (direction): p = D^-1 r + beta p_old, computed on the fly for the
-//            tile and its halo; stores p; sigma = p.Ap; the last work-group
-//            forms alpha = rho / sigma (or flags a breakdown).
-//   kernel 2 (update):    q = A p recomputed from p (cheaper than storing and
-//            re-reading q); x += alpha p; r = r - alpha q; rr = r.r (and
-//            r.z = sum dinv r^2 for a variable Jacobi scale); the last
-//            work-group counts the iteration, tests ||r|| <= rtol ||b|| and
-//            forms beta = rho_new / rho.
+//   kernel 1 (direction): finishes the previous update's reduction (counts
+//            the iteration, tests ||r|| <= rtol ||b||, beta = rho_new / rho);
+//            p = D^-1 r + beta p_old, computed on the fly for the tile and its
+//            halo; stores p; partials of sigma = p.Ap.
+//   kernel 2 (update):    finishes sigma (alpha = rho / sigma, or a
+//            breakdown); q = A p recomputed from p (cheaper than storing and
+//            re-reading q); x += alpha p; r = r - alpha q; partials of r.r
+//            (and r.z = sum dinv r^2 for a variable Jacobi scale).
+//
+// Each kernel finishes the reduction its predecessor left (chained
+// reductions: no finishing kernel between them); a run of iterations ends
+// with a one-wavefront closing kernel for the last update's partials.
 //
 // p ping-pongs between two buffers: kernel 1 reads halo points of p_old that
 // neighbouring work-groups are overwriting in the same launch otherwise.
@@ -19,8 +23,24 @@
 
 namespace pcgmi {
 
+namespace {
+
+// Launch of one chained iteration kernel (NC own partials, NCP consumed).
+template <int FAM, typename C, class SP, int BX, int BY, int VX, int NC, int NCP, class L, class O, class FP>
+hipError_t run_chain(const Geometry& g, const L& ld, const O& op, const FP& fp, const Chain& ch, hipStream_t s) {
+    if (g.nblocks == 0) return hipSuccess;
+    const dim3 grid(g.nblocks), block(BX * BY);
+    if constexpr (FAM == 0)
+        hipLaunchKernelGGL((k_pcg_direction<C, SP, BX, BY, VX, NC, NCP, L, O, FP>), grid, block, 0, s, g, ld, op, fp, ch);
+    else
+        hipLaunchKernelGGL((k_pcg_update<C, SP, BX, BY, VX, NC, NCP, L, O, FP>), grid, block, 0, s, g, ld, op, fp, ch);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_pcg_direction(int dt, const Plan& p, const Geometry& g, OpDesc od, const void* r,
-                                const void* pold, void* pnew, SolveState* st, Red red, hipStream_t s) {
+                                const void* pold, void* pnew, const Chain& ch, hipStream_t s) {
     return dispatch_dt(dt, [&](auto tag) {
         using T = decltype(tag);
         using C = typename Traits<T>::C;
@@ -29,21 +49,21 @@ hipError_t launch_pcg_direction(int dt, const Plan& p, const Geometry& g, OpDesc
             if (od.kc) {
                 if constexpr (VAR_TYPE<T>) {
                     LoadDirectionVar<T> ld{static_cast<const T*>(r), static_cast<const T*>(pold),
-                                           static_cast<const T*>(od.dinv), od.kc, st, C(0)};
-                    return run_zmarch<ZF_DIRECTION, C, StencilVar<C>, BX, BY, VX, 1, 0u, true>(
-                        g, ld, op, FinAlpha{st}, red, &st->done, s);
+                                           static_cast<const T*>(od.dinv), od.kc, nullptr, C(0)};
+                    return run_chain<0, C, StencilVar<C>, BX, BY, VX, 1, 2>(g, ld, op, FinBeta{nullptr, nullptr, true},
+                                                                           ch, s);
                 }
                 return hipErrorInvalidValue;
             }
-            LoadDirection<T> ld{static_cast<const T*>(r), static_cast<const T*>(pold), st, C(0), C(0)};
-            return run_zmarch<ZF_DIRECTION, C, StencilConst<C>, BX, BY, VX, 1, 0u, true>(g, ld, op, FinAlpha{st},
-                                                                                         red, &st->done, s);
+            LoadDirection<T> ld{static_cast<const T*>(r), static_cast<const T*>(pold), nullptr, C(0), C(0)};
+            return run_chain<0, C, StencilConst<C>, BX, BY, VX, 1, 1>(g, ld, op, FinBeta{nullptr, nullptr, false}, ch,
+                                                                     s);
         });
     });
 }
 
 hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, OpDesc od, const void* pdir, void* x,
-                             int xdt, void* r, SolveState* st, double* hist, Red red, hipStream_t s) {
+                             int xdt, void* r, const Chain& ch, hipStream_t s) {
     return dispatch_dt(dt, [&](auto tag) {
         using T = decltype(tag);
         using C = typename Traits<T>::C;
@@ -53,17 +73,15 @@ hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, OpDesc od
                 if (od.kc) {
                     if constexpr (VAR_TYPE<T>) {
                         LoadUK<T> ld{static_cast<const T*>(pdir), od.kc};
-                        OpUpdate<T, X, VX, true> op{static_cast<X*>(x), static_cast<T*>(r), st,
+                        OpUpdate<T, X, VX, true> op{static_cast<X*>(x), static_cast<T*>(r), nullptr,
                                                     static_cast<const T*>(od.dinv), C(0), 0.0};
-                        return run_zmarch<ZF_UPDATE, C, StencilVar<C>, BX, BY, VX, 2, 0u, true>(
-                            g, ld, op, FinBeta{st, hist, true}, red, &st->done, s);
+                        return run_chain<1, C, StencilVar<C>, BX, BY, VX, 2, 1>(g, ld, op, FinAlpha{nullptr}, ch, s);
                     }
                     return hipErrorInvalidValue;
                 }
                 LoadField<T> ld{static_cast<const T*>(pdir)};
-                OpUpdate<T, X, VX> op{static_cast<X*>(x), static_cast<T*>(r), st, nullptr, C(0), 0.0};
-                return run_zmarch<ZF_UPDATE, C, StencilConst<C>, BX, BY, VX, 1, 0u, true>(
-                    g, ld, op, FinBeta{st, hist, false}, red, &st->done, s);
+                OpUpdate<T, X, VX> op{static_cast<X*>(x), static_cast<T*>(r), nullptr, nullptr, C(0), 0.0};
+                return run_chain<1, C, StencilConst<C>, BX, BY, VX, 1, 1>(g, ld, op, FinAlpha{nullptr}, ch, s);
             };
             if (xdt == DT_F64) return go(double{});
             if (xdt == DT_F32) return go(float{});
@@ -71,6 +89,12 @@ hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, OpDesc od
             return hipErrorInvalidValue;
         });
     });
+}
+
+hipError_t launch_pcg_close(bool var, const Chain& ch, hipStream_t s) {
+    if (var) hipLaunchKernelGGL((k_pcg_close<2, FinBeta>), dim3(1), dim3(64), 0, s, FinBeta{nullptr, nullptr, true}, ch);
+    else hipLaunchKernelGGL((k_pcg_close<1, FinBeta>), dim3(1), dim3(64), 0, s, FinBeta{nullptr, nullptr, false}, ch);
+    return hipGetLastError();
 }
 
 hipError_t launch_pcg_start_x0(int dt, int xdt, const Plan& pres, const Geometry& gres, OpDesc od, const void* b,

@@ -215,22 +215,33 @@ pcg_status ensure_hist(pcg_ctx c, int maxit) {
 }
 
 // Enqueue iterations [first, first + count) on stream s. Iteration i reads
-// the direction buffer p[(i - 1) & 1] and writes p[i & 1].
+// the direction buffer p[(i - 1) & 1] and writes p[i & 1]. The kernels chain
+// their reductions: the state the host reads (st[0]) is current before the
+// first direction kernel and after the closing kernel; in between, each
+// update kernel writes st[1] from st[0] and each later direction kernel st[0]
+// from st[1]. Direction partials go to the first half of the partials
+// buffer, update partials (two components at most) to the second.
 hipError_t enqueue_iters(pcg_ctx c, int first, int count, hipStream_t s, hipEvent_t* evs) {
+    if (count <= 0) return hipSuccess;
+    SolveState* s0 = c->st;
+    SolveState* s1 = c->st + 1;
+    double* pdir = c->partials;
+    double* pupd = c->partials + c->partials_cap / 2;
+    const unsigned nb = c->geo.nblocks;
     for (int i = first; i < first + count; ++i) {
         void* pold = c->p[(i - 1) & 1];
         void* pnew = c->p[i & 1];
         if (evs) (void)hipEventRecord(evs[3 * (i - first)], s);
-        hipError_t e =
-            launch_pcg_direction(c->dt, c->plan, c->geo, op_of(c), c->r, pold, pnew, c->st, red_of(c), s);
+        const Chain dch = i == first ? Chain{nullptr, nb, s0, s0, c->hist, pdir} : Chain{pupd, nb, s1, s0, c->hist, pdir};
+        hipError_t e = launch_pcg_direction(c->dt, c->plan, c->geo, op_of(c), c->r, pold, pnew, dch, s);
         if (e != hipSuccess) return e;
         if (evs) (void)hipEventRecord(evs[3 * (i - first) + 1], s);
-        e = launch_pcg_update(c->dt, c->plan, c->geo, op_of(c), pnew, c->xacc, c->opt.x_accum, c->r, c->st,
-                              c->hist, red_of(c), s);
+        const Chain uch{pdir, nb, s0, s1, c->hist, pupd};
+        e = launch_pcg_update(c->dt, c->plan, c->geo, op_of(c), pnew, c->xacc, c->opt.x_accum, c->r, uch, s);
         if (e != hipSuccess) return e;
         if (evs) (void)hipEventRecord(evs[3 * (i - first) + 2], s);
     }
-    return hipSuccess;
+    return launch_pcg_close(op_of(c).kc != nullptr, Chain{pupd, nb, s1, s0, c->hist, nullptr}, s);
 }
 
 pcg_status ensure_chunk(pcg_ctx c) {
@@ -444,7 +455,7 @@ pcg_status pcg_create(pcg_ctx* out, int nx, int ny, int nz, pcg_dtype storage, v
     if (e == hipSuccess) e = hipMalloc(&c->xacc, xs * n);
     if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * c->partials_cap);
     if (e == hipSuccess) e = hipMalloc(&c->ticket, 256);
-    if (e == hipSuccess) e = hipMalloc(&c->st, sizeof(SolveState));
+    if (e == hipSuccess) e = hipMalloc(&c->st, 2 * sizeof(SolveState));  // current state and the chain's second
     if (e == hipSuccess) e = hipMalloc(&c->res2, 2 * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc(&c->hst, 2 * sizeof(SolveState), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(&c->hres, 2 * sizeof(double), hipHostMallocDefault);

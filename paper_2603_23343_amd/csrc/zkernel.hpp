@@ -82,13 +82,12 @@ constexpr unsigned SPLIT_MIN_BLOCKS = 64;
         zmarch_body<C, SP, BX, BY, VX, NC, MM, RED>(g, ld, op, fin, red, done, split);                    \
     }
 PCGMI_ZKERNEL(k_stencil)
-PCGMI_ZKERNEL(k_pcg_direction)
-PCGMI_ZKERNEL(k_pcg_update)
+PCGMI_ZKERNEL(k_flex_direction)
 PCGMI_ZKERNEL(k_residual64)
 PCGMI_ZKERNEL(k_start_x0)
 PCGMI_ZKERNEL(k_zgeneric)
 
-enum ZFamily { ZF_STENCIL, ZF_DIRECTION, ZF_UPDATE, ZF_RESIDUAL64, ZF_START_X0, ZF_GENERIC };
+enum ZFamily { ZF_STENCIL, ZF_FLEX_DIRECTION, ZF_RESIDUAL64, ZF_START_X0, ZF_GENERIC };
 
 template <int FAM, typename C, class SP, int BX, int BY, int VX, int NC, unsigned MM, bool RED, class L, class O,
           class F>
@@ -100,10 +99,8 @@ hipError_t run_zmarch(const Grid3& g, const L& ld, const O& op, const F& fin, Re
     const int split = (RED && g.nblocks >= SPLIT_MIN_BLOCKS) ? 1 : 0;
     if constexpr (FAM == ZF_STENCIL)
         hipLaunchKernelGGL((k_stencil<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
-    else if constexpr (FAM == ZF_DIRECTION)
-        hipLaunchKernelGGL((k_pcg_direction<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
-    else if constexpr (FAM == ZF_UPDATE)
-        hipLaunchKernelGGL((k_pcg_update<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
+    else if constexpr (FAM == ZF_FLEX_DIRECTION)
+        hipLaunchKernelGGL((k_flex_direction<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
     else if constexpr (FAM == ZF_RESIDUAL64)
         hipLaunchKernelGGL((k_residual64<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
     else if constexpr (FAM == ZF_START_X0)
@@ -112,6 +109,98 @@ hipError_t run_zmarch(const Grid3& g, const L& ld, const O& op, const F& fin, Re
         hipLaunchKernelGGL((k_zgeneric<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
     if (split) hipLaunchKernelGGL((k_zfinish<NC, MM, F>), dim3(1), block, 0, s, red.partials, g.nblocks, fin, done);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Chained reductions of the PCG iteration kernels. Each iteration kernel
+// leaves one partial per work-group (and component); the NEXT kernel on the
+// stream finishes that reduction itself instead of a one-work-group kernel in
+// between: every work-group sums the partials (wave 0, lanes striding the
+// partials in index order, then the fixed butterfly, so every work-group and
+// the closing kernel get bit-identical totals whatever their size), applies
+// the finisher to its own LDS copy of the solve state and continues with
+// those scalars; work-group 0 stores the copy as the next state. The state is
+// double-buffered (sin read, sout written) so no work-group reads a state that
+// another work-group of the same launch is writing. A done state is passed
+// on (copied) and skips the work.
+template <class T> __device__ __forceinline__ void bind_state(T& t, SolveState* s) {
+    if constexpr (requires { t.st = s; }) t.st = s;
+}
+
+// Returns whether the work-group goes on to its own work (uniform).
+template <int NCP, class FP>
+__device__ __forceinline__ bool chain_enter(const Chain& ch, const FP& fp, SolveState& s_st) {
+    // The partials are summed while the state is read (both are loads of the
+    // previous kernel's output); a done state discards the sum.
+    double v[NCP];
+#pragma unroll
+    for (int c = 0; c < NCP; ++c) v[c] = 0.0;
+    if (ch.pin != nullptr && threadIdx.x < 64)
+        for (unsigned i = threadIdx.x; i < ch.nin; i += 64)
+#pragma unroll
+            for (int c = 0; c < NCP; ++c) v[c] += ch.pin[NCP * i + c];
+    if (threadIdx.x == 0) s_st = *ch.sin;
+    __syncthreads();
+    if (s_st.done != 0) {
+        if (ch.pin != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *ch.sout = s_st;
+        return false;
+    }
+    if (ch.pin != nullptr) {
+        if (threadIdx.x < 64) {
+#pragma unroll
+            for (int c = 0; c < NCP; ++c) v[c] = wave_sum(v[c]);
+            if (threadIdx.x == 0) {
+                FP f = fp;
+                bind_state(f, &s_st);
+                if constexpr (requires { f.hist; }) f.hist = blockIdx.x == 0 ? ch.hist : nullptr;
+                f(v);
+                if (blockIdx.x == 0) *ch.sout = s_st;
+            }
+        }
+        __syncthreads();
+        if (s_st.done != 0) return false;
+    }
+    return true;
+}
+
+template <typename C, class SP, int BX, int BY, int VX, int NC, int NCP, class L, class O, class FP>
+__device__ __forceinline__ void chain_body(const Grid3& g, const L& ld, const O& op, const FP& fp, const Chain& ch) {
+    using Cell = typename SP::Cell;
+    using ZT = ZTile<Cell, BX, BY, VX>;
+    __shared__ __attribute__((aligned(16))) Cell lds[2 * ZT::PLANE];
+    __shared__ double rscratch[NC * 16];
+    __shared__ SolveState s_st;
+    if (!chain_enter<NCP>(ch, fp, s_st)) return;
+    L l = ld;
+    O o = op;
+    bind_state(l, &s_st);
+    bind_state(o, &s_st);
+    l.init();
+    o.init();
+    const unsigned tile = xcd_remap(blockIdx.x, g.nblocks);
+    C acc[NC];
+    zmarch<C, SP, BX, BY, VX, NC>(g, tile, l, o, acc, lds);
+    double v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = (double)acc[c];
+    block_reduce<NC, 0u>(v, rscratch);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ch.pout[NC * blockIdx.x + c] = v[c];
+}
+
+#define PCGMI_CHAIN_KERNEL(NAME)                                                                          \
+    template <typename C, class SP, int BX, int BY, int VX, int NC, int NCP, class L, class O, class FP>  \
+    __global__ void __launch_bounds__(BX* BY) NAME(Grid3 g, L ld, O op, FP fp, Chain ch) {                \
+        chain_body<C, SP, BX, BY, VX, NC, NCP>(g, ld, op, fp, ch);                                        \
+    }
+PCGMI_CHAIN_KERNEL(k_pcg_direction)
+PCGMI_CHAIN_KERNEL(k_pcg_update)
+
+// Finishes the last kernel's partials of a run of chained kernels (one wavefront).
+template <int NCP, class FP> __global__ void __launch_bounds__(64) k_pcg_close(FP fp, Chain ch) {
+    __shared__ SolveState s_st;
+    (void)chain_enter<NCP>(ch, fp, s_st);
 }
 
 // Calls f.template operator()<BX, BY, VX>() for compiled shape cfg, W being

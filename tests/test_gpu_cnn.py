@@ -115,6 +115,47 @@ def test_forward_scaled(P, orc):
     assert np.linalg.norm(got - rho * ref.reshape(-1)) <= 1e-3 * np.linalg.norm(rho * ref)
 
 
+@pytest.mark.parametrize("n", [64, 128])
+def test_forward_full_size_sampled(P, orc, n):
+    """The scaled forward at the learned-preconditioner workload's grid sizes
+    (g the standardised Gaussian random field), checked at sampled voxels:
+    the output at p depends only on inputs within 4 voxels of p (four 3x3x3
+    layers), so the oracle runs on that window clipped to the grid, whose
+    cut faces lie outside every intermediate value the output needs."""
+    shape = (n, n, n)
+    N = n ** 3
+    ws = _init_weights(11)
+    r = synthetic.uniform_f32(30, N)
+    g = synthetic.gaussian_random_field(n).astype(np.float32)
+    net = P.cnn_create()
+    P.cnn_set_weights(net, torch.from_numpy(_flat(ws)).cuda())
+    z = torch.empty(N, dtype=torch.float32, device="cuda")
+    rr = torch.tensor([float(np.dot(r.astype(np.float64), r))], dtype=torch.float64, device="cuda")
+    P.cnn_forward(net, shape, torch.from_numpy(r).cuda(), torch.from_numpy(g).cuda(), z, rr=rr)
+    got_all = z.cpu().numpy().astype(np.float64).reshape(shape)
+    rho = np.sqrt(rr.item() / N)
+    r3 = (r / np.float32(rho)).reshape(shape)
+    g3 = g.reshape(shape)
+    rng = np.random.default_rng(31)
+    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 5), (n // 2, 0, n - 1), (3, 7, 15), (4, 8, 16)]
+    pts += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(18)]
+    got, ref = [], []
+    for p in pts:
+        lo = [max(0, c - 4) for c in p]
+        hi = [min(n, c + 5) for c in p]
+        win = tuple(slice(a, b) for a, b in zip(lo, hi))
+        inp = np.stack([r3[win], g3[win]], axis=-1).astype(np.float64)
+        out, _, _ = _fwd_emulated(orc, ws, inp)
+        ref.append(rho * out[tuple(c - a for c, a in zip(p, lo))][0])
+        got.append(got_all[p])
+    got, ref = np.array(got), np.array(ref)
+    err = np.abs(got - ref)
+    print(n, "sampled forward max abs err", err.max(), "rms ref", np.sqrt(np.mean(ref ** 2)), flush=True)
+    assert np.linalg.norm(err) <= 1e-3 * np.linalg.norm(ref)
+    assert err.max() <= 5e-3 * np.abs(ref).max()
+    assert np.isfinite(got_all).all()
+
+
 def test_stencil_network_exact(P, orc):
     """A network that carries r through ReLU as (relu(r), relu(-r)) and applies
     the seven-point taps in its last layer computes A r exactly on integers
