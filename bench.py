@@ -413,6 +413,10 @@ def main():
                 "bytes_per_launch": BYTES_UPDATE * N, "avg_us": round(k2_us, 2),
                 "direction_kernel_avg_us": round(k1_us, 2),
                 "direction_kernel_GB/s": round(BYTES_DIRECTION * N / (k1_us * 1e-6) / 1e9, 1),
+                # both kernels' algorithmic bytes over the timed solve's time per iteration
+                "iteration_GB/s": round((BYTES_DIRECTION + BYTES_UPDATE) * N / (dt_solve / iters) / 1e9, 1),
+                "iteration_frac": round((BYTES_DIRECTION + BYTES_UPDATE) * N / (dt_solve / iters) / 1e9
+                                        / HBM_PEAK_GBS, 4),
                 "event_timed_solve_ms": round(tinfo["seconds"] * 1e3, 2)}
     P.pcg_destroy(tctx)
 

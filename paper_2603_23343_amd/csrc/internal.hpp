@@ -15,6 +15,8 @@ enum DT : int { DT_F32 = PCG_F32, DT_BF16 = PCG_BF16, DT_F16 = PCG_F16, DT_F64 =
 
 inline size_t dt_size(int dt) { return dt == DT_F64 ? 8 : dt == DT_F32 ? 4 : 2; }
 inline int dt_width(int dt) { return (int)(16 / dt_size(dt)); }  // elements per 16 bytes
+// MI355X's last-level cache (AMD Infinity Cache) in front of HBM.
+constexpr size_t LLC_BYTES = (size_t)256 << 20;
 
 // Compiled work-group shapes of the z-march kernels: BX x BY threads, each
 // thread owning VX consecutive x points (VX = 16 bytes of the storage type,

@@ -64,24 +64,34 @@ hipError_t launch_pcg_direction(int dt, const Plan& p, const Geometry& g, OpDesc
 
 hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, OpDesc od, const void* pdir, void* x,
                              int xdt, void* r, const Chain& ch, hipStream_t s) {
+    // r, p, p_old and x of one iteration against the last-level cache
+    const size_t footprint = (size_t)g.nx * g.ny * g.nz * (3 * dt_size(dt) + dt_size(xdt));
+    const bool ntx = footprint > LLC_BYTES;
     return dispatch_dt(dt, [&](auto tag) {
         using T = decltype(tag);
         using C = typename Traits<T>::C;
         return dispatch_cfg<Traits<T>::W>(p.cfg, [&]<int BX, int BY, int VX>() {
-            auto go = [&](auto xtag) -> hipError_t {
+            // NTX is compiled for the FP64 accumulator only (the widest x stream).
+            auto go_nt = [&]<bool NTX>(auto xtag) -> hipError_t {
                 using X = decltype(xtag);
                 if (od.kc) {
                     if constexpr (VAR_TYPE<T>) {
                         LoadUK<T> ld{static_cast<const T*>(pdir), od.kc};
-                        OpUpdate<T, X, VX, true> op{static_cast<X*>(x), static_cast<T*>(r), nullptr,
-                                                    static_cast<const T*>(od.dinv), C(0), 0.0};
+                        OpUpdate<T, X, VX, true, NTX> op{static_cast<X*>(x), static_cast<T*>(r), nullptr,
+                                                         static_cast<const T*>(od.dinv), C(0), 0.0};
                         return run_chain<1, C, StencilVar<C>, BX, BY, VX, 2, 1>(g, ld, op, FinAlpha{nullptr}, ch, s);
                     }
                     return hipErrorInvalidValue;
                 }
                 LoadField<T> ld{static_cast<const T*>(pdir)};
-                OpUpdate<T, X, VX> op{static_cast<X*>(x), static_cast<T*>(r), nullptr, nullptr, C(0), 0.0};
+                OpUpdate<T, X, VX, false, NTX> op{static_cast<X*>(x), static_cast<T*>(r), nullptr, nullptr, C(0), 0.0};
                 return run_chain<1, C, StencilConst<C>, BX, BY, VX, 1, 1>(g, ld, op, FinAlpha{nullptr}, ch, s);
+            };
+            auto go = [&](auto xtag) -> hipError_t {
+                using X = decltype(xtag);
+                if constexpr (std::is_same_v<X, double>)
+                    if (ntx) return go_nt.template operator()<true>(xtag);
+                return go_nt.template operator()<false>(xtag);
             };
             if (xdt == DT_F64) return go(double{});
             if (xdt == DT_F32) return go(float{});

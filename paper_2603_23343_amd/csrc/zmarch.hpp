@@ -52,6 +52,15 @@ template <typename T, int N> struct RawN<T, N, true> {
 #pragma unroll
         for (int i = 0; i < NV; ++i) v[i] = reinterpret_cast<const Vec16<T>*>(p)[i];
     }
+    // Non-temporal: the lines do not displace others in L2 and the last-level cache.
+    __device__ __forceinline__ void load_nt(const T* p) {
+        using U = __attribute__((__vector_size__(16))) unsigned int;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            U raw = __builtin_nontemporal_load(reinterpret_cast<const U*>(p) + i);
+            __builtin_memcpy(&v[i], &raw, 16);
+        }
+    }
     __device__ __forceinline__ typename Traits<T>::C get(int i) const { return to_c(v[i / W].e[i % W]); }
 };
 template <typename T, int N> struct RawN<T, N, false> {
@@ -60,6 +69,7 @@ template <typename T, int N> struct RawN<T, N, false> {
 #pragma unroll
         for (int i = 0; i < N; ++i) e[i] = p[i];
     }
+    __device__ __forceinline__ void load_nt(const T* p) { load(p); }
     __device__ __forceinline__ typename Traits<T>::C get(int i) const { return to_c(e[i]); }
 };
 
