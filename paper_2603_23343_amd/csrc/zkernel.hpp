@@ -132,13 +132,27 @@ template <int NCP, class FP>
 __device__ __forceinline__ bool chain_enter(const Chain& ch, const FP& fp, SolveState& s_st) {
     // The partials are summed while the state is read (both are loads of the
     // previous kernel's output); a done state discards the sum.
+    // Each lane issues eight loads before it adds (a dependent load per add
+    // costs one L2 round trip each: 16 of them at 1024 work-groups); the
+    // additions keep index order, so the totals do not depend on it.
+    constexpr int PU = 8;
     double v[NCP];
 #pragma unroll
     for (int c = 0; c < NCP; ++c) v[c] = 0.0;
     if (ch.pin != nullptr && threadIdx.x < 64)
-        for (unsigned i = threadIdx.x; i < ch.nin; i += 64)
+        for (unsigned base = threadIdx.x; base < ch.nin; base += 64 * PU) {
+            double t[PU][NCP];
 #pragma unroll
-            for (int c = 0; c < NCP; ++c) v[c] += ch.pin[NCP * i + c];
+            for (int u = 0; u < PU; ++u) {
+                const unsigned i = base + 64 * u;
+#pragma unroll
+                for (int c = 0; c < NCP; ++c) t[u][c] = i < ch.nin ? ch.pin[NCP * i + c] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < PU; ++u)
+#pragma unroll
+                for (int c = 0; c < NCP; ++c) v[c] += t[u][c];
+        }
     if (threadIdx.x == 0) s_st = *ch.sin;
     __syncthreads();
     if (s_st.done != 0) {
