@@ -20,6 +20,9 @@ Also reported on the same JSON line:
                    training, flexible CG on a held-out right-hand side)
                    against Jacobi-PCG at each grid of --learned-n (64 and 128
                    by default);
+  paper_grid    -- PCG time per iteration on the paper's 512 x 112 x 64
+                   comparison grid (FP32 and BF16 storage), beside the
+                   paper's own per-iteration times (context, other hardware);
   kernels_512   -- standalone stencil / axpy / dot at 512^3 (FP32 and BF16),
                    achieved GB/s of algorithmic bytes;
   batched       -- 64 uneven problems (edges log-uniform in [16, 128], seed 5;
@@ -128,6 +131,41 @@ def time_kernels_512(P, torch, n, reps):
         P.pcg_destroy(ctx)
         del x, y, z
         torch.cuda.empty_cache()
+    return out
+
+
+# The paper's per-iteration times on its comparison grid (its Table III):
+# context only (other hardware), never the target.
+PAPER_GRID_MS_PER_ITER = {"H100 FP32 (four separate kernels)": 0.28, "Wormhole BF16": 1.20, "Wormhole FP32": 2.45}
+
+
+def bench_paper_grid(P, torch, steps):
+    """PCG time per iteration on the paper's 512 x 112 x 64 comparison grid
+    (b ~ U[-1, 1], to recursive 1e-6 for FP32 and 1e-3 for BF16). 3.67 M
+    points: an iteration's vectors (73 MB FP32) sit in the last-level cache,
+    so this measures latency and cache bandwidth rather than HBM."""
+    import synthetic
+
+    nx, ny, nz = synthetic.PAPER_GRID
+    N = nx * ny * nz
+    b32 = torch.from_numpy(synthetic.uniform_f32(synthetic.SEED_PAPER_GRID_B, N)).cuda()
+    out = {"grid": [nx, ny, nz], "paper_ms_per_iteration": PAPER_GRID_MS_PER_ITER}
+    for name, dt, xacc, xdt, tol in (("f32", torch.float32, torch.float64, torch.float64, 1e-6),
+                                     ("bf16", torch.bfloat16, torch.float32, torch.float64, 1e-3)):
+        ctx = P.pcg_create(nx, ny, nz, dt, x_accum=xacc, x_dtype=xdt)
+        b = b32.to(dt)
+        x = torch.empty(N, dtype=xdt, device="cuda")
+        P.pcg_solve(ctx, b, x, tol, 5000, raise_on_error=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = P.pcg_solve(ctx, b, x, tol, 5000, raise_on_error=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        out[name] = {"rtol": tol, "iters": info["iters"], "ms_per_solve": round(ms, 3),
+                     "ms_per_iteration": round(ms / max(info["iters"], 1), 5),
+                     "true_relres": info["rel_res_true_fp64"]}
+        P.pcg_destroy(ctx)
     return out
 
 
@@ -352,6 +390,7 @@ def main():
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-paper-grid", action="store_true")
     ap.add_argument("--learned-n", default="64,128",
                     help="comma-separated grid sizes of the learned-preconditioner workflow")
     ap.add_argument("--learned-rounds", type=int, default=12)
@@ -443,6 +482,11 @@ def main():
         batched = bench_batched(P, torch, args.batched_reps, 0.0 if args.no_cpu_baseline else 3.0)
         print(f"# batched: {batched}", file=sys.stderr, flush=True)
 
+    paper_grid = None
+    if not args.no_paper_grid:
+        paper_grid = bench_paper_grid(P, torch, max(args.steps, 3))
+        print(f"# paper_grid: {paper_grid}", file=sys.stderr, flush=True)
+
     learned = None
     if not args.no_learned:
         sizes = [int(v) for v in args.learned_n.split(",")]
@@ -472,6 +516,7 @@ def main():
         "roofline": roofline,
         "refined": refined or None,
         "batched": batched,
+        "paper_grid": paper_grid,
         "learned": learned,
         "kernels_512": kern,
         "cpu_baseline": cpu,

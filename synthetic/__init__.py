@@ -28,6 +28,9 @@ SEED_C4_B_BASE = 1000
 SEED_C5_GRF = 6
 SEED_C5_TRAIN_BASE = 10000
 SEED_C5_HELDOUT_BASE = 20000
+# The paper's GPU comparison grid (its Table III): nx x ny x nz, b ~ U[-1, 1].
+PAPER_GRID = (512, 112, 64)
+SEED_PAPER_GRID_B = 7
 
 
 def uniform(seed: int, n: int) -> np.ndarray:

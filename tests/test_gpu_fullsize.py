@@ -103,3 +103,41 @@ def test_pcg_256_bench_configuration(P, orc):
     print("restarts", info["restarts"], "iters", info["iters"], "true relres", tr, flush=True)
     assert tr <= 1e-6
     assert abs(info["rel_res_true_fp64"] - tr) <= 1e-6 * tr
+
+
+def test_pcg_paper_comparison_grid(P, orc):
+    """The paper's comparison grid (Table III), 512 x 112 x 64 (x fastest),
+    b ~ U[-1, 1]: FP32 PCG iterations within 2 of the FP64 oracle's on the
+    recursion, FP64 true residual <= 1e-6 with restarts, and BF16 storage
+    reaching its own recursive tolerance."""
+    nx, ny, nz = synthetic.PAPER_GRID
+    N = nx * ny * nz
+    shape = (nz, ny, nx)
+    b32 = synthetic.uniform_f32(synthetic.SEED_PAPER_GRID_B, N)
+    bb = b32.astype(np.float64)
+    b = torch.from_numpy(b32).cuda()
+    x = torch.empty(N, dtype=torch.float64, device="cuda")
+    print("paper grid PCG", nx, ny, nz, flush=True)
+    ctx0 = P.pcg_create(nx, ny, nz, torch.float32, x_dtype=torch.float64, max_restarts=0)
+    i0 = P.pcg_solve(ctx0, b, x, 1e-6, 5000)
+    ctx0.close()
+    ref = orc.pcg(shape, bb, rtol=1e-6, maxit=5000)
+    print("iterations", i0["iters"], "oracle", ref["iters"], flush=True)
+    assert abs(i0["iters"] - ref["iters"]) <= 2
+    ctx = P.pcg_create(nx, ny, nz, torch.float32, x_dtype=torch.float64)
+    info = P.pcg_solve(ctx, b, x, 1e-6, 5000)
+    tr = orc.true_relres(shape, bb, x.cpu().numpy())
+    print("restarts", info["restarts"], "iters", info["iters"], "true relres", tr, flush=True)
+    assert tr <= 1e-6
+    ctx.close()
+    # BF16 storage, FP32 x: the recursion reaches 1e-3. Rounding r to BF16 each
+    # iteration adds a drift of about 2^-9 ||r_k|| per step; in quadrature over the
+    # first iterations (where ||r_k|| ~ ||b||) that stays below ~10 * 2^-9 = 2e-2.
+    cb = P.pcg_create(nx, ny, nz, torch.bfloat16, x_accum=torch.float32, x_dtype=torch.float64)
+    xb = torch.empty(N, dtype=torch.float64, device="cuda")
+    ib = P.pcg_solve(cb, b.to(torch.bfloat16), xb, 1e-3, 5000, raise_on_error=False)
+    trb = orc.true_relres(shape, b.to(torch.bfloat16).double().cpu().numpy(), xb.double().cpu().numpy())
+    print("bf16 iters", ib["iters"], "recursive", ib["rel_res_recursive"], "true", trb, flush=True)
+    assert ib["rel_res_recursive"] <= 1e-3
+    assert trb <= 2e-2
+    cb.close()
