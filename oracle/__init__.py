@@ -63,6 +63,9 @@ def _load():
     lib.oracle_pcg.argtypes = [i, i, i, _dp, _dp, _dp, d, i, _dp,
                                ctypes.POINTER(i), ctypes.POINTER(d)]
     lib.oracle_pcg.restype = i
+    lib.oracle_pcg_sr.argtypes = [i, i, i, _dp, _dp, _dp, d, i, _dp,
+                                  ctypes.POINTER(i), ctypes.POINTER(d)]
+    lib.oracle_pcg_sr.restype = i
     lib.oracle_residual.argtypes = [i, i, i, _dp, _dp, _dp, _dp,
                                     ctypes.POINTER(d), ctypes.POINTER(d)]
     lib.oracle_threads.restype = i
@@ -142,6 +145,25 @@ def pcg(shape, b, rtol=1e-6, maxit=500, kcell=None, x0=None, history=False):
     st = _load().oracle_pcg(nx, ny, nz, None if k is None else _ptr(k), _ptr(b), _ptr(x),
                             float(rtol), int(maxit), None if hist is None else _ptr(hist),
                             ctypes.byref(it), ctypes.byref(rr))
+    out = dict(x=x, iters=it.value, status=st, relres=rr.value)
+    if history:
+        out["hist"] = hist[: it.value + 1]
+    return out
+
+
+def pcg_sr(shape, b, rtol=1e-6, maxit=500, kcell=None, x0=None, history=False):
+    """FP64 Jacobi-PCG with one reduction per iteration (Chronopoulos-Gear,
+    J. Comput. Appl. Math. 25, 1989); same results as pcg() in exact
+    arithmetic. Returns dict(x, iters, status, relres[, hist])."""
+    nx, ny, nz = _dims(shape)
+    b = _f64(b)
+    x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
+    k = None if kcell is None else _f64(kcell)
+    hist = np.full(maxit + 1, np.nan) if history else None
+    it, rr = ctypes.c_int(0), ctypes.c_double(0.0)
+    st = _load().oracle_pcg_sr(nx, ny, nz, None if k is None else _ptr(k), _ptr(b), _ptr(x),
+                               float(rtol), int(maxit), None if hist is None else _ptr(hist),
+                               ctypes.byref(it), ctypes.byref(rr))
     out = dict(x=x, iters=it.value, status=st, relres=rr.value)
     if history:
         out["hist"] = hist[: it.value + 1]

@@ -17,7 +17,8 @@
  *   - axpy, dot (Sec. IV, Sec. V: element-wise update and global sum);
  *   - Jacobi-preconditioned CG in the Hestenes-Stiefel form (Saad,
  *     Iterative Methods for Sparse Linear Systems, 2nd ed., Alg. 9.1),
- *     stopping on the recursive residual relative to ||b||.
+ *     stopping on the recursive residual relative to ||b||, and the same
+ *     method with one global reduction per iteration (Chronopoulos-Gear).
  *
  * Arrays are C-order [nz][ny][nx], x contiguous. All arithmetic is FP64.
  * Reductions use a fixed order (contiguous chunks summed left to right, chunk
@@ -263,6 +264,115 @@ int oracle_pcg(int nx, int ny, int nz, const double *kc, const double *b, double
     }
 done:
     free(r); free(z); free(p); free(q); free(dinv);
+    return status;
+}
+
+/*
+ * Jacobi-preconditioned CG with one global reduction per iteration, in the
+ * form of Chronopoulos and Gear (J. Comput. Appl. Math. 25 (1989), the s = 1
+ * case of their s-step CG): the search direction's product s = A p is
+ * carried by a recurrence, so the two inner products of an iteration are
+ * taken together on the new residual. In exact arithmetic its iterates are
+ * those of oracle_pcg. With M = D^-1:
+ *
+ *   r0 = b - A x0, u0 = M r0, w0 = A u0,
+ *   gamma0 = r0.u0, delta0 = w0.u0, alpha0 = gamma0 / delta0, beta0 = 0;
+ *   iteration i = 0, 1, ...:
+ *     p_i = u_i + beta_i p_{i-1};   s_i = w_i + beta_i s_{i-1}   (p, s = 0 before)
+ *     x_{i+1} = x_i + alpha_i p_i;  r_{i+1} = r_i - alpha_i s_i
+ *     stop when ||r_{i+1}|| <= rtol ||b||
+ *     u_{i+1} = M r_{i+1};  w_{i+1} = A u_{i+1}
+ *     gamma_{i+1} = r_{i+1}.u_{i+1};  delta_{i+1} = w_{i+1}.u_{i+1}
+ *     beta_{i+1} = gamma_{i+1} / gamma_i
+ *     alpha_{i+1} = gamma_{i+1} / (delta_{i+1} - beta_{i+1} gamma_{i+1} / alpha_i)
+ *
+ * Arguments and results as oracle_pcg (*iters = updates of x); a
+ * non-positive or non-finite alpha denominator is a breakdown.
+ */
+int oracle_pcg_sr(int nx, int ny, int nz, const double *kc, const double *b, double *x, double rtol,
+                  int maxit, double *hist, int *iters, double *relres)
+{
+    int64_t n = (int64_t)nx * ny * nz;
+    double *r = malloc(sizeof(double) * n), *u = malloc(sizeof(double) * n);
+    double *w = malloc(sizeof(double) * n), *p = calloc(n, sizeof(double));
+    double *sv = calloc(n, sizeof(double)), *dinv = malloc(sizeof(double) * n);
+    if (!r || !u || !w || !p || !sv || !dinv) {
+        free(r); free(u); free(w); free(p); free(sv); free(dinv);
+        return ORACLE_NOMEM;
+    }
+    if (kc) {
+        oracle_vdiag(nx, ny, nz, kc, dinv);
+        for (int64_t i = 0; i < n; ++i)
+            dinv[i] = 1.0 / dinv[i];
+    } else {
+        for (int64_t i = 0; i < n; ++i)
+            dinv[i] = 1.0 / 6.0;
+    }
+    int status = ORACLE_OK;
+    *iters = 0;
+    double nb = sqrt(oracle_dot(n, b, b));
+    if (nb == 0.0) {
+        memset(x, 0, sizeof(double) * n);
+        *relres = 0.0;
+        if (hist)
+            hist[0] = 0.0;
+        goto done;
+    }
+    apply_op(nx, ny, nz, kc, x, w);
+    for (int64_t i = 0; i < n; ++i)
+        r[i] = b[i] - w[i];
+    double rn = sqrt(oracle_dot(n, r, r));
+    if (hist)
+        hist[0] = rn / nb;
+    *relres = rn / nb;
+    if (rn <= rtol * nb)
+        goto done;
+    for (int64_t i = 0; i < n; ++i)
+        u[i] = dinv[i] * r[i];
+    apply_op(nx, ny, nz, kc, u, w);
+    double gamma = oracle_dot(n, r, u), delta = oracle_dot(n, w, u);
+    if (!(delta > 0.0) || !isfinite(delta) || !isfinite(gamma)) {
+        status = ORACLE_BREAKDOWN;
+        goto done;
+    }
+    double alpha = gamma / delta, beta = 0.0;
+    status = ORACLE_NOCONV;
+    for (int k = 1; k <= maxit; ++k) {
+        for (int64_t i = 0; i < n; ++i) {
+            p[i] = u[i] + beta * p[i];
+            sv[i] = w[i] + beta * sv[i];
+            x[i] += alpha * p[i];
+            r[i] -= alpha * sv[i];
+        }
+        *iters = k;
+        rn = sqrt(oracle_dot(n, r, r));
+        *relres = rn / nb;
+        if (hist)
+            hist[k] = rn / nb;
+        if (!isfinite(rn)) {
+            status = ORACLE_BREAKDOWN;
+            break;
+        }
+        if (rn <= rtol * nb) {
+            status = ORACLE_OK;
+            break;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            u[i] = dinv[i] * r[i];
+        apply_op(nx, ny, nz, kc, u, w);
+        double gamma_new = oracle_dot(n, r, u);
+        delta = oracle_dot(n, w, u);
+        beta = gamma_new / gamma;
+        double denom = delta - beta * gamma_new / alpha;
+        if (!(denom > 0.0) || !isfinite(denom)) {
+            status = ORACLE_BREAKDOWN;
+            break;
+        }
+        alpha = gamma_new / denom;
+        gamma = gamma_new;
+    }
+done:
+    free(r); free(u); free(w); free(p); free(sv); free(dinv);
     return status;
 }
 
