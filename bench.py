@@ -21,8 +21,10 @@ Also reported on the same JSON line:
                    against Jacobi-PCG at each grid of --learned-n (64 and 128
                    by default);
   paper_grid    -- PCG time per iteration on the paper's 512 x 112 x 64
-                   comparison grid (FP32 and BF16 storage), beside the
+                   comparison grid (FP32 with two kernels or the
+                   single-reduction form, and BF16 storage), beside the
                    paper's own per-iteration times (context, other hardware);
+  small_grid    -- the 32^3 workload with both iteration forms;
   kernels_512   -- standalone stencil / axpy / dot at 512^3 (FP32 and BF16),
                    achieved GB/s of algorithmic bytes;
   batched       -- 64 uneven problems (edges log-uniform in [16, 128], seed 5;
@@ -150,9 +152,10 @@ def bench_paper_grid(P, torch, steps):
     N = nx * ny * nz
     b32 = torch.from_numpy(synthetic.uniform_f32(synthetic.SEED_PAPER_GRID_B, N)).cuda()
     out = {"grid": [nx, ny, nz], "paper_ms_per_iteration": PAPER_GRID_MS_PER_ITER}
-    for name, dt, xacc, xdt, tol in (("f32", torch.float32, torch.float64, torch.float64, 1e-6),
-                                     ("bf16", torch.bfloat16, torch.float32, torch.float64, 1e-3)):
-        ctx = P.pcg_create(nx, ny, nz, dt, x_accum=xacc, x_dtype=xdt)
+    for name, dt, xacc, xdt, tol, sr in (("f32", torch.float32, torch.float64, torch.float64, 1e-6, 0),
+                                         ("f32_single_reduction", torch.float32, torch.float64, torch.float64, 1e-6, 1),
+                                         ("bf16", torch.bfloat16, torch.float32, torch.float64, 1e-3, 0)):
+        ctx = P.pcg_create(nx, ny, nz, dt, x_accum=xacc, x_dtype=xdt, single_reduction=sr)
         b = b32.to(dt)
         x = torch.empty(N, dtype=xdt, device="cuda")
         P.pcg_solve(ctx, b, x, tol, 5000, raise_on_error=False)
@@ -164,6 +167,32 @@ def bench_paper_grid(P, torch, steps):
         ms = (time.perf_counter() - t0) / steps * 1e3
         out[name] = {"rtol": tol, "iters": info["iters"], "ms_per_solve": round(ms, 3),
                      "ms_per_iteration": round(ms / max(info["iters"], 1), 5),
+                     "true_relres": info["rel_res_true_fp64"]}
+        P.pcg_destroy(ctx)
+    return out
+
+
+def bench_small_grid(P, torch, steps, n=32):
+    """The small workload (n^3, b ~ U[-1, 1] seed 1, FP32 to 1e-6): solve time
+    with two kernels per iteration and with the single-reduction form (the
+    default at this size). Latency-bound: a few microseconds of work per kernel."""
+    import synthetic
+
+    N = n ** 3
+    b = torch.from_numpy(synthetic.uniform_f32(synthetic.SEED_C1_B, N)).cuda()
+    out = {"grid": n}
+    for name, sr in (("two_kernel", 0), ("single_reduction", 1)):
+        ctx = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64, single_reduction=sr)
+        x = torch.empty(N, dtype=torch.float64, device="cuda")
+        P.pcg_solve(ctx, b, x, 1e-6, 500)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = P.pcg_solve(ctx, b, x, 1e-6, 500)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        out[name] = {"iters": info["iters"], "ms_per_solve": round(ms, 4),
+                     "us_per_iteration": round(ms * 1e3 / max(info["iters"], 1), 2),
                      "true_relres": info["rel_res_true_fp64"]}
         P.pcg_destroy(ctx)
     return out
@@ -482,10 +511,12 @@ def main():
         batched = bench_batched(P, torch, args.batched_reps, 0.0 if args.no_cpu_baseline else 3.0)
         print(f"# batched: {batched}", file=sys.stderr, flush=True)
 
-    paper_grid = None
+    paper_grid = small_grid = None
     if not args.no_paper_grid:
         paper_grid = bench_paper_grid(P, torch, max(args.steps, 3))
         print(f"# paper_grid: {paper_grid}", file=sys.stderr, flush=True)
+        small_grid = bench_small_grid(P, torch, max(args.steps, 3) * 4)
+        print(f"# small_grid: {small_grid}", file=sys.stderr, flush=True)
 
     learned = None
     if not args.no_learned:
@@ -517,6 +548,7 @@ def main():
         "refined": refined or None,
         "batched": batched,
         "paper_grid": paper_grid,
+        "small_grid": small_grid,
         "learned": learned,
         "kernels_512": kern,
         "cpu_baseline": cpu,

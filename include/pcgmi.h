@@ -67,6 +67,12 @@ typedef struct {
                           residual ||b - A x|| > rtol ||b||, restart from x with r = b - A x
                           (computed in FP64, stored in the storage type) and beta = 0, at
                           most this many times; 0 = never; -1 = default (3) */
+    int single_reduction; /* iteration form of pcg_solve / pcg_solve_refined with constant
+                          coefficients: 0 = two kernels and two grid reductions per
+                          iteration (Hestenes-Stiefel PCG); 1 = one fused kernel and one
+                          reduction per iteration (Chronopoulos-Gear single-reduction
+                          PCG, the same iterates in exact arithmetic; moves 48 instead of
+                          40 bytes per point); -1 = default (chosen by grid size) */
 } pcg_options;
 
 typedef struct {

@@ -54,7 +54,7 @@ struct Red {
     unsigned* ticket;
     size_t cap;
 };
-constexpr int MAX_RED_COMPONENTS = 4;
+constexpr int MAX_RED_COMPONENTS = 6;  // two chained halves of up to 3 components
 
 // The operator of a context: constant coefficients (kc == null) or the
 // variable-coefficient operator with cell coefficients kc (FP32) and the
@@ -94,6 +94,25 @@ hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, OpDesc od
                              int xdt, void* r, const Chain& ch, hipStream_t s);
 // Finishes the last update's partials of a chain (beta, count, convergence).
 hipError_t launch_pcg_close(bool var, const Chain& ch, hipStream_t s);
+
+// Single-reduction form (constant coefficients). Vectors of one iteration.
+struct SRBufs {
+    const void* r_in;
+    const void* w_in;
+    const void* s_in;
+    void* r_out;
+    void* w_out;
+    void* s_out;
+    void* p;  // in place
+};
+// Start: w = stored(A D^-1 r), {gamma, delta} -> alpha (grid reduction into st).
+hipError_t launch_pcg_sr_start(int dt, const Plan& p, const Geometry& g, const void* r, void* w, SolveState* st,
+                               Red red, hipStream_t s);
+// One iteration: finishes the previous iteration's {gamma, delta, r.r}, then
+// the fused update and stencil; x (type xdt) in place.
+hipError_t launch_pcg_sr(int dt, const Plan& p, const Geometry& g, const SRBufs& b, void* x, int xdt, const Chain& ch,
+                         hipStream_t s);
+hipError_t launch_pcg_sr_close(const Chain& ch, hipStream_t s);
 // r = stored(b - A x0) computed in FP64 (x0 of type xdt), totals {r.r, b.b}
 // -> solve start. Uses the FP64 residual shape (pres, gres).
 hipError_t launch_pcg_start_x0(int dt, int xdt, const Plan& pres, const Geometry& gres, OpDesc od, const void* b,

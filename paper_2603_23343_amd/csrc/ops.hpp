@@ -168,6 +168,55 @@ template <typename T> struct LoadDirectionVar {
     }
 };
 
+// Single-reduction PCG (Chronopoulos-Gear): the preconditioned new
+// residual u_{i+1} = D^-1 r_{i+1}, with s_i = stored(w_i + beta s_{i-1}) and
+// r_{i+1} = stored(r_i - alpha s_i) computed on the fly for the tile and its
+// halo (constant Jacobi scale).
+template <typename T> struct LoadSR {
+    using C = typename Traits<T>::C;
+    template <int N> struct Raw {
+        RawN<T, N> r, w, s;
+    };
+    const T* __restrict__ r;
+    const T* __restrict__ w;
+    const T* __restrict__ s;
+    const SolveState* st;
+    C alpha, beta, dinv;
+    __device__ void init() {
+        alpha = (C)st->alpha;
+        beta = (C)st->beta;
+        dinv = (C)st->dinv;
+    }
+    template <int N> __device__ __forceinline__ void fetch(int64_t i, Raw<N>& raw) const {
+        raw.r.load(r + i);
+        raw.w.load(w + i);
+        raw.s.load(s + i);
+    }
+    template <int N> __device__ __forceinline__ void finish(const Raw<N>& raw, C* out) const {
+#pragma unroll
+        for (int v = 0; v < N; ++v) {
+            const C sv = stored<T>(raw.w.get(v) + beta * raw.s.get(v));
+            out[v] = dinv * stored<T>(raw.r.get(v) - alpha * sv);
+        }
+    }
+};
+
+// u = D^-1 r (constant Jacobi scale), not rounded: the start of the
+// single-reduction form.
+template <typename T> struct LoadPrecond {
+    using C = typename Traits<T>::C;
+    template <int N> using Raw = RawN<T, N>;
+    const T* __restrict__ r;
+    const SolveState* st;
+    C dinv;
+    __device__ void init() { dinv = (C)st->dinv; }
+    template <int N> __device__ __forceinline__ void fetch(int64_t i, Raw<N>& raw) const { raw.load(r + i); }
+    template <int N> __device__ __forceinline__ void finish(const Raw<N>& raw, C* out) const {
+#pragma unroll
+        for (int v = 0; v < N; ++v) out[v] = dinv * raw.get(v);
+    }
+};
+
 // ---------------------------------------------------------------- store helpers
 
 template <typename T, int VX>
@@ -308,6 +357,90 @@ template <typename T, typename X, int VX, bool VAR = false, bool NTX = false> st
         if constexpr (NTX) st_any_nt<X, VX>(x, i, xv);
         else st_any<X, VX>(x, i, xv);
         st_pts<T, VX>(r, i, rv);
+    }
+};
+
+// Single-reduction iteration: with u_{i+1} (the cell) and w_{i+1} = A u_{i+1}
+// (ax) from the stencil, and s_i, r_{i+1} recomputed exactly as the loader
+// did: p_i = stored(D^-1 r_i + beta p_{i-1}) (in place), x += alpha p_i,
+// stores s_i, r_{i+1}, w_{i+1}; accumulates gamma = r.u, delta = w.u and
+// ||r||^2 of the new residual.
+template <typename T, typename X, int VX> struct OpSR {
+    using C = typename Traits<T>::C;
+    struct Raw {
+        RawN<T, VX> r, w, s, p;
+        RawN<X, VX> x;
+    };
+    const T* __restrict__ r_in;
+    const T* __restrict__ w_in;
+    const T* __restrict__ s_in;
+    T* __restrict__ r_out;
+    T* __restrict__ w_out;
+    T* __restrict__ s_out;
+    T* __restrict__ p;
+    X* __restrict__ x;
+    const SolveState* st;
+    C alpha, beta, dinv;
+    double alpha_d;
+    __device__ void init() {
+        alpha = (C)st->alpha;
+        beta = (C)st->beta;
+        dinv = (C)st->dinv;
+        alpha_d = (double)alpha;
+    }
+    __device__ __forceinline__ void fetch(int64_t i, Raw& raw) const {
+        raw.r.load(r_in + i);
+        raw.w.load(w_in + i);
+        raw.s.load(s_in + i);
+        raw.p.load(p + i);
+        raw.x.load(x + i);
+    }
+    template <int NC, class Cell>
+    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const Cell* c, const C* ax, C (&acc)[NC]) const {
+        C sv[VX], rn[VX], pv[VX], wn[VX];
+        double xv[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            sv[v] = stored<T>(raw.w.get(v) + beta * raw.s.get(v));
+            rn[v] = stored<T>(raw.r.get(v) - alpha * sv[v]);
+            pv[v] = stored<T>(dinv * raw.r.get(v) + beta * raw.p.get(v));
+            xv[v] = (double)raw.x.get(v) + alpha_d * (double)pv[v];
+            wn[v] = stored<T>(ax[v]);
+            const C un = cell_u(c[v]);
+            acc[0] += rn[v] * un;
+            acc[1] += wn[v] * un;
+            acc[2] += rn[v] * rn[v];
+        }
+        st_pts<T, VX>(s_out, i, sv);
+        st_pts<T, VX>(r_out, i, rn);
+        st_pts<T, VX>(w_out, i, wn);
+        st_pts<T, VX>(p, i, pv);
+        st_any<X, VX>(x, i, xv);
+    }
+};
+
+// Start of the single-reduction form: w = stored(A u) with u = D^-1 r (the
+// cell); accumulates gamma = r.u and delta = w.u.
+template <typename T, int VX> struct OpSRStart {
+    using C = typename Traits<T>::C;
+    struct Raw {
+        RawN<T, VX> r;
+    };
+    const T* __restrict__ r;
+    T* __restrict__ w;
+    __device__ void init() {}
+    __device__ __forceinline__ void fetch(int64_t i, Raw& raw) const { raw.r.load(r + i); }
+    template <int NC, class Cell>
+    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const Cell* c, const C* ax, C (&acc)[NC]) const {
+        C wn[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            wn[v] = stored<T>(ax[v]);
+            const C un = cell_u(c[v]);
+            acc[0] += raw.r.get(v) * un;
+            acc[1] += wn[v] * un;
+        }
+        st_pts<T, VX>(w, i, wn);
     }
 };
 
@@ -460,6 +593,68 @@ struct FinBeta {
         double rho_new = var ? tot[1] : st->dinv * rr;
         st->beta = rho_new / st->rho;
         st->rho = rho_new;
+    }
+};
+
+// Single-reduction form, after the start's {gamma, delta}: alpha = gamma /
+// delta, beta = 0.
+struct FinSRStart {
+    SolveState* st;
+    __device__ void operator()(const double* tot) const {
+        const double gamma = tot[0], delta = tot[1];
+        st->rho = gamma;
+        st->beta = 0.0;
+        if (!(delta > 0.0) || !isfinite(delta) || !isfinite(gamma)) {
+            st->done = 2;
+            return;
+        }
+        st->alpha = gamma / delta;
+    }
+};
+
+// Single-reduction form, after an iteration's {gamma, delta, ||r||^2}: count
+// the iteration, test convergence (and stagnation, as FinBeta), then beta =
+// gamma / gamma_old and alpha = gamma / (delta - beta gamma / alpha_old).
+struct FinSR {
+    SolveState* st;
+    double* hist;
+    __device__ void operator()(const double* tot) const {
+        const double gamma = tot[0], delta = tot[1], rr = tot[2];
+        const int it = st->iters + 1;
+        st->iters = it;
+        st->rr = rr;
+        if (hist) hist[it] = sqrt(rr / st->rr0);
+        if (!isfinite(rr) || !isfinite(gamma) || !isfinite(delta)) {
+            st->done = 2;
+            return;
+        }
+        if (rr <= st->tol2) {
+            st->done = 1;
+            return;
+        }
+        if (it >= st->maxit) {
+            st->done = 3;
+            return;
+        }
+        if (st->stag > 0) {
+            const double rel = sqrt(rr / st->rr0);
+            if (rel < 0.9 * st->stag_best) {
+                st->stag_best = rel;
+                st->stag_at = it;
+            } else if (it - st->stag_at >= st->stag) {
+                st->done = 4;
+                return;
+            }
+        }
+        const double beta = gamma / st->rho;
+        const double denom = delta - beta * gamma / st->alpha;
+        if (!(denom > 0.0) || !isfinite(denom)) {
+            st->done = 2;
+            return;
+        }
+        st->alpha = gamma / denom;
+        st->beta = beta;
+        st->rho = gamma;
     }
 };
 

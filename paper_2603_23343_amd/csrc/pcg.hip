@@ -32,8 +32,10 @@ hipError_t run_chain(const Geometry& g, const L& ld, const O& op, const FP& fp, 
     const dim3 grid(g.nblocks), block(BX * BY);
     if constexpr (FAM == 0)
         hipLaunchKernelGGL((k_pcg_direction<C, SP, BX, BY, VX, NC, NCP, L, O, FP>), grid, block, 0, s, g, ld, op, fp, ch);
-    else
+    else if constexpr (FAM == 1)
         hipLaunchKernelGGL((k_pcg_update<C, SP, BX, BY, VX, NC, NCP, L, O, FP>), grid, block, 0, s, g, ld, op, fp, ch);
+    else
+        hipLaunchKernelGGL((k_pcg_sr<C, SP, BX, BY, VX, NC, NCP, L, O, FP>), grid, block, 0, s, g, ld, op, fp, ch);
     return hipGetLastError();
 }
 
@@ -104,6 +106,49 @@ hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, OpDesc od
 hipError_t launch_pcg_close(bool var, const Chain& ch, hipStream_t s) {
     if (var) hipLaunchKernelGGL((k_pcg_close<2, FinBeta>), dim3(1), dim3(64), 0, s, FinBeta{nullptr, nullptr, true}, ch);
     else hipLaunchKernelGGL((k_pcg_close<1, FinBeta>), dim3(1), dim3(64), 0, s, FinBeta{nullptr, nullptr, false}, ch);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_sr_start(int dt, const Plan& p, const Geometry& g, const void* r, void* w, SolveState* st,
+                               Red red, hipStream_t s) {
+    return dispatch_dt(dt, [&](auto tag) {
+        using T = decltype(tag);
+        using C = typename Traits<T>::C;
+        return dispatch_cfg<Traits<T>::W>(p.cfg, [&]<int BX, int BY, int VX>() {
+            LoadPrecond<T> ld{static_cast<const T*>(r), st, C(0)};
+            OpSRStart<T, VX> op{static_cast<const T*>(r), static_cast<T*>(w)};
+            return run_zmarch<ZF_SR_START, C, StencilConst<C>, BX, BY, VX, 2, 0u, true>(g, ld, op, FinSRStart{st}, red,
+                                                                                      &st->done, s);
+        });
+    });
+}
+
+hipError_t launch_pcg_sr(int dt, const Plan& p, const Geometry& g, const SRBufs& b, void* x, int xdt, const Chain& ch,
+                         hipStream_t s) {
+    return dispatch_dt(dt, [&](auto tag) {
+        using T = decltype(tag);
+        using C = typename Traits<T>::C;
+        return dispatch_cfg<Traits<T>::W>(p.cfg, [&]<int BX, int BY, int VX>() {
+            auto go = [&](auto xtag) -> hipError_t {
+                using X = decltype(xtag);
+                LoadSR<T> ld{static_cast<const T*>(b.r_in), static_cast<const T*>(b.w_in),
+                             static_cast<const T*>(b.s_in), nullptr, C(0), C(0), C(0)};
+                OpSR<T, X, VX> op{static_cast<const T*>(b.r_in), static_cast<const T*>(b.w_in),
+                                  static_cast<const T*>(b.s_in), static_cast<T*>(b.r_out), static_cast<T*>(b.w_out),
+                                  static_cast<T*>(b.s_out), static_cast<T*>(b.p), static_cast<X*>(x), nullptr,
+                                  C(0), C(0), C(0), 0.0};
+                return run_chain<2, C, StencilConst<C>, BX, BY, VX, 3, 3>(g, ld, op, FinSR{nullptr, nullptr}, ch, s);
+            };
+            if (xdt == DT_F64) return go(double{});
+            if (xdt == DT_F32) return go(float{});
+            if (xdt == dt) return go(T{});
+            return hipErrorInvalidValue;
+        });
+    });
+}
+
+hipError_t launch_pcg_sr_close(const Chain& ch, hipStream_t s) {
+    hipLaunchKernelGGL((k_pcg_close<3, FinSR>), dim3(1), dim3(64), 0, s, FinSR{nullptr, nullptr}, ch);
     return hipGetLastError();
 }
 

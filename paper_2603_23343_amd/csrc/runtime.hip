@@ -111,7 +111,11 @@ struct pcg_ctx_s {
     double* hres = nullptr;     // [2]
     // graph chunk
     hipGraphExec_t chunk = nullptr;
+    bool chunk_sr = false;  // the captured chunk holds single-reduction iterations
     int chunk_iters = 0;
+    // single-reduction form: r (second), w (two), s (two) in one allocation
+    void* sr = nullptr;
+    bool sr_active = false;
     hipEvent_t ev_chunk[2] = {nullptr, nullptr};
     int last_iters = 0;
     // operator: constant coefficients unless pcg_set_coefficients gave k
@@ -154,7 +158,7 @@ void free_ctx(pcg_ctx c) {
     for (auto& e : c->ev_chunk)
         if (e) (void)hipEventDestroy(e);
     void* dev[] = {c->r, c->p[0], c->p[1], c->xacc, c->partials, c->ticket, c->st, c->hist, c->res2, c->rhat,
-                   c->dinv, c->q, c->z};
+                   c->dinv, c->q, c->z, c->sr};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     if (c->hst) (void)hipHostFree(c->hst);
@@ -221,7 +225,42 @@ pcg_status ensure_hist(pcg_ctx c, int maxit) {
 // update kernel writes st[1] from st[0] and each later direction kernel st[0]
 // from st[1]. Direction partials go to the first half of the partials
 // buffer, update partials (two components at most) to the second.
+// Single-reduction iterations [first, first + count) (count even). Global
+// iteration k = i - 1 reads r[k & 1], w[k & 1], s[(k + 1) & 1] and writes
+// the other buffer of each (halo points of the inputs are read while
+// neighbouring work-groups write their outputs); p and x are updated in
+// place (own points only). The kernels chain their reductions over the two
+// state buffers as the two-kernel form does, so st[0] is current again after
+// the closing kernel.
+hipError_t enqueue_iters_sr(pcg_ctx c, int first, int count, hipStream_t s, hipEvent_t* evs) {
+    if (count <= 0) return hipSuccess;
+    if (count & 1) return hipErrorInvalidValue;
+    const size_t vb = (size_t)c->n * dt_size(c->dt);
+    char* base = static_cast<char*>(c->sr);
+    void* R[2] = {c->r, base};
+    void* W[2] = {base + vb, base + 2 * vb};
+    void* S[2] = {base + 3 * vb, base + 4 * vb};
+    SolveState* st[2] = {c->st, c->st + 1};
+    double* part[2] = {c->partials, c->partials + c->partials_cap / 2};
+    const unsigned nb = c->geo.nblocks;
+    for (int i = first; i < first + count; ++i) {
+        const int k = i - 1, j = i - first;
+        const SRBufs bufs{R[k & 1], W[k & 1], S[(k + 1) & 1], R[(k + 1) & 1], W[(k + 1) & 1], S[k & 1], c->p[0]};
+        const Chain ch = j == 0 ? Chain{nullptr, nb, st[0], st[0], c->hist, part[0]}
+                                : Chain{part[(j - 1) & 1], nb, st[(j + 1) & 1], st[j & 1], c->hist, part[j & 1]};
+        if (evs) (void)hipEventRecord(evs[3 * j], s);
+        hipError_t e = launch_pcg_sr(c->dt, c->plan, c->geo, bufs, c->xacc, c->opt.x_accum, ch, s);
+        if (e != hipSuccess) return e;
+        if (evs) {
+            (void)hipEventRecord(evs[3 * j + 1], s);
+            (void)hipEventRecord(evs[3 * j + 2], s);
+        }
+    }
+    return launch_pcg_sr_close(Chain{part[(count - 1) & 1], nb, st[(count + 1) & 1], st[count & 1], c->hist, nullptr}, s);
+}
+
 hipError_t enqueue_iters(pcg_ctx c, int first, int count, hipStream_t s, hipEvent_t* evs) {
+    if (c->sr_active) return enqueue_iters_sr(c, first, count, s, evs);
     if (count <= 0) return hipSuccess;
     SolveState* s0 = c->st;
     SolveState* s1 = c->st + 1;
@@ -245,7 +284,12 @@ hipError_t enqueue_iters(pcg_ctx c, int first, int count, hipStream_t s, hipEven
 }
 
 pcg_status ensure_chunk(pcg_ctx c) {
+    if (c->chunk && c->chunk_sr != c->sr_active) {
+        HIPCHK(hipGraphExecDestroy(c->chunk));
+        c->chunk = nullptr;
+    }
     if (c->chunk) return PCG_OK;
+    c->chunk_sr = c->sr_active;
     if (!c->capture) HIPCHK(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
     hipError_t e = enqueue_iters(c, 1, c->chunk_iters, c->capture, nullptr);
@@ -271,6 +315,18 @@ struct IterResult {
     double k1_ms = 0.0, k2_ms = 0.0;
     int nk = 0;
 };
+
+// Single-reduction iterations (constant coefficients only): forced by the
+// option, or chosen by size when it is -1. Measured per iteration on MI355X
+// (FP32 storage, FP64 x): 64^3 12.5 us against 14.8 us for two kernels,
+// 128^3 equal, 512 x 112 x 64 37.1 against 33.1, 256^3 174 against 113 (the
+// fused kernel moves 48 B/pt and stages three halo streams). With 16-bit
+// storage it also takes more iterations. So: FP32/FP64 storage up to 64^3.
+bool want_single_reduction(pcg_ctx c) {
+    if (c->kc != nullptr) return false;
+    if (c->opt.single_reduction >= 0) return c->opt.single_reduction != 0;
+    return (c->dt == DT_F32 || c->dt == DT_F64) && c->n <= (int64_t)64 * 64 * 64;
+}
 
 // Start a solve of A x = b on the workspace (x0 = 0, or x0 given in x0 of
 // type x0_dt) and run PCG iterations until the device state says done:
@@ -300,6 +356,15 @@ pcg_status run_iterations(pcg_ctx c, const void* b, const void* x0, int x0_dt, d
     } else {
         HIPCHK(launch_pcg_start_zero(c->dt, c->n, b, c->r, c->xacc, xacc_dt, c->p[0], op_of(c).dinv, c->st,
                                      c->hist, red_of(c), st));
+    }
+    c->sr_active = want_single_reduction(c);
+    if (c->sr_active) {
+        // w0 = A D^-1 r0 and {gamma0, delta0}; s_{-1} = 0 (p_{-1} = 0 from the start above)
+        const size_t vb = (size_t)c->n * dt_size(c->dt);
+        if (!c->sr) HIPCHK(hipMalloc(&c->sr, 5 * vb));
+        char* base = static_cast<char*>(c->sr);
+        HIPCHK(launch_zero(c->dt, c->n, base + 4 * vb, st));
+        HIPCHK(launch_pcg_sr_start(c->dt, c->plan, c->geo, c->r, base + vb, c->st, red_of(c), st));
     }
 
     const int C = c->chunk_iters;
@@ -403,6 +468,7 @@ pcg_status pcg_options_default(pcg_options* o) {
     o->use_graph = 1;
     o->stag_window = -1;
     o->max_restarts = -1;
+    o->single_reduction = -1;
     return PCG_OK;
 }
 
@@ -808,6 +874,7 @@ pcg_status pcg_solve_snapshots(pcg_ctx c, const void* b, void* x, double rtol, i
     init.maxit = maxit;
     c->hst[0] = init;
     HIPCHK(hipMemcpyAsync(c->st, &c->hst[0], sizeof(SolveState), hipMemcpyHostToDevice, st));
+    c->sr_active = false;  // snapshots step one two-kernel iteration at a time
     HIPCHK(launch_pcg_start_zero(c->dt, c->n, b, c->r, c->xacc, c->opt.x_accum, c->p[0], op_of(c).dinv, c->st,
                                  c->hist, red_of(c), st));
     int j = 0;

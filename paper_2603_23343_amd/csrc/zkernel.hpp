@@ -85,9 +85,10 @@ PCGMI_ZKERNEL(k_stencil)
 PCGMI_ZKERNEL(k_flex_direction)
 PCGMI_ZKERNEL(k_residual64)
 PCGMI_ZKERNEL(k_start_x0)
+PCGMI_ZKERNEL(k_sr_start)
 PCGMI_ZKERNEL(k_zgeneric)
 
-enum ZFamily { ZF_STENCIL, ZF_FLEX_DIRECTION, ZF_RESIDUAL64, ZF_START_X0, ZF_GENERIC };
+enum ZFamily { ZF_STENCIL, ZF_FLEX_DIRECTION, ZF_RESIDUAL64, ZF_START_X0, ZF_SR_START, ZF_GENERIC };
 
 template <int FAM, typename C, class SP, int BX, int BY, int VX, int NC, unsigned MM, bool RED, class L, class O,
           class F>
@@ -103,6 +104,8 @@ hipError_t run_zmarch(const Grid3& g, const L& ld, const O& op, const F& fin, Re
         hipLaunchKernelGGL((k_flex_direction<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
     else if constexpr (FAM == ZF_RESIDUAL64)
         hipLaunchKernelGGL((k_residual64<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
+    else if constexpr (FAM == ZF_SR_START)
+        hipLaunchKernelGGL((k_sr_start<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
     else if constexpr (FAM == ZF_START_X0)
         hipLaunchKernelGGL((k_start_x0<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
     else
@@ -210,6 +213,7 @@ __device__ __forceinline__ void chain_body(const Grid3& g, const L& ld, const O&
     }
 PCGMI_CHAIN_KERNEL(k_pcg_direction)
 PCGMI_CHAIN_KERNEL(k_pcg_update)
+PCGMI_CHAIN_KERNEL(k_pcg_sr)
 
 // Finishes the last kernel's partials of a run of chained kernels (one wavefront).
 template <int NCP, class FP> __global__ void __launch_bounds__(64) k_pcg_close(FP fp, Chain ch) {

@@ -70,6 +70,7 @@ def test_options_default(lib):
     o = P.pcg_options_default()
     assert o.chunk_iters == 16 and o.x_accum == -1 and o.use_graph == 1 and o.use_x0 == 0
     assert o.kernel_timing == 0 and o.x_dtype == -1 and o.stag_window == -1 and o.max_restarts == -1
+    assert o.single_reduction == -1
 
 
 def test_product_path_does_not_import_oracle():
