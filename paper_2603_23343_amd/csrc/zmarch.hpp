@@ -181,8 +181,16 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
     // x-halo columns (left: last element of the vector before the tile,
     // right: first element of the vector after it), so every halo load is
     // the same 16-byte load and needs no branch.
+    // LDS column of element e of the vector of thread column t. Eight 4-byte
+    // cells per thread (16-bit storage) go as two halves, elements 0-3 at
+    // 4t and 4-7 at TX/2 + 4t, so a wavefront's 16-byte LDS accesses cover
+    // consecutive banks; stored whole at 8t they hit every other group of
+    // four banks (measured: half of the wave-cycles of the 16-bit stencil
+    // waited on LDS).
+    constexpr bool SPLIT = VX == 8 && sizeof(Cell) == 4;
+    auto lcol = [](int t, int e) { return SPLIT ? (e < 4 ? 4 * t + e : ZT::TX / 2 + 4 * t + e - 4) : VX * t + e; };
     int hkind = 0;  // 0 none, 1 y-row vector, 2 x-column point
-    int hvx = 0, hy = 0, lds_off = 0, hsel = 0;
+    int hvx = 0, hy = 0, lds_off = 0, hsel = 0, hv_t = 0;
     bool hvalid = false;
     if (tid < 2 * BX) {
         hkind = 1;
@@ -191,7 +199,8 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
         hvx = x0 + v * VX;
         hy = y0 + row;
         hvalid = hvx < g.nx && hy >= 0 && hy < g.ny;
-        lds_off = (row + 1) * ZT::PITCH + ZT::PAD + v * VX;
+        lds_off = (row + 1) * ZT::PITCH + ZT::PAD;
+        hv_t = v;
     } else if (tid < 2 * BX + 2 * ZT::TY) {
         hkind = 2;
         int t = tid - 2 * BX;
@@ -266,15 +275,18 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = C(0);
 
-    const int lrow = (ty + 1) * ZT::PITCH + ZT::PAD + tx * VX;
+    const int lrow = (ty + 1) * ZT::PITCH + ZT::PAD;  // start of this thread's row in LDS
+    // x-neighbours of the vector's first and last elements
+    const int lleft = tx == 0 ? -1 : lcol(tx - 1, VX - 1);
+    const int lright = tx == BX - 1 ? ZT::TX : lcol(tx + 1, 0);
     auto step = [&](int k, FRaw& fs, FRaw& hs, ORaw& os) {
         Cell* buf = lds + ((k - z0) & 1) * ZT::PLANE;
         // Stage plane k: own points and halo.
 #pragma unroll
-        for (int i = 0; i < VX; ++i) buf[lrow + i] = zcur.v[i];
+        for (int i = 0; i < VX; ++i) buf[lrow + lcol(tx, i)] = zcur.v[i];
         if (hkind == 1) {
 #pragma unroll
-            for (int i = 0; i < VX; ++i) buf[lds_off + i] = hv.v[i];
+            for (int i = 0; i < VX; ++i) buf[lds_off + lcol(hv_t, i)] = hv.v[i];
         } else if (hkind == 2) {
             buf[lds_off] = hv.v[0];
         }
@@ -288,12 +300,12 @@ __device__ __forceinline__ void zmarch(const Grid3& g, unsigned tile, const Load
         Pts<C, VX> ax;
         const Cell* up = buf + lrow + ZT::PITCH;
         const Cell* dn = buf + lrow - ZT::PITCH;
-        const Cell left = buf[lrow - 1], right = buf[lrow + VX];
+        const Cell left = buf[lrow + lleft], right = buf[lrow + lright];
 #pragma unroll
         for (int i = 0; i < VX; ++i) {
             const Cell l = i == 0 ? left : zcur.v[i - 1];
             const Cell r = i == VX - 1 ? right : zcur.v[i + 1];
-            ax.v[i] = SP::apply(zcur.v[i], l, r, dn[i], up[i], zm.v[i], zp.v[i]);
+            ax.v[i] = SP::apply(zcur.v[i], l, r, dn[lcol(tx, i)], up[lcol(tx, i)], zm.v[i], zp.v[i]);
             if constexpr (LM) ax.v[i] = lane_ok[i] ? ax.v[i] : C(0);
         }
         if (own) op.apply(col + k * sz, os, zcur.v, ax.v, acc);
