@@ -320,12 +320,16 @@ struct IterResult {
 // option, or chosen by size when it is -1. Measured per iteration on MI355X
 // (FP32 storage, FP64 x): 64^3 12.5 us against 14.8 us for two kernels,
 // 128^3 equal, 512 x 112 x 64 37.1 against 33.1, 256^3 174 against 113 (the
-// fused kernel moves 48 B/pt and stages three halo streams). With 16-bit
-// storage it also takes more iterations. So: FP32/FP64 storage up to 64^3.
+// fused kernel moves 48 B/pt and stages three halo streams). Its recursive
+// residual also drifts further from b - A x (the recurrence for s = A p adds
+// rounding): with b = A x* for a smooth x* the FP64 judge restarts it later,
+// and whole solves to a true 1e-6 measured 32^3 1.23 against 1.38 ms, 48^3
+// 1.83 against 1.86, 64^3 2.43 against 2.21. With 16-bit storage it takes
+// more iterations. So: FP32/FP64 storage up to 2^17 points (about 50^3).
 bool want_single_reduction(pcg_ctx c) {
     if (c->kc != nullptr) return false;
     if (c->opt.single_reduction >= 0) return c->opt.single_reduction != 0;
-    return (c->dt == DT_F32 || c->dt == DT_F64) && c->n <= (int64_t)64 * 64 * 64;
+    return (c->dt == DT_F32 || c->dt == DT_F64) && c->n <= ((int64_t)1 << 17);
 }
 
 // Start a solve of A x = b on the workspace (x0 = 0, or x0 given in x0 of
