@@ -8,7 +8,8 @@
  * matrix-free (Sec. VI), with the Jacobi preconditioner D = diag(A) applied
  * as element-wise scaling. PCG is composed of the element-wise update
  * (Sec. IV), the global dot-product reduction (Sec. V) and the stencil
- * (Sec. VI); here they are fused into two kernels per iteration.
+ * (Sec. VI); here they are fused into two kernels per iteration, or into one
+ * kernel with one grid reduction on small grids (pcg_options.single_reduction).
  *
  * Conventions for every entry point:
  *  - Grids are contiguous C-order [nz][ny][nx] arrays, x fastest.
