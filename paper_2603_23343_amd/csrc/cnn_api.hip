@@ -89,6 +89,7 @@ struct cnn_s {
     // the vectors u = N + D^-1 rh - eh and A u
     pcg_ctx op = nullptr;
     float *u = nullptr, *au = nullptr;
+    uint64_t grid_epoch = 0;  // bumped whenever the grid workspace is reallocated
 };
 
 namespace {
@@ -129,6 +130,7 @@ pcg_status ensure_grid(cnn_net n, int nx, int ny, int nz) {
     n->ny = ny;
     n->nz = nz;
     n->nvox = nv;
+    ++n->grid_epoch;
     return PCG_OK;
 }
 
@@ -160,6 +162,24 @@ pcg_status forward(cnn_net n, float* out, const double* rr, double mul) {
 
 namespace pcgmi {
 hipStream_t cnn_stream_of(cnn_net n) { return n->stream; }
+// The stream the network launches on (a capturing stream while a solver
+// records a graph of its iterations); returns the previous one.
+hipStream_t cnn_swap_stream(cnn_net n, hipStream_t s) {
+    hipStream_t old = n->stream;
+    n->stream = s;
+    return old;
+}
+// Grid workspace and swizzled weights ready for nx x ny x nz (nothing is
+// allocated or launched later by cnn_forward on that grid until the weights
+// change); *epoch identifies the workspace's buffers.
+pcg_status cnn_prepare(cnn_net n, int nx, int ny, int nz, uint64_t* epoch) {
+    pcg_status st = ensure_grid(n, nx, ny, nz);
+    if (st != PCG_OK) return st;
+    st = ensure_swizzled(n);
+    if (st != PCG_OK) return st;
+    *epoch = n->grid_epoch;
+    return PCG_OK;
+}
 }  // namespace pcgmi
 
 extern "C" {

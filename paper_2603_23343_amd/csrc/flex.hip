@@ -10,7 +10,8 @@
 //   direction: p = z + beta p_old on the fly for the tile and its halo,
 //              q = A p stored, sigma = p.q and p.r -> alpha;
 //   update:    x += alpha p, r -= alpha q, ||r||^2 -> convergence, and the
-//              stagnation test that switches to Jacobi;
+//              stagnation test that switches to Jacobi (per-work-group
+//              partials, finished by a one-work-group kernel);
 //   M:         the network's correction (cnn_forward, scaled by rms(r)
 //              from the state) or nothing when Jacobi is selected;
 //   select:    z = D^-1 r, plus the correction while the network is in use,
@@ -184,9 +185,11 @@ __global__ void __launch_bounds__(NT) k_flex_update(int64_t n, const T* __restri
         r[i] = from_c<T>(rv);
         acc += rv * rv;
     }
-    double v[1] = {(double)acc}, tot[1];
-    if (grid_reduce<1, 0u>(v, red.partials, red.ticket, gridDim.x, blockIdx.x, scratch, tot) && threadIdx.x == 0)
-        FinFlexRes{st, hist}(tot);
+    // partial per work-group; k_flex_finish applies FinFlexRes (a kernel
+    // boundary instead of an agent-scope release fence per work-group)
+    double v[1] = {(double)acc};
+    block_reduce<1, 0u>(v, scratch);
+    if (threadIdx.x == 0) red.partials[blockIdx.x] = v[0];
 }
 
 // z = D^-1 r (+ the network's correction in z unless Jacobi is selected or
@@ -213,9 +216,31 @@ __global__ void __launch_bounds__(NT) k_flex_select(int64_t n, T* __restrict__ z
         zq += zv * to_c(q[i]);
         zr += zv * rv;
     }
-    double v[2] = {(double)zq, (double)zr}, tot[2];
-    if (grid_reduce<2, 0u>(v, red.partials, red.ticket, gridDim.x, blockIdx.x, scratch, tot) && threadIdx.x == 0)
-        FinFlexBeta{st, redo_pass != 0}(tot);
+    double v[2] = {(double)zq, (double)zr};
+    block_reduce<2, 0u>(v, scratch);
+    if (threadIdx.x == 0) {
+        red.partials[2 * blockIdx.x] = v[0];
+        red.partials[2 * blockIdx.x + 1] = v[1];
+    }
+}
+
+// One work-group: sums the partials of the kernel before it in index order
+// and applies its finisher, unless that kernel skipped (done, or the redo
+// pass without a redo).
+template <int NC, class F>
+__global__ void __launch_bounds__(NT) k_flex_finish(const double* __restrict__ partials, unsigned nblocks, F fin,
+                                                    const SolveState* st, int redo_pass) {
+    if (st->done) return;
+    if (redo_pass && !(st->flags & FLEX_REDO)) return;
+    __shared__ double lds[NC * 16];
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    for (unsigned i = threadIdx.x; i < nblocks; i += NT)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += partials[NC * i + c];
+    block_reduce<NC, 0u>(acc, lds);
+    if (threadIdx.x == 0) fin(acc);
 }
 
 inline unsigned nblk(int64_t n) {
@@ -247,6 +272,8 @@ hipError_t launch_flex_update(int64_t n, const float* p, const float* q, float* 
     const unsigned nb = nblk(n);
     if ((size_t)nb > red.cap) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_flex_update<float>, dim3(nb), dim3(NT), 0, s, n, p, q, r, x, st, hist, red);
+    hipLaunchKernelGGL((k_flex_finish<1, FinFlexRes>), dim3(1), dim3(NT), 0, s, red.partials, nb, FinFlexRes{st, hist},
+                       st, 0);
     return hipGetLastError();
 }
 
@@ -255,6 +282,8 @@ hipError_t launch_flex_select(int64_t n, float* z, const float* r, const float* 
     const unsigned nb = nblk(n);
     if ((size_t)2 * nb > red.cap) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_flex_select<float>, dim3(nb), dim3(NT), 0, s, n, z, r, q, dinv, st, redo_pass ? 1 : 0, red);
+    hipLaunchKernelGGL((k_flex_finish<2, FinFlexBeta>), dim3(1), dim3(NT), 0, s, red.partials, nb,
+                       FinFlexBeta{st, redo_pass}, st, redo_pass ? 1 : 0);
     return hipGetLastError();
 }
 

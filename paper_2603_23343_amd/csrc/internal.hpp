@@ -152,6 +152,8 @@ hipError_t launch_flex_select(int64_t n, float* z, const float* r, const float* 
 hipError_t launch_make_pair(int64_t n, const double* r, const double* x, const double* xs, const double* rr,
                             void* out, hipStream_t s);
 hipStream_t cnn_stream_of(cnn_net n);
+hipStream_t cnn_swap_stream(cnn_net n, hipStream_t s);
+pcg_status cnn_prepare(cnn_net n, int nx, int ny, int nz, uint64_t* epoch);
 
 constexpr int DOT_MAX_BLOCKS = 2048;
 constexpr int STREAM_THREADS = 256;

@@ -124,6 +124,17 @@ struct pcg_ctx_s {
     // flexible CG
     void* q = nullptr;  // A p (storage type)
     void* z = nullptr;  // preconditioned residual (storage type)
+    // captured flexible iterations: [0] Jacobi, [1] with the network, and
+    // what they were recorded with
+    hipGraphExec_t flex_exec[2] = {nullptr, nullptr};
+    struct FlexKey {
+        cnn_net net = nullptr;
+        const float* g = nullptr;
+        uint64_t epoch = 0;
+        const void* hist = nullptr;
+        const float* kc = nullptr;
+        int chunk = 0;
+    } flex_key[2];
     // iterative refinement
     void* rhat = nullptr;  // scaled residual in the storage type
     std::vector<double> ref_relres;
@@ -155,6 +166,8 @@ namespace {
 void free_ctx(pcg_ctx c) {
     if (!c) return;
     if (c->chunk) (void)hipGraphExecDestroy(c->chunk);
+    for (auto& fe : c->flex_exec)
+        if (fe) (void)hipGraphExecDestroy(fe);
     for (auto& e : c->ev_chunk)
         if (e) (void)hipEventDestroy(e);
     void* dev[] = {c->r, c->p[0], c->p[1], c->xacc, c->partials, c->ticket, c->st, c->hist, c->res2, c->rhat,
@@ -793,31 +806,96 @@ pcg_status pcg_solve_flexible(pcg_ctx c, cnn_net net, const float* g, const void
     s = precond(net_on);
     if (s != PCG_OK) return s;
 
+    // Iterations k = 1..C of a chunk (C even, so iteration parity repeats) on
+    // stream s; the network launches on its own stream, swapped to s.
+    const int C = c->chunk_iters;
+    auto enqueue_chunk = [&](bool use_net, hipStream_t sq) -> pcg_status {
+        for (int k = 1; k <= C; ++k) {
+            void* pold = c->p[(k - 1) & 1];
+            void* pnew = c->p[k & 1];
+            HIPCHK(launch_flex_direction(c->plan, c->geo, od, z, static_cast<const float*>(pold),
+                                         static_cast<float*>(pnew), q, r, c->st, red_of(c), sq));
+            HIPCHK(launch_flex_update(c->n, static_cast<const float*>(pnew), q, r, xacc, c->st, c->hist, red_of(c),
+                                      sq));
+            if (use_net) {
+                pcg_status ps = cnn_forward(net, c->nx, c->ny, c->nz, PCG_F32, r, g, &c->st->rr, z);
+                if (ps != PCG_OK) return ps;
+            }
+            HIPCHK(launch_flex_select(c->n, z, r, q, dinv, c->st, false, red_of(c), sq));
+            HIPCHK(launch_flex_select(c->n, z, r, q, dinv, c->st, true, red_of(c), sq));
+        }
+        return PCG_OK;
+    };
+    // A chunk is replayed from a captured graph (recorded once per network,
+    // field, workspace and operator): the flexible iteration is ~9 launches,
+    // latency-bound on small grids. Kernels after convergence or a switch to
+    // Jacobi skip their work on the device state, as in the eager loop.
+    uint64_t epoch = 0;
+    if (net) {
+        s = cnn_prepare(net, c->nx, c->ny, c->nz, &epoch);
+        if (s != PCG_OK) return s;
+    }
+    auto chunk_graph = [&](bool use_net, hipGraphExec_t* out) -> pcg_status {
+        const int slot = use_net ? 1 : 0;
+        const pcg_ctx_s::FlexKey key{use_net ? net : nullptr, use_net ? g : nullptr, use_net ? epoch : 0, c->hist,
+                                     c->kc, C};
+        auto& have = c->flex_key[slot];
+        if (c->flex_exec[slot] && have.net == key.net && have.g == key.g && have.epoch == key.epoch &&
+            have.hist == key.hist && have.kc == key.kc && have.chunk == key.chunk) {
+            *out = c->flex_exec[slot];
+            return PCG_OK;
+        }
+        if (c->flex_exec[slot]) {
+            HIPCHK(hipGraphExecDestroy(c->flex_exec[slot]));
+            c->flex_exec[slot] = nullptr;
+        }
+        if (!c->capture) HIPCHK(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+        hipStream_t old = use_net ? cnn_swap_stream(net, c->capture) : nullptr;
+        hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
+        pcg_status ps = e == hipSuccess ? enqueue_chunk(use_net, c->capture) : PCG_E_HIP;
+        hipGraph_t gr = nullptr;
+        hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(c->capture, &gr) : e;
+        if (use_net) (void)cnn_swap_stream(net, old);
+        if (ps != PCG_OK || e2 != hipSuccess) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return ps != PCG_OK ? ps : fail(PCG_E_HIP, "capturing flexible iterations failed: %s", hipGetErrorString(e2));
+        }
+        hipError_t e3 = hipGraphInstantiate(&c->flex_exec[slot], gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e3 != hipSuccess) {
+            c->flex_exec[slot] = nullptr;
+            return fail(PCG_E_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
+        }
+        have = key;
+        *out = c->flex_exec[slot];
+        return PCG_OK;
+    };
+
     SolveState fin{};
     int it = 0;
-    const int C = c->chunk_iters;
+    const bool graph = c->opt.use_graph && !c->opt.kernel_timing;
     for (;;) {
         HIPCHK(hipMemcpyAsync(&c->hst[1], c->st, sizeof(SolveState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         fin = c->hst[1];
         if (fin.done != 0 || it >= maxit) break;
         if (fin.flags & FLEX_JACOBI) net_on = false;
-        for (int k = 0; k < C && it < maxit; ++k) {
-            ++it;
-            void* pold = c->p[(it - 1) & 1];
-            void* pnew = c->p[it & 1];
-            HIPCHK(launch_flex_direction(c->plan, c->geo, od, z, static_cast<const float*>(pold),
-                                         static_cast<float*>(pnew), q, r, c->st, red_of(c), st));
-            HIPCHK(launch_flex_update(c->n, static_cast<const float*>(pnew), q, r, xacc, c->st, c->hist, red_of(c),
-                                      st));
-            s = precond(net_on);
+        if (graph) {
+            hipGraphExec_t ge = nullptr;
+            s = chunk_graph(net_on, &ge);
+            if (s != PCG_OK) return s;
+            HIPCHK(hipGraphLaunch(ge, st));
+        } else {
+            s = enqueue_chunk(net_on, st);
             if (s != PCG_OK) return s;
         }
+        it += C;
     }
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipMemcpy(&fin, c->st, sizeof(SolveState), hipMemcpyDeviceToHost));
     int iters = fin.iters;
     int fallback = fin.fallback_at >= 0 ? 1 : 0;
+    int status = fin.done;
 
     // The FP64 true residual judges the result; if the recursion converged
     // but the true residual did not, continue with Jacobi-PCG from this x.
@@ -825,8 +903,7 @@ pcg_status pcg_solve_flexible(pcg_ctx c, cnn_net net, const float* g, const void
     HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     double true_rel = fin.rr0 > 0 ? std::sqrt(c->hres[0] / fin.rr0) : 0.0;
-    int status = fin.done;
-    if (fin.done == 1 && true_rel > rtol && iters < maxit) {
+    if (status == 1 && true_rel > rtol && iters < maxit) {
         IterResult res;
         s = run_iterations(c, b, xacc, DT_F64, rtol, maxit - iters, 0, &res);
         if (s != PCG_OK) return s;

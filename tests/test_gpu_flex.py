@@ -159,3 +159,37 @@ def test_snapshots_and_pairs(P, orc):
         rho = np.sqrt(np.dot(rk, rk) / N)
         assert np.array_equal(pf[2 * j * N:(2 * j + 1) * N], orc.round_bf16(rk / rho))
         assert np.array_equal(pf[(2 * j + 1) * N:(2 * j + 2) * N], orc.round_bf16((xst - xk) / rho))
+
+
+def test_fcg_graph_replay_matches_eager(P, orc):
+    """The captured chunk graphs (cached per network, field and workspace)
+    give the eager loop's bits: the same solve graph-replayed twice, with a
+    weight change in between (the swizzled weights are refreshed outside the
+    graph), against eager solves with the same weights."""
+    n = 20
+    shape = (n, n, n)
+    k32 = synthetic.coefficient_field(n)
+    kd = torch.from_numpy(k32).cuda()
+    g = torch.from_numpy(synthetic.gaussian_random_field(n).astype(np.float32)).cuda()
+    b, b64 = make_vec(45, n ** 3, torch.float32)
+    net = P.cnn_create()
+
+    def solve(use_graph):
+        ctx = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64, use_graph=use_graph)
+        P.pcg_set_coefficients(ctx, kd)
+        x = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+        out = []
+        for c in (-0.05, 0.08):
+            P.cnn_set_weights(net, torch.from_numpy(_flat(_scaled_identity_net(c))).cuda())
+            info = P.pcg_solve_flexible(ctx, net, g, b, x, rtol=1e-6, maxit=3000, raise_on_error=False)
+            out.append((info["iters"], info["fallback_used"], x.clone()))
+        ctx.close()
+        return out
+
+    eager = solve(0)
+    graph = solve(1)
+    for (ie, fe, xe), (ig, fg, xg) in zip(eager, graph):
+        assert ie == ig and fe == fg
+        assert torch.equal(xe, xg)
+        assert orc.true_relres(shape, b64, xg.cpu().numpy(), kcell=k32.astype(np.float64)) <= 1e-6
+    net.close()
