@@ -190,10 +190,11 @@ __global__ void __launch_bounds__(256) k_loss_sums(int64_t n, const float* __res
         a += dlt * dlt;
         b += t * t;
     }
-    double v[2] = {a, b}, tot[2];
-    if (grid_reduce<2, 0u>(v, red.partials, red.ticket, gridDim.x, blockIdx.x, scratch, tot) && threadIdx.x == 0) {
-        *loss_acc += tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
-        *coef = tot[1] > 0.0 ? 2.0 / tot[1] : 0.0;
+    double v[2] = {a, b};
+    block_reduce<2, 0u>(v, scratch);
+    if (threadIdx.x == 0) {
+        red.partials[2 * blockIdx.x] = v[0];
+        red.partials[2 * blockIdx.x + 1] = v[1];
     }
 }
 
@@ -239,10 +240,29 @@ __global__ void __launch_bounds__(256) k_anorm_sums(int64_t n, const float* __re
         a += (double)u[i] * (double)au[i];
         b += (dinv ? (double)dinv[i] : 1.0 / 6.0) * r * r;
     }
-    double v[2] = {a, b}, tot[2];
-    if (grid_reduce<2, 0u>(v, red.partials, red.ticket, gridDim.x, blockIdx.x, scratch, tot) && threadIdx.x == 0) {
-        *loss_acc += tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
-        *coef = tot[1] > 0.0 ? 2.0 / tot[1] : 0.0;
+    double v[2] = {a, b};
+    block_reduce<2, 0u>(v, scratch);
+    if (threadIdx.x == 0) {
+        red.partials[2 * blockIdx.x] = v[0];
+        red.partials[2 * blockIdx.x + 1] = v[1];
+    }
+}
+
+// One work-group: the loss sums' partials in index order -> loss_acc +=
+// tot0 / tot1 and coef = 2 / tot1 (a kernel boundary instead of an
+// agent-scope release fence per work-group of the sums).
+__global__ void __launch_bounds__(256) k_loss_finish(const double* __restrict__ partials, unsigned nblocks,
+                                                     double* loss_acc, double* coef) {
+    __shared__ double lds[32];
+    double acc[2] = {0.0, 0.0};
+    for (unsigned i = threadIdx.x; i < nblocks; i += 256) {
+        acc[0] += partials[2 * i];
+        acc[1] += partials[2 * i + 1];
+    }
+    block_reduce<2, 0u>(acc, lds);
+    if (threadIdx.x == 0) {
+        *loss_acc += acc[1] > 0.0 ? acc[0] / acc[1] : 0.0;
+        *coef = acc[1] > 0.0 ? 2.0 / acc[1] : 0.0;
     }
 }
 
@@ -335,6 +355,7 @@ hipError_t launch_loss(int64_t n, const float* out, const void* tgt, double* los
     if ((size_t)2 * nb > red.cap) return hipErrorInvalidValue;
     auto t16 = static_cast<const uint16_t*>(tgt);
     hipLaunchKernelGGL(k_loss_sums, dim3((unsigned)nb), dim3(256), 0, s, n, out, t16, loss_acc, coef, red);
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, s, red.partials, (unsigned)nb, loss_acc, coef);
     hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)nb), dim3(256), 0, s, n, out, t16, coef, dout,
                        static_cast<uint32_t*>(dpack));
     return hipGetLastError();
@@ -356,6 +377,7 @@ hipError_t launch_anorm_loss(int64_t n, const float* u, const float* au, const v
     if ((size_t)2 * nb > red.cap) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_anorm_sums, dim3((unsigned)nb), dim3(256), 0, s, n, u, au,
                        static_cast<const uint16_t*>(rh), dinv, loss_acc, coef, red);
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, s, red.partials, (unsigned)nb, loss_acc, coef);
     hipLaunchKernelGGL(k_scale_grad, dim3((unsigned)nb), dim3(256), 0, s, n, au, coef, dout,
                        static_cast<uint32_t*>(dpack));
     return hipGetLastError();
