@@ -10,6 +10,9 @@ Contents, with the passage each follows:
       -> oracle.c (paper Sec. VII: matrix-free seven-point operator with zero
          Dirichlet boundaries, Jacobi preconditioner, PCG; Sec. IV/V:
          element-wise update and global dot).
+  csr_spmv
+      -> oracle.c: y = A x for a compressed-row matrix (Sec. VII-A: the GPU
+         comparison system's SpMV, there on a sliced-ELLPACK matrix).
   stencil_loops, assemble_dense
       -> pure-Python twins for tiny grids (brute force).
   round_f32 / round_bf16 / round_f16
@@ -58,6 +61,8 @@ def _load():
     lib.oracle_vstencil.argtypes = [i, i, i, _dp, _dp, _dp]
     lib.oracle_vdiag.argtypes = [i, i, i, _dp, _dp]
     lib.oracle_axpy.argtypes = [i64, d, _dp, _dp, _dp]
+    lib.oracle_csr_spmv.argtypes = [i64, ctypes.c_void_p, ctypes.c_void_p, _dp, _dp, _dp]
+    lib.oracle_csr_spmv.restype = None
     lib.oracle_dot.argtypes = [i64, _dp, _dp]
     lib.oracle_dot.restype = d
     lib.oracle_pcg.argtypes = [i, i, i, _dp, _dp, _dp, d, i, _dp,
@@ -132,6 +137,22 @@ def axpy(alpha, x, y) -> np.ndarray:
 def dot(x, y) -> float:
     x, y = _f64(x), _f64(y)
     return float(_load().oracle_dot(x.size, _ptr(x), _ptr(y)))
+
+
+def csr_spmv(rowptr, col, val, x) -> np.ndarray:
+    """y = A x for A in compressed-row form (rowptr int64, col int32), FP64."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val, x = _f64(val), _f64(x)
+    nrows = rowptr.size - 1
+    if rowptr[0] != 0 or rowptr[-1] != col.size or col.size != val.size:
+        raise ValueError("csr_spmv: inconsistent compressed-row arrays")
+    if col.size and (col.min() < 0 or col.max() >= x.size):
+        raise ValueError("csr_spmv: column index out of range")
+    y = np.empty(nrows, dtype=np.float64)
+    if nrows:
+        _load().oracle_csr_spmv(nrows, rowptr.ctypes.data, col.ctypes.data, _ptr(val), _ptr(x), _ptr(y))
+    return y
 
 
 def pcg(shape, b, rtol=1e-6, maxit=500, kcell=None, x0=None, history=False):

@@ -15,6 +15,8 @@
  *     k_f the harmonic mean of the two cell values, k_f = k_p on a boundary
  *     face, u = 0 outside, and its diagonal D_p = sum_f k_f;
  *   - axpy, dot (Sec. IV, Sec. V: element-wise update and global sum);
+ *   - SpMV of a general sparse matrix in compressed-row form (Sec. VII-A's
+ *     GPU comparison system builds CG from norm, dot, axpy and SpMV);
  *   - Jacobi-preconditioned CG in the Hestenes-Stiefel form (Saad,
  *     Iterative Methods for Sparse Linear Systems, 2nd ed., Alg. 9.1),
  *     stopping on the recursive residual relative to ||b||, and the same
@@ -160,6 +162,25 @@ double oracle_dot(int64_t n, const double *x, const double *y)
         s += part[c];
     free(part);
     return s;
+}
+
+/*
+ * y = A x for a general sparse matrix in compressed-row form: row i holds the
+ * entries val[k] at columns col[k] for rowptr[i] <= k < rowptr[i+1], and
+ * y_i is their sum of val[k] * x[col[k]], taken in storage order. This is the
+ * SpMV of the GPU comparison system in Sec. VII-A (which stores the operator
+ * in a sliced-ELLPACK format); compressed rows are the plain definition.
+ */
+void oracle_csr_spmv(int64_t nrows, const int64_t *rowptr, const int32_t *col, const double *val,
+                     const double *x, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nrows; ++i) {
+        double s = 0.0;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            s += val[k] * x[col[k]];
+        y[i] = s;
+    }
 }
 
 static void apply_op(int nx, int ny, int nz, const double *kc, const double *x, double *y)

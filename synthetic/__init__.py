@@ -31,6 +31,8 @@ SEED_C5_HELDOUT_BASE = 20000
 # The paper's GPU comparison grid (its Table III): nx x ny x nz, b ~ U[-1, 1].
 PAPER_GRID = (512, 112, 64)
 SEED_PAPER_GRID_B = 7
+# Sparse matrices for the general (compressed-row / sliced-ELLPACK) SpMV.
+SEED_SPARSE = 8
 
 
 def uniform(seed: int, n: int) -> np.ndarray:
@@ -125,3 +127,58 @@ def gaussian_random_field(n: int, seed: int = SEED_C5_GRF, corr_len: float = 8.0
 def coefficient_field(n: int, seed: int = SEED_C5_GRF) -> np.ndarray:
     """Cell coefficient k = exp(g) of the variable-coefficient workload, FP32."""
     return np.exp(gaussian_random_field(n, seed)).astype(np.float32)
+
+
+def poisson7_csr(nx: int, ny: int, nz: int):
+    """The seven-point operator's matrix in compressed-row form.
+
+    Row p of the [nz][ny][nx] grid holds 6 at column p and -1 at each face
+    neighbour inside the grid, columns ascending (-z, -y, -x, p, +x, +y, +z).
+    Returns (rowptr int64, col int32, val float32).
+    """
+    n = nx * ny * nz
+    idx = np.arange(n, dtype=np.int64)
+    i = idx % nx
+    j = (idx // nx) % ny
+    k = idx // (nx * ny)
+    offs = (-nx * ny, -nx, -1, 0, 1, nx, nx * ny)
+    ok = (k > 0, j > 0, i > 0, np.ones(n, dtype=bool), i < nx - 1, j < ny - 1, k < nz - 1)
+    cols = np.empty((n, 7), dtype=np.int32)
+    mask = np.empty((n, 7), dtype=bool)
+    for t in range(7):
+        cols[:, t] = idx + offs[t] if offs[t] else idx
+        mask[:, t] = ok[t]
+    del idx, i, j, k
+    counts = mask.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    col = cols[mask]
+    val = np.where(col.astype(np.int64) == np.repeat(np.arange(n, dtype=np.int64), counts), 6.0, -1.0)
+    return rowptr, col, val.astype(np.float32)
+
+
+def random_csr(nrows: int, ncols: int, seed: int = SEED_SPARSE, max_len: int = 40,
+               empty_frac: float = 0.0, integer: bool = False):
+    """A random compressed-row matrix with ragged rows.
+
+    Row lengths are uniform on 1..max_len (a fraction empty_frac of rows is
+    empty), columns distinct, uniform over 0..ncols-1 and ascending; values
+    U[-1, 1) cast to FP32, or integers in [-3, 3] when integer is set.
+    Returns (rowptr int64, col int32, val float32).
+    """
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(1, max_len + 1, nrows)
+    lens = np.minimum(lens, ncols)
+    if empty_frac > 0:
+        lens[rng.random(nrows) < empty_frac] = 0
+    rowptr = np.zeros(nrows + 1, dtype=np.int64)
+    np.cumsum(lens, out=rowptr[1:])
+    col = np.empty(int(rowptr[-1]), dtype=np.int32)
+    for r in range(nrows):
+        if lens[r]:
+            col[rowptr[r]:rowptr[r + 1]] = np.sort(rng.choice(ncols, int(lens[r]), replace=False))
+    if integer:
+        val = rng.integers(-3, 4, col.size).astype(np.float32)
+    else:
+        val = rng.uniform(-1.0, 1.0, col.size).astype(np.float32)
+    return rowptr, col, val
