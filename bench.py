@@ -27,6 +27,9 @@ Also reported on the same JSON line:
   small_grid    -- the 32^3 workload with both iteration forms;
   kernels_512   -- standalone stencil / axpy / dot at 512^3 (FP32 and BF16),
                    achieved GB/s of algorithmic bytes;
+  sell_spmv     -- general sparse SpMV (sliced ELLPACK) of the explicitly
+                   stored seven-point matrix at 256^3 and on the paper's
+                   comparison grid, beside the matrix-free stencil;
   batched       -- 64 uneven problems (edges log-uniform in [16, 128], seed 5;
                    b_i ~ U[-1,1], seeds 1000 + i) in one persistent
                    hipGraph-captured launch: solves/s, per-problem latency,
@@ -132,6 +135,48 @@ def time_kernels_512(P, torch, n, reps):
                                    "frac": round(gbs / HBM_PEAK_GBS, 4)}
         P.pcg_destroy(ctx)
         del x, y, z
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_sell(P, torch, reps, grids=((256, 256, 256), None)):
+    """General sparse SpMV in sliced ELLPACK (C = 64, sigma = 1) on the
+    seven-point matrix stored explicitly, the form the paper's GPU comparison
+    system uses, beside the matrix-free stencil on the same grid. Algorithmic
+    bytes: 8 per stored entry (FP32 value, int32 column) + 4 per row for x
+    and 4 for y; padding slots are reported apart."""
+    import synthetic
+
+    out = {}
+    for dims in grids:
+        nx, ny, nz = synthetic.PAPER_GRID if dims is None else dims
+        N = nx * ny * nz
+        rowptr, col, val = synthetic.poisson7_csr(nx, ny, nz)
+        A = P.pcg_sell_create(rowptr, col, val, N, sigma=1)
+        del rowptr, col, val
+        x = torch.from_numpy(synthetic.uniform_f32(synthetic.SEED_C2_X, N)).cuda()
+        y = torch.empty_like(x)
+        ctx = P.pcg_create(nx, ny, nz, torch.float32)
+        res = {"grid": [nx, ny, nz], "nnz": A.nnz, "slots": A.nslots}
+        for name, fn, nbytes in (("sell_spmv", lambda: P.pcg_sell_spmv(A, x, y), 8 * A.nnz + 8 * N),
+                                 ("matrix_free_stencil", lambda: P.stencil_apply(ctx, x, y), 8 * N)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            e1.synchronize()
+            us = e0.elapsed_time(e1) / reps * 1e3
+            gbs = nbytes / (us * 1e-6) / 1e9
+            res[name] = {"us": round(us, 2), "bytes": nbytes, "GB/s": round(gbs, 1),
+                         "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        out["x".join(str(v) for v in (nx, ny, nz))] = res
+        P.pcg_destroy(ctx)
+        A.close()
+        del x, y
         torch.cuda.empty_cache()
     return out
 
@@ -420,6 +465,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-paper-grid", action="store_true")
+    ap.add_argument("--no-sell", action="store_true")
     ap.add_argument("--learned-n", default="64,128",
                     help="comma-separated grid sizes of the learned-preconditioner workflow")
     ap.add_argument("--learned-rounds", type=int, default=12)
@@ -524,6 +570,11 @@ def main():
         learned = bench_learned(P, torch, sizes, args.learned_rounds, oracle_cpu=not args.no_cpu_baseline)
         print(f"# learned: {learned}", file=sys.stderr, flush=True)
 
+    sell = None
+    if not args.no_sell:
+        sell = bench_sell(P, torch, args.kernel_reps)
+        print(f"# sell: {sell}", file=sys.stderr, flush=True)
+
     kern = None
     if not args.no_kernels:
         del ctx
@@ -551,6 +602,7 @@ def main():
         "small_grid": small_grid,
         "learned": learned,
         "kernels_512": kern,
+        "sell_spmv": sell,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

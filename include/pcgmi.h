@@ -334,6 +334,55 @@ pcg_status pcg_batch_layout(pcg_batch batch, int64_t *offsets, int64_t *total, i
 pcg_status pcg_batch_solve(pcg_batch batch, const float *b, double *x, double rtol, int maxit, int use_graph,
                            int *iters, double *relres, double *latency_s, int *restarts, double *seconds);
 
+/* ------------------------------------------------------------------------
+ * General sparse matrices: SpMV in sliced ELLPACK (SELL-C-sigma).
+ *
+ * Sec. VII-A builds its GPU comparison system's CG from norm, dot, axpy and
+ * SpMV, with the seven-point operator stored as a general sparse matrix in a
+ * sliced-ELLPACK format. These entry points take any matrix in compressed-row
+ * form: row i holds values[k] at column colidx[k] for rowptr[i] <= k <
+ * rowptr[i+1] (rowptr[0] = 0, rowptr non-decreasing, 0 <= colidx < ncols).
+ *
+ * Layout (SELL-C-sigma of Kreutzer, Hager, Wellein, Fehske and Bishop, SIAM
+ * J. Sci. Comput. 36(5), 2014): rows are sorted by decreasing length inside
+ * windows of sigma consecutive rows (a stable sort: equal lengths keep their
+ * order; sigma = 1 keeps the original order), then cut into chunks of C
+ * consecutive sorted rows. Chunk c stores width_c slots per row, width_c
+ * being the longest row of the chunk, column-major: entry j of the chunk's
+ * row l is slot chunk_ptr[c] + j * C + l. A row keeps its entries in storage
+ * order; padding slots hold column -1 and value 0. perm[s] is the original
+ * row at sorted position s.
+ * ------------------------------------------------------------------------ */
+typedef struct pcg_sell_s *pcg_sell;
+
+/* Host-only layout of a compressed-row matrix (all pointers HOST). chunk >= 1;
+ * sigma = 1 or a multiple of chunk; nrows, ncols in [0, 2^31 - 1]. First call
+ * with chunk_ptr, perm, col_out and val_out all NULL: fills *nchunks
+ * (ceil(nrows / chunk)) and *nslots (total slots). Second call with
+ * chunk_ptr int64[nchunks + 1], perm int32[nrows], col_out int32[nslots] and
+ * val_out float[nslots]. PCG_E_ARG for an inconsistent rowptr or a column
+ * out of range. No GPU call is made. */
+pcg_status pcg_sell_build(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *colidx,
+                          const float *values, int chunk, int sigma, int64_t *nchunks, int64_t *nslots,
+                          int64_t *chunk_ptr, int32_t *perm, int32_t *col_out, float *val_out);
+
+/* Build the layout with C = 64 (one wavefront per chunk) from HOST arrays
+ * and copy it to device memory that the handle owns (freed by
+ * pcg_sell_destroy). hip_stream: the stream the SpMV runs on (NULL: the null
+ * stream). PCG_E_NOMEM if the device memory cannot be allocated. */
+pcg_status pcg_sell_create(pcg_sell *out, int64_t nrows, int64_t ncols, const int64_t *rowptr,
+                           const int32_t *colidx, const float *values, int sigma, void *hip_stream);
+pcg_status pcg_sell_destroy(pcg_sell A);
+/* Host outputs, each optional: stored entries, slots (padding included),
+ * chunks. */
+pcg_status pcg_sell_info(pcg_sell A, int64_t *nnz, int64_t *nslots, int64_t *nchunks);
+
+/* y = A x on the handle's stream, asynchronous. x: DEVICE float[ncols]; y:
+ * DEVICE float[nrows], 4-byte aligned, not overlapping x (PCG_E_ARG). Each
+ * row is summed in FP32 with fused multiply-adds over its entries in storage
+ * order, starting from 0. */
+pcg_status pcg_sell_spmv(pcg_sell A, const float *x, float *y);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *pcg_last_error(void);
 

@@ -12,4 +12,5 @@ from ._binding import (  # noqa: F401
     PCG_E_UNSUPPORTED, PCG_F16, PCG_F32, PCG_F64, PCG_OK, Context, PcgError, PcgInfo, PcgOptions, axpy,
     dot, dot_f64, dtype_code, lib, pcg_create, pcg_destroy, pcg_get_history, pcg_last_error,
     pcg_options_default, pcg_make_pairs, pcg_refine_history, pcg_set_coefficients, pcg_solve, pcg_solve_flexible, pcg_solve_refined,
-    pcg_solve_snapshots, stencil_apply)
+    pcg_solve_snapshots, stencil_apply,
+    Sell, pcg_sell_build, pcg_sell_create, pcg_sell_destroy, pcg_sell_spmv)

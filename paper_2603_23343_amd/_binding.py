@@ -10,6 +10,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 import torch  # loads the HIP runtime the library binds to
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -87,6 +89,11 @@ def _load():
         "pcg_batch_layout": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i), ctypes.POINTER(i)], i),
         "pcg_batch_solve": ([vp, vp, vp, d, i, i, ctypes.POINTER(i), ctypes.POINTER(d), ctypes.POINTER(d),
                              ctypes.POINTER(i), ctypes.POINTER(d)], i),
+        "pcg_sell_build": ([i64, i64, vp, vp, vp, i, i, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp, vp], i),
+        "pcg_sell_create": ([ctypes.POINTER(vp), i64, i64, vp, vp, vp, i, vp], i),
+        "pcg_sell_destroy": ([vp], i),
+        "pcg_sell_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)], i),
+        "pcg_sell_spmv": ([vp, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -473,3 +480,73 @@ def pcg_batch_solve(batch: Batch, b, x, rtol=1e-6, maxit=500, use_graph=True, ra
     _check(lib.pcg_batch_layout(batch.handle, None, None, None, grid))
     return {"status": st, "iters": list(its), "relres": list(rel), "latency_s": list(lat), "restarts": list(rst),
             "seconds": secs.value, "xcd_local": int(grid[2])}
+
+
+def _csr_host(rowptr, col, val):
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float32)
+    if rowptr.ndim != 1 or rowptr.size < 1 or col.size != val.size or int(rowptr[-1]) != col.size:
+        raise PcgError(PCG_E_ARG, "compressed rows: rowptr needs nrows + 1 entries ending at len(col) = len(val)")
+    return rowptr, col, val
+
+
+def pcg_sell_build(rowptr, col, val, ncols, chunk=64, sigma=1) -> dict:
+    """Host-only sliced-ELLPACK layout of a compressed-row matrix (numpy in
+    and out): chunk_ptr, perm, col, val."""
+    rowptr, col, val = _csr_host(rowptr, col, val)
+    nrows = rowptr.size - 1
+    nch, nsl = ctypes.c_int64(), ctypes.c_int64()
+    args = (int(nrows), int(ncols), rowptr.ctypes.data, col.ctypes.data, val.ctypes.data, int(chunk), int(sigma))
+    _check(lib.pcg_sell_build(*args, ctypes.byref(nch), ctypes.byref(nsl), None, None, None, None))
+    cptr = np.empty(nch.value + 1, dtype=np.int64)
+    perm = np.empty(nrows, dtype=np.int32)
+    scol = np.empty(nsl.value, dtype=np.int32)
+    sval = np.empty(nsl.value, dtype=np.float32)
+    _check(lib.pcg_sell_build(*args, ctypes.byref(nch), ctypes.byref(nsl), cptr.ctypes.data, perm.ctypes.data,
+                              scol.ctypes.data, sval.ctypes.data))
+    return {"chunk_ptr": cptr, "perm": perm, "col": scol, "val": sval}
+
+
+class Sell:
+    """Owns a pcg_sell handle: a general sparse matrix in sliced ELLPACK
+    (C = 64) in device memory."""
+
+    def __init__(self, handle, nrows, ncols):
+        self.handle = handle
+        self.nrows, self.ncols = int(nrows), int(ncols)
+        nnz, nsl, nch = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.pcg_sell_info(handle, ctypes.byref(nnz), ctypes.byref(nsl), ctypes.byref(nch)))
+        self.nnz, self.nslots, self.nchunks = int(nnz.value), int(nsl.value), int(nch.value)
+
+    def close(self):
+        if self.handle:
+            lib.pcg_sell_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pcg_sell_create(rowptr, col, val, ncols, sigma=1, stream=None) -> Sell:
+    """Upload a compressed-row matrix (host arrays) as sliced ELLPACK."""
+    rowptr, col, val = _csr_host(rowptr, col, val)
+    nrows = rowptr.size - 1
+    h = ctypes.c_void_p()
+    _check(lib.pcg_sell_create(ctypes.byref(h), int(nrows), int(ncols), rowptr.ctypes.data, col.ctypes.data,
+                               val.ctypes.data, int(sigma), _stream(stream)))
+    return Sell(h, nrows, ncols)
+
+
+def pcg_sell_destroy(A: Sell):
+    A.close()
+
+
+def pcg_sell_spmv(A: Sell, x, y):
+    """y = A x (FP32 device tensors), asynchronous on the matrix's stream."""
+    _need(x, A.ncols, "x", torch.float32)
+    _need(y, A.nrows, "y", torch.float32)
+    _check(lib.pcg_sell_spmv(A.handle, _ptr(x), _ptr(y)))
