@@ -13,6 +13,9 @@ Contents, with the passage each follows:
   csr_spmv
       -> oracle.c: y = A x for a compressed-row matrix (Sec. VII-A: the GPU
          comparison system's SpMV, there on a sliced-ELLPACK matrix).
+  csr_pcg
+      -> oracle.c: the Jacobi-PCG above on a square compressed-row matrix
+         (Sec. VII-A's comparison system runs CG on a stored matrix).
   stencil_loops, assemble_dense
       -> pure-Python twins for tiny grids (brute force).
   round_f32 / round_bf16 / round_f16
@@ -63,6 +66,9 @@ def _load():
     lib.oracle_axpy.argtypes = [i64, d, _dp, _dp, _dp]
     lib.oracle_csr_spmv.argtypes = [i64, ctypes.c_void_p, ctypes.c_void_p, _dp, _dp, _dp]
     lib.oracle_csr_spmv.restype = None
+    lib.oracle_csr_pcg.argtypes = [i64, ctypes.c_void_p, ctypes.c_void_p, _dp, _dp, _dp, d, i, _dp,
+                                   ctypes.POINTER(i), ctypes.POINTER(d)]
+    lib.oracle_csr_pcg.restype = i
     lib.oracle_dot.argtypes = [i64, _dp, _dp]
     lib.oracle_dot.restype = d
     lib.oracle_pcg.argtypes = [i, i, i, _dp, _dp, _dp, d, i, _dp,
@@ -166,6 +172,29 @@ def pcg(shape, b, rtol=1e-6, maxit=500, kcell=None, x0=None, history=False):
     st = _load().oracle_pcg(nx, ny, nz, None if k is None else _ptr(k), _ptr(b), _ptr(x),
                             float(rtol), int(maxit), None if hist is None else _ptr(hist),
                             ctypes.byref(it), ctypes.byref(rr))
+    out = dict(x=x, iters=it.value, status=st, relres=rr.value)
+    if history:
+        out["hist"] = hist[: it.value + 1]
+    return out
+
+
+def csr_pcg(rowptr, col, val, b, rtol=1e-6, maxit=500, x0=None, history=False):
+    """FP64 Jacobi-PCG (the same steps as pcg()) on a square compressed-row
+    matrix; D = the sum of each row's diagonal entries. Returns dict(x, iters,
+    status, relres[, hist]); status BREAKDOWN if a diagonal is not positive."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val, b = _f64(val), _f64(b)
+    n = rowptr.size - 1
+    if b.size != n or rowptr[-1] != col.size or col.size != val.size:
+        raise ValueError("csr_pcg: inconsistent sizes")
+    if col.size and (col.min() < 0 or col.max() >= n):
+        raise ValueError("csr_pcg: column index out of range")
+    x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
+    hist = np.full(maxit + 1, np.nan) if history else None
+    it, rr = ctypes.c_int(0), ctypes.c_double(0.0)
+    st = _load().oracle_csr_pcg(n, rowptr.ctypes.data, col.ctypes.data, _ptr(val), _ptr(b), _ptr(x), float(rtol),
+                                int(maxit), None if hist is None else _ptr(hist), ctypes.byref(it), ctypes.byref(rr))
     out = dict(x=x, iters=it.value, status=st, relres=rr.value)
     if history:
         out["hist"] = hist[: it.value + 1]

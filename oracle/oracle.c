@@ -207,24 +207,33 @@ static void apply_op(int nx, int ny, int nz, const double *kc, const double *x, 
  * Returns ORACLE_OK, ORACLE_NOCONV (maxit reached, last iterate kept) or
  * ORACLE_BREAKDOWN.
  */
-int oracle_pcg(int nx, int ny, int nz, const double *kc, const double *b, double *x, double rtol,
-               int maxit, double *hist, int *iters, double *relres)
+/* The operator of a solve: the grid operators (kc NULL or cell coefficients)
+ * or a compressed-row matrix. */
+typedef struct {
+    int nx, ny, nz;
+    const double *kc;
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double *val;
+} op_t;
+
+static void op_apply(const op_t *op, int64_t n, const double *x, double *y)
 {
-    int64_t n = (int64_t)nx * ny * nz;
+    if (op->rowptr)
+        oracle_csr_spmv(n, op->rowptr, op->col, op->val, x, y);
+    else
+        apply_op(op->nx, op->ny, op->nz, op->kc, x, y);
+}
+
+/* Jacobi-PCG as above for an operator with inverse diagonal dinv. */
+static int pcg_core(const op_t *op, int64_t n, const double *dinv, const double *b, double *x, double rtol,
+                    int maxit, double *hist, int *iters, double *relres)
+{
     double *r = malloc(sizeof(double) * n), *z = malloc(sizeof(double) * n);
     double *p = malloc(sizeof(double) * n), *q = malloc(sizeof(double) * n);
-    double *dinv = malloc(sizeof(double) * n);
-    if (!r || !z || !p || !q || !dinv) {
-        free(r); free(z); free(p); free(q); free(dinv);
+    if (!r || !z || !p || !q) {
+        free(r); free(z); free(p); free(q);
         return ORACLE_NOMEM;
-    }
-    if (kc) {
-        oracle_vdiag(nx, ny, nz, kc, dinv);
-        for (int64_t i = 0; i < n; ++i)
-            dinv[i] = 1.0 / dinv[i];
-    } else {
-        for (int64_t i = 0; i < n; ++i)
-            dinv[i] = 1.0 / 6.0;
     }
     int status = ORACLE_OK;
     *iters = 0;
@@ -236,7 +245,7 @@ int oracle_pcg(int nx, int ny, int nz, const double *kc, const double *b, double
             hist[0] = 0.0;
         goto done;
     }
-    apply_op(nx, ny, nz, kc, x, q);
+    op_apply(op, n, x, q);
     for (int64_t i = 0; i < n; ++i)
         r[i] = b[i] - q[i];
     double rn = sqrt(oracle_dot(n, r, r));
@@ -251,7 +260,7 @@ int oracle_pcg(int nx, int ny, int nz, const double *kc, const double *b, double
     double rho = oracle_dot(n, r, z);
     status = ORACLE_NOCONV;
     for (int k = 1; k <= maxit; ++k) {
-        apply_op(nx, ny, nz, kc, p, q);
+        op_apply(op, n, p, q);
         double sigma = oracle_dot(n, p, q);
         if (!(sigma > 0.0) || !isfinite(sigma)) {
             status = ORACLE_BREAKDOWN;
@@ -284,7 +293,59 @@ int oracle_pcg(int nx, int ny, int nz, const double *kc, const double *b, double
             p[i] = z[i] + beta * p[i];
     }
 done:
-    free(r); free(z); free(p); free(q); free(dinv);
+    free(r); free(z); free(p); free(q);
+    return status;
+}
+
+int oracle_pcg(int nx, int ny, int nz, const double *kc, const double *b, double *x, double rtol,
+               int maxit, double *hist, int *iters, double *relres)
+{
+    int64_t n = (int64_t)nx * ny * nz;
+    double *dinv = malloc(sizeof(double) * n);
+    if (!dinv)
+        return ORACLE_NOMEM;
+    if (kc) {
+        oracle_vdiag(nx, ny, nz, kc, dinv);
+        for (int64_t i = 0; i < n; ++i)
+            dinv[i] = 1.0 / dinv[i];
+    } else {
+        for (int64_t i = 0; i < n; ++i)
+            dinv[i] = 1.0 / 6.0;
+    }
+    op_t op = {nx, ny, nz, kc, NULL, NULL, NULL};
+    int status = pcg_core(&op, n, dinv, b, x, rtol, maxit, hist, iters, relres);
+    free(dinv);
+    return status;
+}
+
+/*
+ * Jacobi-PCG as oracle_pcg for a square compressed-row matrix (the CG of the
+ * GPU comparison system in Sec. VII-A runs on a stored sparse matrix). The
+ * diagonal D_i is the sum of row i's entries in column i; a row whose D_i is
+ * not positive gives ORACLE_BREAKDOWN before any iteration.
+ */
+int oracle_csr_pcg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, const double *b,
+                   double *x, double rtol, int maxit, double *hist, int *iters, double *relres)
+{
+    double *dinv = malloc(sizeof(double) * (n > 0 ? n : 1));
+    if (!dinv)
+        return ORACLE_NOMEM;
+    *iters = 0;
+    *relres = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            if (col[k] == i)
+                d += val[k];
+        if (!(d > 0.0)) {
+            free(dinv);
+            return ORACLE_BREAKDOWN;
+        }
+        dinv[i] = 1.0 / d;
+    }
+    op_t op = {0, 0, 0, NULL, rowptr, col, val};
+    int status = pcg_core(&op, n, dinv, b, x, rtol, maxit, hist, iters, relres);
+    free(dinv);
     return status;
 }
 

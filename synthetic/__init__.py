@@ -182,3 +182,33 @@ def random_csr(nrows: int, ncols: int, seed: int = SEED_SPARSE, max_len: int = 4
     else:
         val = rng.uniform(-1.0, 1.0, col.size).astype(np.float32)
     return rowptr, col, val
+
+
+def random_spd_csr(n: int, seed: int = SEED_SPARSE, max_partners: int = 12):
+    """A random symmetric, strictly diagonally dominant matrix (hence SPD).
+
+    Each row i picks 1..max_partners partners j != i uniformly; the pattern is
+    made symmetric, each off-diagonal pair gets one value -U(0, 1), and the
+    diagonal is 1 + the sum of the row's off-diagonal magnitudes. Values are
+    cast to FP32 (dominance keeps a margin of about 1). Columns ascending.
+    Returns (rowptr int64, col int32, val float32).
+    """
+    rng = np.random.default_rng(seed)
+    k = rng.integers(1, max_partners + 1, n)
+    rows = np.repeat(np.arange(n, dtype=np.int64), k)
+    cols = rng.integers(0, n - 1, rows.size)
+    cols = np.where(cols >= rows, cols + 1, cols)  # j != i
+    lo, hi = np.minimum(rows, cols), np.maximum(rows, cols)
+    pairs = np.unique(lo * n + hi)
+    vals = -rng.uniform(0.0, 1.0, pairs.size)
+    pi, pj = pairs // n, pairs % n
+    r = np.concatenate([pi, pj, np.arange(n)])
+    c = np.concatenate([pj, pi, np.arange(n)])
+    off = np.abs(vals)
+    diag = 1.0 + np.bincount(pi, off, n) + np.bincount(pj, off, n)
+    v = np.concatenate([vals, vals, diag])
+    order = np.lexsort((c, r))
+    r, c, v = r[order], c[order], v[order]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=n), out=rowptr[1:])
+    return rowptr, c.astype(np.int32), v.astype(np.float32)

@@ -5,7 +5,11 @@ the paper's Sec. VII-A (norm, dot, axpy, SpMV), there on the seven-point
 operator stored in a sliced-ELLPACK format. The oracle computes the plain
 definition y_i = sum over row i's entries of a_ij x_j; the pins below fix it
 by closed forms (sine eigenvectors of the seven-point matrix, its row sums),
-brute force on a dense copy built entry by entry, and symmetry.
+brute force on a dense copy built entry by entry, and symmetry. Jacobi-PCG
+on a compressed-row matrix is pinned to the matrix-free oracle's steps on the
+stored seven-point matrix, to a dense Cholesky solve, to the monotone A-norm
+error of CG, to the one-step solve of a diagonal matrix, and to its status
+paths.
 """
 import math
 
@@ -81,3 +85,79 @@ def test_csr_spmv_empty_rows_and_matrix(orc):
     assert y.tolist() == [0.0, 7.0, 0.0]
     assert orc.csr_spmv(np.zeros(1, dtype=np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32),
                         np.zeros(4)).size == 0
+
+
+# ---------------------------------------------------------------------------
+# Jacobi-PCG on a compressed-row matrix
+# ---------------------------------------------------------------------------
+
+def test_csr_pcg_matches_matrix_free_pcg(orc):
+    """On the stored seven-point matrix the CSR solve takes the matrix-free
+    oracle's steps: same iteration count and residual history, same x."""
+    nx, ny, nz = 12, 10, 9
+    b = synthetic.uniform(7, nx * ny * nz)
+    a = orc.csr_pcg(*synthetic.poisson7_csr(nx, ny, nz), b, rtol=1e-8, maxit=500, history=True)
+    m = orc.pcg((nz, ny, nx), b, rtol=1e-8, maxit=500, history=True)
+    assert a["status"] == m["status"] == orc.OK and a["iters"] == m["iters"]
+    assert np.max(np.abs(a["hist"] - m["hist"])) <= 1e-12
+    assert np.max(np.abs(a["x"] - m["x"])) <= 1e-12 * np.max(np.abs(m["x"]))
+
+
+def _dense(rowptr, col, val, n):
+    A = np.zeros((n, n))
+    for r in range(n):
+        for k in range(rowptr[r], rowptr[r + 1]):
+            A[r, col[k]] += float(val[k])
+    return A
+
+
+def test_random_spd_generator_is_spd(orc):
+    rowptr, col, val = synthetic.random_spd_csr(200, seed=3)
+    A = _dense(rowptr, col, val, 200)
+    assert np.array_equal(A, A.T)
+    np.linalg.cholesky(A)
+    assert np.all(np.diff(col[rowptr[0]:rowptr[1]]) > 0)
+
+
+def test_csr_pcg_against_cholesky(orc):
+    """Converged x against a dense Cholesky solve: ||x - x*||_A <= rtol ||b||
+    times ||A^-1||^(1/2), and the A-norm error falls monotonically (a CG
+    property) along truncated runs."""
+    n = 300
+    rowptr, col, val = synthetic.random_spd_csr(n, seed=5)
+    A = _dense(rowptr, col, val, n)
+    b = synthetic.uniform(9, n)
+    L = np.linalg.cholesky(A)
+    xs = np.linalg.solve(L.T, np.linalg.solve(L, b))
+    res = orc.csr_pcg(rowptr, col, val, b, rtol=1e-10, maxit=1000)
+    assert res["status"] == orc.OK
+    lam_min = np.linalg.eigvalsh(A)[0]
+    e = res["x"] - xs
+    assert math.sqrt(e @ A @ e) <= 1e-10 * np.linalg.norm(b) / math.sqrt(lam_min) * 1.01
+    prev = math.inf
+    for k in range(1, 12):
+        xk = orc.csr_pcg(rowptr, col, val, b, rtol=0.0, maxit=k)["x"]
+        ek = xk - xs
+        en = math.sqrt(ek @ A @ ek)
+        assert en < prev
+        prev = en
+
+
+def test_csr_pcg_diagonal_matrix_one_step(orc):
+    """A diagonal matrix is its own Jacobi preconditioner: one step, exact."""
+    n = 50
+    d = 1.0 + np.arange(n, dtype=np.float64)
+    rowptr = np.arange(n + 1, dtype=np.int64)
+    res = orc.csr_pcg(rowptr, np.arange(n, dtype=np.int32), d, np.ones(n), rtol=1e-14, maxit=10)
+    assert res["status"] == orc.OK and res["iters"] == 1
+    assert np.max(np.abs(res["x"] - 1.0 / d)) <= 1e-15
+
+
+def test_csr_pcg_status_paths(orc):
+    rowptr, col, val = synthetic.random_spd_csr(40, seed=6)
+    zero = orc.csr_pcg(rowptr, col, val, np.zeros(40))
+    assert zero["status"] == orc.OK and zero["iters"] == 0 and np.all(zero["x"] == 0)
+    noconv = orc.csr_pcg(rowptr, col, val, synthetic.uniform(1, 40), rtol=1e-14, maxit=2)
+    assert noconv["status"] == orc.NOCONV and noconv["iters"] == 2
+    neg = orc.csr_pcg(rowptr, col, -val, synthetic.uniform(1, 40))  # diagonal not positive
+    assert neg["status"] == orc.BREAKDOWN and neg["iters"] == 0
