@@ -139,7 +139,7 @@ def time_kernels_512(P, torch, n, reps):
     return out
 
 
-def bench_sell(P, torch, reps, grids=((256, 256, 256), None)):
+def bench_sell(P, torch, reps, grids=((256, 256, 256), None), b256=None, mf_solve_s=None):
     """General sparse SpMV in sliced ELLPACK (C = 64, sigma = 1) on the
     seven-point matrix stored explicitly, the form the paper's GPU comparison
     system uses, beside the matrix-free stencil on the same grid. Algorithmic
@@ -173,6 +173,25 @@ def bench_sell(P, torch, reps, grids=((256, 256, 256), None)):
             gbs = nbytes / (us * 1e-6) / 1e9
             res[name] = {"us": round(us, 2), "bytes": nbytes, "GB/s": round(gbs, 1),
                          "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        if b256 is not None and (nx, ny, nz) == (256, 256, 256):
+            # Jacobi-PCG on the stored matrix, the benchmark's b; per
+            # iteration 8 B per entry + 60 B per row (q = A p: x and q 8;
+            # update: p, q, r, r', D^-1 20 and x 16; direction: r, D^-1, p, p' 16).
+            xs = torch.zeros(N, dtype=torch.float64, device="cuda")
+            P.pcg_sell_solve(A, b256, xs, 1e-6, 5000)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = P.pcg_sell_solve(A, b256, xs, 1e-6, 5000)
+            torch.cuda.synchronize()
+            s = time.perf_counter() - t0
+            it = max(info["iters"], 1)
+            per_it = 8 * A.nnz + 60 * N
+            res["pcg_solve"] = {"iters": info["iters"], "restarts": info["restarts"], "ms": round(s * 1e3, 2),
+                                "us_per_iteration": round(s * 1e6 / it, 1),
+                                "iteration_GB/s": round(per_it * it / s / 1e9, 1),
+                                "true_relres": info["rel_res_true_fp64"],
+                                "matrix_free_ms": None if mf_solve_s is None else round(mf_solve_s * 1e3, 2)}
+            del xs
         out["x".join(str(v) for v in (nx, ny, nz))] = res
         P.pcg_destroy(ctx)
         A.close()
@@ -572,7 +591,7 @@ def main():
 
     sell = None
     if not args.no_sell:
-        sell = bench_sell(P, torch, args.kernel_reps)
+        sell = bench_sell(P, torch, args.kernel_reps, b256=b if n == 256 else None, mf_solve_s=dt_solve)
         print(f"# sell: {sell}", file=sys.stderr, flush=True)
 
     kern = None

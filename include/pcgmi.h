@@ -383,6 +383,24 @@ pcg_status pcg_sell_info(pcg_sell A, int64_t *nnz, int64_t *nslots, int64_t *nch
  * order, starting from 0. */
 pcg_status pcg_sell_spmv(pcg_sell A, const float *x, float *y);
 
+/* Jacobi-PCG on a square stored matrix (symmetric positive definite, with a
+ * positive diagonal), the CG of Sec. VII-A's comparison system built on this
+ * SpMV: the steps of pcg_solve (Hestenes-Stiefel PCG, Saad Alg. 9.1, M = D,
+ * D_i = the sum of row i's entries in column i) from x0 = 0 until the
+ * recursive ||r|| <= rtol ||b|| or maxit A p products. r, p, q and D^-1 are
+ * FP32, the products and updates FP32, the inner products accumulated in
+ * FP64, x accumulated in FP64. When the recursion has converged but the FP64
+ * true residual ||b - A x|| is above rtol ||b||, the solve restarts from x
+ * with r = fl32(b - A x) (at most 3 times). b: DEVICE float[n]; x: DEVICE
+ * double[n] (written). The first call allocates the workspace (4 FP32 vectors)
+ * and checks the diagonal: PCG_E_ARG if a row's diagonal is missing or not
+ * positive. Returns after the solve with info filled (iters, status,
+ * rel_res_recursive, rel_res_true_fp64, restarts, seconds); PCG_E_NOCONV or
+ * PCG_E_BREAKDOWN (p.Ap <= 0 or a non-finite value) keep the last iterate in
+ * x. Iterations are enqueued 16 at a time; the kernels of iterations past the
+ * end return at once. */
+pcg_status pcg_sell_solve(pcg_sell A, const float *b, double *x, double rtol, int maxit, pcg_info *info);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *pcg_last_error(void);
 

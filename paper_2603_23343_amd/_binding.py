@@ -94,6 +94,7 @@ def _load():
         "pcg_sell_destroy": ([vp], i),
         "pcg_sell_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)], i),
         "pcg_sell_spmv": ([vp, vp, vp], i),
+        "pcg_sell_solve": ([vp, vp, vp, d, i, ctypes.POINTER(PcgInfo)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -550,3 +551,16 @@ def pcg_sell_spmv(A: Sell, x, y):
     _need(x, A.ncols, "x", torch.float32)
     _need(y, A.nrows, "y", torch.float32)
     _check(lib.pcg_sell_spmv(A.handle, _ptr(x), _ptr(y)))
+
+
+def pcg_sell_solve(A: Sell, b, x, rtol=1e-6, maxit=500, raise_on_error=True) -> dict:
+    """Jacobi-PCG on the stored matrix: b FP32, x FP64 device tensors."""
+    _need(b, A.nrows, "b", torch.float32)
+    _need(x, A.nrows, "x", torch.float64)
+    info = PcgInfo()
+    st = lib.pcg_sell_solve(A.handle, _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(info))
+    out = info.as_dict()
+    out["status"] = st
+    if st != PCG_OK and (raise_on_error or st not in (PCG_E_NOCONV, PCG_E_BREAKDOWN)):
+        raise PcgError(st, pcg_last_error())
+    return out

@@ -12,6 +12,8 @@
 // row's neighbours share (for a grid operator, the planes above and below)
 // stay in that XCD's L2.
 #include <algorithm>
+#include <chrono>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -28,6 +30,26 @@ const char* set_error(pcg_status st, const char* msg);
 
 using namespace pcgmi;
 
+namespace {
+
+// Device-resident scalars of a Jacobi-PCG solve on a stored matrix.
+struct SellState {
+    double rho;      // r.z of the current residual
+    double sigma;    // p.Ap
+    double alpha;    // rho / sigma
+    double beta;     // rho_new / rho
+    double rr;       // ||r||^2 from the recursion
+    double bb;       // ||b||^2
+    double tol2;     // (rtol ||b||)^2
+    double true_rr;  // ||b - A x||^2 in FP64
+    int iters;       // A p products
+    int done;        // 0 running, 1 converged, 2 breakdown, 3 maxit reached
+    int maxit;
+    int pad;
+};
+
+}  // namespace
+
 struct pcg_sell_s {
     int64_t nrows = 0, ncols = 0, nnz = 0, nchunks = 0, nslots = 0;
     int64_t* chunk_ptr = nullptr;  // device, nchunks + 1
@@ -35,6 +57,12 @@ struct pcg_sell_s {
     float* val = nullptr;          // device, nslots
     int32_t* perm = nullptr;       // device, nrows (null when sigma = 1)
     hipStream_t stream = nullptr;
+    // solver workspace (allocated by the first pcg_sell_solve)
+    float *r = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
+    double* part = nullptr;
+    SellState* st = nullptr;
+    int* bad = nullptr;
+    int diag_state = 0;  // 0 not checked, 1 positive diagonal, -1 not
 };
 
 namespace {
@@ -92,6 +120,265 @@ __global__ void __launch_bounds__(SELL_C * SELL_WAVES)
         const int64_t dst = PERM ? (int64_t)perm[s] : s;
         __builtin_nontemporal_store(acc, y + dst);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi-PCG on the stored matrix (the Hestenes-Stiefel form, Saad Alg. 9.1
+// with M = D): per iteration q = A p with p.q (sliced-ELLPACK kernel), the
+// update x += alpha p, r -= alpha q with r.r and r.z, and the direction
+// p = D^-1 r + beta p. Each reducing kernel leaves one partial per
+// work-group (fixed grid, contiguous ranges); a one-work-group finisher sums
+// them in index order and updates the device state; every kernel returns at
+// once when the state says the solve has ended, so the host can enqueue
+// iterations in batches.
+// ---------------------------------------------------------------------------
+constexpr int SNT = 256;
+constexpr unsigned SELL_MAX_GRID = 2048;
+enum : int { FIN_START = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_TRUE = 3 };
+
+__device__ __forceinline__ void block_range(int64_t n, int64_t& lo, int64_t& hi, unsigned& b) {
+    b = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    lo = (int64_t)b * per;
+    hi = lo + per < n ? lo + per : n;
+}
+
+// The row at sorted position s of chunk c (lane = s mod 64): the sum of
+// val * v[col] in storage order with fused multiply-adds in type A (FP32 as
+// k_sell_spmv, or FP64).
+template <typename V, typename A>
+__device__ __forceinline__ A sell_row(const int64_t* __restrict__ chunk_ptr, const int32_t* __restrict__ col,
+                                      const float* __restrict__ val, const V* __restrict__ v, int64_t c, int lane) {
+    const int64_t base = chunk_ptr[c];
+    const int w = (int)((chunk_ptr[c + 1] - base) / SELL_C);
+    const int32_t* cp = col + base + lane;
+    const float* vp = val + base + lane;
+    A acc = A(0);
+    for (int j = 0; j < w; j += SELL_UNROLL) {
+        int ci[SELL_UNROLL];
+        float vi[SELL_UNROLL];
+        V xv[SELL_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SELL_UNROLL; ++u) {
+            ci[u] = -1;
+            vi[u] = 0.0f;
+            if (j + u < w) {
+                ci[u] = __builtin_nontemporal_load(cp + (int64_t)(j + u) * SELL_C);
+                vi[u] = __builtin_nontemporal_load(vp + (int64_t)(j + u) * SELL_C);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SELL_UNROLL; ++u) xv[u] = ci[u] >= 0 ? v[ci[u]] : V(0);
+#pragma unroll
+        for (int u = 0; u < SELL_UNROLL; ++u)
+            if (ci[u] >= 0) {
+                if constexpr (sizeof(A) == 4) acc = __builtin_fmaf(vi[u], (float)xv[u], acc);
+                else acc = __builtin_fma((double)vi[u], (double)xv[u], acc);
+            }
+    }
+    return acc;
+}
+
+// dinv[i] = 1 / (sum of row i's entries in column i); *bad = 1 if that sum
+// is not positive for some row.
+__global__ void __launch_bounds__(SELL_C * SELL_WAVES)
+    k_sell_dinv(int64_t nrows, int64_t nchunks, const int64_t* __restrict__ chunk_ptr,
+                const int32_t* __restrict__ col, const float* __restrict__ val, const int32_t* __restrict__ perm,
+                float* __restrict__ dinv, int* bad) {
+    const int64_t c = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * SELL_WAVES + (threadIdx.x >> 6);
+    if (c >= nchunks) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t s = c * SELL_C + lane;
+    if (s >= nrows) return;
+    const int32_t row = perm ? perm[s] : (int32_t)s;
+    const int64_t base = chunk_ptr[c];
+    const int w = (int)((chunk_ptr[c + 1] - base) / SELL_C);
+    float d = 0.0f;
+    for (int j = 0; j < w; ++j)
+        if (col[base + (int64_t)j * SELL_C + lane] == row) d += val[base + (int64_t)j * SELL_C + lane];
+    if (d > 0.0f) {
+        dinv[row] = 1.0f / d;
+    } else {
+        dinv[row] = 0.0f;
+        *bad = 1;
+    }
+}
+
+// Start of a segment: zero = 1: r = b, x = 0; zero = 0: r holds the restart
+// residual. p = D^-1 r; partials {r.z, r.r}.
+__global__ void __launch_bounds__(SNT) k_sell_start(int64_t n, const float* __restrict__ b, float* __restrict__ r,
+                                                    double* __restrict__ x, const float* __restrict__ dinv,
+                                                    float* __restrict__ p, double* __restrict__ part, int zero) {
+    __shared__ double scratch[32];
+    int64_t lo, hi;
+    unsigned bl;
+    block_range(n, lo, hi, bl);
+    double v[2] = {0.0, 0.0};
+#pragma unroll 4
+    for (int64_t i = lo + threadIdx.x; i < hi; i += SNT) {
+        float ri;
+        if (zero) {
+            ri = b[i];
+            r[i] = ri;
+            x[i] = 0.0;
+        } else {
+            ri = r[i];
+        }
+        const float z = dinv[i] * ri;
+        p[i] = z;
+        v[0] += (double)ri * (double)z;
+        v[1] += (double)ri * (double)ri;
+    }
+    block_reduce<2, 0u>(v, scratch);
+    if (threadIdx.x == 0) {
+        part[2 * bl] = v[0];
+        part[2 * bl + 1] = v[1];
+    }
+}
+
+// q = A p and partials {p.q, 0}; also, with R64, r = fl32(b - A x) computed
+// in FP64 with partials {||b - A x||^2, 0} (the true residual).
+template <bool PERM, bool R64>
+__global__ void __launch_bounds__(SELL_C * SELL_WAVES)
+    k_sell_q(int64_t nrows, int64_t nchunks, const int64_t* __restrict__ chunk_ptr, const int32_t* __restrict__ col,
+             const float* __restrict__ val, const int32_t* __restrict__ perm, const float* __restrict__ p,
+             float* __restrict__ q, const float* __restrict__ b, const double* __restrict__ x,
+             double* __restrict__ part, const SellState* __restrict__ st) {
+    __shared__ double scratch[32];
+    if (!R64 && st->done) return;
+    int64_t lo, hi;
+    unsigned bl;
+    block_range(nchunks, lo, hi, bl);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double v[2] = {0.0, 0.0};
+    for (int64_t c = lo + wv; c < hi; c += SELL_WAVES) {
+        const int64_t s = c * SELL_C + lane;
+        if (R64) {
+            const double ax = sell_row<double, double>(chunk_ptr, col, val, x, c, lane);
+            if (s < nrows) {
+                const int64_t dst = PERM ? (int64_t)perm[s] : s;
+                const double rv = (double)b[dst] - ax;
+                q[dst] = (float)rv;
+                v[0] += rv * rv;
+            }
+        } else {
+            const float ap = sell_row<float, float>(chunk_ptr, col, val, p, c, lane);
+            if (s < nrows) {
+                const int64_t dst = PERM ? (int64_t)perm[s] : s;
+                q[dst] = ap;
+                v[0] += (double)p[dst] * (double)ap;
+            }
+        }
+    }
+    block_reduce<2, 0u>(v, scratch);
+    if (threadIdx.x == 0) {
+        part[2 * bl] = v[0];
+        part[2 * bl + 1] = 0.0;
+    }
+}
+
+// x += alpha p, r -= alpha q; partials {r.r, r.z}.
+__global__ void __launch_bounds__(SNT) k_sell_update(int64_t n, const float* __restrict__ p, const float* __restrict__ q,
+                                                     float* __restrict__ r, double* __restrict__ x,
+                                                     const float* __restrict__ dinv, double* __restrict__ part,
+                                                     const SellState* __restrict__ st) {
+    __shared__ double scratch[32];
+    if (st->done) return;
+    const double alpha = st->alpha;
+    const float af = (float)alpha;
+    int64_t lo, hi;
+    unsigned bl;
+    block_range(n, lo, hi, bl);
+    double v[2] = {0.0, 0.0};
+#pragma unroll 4
+    for (int64_t i = lo + threadIdx.x; i < hi; i += SNT) {
+        const float pi = p[i];
+        x[i] += alpha * (double)pi;
+        const float ri = __builtin_fmaf(-af, q[i], r[i]);
+        r[i] = ri;
+        const float z = dinv[i] * ri;
+        v[0] += (double)ri * (double)ri;
+        v[1] += (double)ri * (double)z;
+    }
+    block_reduce<2, 0u>(v, scratch);
+    if (threadIdx.x == 0) {
+        part[2 * bl] = v[0];
+        part[2 * bl + 1] = v[1];
+    }
+}
+
+// p = D^-1 r + beta p.
+__global__ void __launch_bounds__(SNT) k_sell_direction(int64_t n, const float* __restrict__ r,
+                                                        const float* __restrict__ dinv, float* __restrict__ p,
+                                                        const SellState* __restrict__ st) {
+    if (st->done) return;
+    const float beta = (float)st->beta;
+    int64_t lo, hi;
+    unsigned bl;
+    block_range(n, lo, hi, bl);
+#pragma unroll 4
+    for (int64_t i = lo + threadIdx.x; i < hi; i += SNT) p[i] = __builtin_fmaf(beta, p[i], dinv[i] * r[i]);
+}
+
+// One work-group: sums nparts partial pairs in index order and advances the
+// state (see the FIN_* modes).
+template <int MODE>
+__global__ void __launch_bounds__(SNT) k_sell_finish(const double* __restrict__ part, unsigned nparts, SellState* st,
+                                                     int zero, double rtol, int maxit) {
+    __shared__ double scratch[32];
+    if ((MODE == FIN_ALPHA || MODE == FIN_BETA) && st->done) return;
+    double v[2] = {0.0, 0.0};
+    for (unsigned i = threadIdx.x; i < nparts; i += SNT) {
+        v[0] += part[2 * i];
+        v[1] += part[2 * i + 1];
+    }
+    block_reduce<2, 0u>(v, scratch);
+    if (threadIdx.x != 0) return;
+    SellState s = *st;
+    if (MODE == FIN_START) {
+        s.rho = v[0];
+        s.rr = v[1];
+        if (zero) {
+            s.bb = v[1];
+            s.tol2 = rtol * rtol * v[1];
+            s.iters = 0;
+            s.maxit = maxit;
+        }
+        s.done = !__builtin_isfinite(v[1]) ? 2 : (s.bb == 0.0 || v[1] <= s.tol2) ? 1 : 0;
+    } else if (MODE == FIN_ALPHA) {
+        s.sigma = v[0];
+        if (!(v[0] > 0.0) || !__builtin_isfinite(v[0])) {
+            s.done = 2;
+        } else {
+            s.alpha = s.rho / v[0];
+            s.iters += 1;
+        }
+    } else if (MODE == FIN_BETA) {
+        s.rr = v[0];
+        if (!__builtin_isfinite(v[0])) {
+            s.done = 2;
+        } else if (v[0] <= s.tol2) {
+            s.done = 1;
+        } else if (s.iters >= s.maxit) {
+            s.done = 3;
+        } else {
+            s.beta = v[1] / s.rho;
+            s.rho = v[1];
+        }
+    } else {
+        s.true_rr = v[0];
+    }
+    *st = s;
+}
+
+unsigned stream_grid(int64_t n) {
+    const int64_t g = (n + SNT * 4 - 1) / (SNT * 4);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, SELL_MAX_GRID));
+}
+
+unsigned chunk_grid(int64_t nchunks) {
+    const int64_t g = (nchunks + SELL_WAVES - 1) / SELL_WAVES;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, SELL_MAX_GRID));
 }
 
 }  // namespace
@@ -171,6 +458,13 @@ pcg_status pcg_sell_destroy(pcg_sell A) {
     (void)hipFree(A->col);
     (void)hipFree(A->val);
     (void)hipFree(A->perm);
+    (void)hipFree(A->r);
+    (void)hipFree(A->p);
+    (void)hipFree(A->q);
+    (void)hipFree(A->dinv);
+    (void)hipFree(A->part);
+    (void)hipFree(A->st);
+    (void)hipFree(A->bad);
     delete A;
     return PCG_OK;
 }
@@ -244,6 +538,128 @@ pcg_status pcg_sell_spmv(pcg_sell A, const float* x, float* y) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return serr(PCG_E_HIP, "pcg_sell_spmv: launch failed: %s", hipGetErrorString(e));
     return PCG_OK;
+}
+
+// Workspace and Jacobi diagonal of the solver (first call only).
+static pcg_status sell_prepare(pcg_sell A) {
+    if (A->diag_state == 0) {
+        const size_t n = (size_t)A->nrows;
+        const size_t nparts = 2 * (size_t)std::max(stream_grid(A->nrows), chunk_grid(A->nchunks));
+        hipError_t e = hipMalloc((void**)&A->r, n * 4);
+        if (e == hipSuccess) e = hipMalloc((void**)&A->p, n * 4);
+        if (e == hipSuccess) e = hipMalloc((void**)&A->q, n * 4);
+        if (e == hipSuccess) e = hipMalloc((void**)&A->dinv, n * 4);
+        if (e == hipSuccess) e = hipMalloc((void**)&A->part, nparts * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc((void**)&A->st, sizeof(SellState));
+        if (e == hipSuccess) e = hipMalloc((void**)&A->bad, sizeof(int));
+        if (e == hipSuccess) e = hipMemsetAsync(A->bad, 0, sizeof(int), A->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(A->st, 0, sizeof(SellState), A->stream);
+        if (e == hipSuccess) {
+            const dim3 grid((unsigned)((A->nchunks + SELL_WAVES - 1) / SELL_WAVES)), block(SELL_C * SELL_WAVES);
+            hipLaunchKernelGGL(k_sell_dinv, grid, block, 0, A->stream, A->nrows, A->nchunks, A->chunk_ptr, A->col,
+                               A->val, A->perm, A->dinv, A->bad);
+            e = hipGetLastError();
+        }
+        int bad = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&bad, A->bad, sizeof(int), hipMemcpyDeviceToHost, A->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(A->stream);
+        if (e != hipSuccess)
+            return serr(e == hipErrorOutOfMemory ? PCG_E_NOMEM : PCG_E_HIP, "pcg_sell_solve: %s", hipGetErrorString(e));
+        A->diag_state = bad ? -1 : 1;
+    }
+    if (A->diag_state < 0)
+        return serr(PCG_E_ARG, "pcg_sell_solve: the matrix has a row whose diagonal is missing or not positive");
+    return PCG_OK;
+}
+
+pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, int maxit, pcg_info* info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!A) return serr(PCG_E_ARG, "pcg_sell_solve: null handle");
+    if (A->nrows != A->ncols) return serr(PCG_E_ARG, "pcg_sell_solve: the matrix must be square");
+    if (!(rtol >= 0.0) || maxit < 0) return serr(PCG_E_ARG, "pcg_sell_solve: rtol must be >= 0 and maxit >= 0");
+    pcg_info out{};
+    const int64_t n = A->nrows;
+    if (n == 0) {
+        if (info) *info = out;
+        return PCG_OK;
+    }
+    if (!b || !x) return serr(PCG_E_ARG, "pcg_sell_solve: null pointer");
+    if ((reinterpret_cast<uintptr_t>(b) & 3u) || (reinterpret_cast<uintptr_t>(x) & 7u))
+        return serr(PCG_E_ARG, "pcg_sell_solve: b must be 4-byte and x 8-byte aligned");
+    {
+        const auto ba = reinterpret_cast<uintptr_t>(b), xa = reinterpret_cast<uintptr_t>(x);
+        if (ba < xa + (uintptr_t)n * 8 && xa < ba + (uintptr_t)n * 4)
+            return serr(PCG_E_ARG, "pcg_sell_solve: b and x overlap");
+    }
+    pcg_status ps = sell_prepare(A);
+    if (ps != PCG_OK) return ps;
+
+    hipStream_t s = A->stream;
+    const unsigned gs = stream_grid(n), gq = chunk_grid(A->nchunks);
+    const dim3 bs(SNT), bq(SELL_C * SELL_WAVES);
+    auto q_kernel = [&](bool r64) {
+        const float* pp = A->p;
+        if (A->perm) {
+            if (r64) hipLaunchKernelGGL((k_sell_q<true, true>), dim3(gq), bq, 0, s, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->r, b, x, A->part, A->st);
+            else hipLaunchKernelGGL((k_sell_q<true, false>), dim3(gq), bq, 0, s, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->q, b, x, A->part, A->st);
+        } else {
+            if (r64) hipLaunchKernelGGL((k_sell_q<false, true>), dim3(gq), bq, 0, s, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->r, b, x, A->part, A->st);
+            else hipLaunchKernelGGL((k_sell_q<false, false>), dim3(gq), bq, 0, s, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->q, b, x, A->part, A->st);
+        }
+    };
+    SellState hs{};
+    auto read_state = [&]() -> hipError_t {
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(&hs, A->st, sizeof(SellState), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        return e;
+    };
+#define SCHK(expr)                                                                                         \
+    do {                                                                                                   \
+        hipError_t e_ = (expr);                                                                            \
+        if (e_ != hipSuccess) return serr(PCG_E_HIP, "pcg_sell_solve: %s", hipGetErrorString(e_));     \
+    } while (0)
+    constexpr int BATCH = 16;  // iterations enqueued between state reads
+    int restarts = 0;
+    double rel_true = 0.0;
+    for (int zero = 1;; zero = 0) {
+        hipLaunchKernelGGL(k_sell_start, dim3(gs), bs, 0, s, n, b, A->r, x, A->dinv, A->p, A->part, zero);
+        hipLaunchKernelGGL(k_sell_finish<FIN_START>, dim3(1), bs, 0, s, A->part, gs, A->st, zero, rtol, maxit);
+        SCHK(read_state());
+        while (!hs.done && hs.iters < maxit) {
+            const int k = std::min(BATCH, maxit - hs.iters);
+            for (int it = 0; it < k; ++it) {
+                q_kernel(false);
+                hipLaunchKernelGGL(k_sell_finish<FIN_ALPHA>, dim3(1), bs, 0, s, A->part, gq, A->st, 0, rtol, maxit);
+                hipLaunchKernelGGL(k_sell_update, dim3(gs), bs, 0, s, n, A->p, A->q, A->r, x, A->dinv, A->part, A->st);
+                hipLaunchKernelGGL(k_sell_finish<FIN_BETA>, dim3(1), bs, 0, s, A->part, gs, A->st, 0, rtol, maxit);
+                hipLaunchKernelGGL(k_sell_direction, dim3(gs), bs, 0, s, n, A->r, A->dinv, A->p, A->st);
+            }
+            SCHK(read_state());
+        }
+        // FP64 true residual; r = fl32(b - A x) is the restart residual.
+        q_kernel(true);
+        hipLaunchKernelGGL(k_sell_finish<FIN_TRUE>, dim3(1), bs, 0, s, A->part, gq, A->st, 0, rtol, maxit);
+        SCHK(read_state());
+        rel_true = hs.bb > 0.0 ? std::sqrt(hs.true_rr / hs.bb) : 0.0;
+        if (hs.done == 1 && rel_true > rtol && restarts < 3 && hs.iters < maxit) {
+            ++restarts;
+            continue;
+        }
+        break;
+    }
+#undef SCHK
+    const pcg_status status = hs.done == 1 ? PCG_OK : hs.done == 2 ? PCG_E_BREAKDOWN : PCG_E_NOCONV;
+    out.iters = hs.iters;
+    out.status = status;
+    out.rel_res_recursive = hs.bb > 0.0 ? std::sqrt(hs.rr / hs.bb) : 0.0;
+    out.rel_res_true_fp64 = rel_true;
+    out.restarts = restarts;
+    out.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = out;
+    if (status == PCG_E_BREAKDOWN) serr(status, "pcg_sell_solve: breakdown (p.Ap <= 0 or a non-finite value)");
+    if (status == PCG_E_NOCONV) serr(status, "pcg_sell_solve: %d iterations without convergence", hs.iters);
+    return status;
 }
 
 }  // extern "C"

@@ -111,3 +111,103 @@ def test_poisson_full_size(P, orc, dims):
     rowptr, col, val = synthetic.poisson7_csr(nx, ny, nz)
     n = nx * ny * nz
     _check(P, orc, rowptr, col, val, n, 1, synthetic.uniform_f32(synthetic.SEED_C2_X, n))
+
+
+# ---------------------------------------------------------------------------
+# Jacobi-PCG on the stored matrix (pcg_sell_solve) against the oracle's
+# compressed-row Jacobi-PCG: iterations within 2 and the FP64 true residual
+# at or below rtol (the reading for FP32 storage with an FP64 x accumulator).
+# ---------------------------------------------------------------------------
+
+def _solve_pair(P, orc, rowptr, col, val, b32, rtol, maxit, sigma):
+    n = rowptr.size - 1
+    A = P.pcg_sell_create(rowptr, col, val, n, sigma=sigma)
+    b = dev(b32)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    got = P.pcg_sell_solve(A, b, x, rtol, maxit, raise_on_error=False)
+    torch.cuda.synchronize()
+    ref = orc.csr_pcg(rowptr, col, val, b32.astype(np.float64), rtol=rtol, maxit=maxit)
+    xh = x.cpu().numpy()
+    A.close()
+    return got, ref, xh
+
+
+@pytest.mark.parametrize("sigma", [1, 64])
+@pytest.mark.parametrize("dims", [(32, 32, 32), (33, 17, 9)])
+def test_sell_pcg_poisson(P, orc, dims, sigma):
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    print(f"sell pcg poisson {dims} sigma {sigma}", flush=True)
+    rowptr, col, val = synthetic.poisson7_csr(nx, ny, nz)
+    b32 = synthetic.uniform_f32(synthetic.SEED_C1_B, n)
+    got, ref, x = _solve_pair(P, orc, rowptr, col, val, b32, 1e-6, 500, sigma)
+    assert got["status"] == P.PCG_OK and ref["status"] == orc.OK
+    assert abs(got["iters"] - ref["iters"]) <= 2 + 2 * got["restarts"], (got["iters"], ref["iters"])
+    assert got["rel_res_true_fp64"] <= 1e-6
+    r = b32.astype(np.float64) - orc.csr_spmv(rowptr, col, val, x)
+    assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b32.astype(np.float64)) * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("sigma", [1, 256])
+@pytest.mark.parametrize("n,partners", [(10007, 12), (777, 40), (1, 1)])
+def test_sell_pcg_random_spd(P, orc, n, partners, sigma):
+    print(f"sell pcg random spd n {n} partners {partners} sigma {sigma}", flush=True)
+    if n == 1:
+        rowptr, col, val = np.array([0, 1], np.int64), np.array([0], np.int32), np.array([4.0], np.float32)
+    else:
+        rowptr, col, val = synthetic.random_spd_csr(n, seed=51, max_partners=partners)
+    b32 = synthetic.uniform_f32(52, n)
+    got, ref, x = _solve_pair(P, orc, rowptr, col, val, b32, 1e-6, 1000, sigma)
+    assert got["status"] == P.PCG_OK and ref["status"] == orc.OK
+    assert abs(got["iters"] - ref["iters"]) <= 2 + 2 * got["restarts"], (got["iters"], ref["iters"])
+    assert got["rel_res_true_fp64"] <= 1e-6
+
+
+def test_sell_pcg_status_paths(P, orc):
+    rowptr, col, val = synthetic.random_spd_csr(500, seed=53)
+    # b = 0: x = 0 at once
+    got, ref, x = _solve_pair(P, orc, rowptr, col, val, np.zeros(500, np.float32), 1e-6, 100, 1)
+    assert got["status"] == P.PCG_OK and got["iters"] == 0 and np.all(x == 0)
+    # maxit reached: the oracle's count exactly
+    b32 = synthetic.uniform_f32(54, 500)
+    got, ref, x = _solve_pair(P, orc, rowptr, col, val, b32, 1e-14, 3, 1)
+    assert got["status"] == P.PCG_E_NOCONV and ref["status"] == orc.NOCONV and got["iters"] == ref["iters"] == 3
+    # a matrix with a non-positive diagonal is rejected before any iteration
+    A = P.pcg_sell_create(rowptr, col, -val, 500)
+    with pytest.raises(P.PcgError):
+        P.pcg_sell_solve(A, dev(b32), torch.zeros(500, dtype=torch.float64, device="cuda"))
+    A.close()
+    # indefinite matrix with a positive diagonal: breakdown (p.Ap <= 0)
+    ind_val = val.copy()
+    off = col != np.repeat(np.arange(500), np.diff(rowptr))
+    ind_val[off] *= 50.0
+    got, ref, x = _solve_pair(P, orc, rowptr, col, ind_val, b32, 1e-10, 500, 1)
+    assert ref["status"] == orc.BREAKDOWN
+    assert got["status"] == P.PCG_E_BREAKDOWN and abs(got["iters"] - ref["iters"]) <= 2
+
+
+def test_sell_pcg_full_size(P, orc):
+    """The stored seven-point matrix at 256^3 with the benchmark's b (b = A x*,
+    x* = lowest sine mode + 1e-3 noise): the same iteration count as the
+    matrix-free solve within 2 per segment, and the FP64 true residual at or
+    below 1e-6 checked by the oracle's product."""
+    n1 = 256
+    n = n1 ** 3
+    print("sell pcg full size 256^3", flush=True)
+    rowptr, col, val = synthetic.poisson7_csr(n1, n1, n1)
+    xs = synthetic.smooth_plus_noise(n1)
+    b32 = orc.stencil(xs, (n1, n1, n1)).astype(np.float32)
+    A = P.pcg_sell_create(rowptr, col, val, n)
+    b = dev(b32)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    got = P.pcg_sell_solve(A, b, x, 1e-6, 5000)
+    torch.cuda.synchronize()
+    ctx = P.pcg_create(n1, n1, n1, torch.float32, x_dtype=torch.float64)
+    x2 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    mf = P.pcg_solve(ctx, b, x2, 1e-6, 5000)
+    P.pcg_destroy(ctx)
+    assert abs(got["iters"] - mf["iters"]) <= 2 * (1 + got["restarts"] + mf["restarts"]), (got["iters"], mf["iters"])
+    r = b32.astype(np.float64) - orc.csr_spmv(rowptr, col, val, x.cpu().numpy())
+    rel = np.linalg.norm(r) / np.linalg.norm(b32.astype(np.float64))
+    assert rel <= 1e-6 and abs(rel - got["rel_res_true_fp64"]) <= 1e-9
+    A.close()
