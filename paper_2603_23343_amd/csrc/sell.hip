@@ -133,7 +133,9 @@ __global__ void __launch_bounds__(SELL_C * SELL_WAVES)
 // iterations in batches.
 // ---------------------------------------------------------------------------
 constexpr int SNT = 256;
-constexpr unsigned SELL_MAX_GRID = 2048;
+constexpr unsigned SELL_MAX_GRID = 2048;    // streaming kernels
+constexpr unsigned SELL_MAX_QGRID = 16384;  // product kernels (one to four chunks per wavefront at 256^3)
+constexpr int FNT = 1024;                   // finisher threads
 enum : int { FIN_START = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_TRUE = 3 };
 
 __device__ __forceinline__ void block_range(int64_t n, int64_t& lo, int64_t& hi, unsigned& b) {
@@ -293,7 +295,9 @@ __global__ void __launch_bounds__(SNT) k_sell_update(int64_t n, const float* __r
 #pragma unroll 4
     for (int64_t i = lo + threadIdx.x; i < hi; i += SNT) {
         const float pi = p[i];
-        x[i] += alpha * (double)pi;
+        // x is touched once per iteration: non-temporal, leaving the caches
+        // to r, p, q and D^-1, which the next kernels read again
+        __builtin_nontemporal_store(__builtin_nontemporal_load(x + i) + alpha * (double)pi, x + i);
         const float ri = __builtin_fmaf(-af, q[i], r[i]);
         r[i] = ri;
         const float z = dinv[i] * ri;
@@ -323,12 +327,12 @@ __global__ void __launch_bounds__(SNT) k_sell_direction(int64_t n, const float* 
 // One work-group: sums nparts partial pairs in index order and advances the
 // state (see the FIN_* modes).
 template <int MODE>
-__global__ void __launch_bounds__(SNT) k_sell_finish(const double* __restrict__ part, unsigned nparts, SellState* st,
+__global__ void __launch_bounds__(FNT) k_sell_finish(const double* __restrict__ part, unsigned nparts, SellState* st,
                                                      int zero, double rtol, int maxit) {
     __shared__ double scratch[32];
     if ((MODE == FIN_ALPHA || MODE == FIN_BETA) && st->done) return;
     double v[2] = {0.0, 0.0};
-    for (unsigned i = threadIdx.x; i < nparts; i += SNT) {
+    for (unsigned i = threadIdx.x; i < nparts; i += FNT) {
         v[0] += part[2 * i];
         v[1] += part[2 * i + 1];
     }
@@ -378,7 +382,7 @@ unsigned stream_grid(int64_t n) {
 
 unsigned chunk_grid(int64_t nchunks) {
     const int64_t g = (nchunks + SELL_WAVES - 1) / SELL_WAVES;
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, SELL_MAX_GRID));
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, SELL_MAX_QGRID));
 }
 
 }  // namespace
@@ -624,22 +628,22 @@ pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, in
     double rel_true = 0.0;
     for (int zero = 1;; zero = 0) {
         hipLaunchKernelGGL(k_sell_start, dim3(gs), bs, 0, s, n, b, A->r, x, A->dinv, A->p, A->part, zero);
-        hipLaunchKernelGGL(k_sell_finish<FIN_START>, dim3(1), bs, 0, s, A->part, gs, A->st, zero, rtol, maxit);
+        hipLaunchKernelGGL(k_sell_finish<FIN_START>, dim3(1), dim3(FNT), 0, s, A->part, gs, A->st, zero, rtol, maxit);
         SCHK(read_state());
         while (!hs.done && hs.iters < maxit) {
             const int k = std::min(BATCH, maxit - hs.iters);
             for (int it = 0; it < k; ++it) {
                 q_kernel(false);
-                hipLaunchKernelGGL(k_sell_finish<FIN_ALPHA>, dim3(1), bs, 0, s, A->part, gq, A->st, 0, rtol, maxit);
+                hipLaunchKernelGGL(k_sell_finish<FIN_ALPHA>, dim3(1), dim3(FNT), 0, s, A->part, gq, A->st, 0, rtol, maxit);
                 hipLaunchKernelGGL(k_sell_update, dim3(gs), bs, 0, s, n, A->p, A->q, A->r, x, A->dinv, A->part, A->st);
-                hipLaunchKernelGGL(k_sell_finish<FIN_BETA>, dim3(1), bs, 0, s, A->part, gs, A->st, 0, rtol, maxit);
+                hipLaunchKernelGGL(k_sell_finish<FIN_BETA>, dim3(1), dim3(FNT), 0, s, A->part, gs, A->st, 0, rtol, maxit);
                 hipLaunchKernelGGL(k_sell_direction, dim3(gs), bs, 0, s, n, A->r, A->dinv, A->p, A->st);
             }
             SCHK(read_state());
         }
         // FP64 true residual; r = fl32(b - A x) is the restart residual.
         q_kernel(true);
-        hipLaunchKernelGGL(k_sell_finish<FIN_TRUE>, dim3(1), bs, 0, s, A->part, gq, A->st, 0, rtol, maxit);
+        hipLaunchKernelGGL(k_sell_finish<FIN_TRUE>, dim3(1), dim3(FNT), 0, s, A->part, gq, A->st, 0, rtol, maxit);
         SCHK(read_state());
         rel_true = hs.bb > 0.0 ? std::sqrt(hs.true_rr / hs.bb) : 0.0;
         if (hs.done == 1 && rel_true > rtol && restarts < 3 && hs.iters < maxit) {
