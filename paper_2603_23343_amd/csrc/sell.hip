@@ -181,6 +181,51 @@ __device__ __forceinline__ A sell_row(const int64_t* __restrict__ chunk_ptr, con
     return acc;
 }
 
+// Two chunks of one wavefront at once (c1 only when `two`): twice the loads
+// in flight of sell_row, each row summed in the same order.
+template <typename V>
+__device__ __forceinline__ void sell_rows2(const int64_t* __restrict__ chunk_ptr, const int32_t* __restrict__ col,
+                                           const float* __restrict__ val, const V* __restrict__ v, int64_t c0,
+                                           int64_t c1, bool two, int lane, float& a0, float& a1) {
+    const int64_t b0 = chunk_ptr[c0];
+    const int w0 = (int)((chunk_ptr[c0 + 1] - b0) / SELL_C);
+    const int64_t b1 = two ? chunk_ptr[c1] : 0;
+    const int w1 = two ? (int)((chunk_ptr[c1 + 1] - b1) / SELL_C) : 0;
+    const int w = w0 > w1 ? w0 : w1;
+    a0 = 0.0f;
+    a1 = 0.0f;
+    for (int j = 0; j < w; j += SELL_UNROLL) {
+        int i0[SELL_UNROLL], i1[SELL_UNROLL];
+        float v0[SELL_UNROLL], v1[SELL_UNROLL], x0[SELL_UNROLL], x1[SELL_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SELL_UNROLL; ++u) {
+            i0[u] = -1;
+            v0[u] = 0.0f;
+            i1[u] = -1;
+            v1[u] = 0.0f;
+            const int64_t off = (int64_t)(j + u) * SELL_C + lane;
+            if (j + u < w0) {
+                i0[u] = __builtin_nontemporal_load(col + b0 + off);
+                v0[u] = __builtin_nontemporal_load(val + b0 + off);
+            }
+            if (j + u < w1) {
+                i1[u] = __builtin_nontemporal_load(col + b1 + off);
+                v1[u] = __builtin_nontemporal_load(val + b1 + off);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SELL_UNROLL; ++u) {
+            x0[u] = i0[u] >= 0 ? (float)v[i0[u]] : 0.0f;
+            x1[u] = i1[u] >= 0 ? (float)v[i1[u]] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < SELL_UNROLL; ++u) {
+            if (i0[u] >= 0) a0 = __builtin_fmaf(v0[u], x0[u], a0);
+            if (i1[u] >= 0) a1 = __builtin_fmaf(v1[u], x1[u], a1);
+        }
+    }
+}
+
 // dinv[i] = 1 / (sum of row i's entries in column i); *bad = 1 if that sum
 // is not positive for some row.
 __global__ void __launch_bounds__(SELL_C * SELL_WAVES)
@@ -253,7 +298,26 @@ __global__ void __launch_bounds__(SELL_C * SELL_WAVES)
     block_range(nchunks, lo, hi, bl);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double v[2] = {0.0, 0.0};
-    for (int64_t c = lo + wv; c < hi; c += SELL_WAVES) {
+    if (!R64) {
+        for (int64_t c = lo + wv; c < hi; c += 2 * SELL_WAVES) {
+            const int64_t c1 = c + SELL_WAVES;
+            const bool two = c1 < hi;
+            float a0, a1;
+            sell_rows2<float>(chunk_ptr, col, val, p, c, c1, two, lane, a0, a1);
+            const int64_t s0 = c * SELL_C + lane, s1 = c1 * SELL_C + lane;
+            if (s0 < nrows) {
+                const int64_t dst = PERM ? (int64_t)perm[s0] : s0;
+                q[dst] = a0;
+                v[0] += (double)p[dst] * (double)a0;
+            }
+            if (two && s1 < nrows) {
+                const int64_t dst = PERM ? (int64_t)perm[s1] : s1;
+                q[dst] = a1;
+                v[0] += (double)p[dst] * (double)a1;
+            }
+        }
+    }
+    for (int64_t c = lo + wv; R64 && c < hi; c += SELL_WAVES) {
         const int64_t s = c * SELL_C + lane;
         if (R64) {
             const double ax = sell_row<double, double>(chunk_ptr, col, val, x, c, lane);
