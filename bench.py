@@ -197,6 +197,29 @@ def bench_sell(P, torch, reps, grids=((256, 256, 256), None), b256=None, mf_solv
         A.close()
         del x, y
         torch.cuda.empty_cache()
+    # Latency-bound case: the 32^3 workload (b ~ U[-1, 1], seed 1) as a stored
+    # matrix and matrix-free (two kernels per iteration).
+    n1 = 32
+    N = n1 ** 3
+    A = P.pcg_sell_create(*synthetic.poisson7_csr(n1, n1, n1), N, sigma=1)
+    b = torch.from_numpy(synthetic.uniform_f32(synthetic.SEED_C1_B, N)).cuda()
+    xs = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ctx = P.pcg_create(n1, n1, n1, torch.float32, x_dtype=torch.float64, single_reduction=0)
+    small = {}
+    for name, fn in (("stored_matrix", lambda: P.pcg_sell_solve(A, b, xs, 1e-6, 500)),
+                     ("matrix_free", lambda: P.pcg_solve(ctx, b, xs, 1e-6, 500))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            info = fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 5 * 1e3
+        small[name] = {"iters": info["iters"], "ms": round(ms, 3),
+                       "us_per_iteration": round(ms * 1e3 / max(info["iters"], 1), 2)}
+    out["32x32x32_pcg"] = small
+    P.pcg_destroy(ctx)
+    A.close()
     return out
 
 
