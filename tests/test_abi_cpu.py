@@ -102,3 +102,26 @@ def test_batch_argument_validation_without_gpu(lib):
     assert lib.pcg_batch_solve(None, None, None, 1e-6, 10, 1, None, None, None, None, None) == 1
     lib.pcg_batch_destroy.argtypes = [vp]
     assert lib.pcg_batch_destroy(None) == 0
+
+
+def test_sell_argument_validation_without_gpu(lib):
+    """The stored-matrix entry points reject bad arguments before any GPU call."""
+    vp, i, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    lib.pcg_last_error.restype = ctypes.c_char_p
+    lib.pcg_sell_create.argtypes = [ctypes.POINTER(vp), i64, i64, vp, vp, vp, i, vp]
+    h = vp()
+    rowptr = (i64 * 3)(0, 1, 3)
+    col = (ctypes.c_int32 * 3)(0, 0, 2)  # column 2 is out of range for ncols = 2
+    val = (ctypes.c_float * 3)(1.0, 1.0, 1.0)
+    assert lib.pcg_sell_create(ctypes.byref(h), 2, 2, rowptr, col, val, 1, None) == 1
+    assert b"out of range" in lib.pcg_last_error()
+    assert lib.pcg_sell_create(ctypes.byref(h), 2, 3, rowptr, col, val, 3, None) == 1  # sigma not a multiple of 64
+    assert lib.pcg_sell_create(None, 2, 3, rowptr, col, val, 1, None) == 1
+    lib.pcg_sell_spmv.argtypes = [vp, vp, vp]
+    assert lib.pcg_sell_spmv(None, None, None) == 1
+    lib.pcg_sell_solve.argtypes = [vp, vp, vp, ctypes.c_double, i, vp]
+    assert lib.pcg_sell_solve(None, None, None, 1e-6, 10, None) == 1
+    lib.pcg_sell_info.argtypes = [vp, vp, vp, vp]
+    assert lib.pcg_sell_info(None, None, None, None) == 1
+    lib.pcg_sell_destroy.argtypes = [vp]
+    assert lib.pcg_sell_destroy(None) == 0
