@@ -400,6 +400,10 @@ pcg_status pcg_sell_spmv(pcg_sell A, const float *x, float *y);
  * x. Iterations are enqueued 16 at a time; the kernels of iterations past the
  * end return at once. */
 pcg_status pcg_sell_solve(pcg_sell A, const float *b, double *x, double rtol, int maxit, pcg_info *info);
+/* use_graph = 1 (default): full batches of 16 iterations are captured once
+ * as a HIP graph on a private stream and replayed (recaptured when x
+ * changes); 0: every kernel is launched eagerly. Same results either way. */
+pcg_status pcg_sell_set_graph(pcg_sell A, int use_graph);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *pcg_last_error(void);

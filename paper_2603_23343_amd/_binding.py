@@ -95,6 +95,7 @@ def _load():
         "pcg_sell_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)], i),
         "pcg_sell_spmv": ([vp, vp, vp], i),
         "pcg_sell_solve": ([vp, vp, vp, d, i, ctypes.POINTER(PcgInfo)], i),
+        "pcg_sell_set_graph": ([vp, i], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -564,3 +565,7 @@ def pcg_sell_solve(A: Sell, b, x, rtol=1e-6, maxit=500, raise_on_error=True) -> 
     if st != PCG_OK and (raise_on_error or st not in (PCG_E_NOCONV, PCG_E_BREAKDOWN)):
         raise PcgError(st, pcg_last_error())
     return out
+
+
+def pcg_sell_set_graph(A: Sell, use_graph: bool):
+    _check(lib.pcg_sell_set_graph(A.handle, 1 if use_graph else 0))

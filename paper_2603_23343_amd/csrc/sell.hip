@@ -63,6 +63,12 @@ struct pcg_sell_s {
     SellState* st = nullptr;
     int* bad = nullptr;
     int diag_state = 0;  // 0 not checked, 1 positive diagonal, -1 not
+    // 16 iterations captured as one HIP graph (on a private stream), replayed
+    // while the caller's x stays the same
+    int use_graph = 1;
+    hipStream_t capture = nullptr;
+    hipGraphExec_t batch = nullptr;
+    const double* batch_x = nullptr;
 };
 
 namespace {
@@ -533,6 +539,8 @@ pcg_status pcg_sell_destroy(pcg_sell A) {
     (void)hipFree(A->part);
     (void)hipFree(A->st);
     (void)hipFree(A->bad);
+    if (A->batch) (void)hipGraphExecDestroy(A->batch);
+    if (A->capture) (void)hipStreamDestroy(A->capture);
     delete A;
     return PCG_OK;
 }
@@ -665,14 +673,14 @@ pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, in
     hipStream_t s = A->stream;
     const unsigned gs = stream_grid(n), gq = chunk_grid(A->nchunks);
     const dim3 bs(SNT), bq(SELL_C * SELL_WAVES);
-    auto q_kernel = [&](bool r64) {
+    auto q_kernel = [&](bool r64, hipStream_t qs) {
         const float* pp = A->p;
         if (A->perm) {
-            if (r64) hipLaunchKernelGGL((k_sell_q<true, true>), dim3(gq), bq, 0, s, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->r, b, x, A->part, A->st);
-            else hipLaunchKernelGGL((k_sell_q<true, false>), dim3(gq), bq, 0, s, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->q, b, x, A->part, A->st);
+            if (r64) hipLaunchKernelGGL((k_sell_q<true, true>), dim3(gq), bq, 0, qs, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->r, b, x, A->part, A->st);
+            else hipLaunchKernelGGL((k_sell_q<true, false>), dim3(gq), bq, 0, qs, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->q, b, x, A->part, A->st);
         } else {
-            if (r64) hipLaunchKernelGGL((k_sell_q<false, true>), dim3(gq), bq, 0, s, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->r, b, x, A->part, A->st);
-            else hipLaunchKernelGGL((k_sell_q<false, false>), dim3(gq), bq, 0, s, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->q, b, x, A->part, A->st);
+            if (r64) hipLaunchKernelGGL((k_sell_q<false, true>), dim3(gq), bq, 0, qs, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->r, b, x, A->part, A->st);
+            else hipLaunchKernelGGL((k_sell_q<false, false>), dim3(gq), bq, 0, qs, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->q, b, x, A->part, A->st);
         }
     };
     SellState hs{};
@@ -688,6 +696,45 @@ pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, in
         if (e_ != hipSuccess) return serr(PCG_E_HIP, "pcg_sell_solve: %s", hipGetErrorString(e_));     \
     } while (0)
     constexpr int BATCH = 16;  // iterations enqueued between state reads
+    // k iterations on stream es (rtol and maxit are not read by these
+    // finishers: the state holds them, so a captured batch does not depend on them)
+    auto enqueue = [&](int k, hipStream_t es) -> hipError_t {
+        for (int it = 0; it < k; ++it) {
+            q_kernel(false, es);
+            hipLaunchKernelGGL(k_sell_finish<FIN_ALPHA>, dim3(1), dim3(FNT), 0, es, A->part, gq, A->st, 0, 0.0, 0);
+            hipLaunchKernelGGL(k_sell_update, dim3(gs), bs, 0, es, n, A->p, A->q, A->r, x, A->dinv, A->part, A->st);
+            hipLaunchKernelGGL(k_sell_finish<FIN_BETA>, dim3(1), dim3(FNT), 0, es, A->part, gs, A->st, 0, 0.0, 0);
+            hipLaunchKernelGGL(k_sell_direction, dim3(gs), bs, 0, es, n, A->r, A->dinv, A->p, A->st);
+        }
+        return hipGetLastError();
+    };
+    auto ensure_batch = [&](const double* xp) -> hipError_t {
+        if (A->batch && A->batch_x == xp) return hipSuccess;
+        if (A->batch) {
+            (void)hipGraphExecDestroy(A->batch);
+            A->batch = nullptr;
+        }
+        hipError_t e = hipSuccess;
+        if (!A->capture) e = hipStreamCreateWithFlags(&A->capture, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        e = hipStreamBeginCapture(A->capture, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        const hipError_t ek = enqueue(BATCH, A->capture);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(A->capture, &g);
+        if (ek != hipSuccess || ec != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return ek != hipSuccess ? ek : ec;
+        }
+        e = hipGraphInstantiate(&A->batch, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            A->batch = nullptr;
+            return e;
+        }
+        A->batch_x = xp;
+        return hipSuccess;
+    };
     int restarts = 0;
     double rel_true = 0.0;
     for (int zero = 1;; zero = 0) {
@@ -696,17 +743,16 @@ pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, in
         SCHK(read_state());
         while (!hs.done && hs.iters < maxit) {
             const int k = std::min(BATCH, maxit - hs.iters);
-            for (int it = 0; it < k; ++it) {
-                q_kernel(false);
-                hipLaunchKernelGGL(k_sell_finish<FIN_ALPHA>, dim3(1), dim3(FNT), 0, s, A->part, gq, A->st, 0, rtol, maxit);
-                hipLaunchKernelGGL(k_sell_update, dim3(gs), bs, 0, s, n, A->p, A->q, A->r, x, A->dinv, A->part, A->st);
-                hipLaunchKernelGGL(k_sell_finish<FIN_BETA>, dim3(1), dim3(FNT), 0, s, A->part, gs, A->st, 0, rtol, maxit);
-                hipLaunchKernelGGL(k_sell_direction, dim3(gs), bs, 0, s, n, A->r, A->dinv, A->p, A->st);
+            if (k == BATCH && A->use_graph) {
+                SCHK(ensure_batch(x));
+                SCHK(hipGraphLaunch(A->batch, s));
+            } else {
+                SCHK(enqueue(k, s));
             }
             SCHK(read_state());
         }
         // FP64 true residual; r = fl32(b - A x) is the restart residual.
-        q_kernel(true);
+        q_kernel(true, s);
         hipLaunchKernelGGL(k_sell_finish<FIN_TRUE>, dim3(1), dim3(FNT), 0, s, A->part, gq, A->st, 0, rtol, maxit);
         SCHK(read_state());
         rel_true = hs.bb > 0.0 ? std::sqrt(hs.true_rr / hs.bb) : 0.0;
@@ -728,6 +774,12 @@ pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, in
     if (status == PCG_E_BREAKDOWN) serr(status, "pcg_sell_solve: breakdown (p.Ap <= 0 or a non-finite value)");
     if (status == PCG_E_NOCONV) serr(status, "pcg_sell_solve: %d iterations without convergence", hs.iters);
     return status;
+}
+
+pcg_status pcg_sell_set_graph(pcg_sell A, int use_graph) {
+    if (!A) return serr(PCG_E_ARG, "pcg_sell_set_graph: null handle");
+    A->use_graph = use_graph ? 1 : 0;
+    return PCG_OK;
 }
 
 }  // extern "C"

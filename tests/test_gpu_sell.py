@@ -211,3 +211,27 @@ def test_sell_pcg_full_size(P, orc):
     rel = np.linalg.norm(r) / np.linalg.norm(b32.astype(np.float64))
     assert rel <= 1e-6 and abs(rel - got["rel_res_true_fp64"]) <= 1e-9
     A.close()
+
+
+def test_sell_pcg_graph_replay_matches_eager(P, orc):
+    """Graph-replayed batches give the eager launches' bits: three solves
+    each way on one handle, with other GPU work in between, and a second x
+    buffer (recapture)."""
+    rowptr, col, val = synthetic.random_spd_csr(20011, seed=55)
+    n = rowptr.size - 1
+    b = dev(synthetic.uniform_f32(56, n))
+    A = P.pcg_sell_create(rowptr, col, val, n, sigma=64)
+    xs = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(2)]
+    P.pcg_sell_set_graph(A, False)
+    ref = P.pcg_sell_solve(A, b, xs[0], 1e-6, 500)
+    xe = xs[0].clone()
+    P.pcg_sell_set_graph(A, True)
+    for rep in range(3):
+        for x in xs:
+            x.fill_(float("nan"))
+            got = P.pcg_sell_solve(A, b, x, 1e-6, 500)
+            torch.cuda.synchronize()
+            assert got["iters"] == ref["iters"] and got["restarts"] == ref["restarts"]
+            assert torch.equal(x, xe), rep
+            _ = (b * 2.0).sum().item()  # unrelated eager work between replays
+    A.close()
