@@ -197,6 +197,30 @@ def bench_sell(P, torch, reps, grids=((256, 256, 256), None), b256=None, mf_solv
         A.close()
         del x, y
         torch.cuda.empty_cache()
+    # Ragged rows: a random SPD matrix (1 M rows of 3..35 entries, seed 57)
+    # in original order (sigma = 1) and sorted in windows of 4096 rows.
+    rowptr, col, val = synthetic.random_spd_csr(1_000_000, seed=57)
+    N = rowptr.size - 1
+    x = torch.from_numpy(synthetic.uniform_f32(58, N)).cuda()
+    y = torch.empty_like(x)
+    ragged = {"rows": N, "nnz": int(rowptr[-1])}
+    for sigma in (1, 4096):
+        A = P.pcg_sell_create(rowptr, col, val, N, sigma=sigma)
+        for _ in range(3):
+            P.pcg_sell_spmv(A, x, y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            P.pcg_sell_spmv(A, x, y)
+        e1.record()
+        e1.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        nbytes = 8 * A.nnz + 8 * N + (4 * N if sigma > 1 else 0)
+        ragged[f"sigma_{sigma}"] = {"slots": A.nslots, "us": round(us, 2), "GB/s": round(nbytes / (us * 1e-6) / 1e9, 1)}
+        A.close()
+    out["random_spd_1M"] = ragged
+    del rowptr, col, val, x, y
     # Latency-bound case: the 32^3 workload (b ~ U[-1, 1], seed 1) as a stored
     # matrix and matrix-free (two kernels per iteration).
     n1 = 32

@@ -235,3 +235,24 @@ def test_sell_pcg_graph_replay_matches_eager(P, orc):
             assert torch.equal(x, xe), rep
             _ = (b * 2.0).sum().item()  # unrelated eager work between replays
     A.close()
+
+
+@pytest.fixture(scope="module")
+def large_spd():
+    return synthetic.random_spd_csr(2_000_000, seed=57)
+
+
+@pytest.mark.parametrize("sigma", [1, 4096])
+def test_random_spd_large_ragged(P, orc, large_spd, sigma):
+    """2 M rows of 3..35 entries (28 M entries): every row of the product
+    against the oracle with sigma = 1 (1.7x padding) and sigma = 4096 (sorted
+    windows, 1.5% padding), then Jacobi-PCG against the oracle's."""
+    rowptr, col, val = large_spd
+    n = rowptr.size - 1
+    print(f"sell large ragged spd sigma {sigma}", flush=True)
+    _check(P, orc, rowptr, col, val, n, sigma, synthetic.uniform_f32(58, n))
+    b32 = synthetic.uniform_f32(59, n)
+    got, ref, x = _solve_pair(P, orc, rowptr, col, val, b32, 1e-6, 500, sigma)
+    assert got["status"] == P.PCG_OK and ref["status"] == orc.OK
+    assert abs(got["iters"] - ref["iters"]) <= 2 + 2 * got["restarts"], (got["iters"], ref["iters"])
+    assert got["rel_res_true_fp64"] <= 1e-6
