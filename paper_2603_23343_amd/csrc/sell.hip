@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(SELL_C * SELL_WAVES)
 constexpr int SNT = 256;
 constexpr unsigned SELL_MAX_GRID = 2048;    // streaming kernels
 constexpr unsigned SELL_MAX_QGRID = 16384;  // product kernels (one to four chunks per wavefront at 256^3)
-constexpr int FNT = 1024;                   // finisher threads
+constexpr int FNT = 1024;                   // finisher threads for more than 4096 partials, else SNT
 enum : int { FIN_START = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_TRUE = 3 };
 
 __device__ __forceinline__ void block_range(int64_t n, int64_t& lo, int64_t& hi, unsigned& b) {
@@ -396,13 +396,13 @@ __global__ void __launch_bounds__(SNT) k_sell_direction(int64_t n, const float* 
 
 // One work-group: sums nparts partial pairs in index order and advances the
 // state (see the FIN_* modes).
-template <int MODE>
-__global__ void __launch_bounds__(FNT) k_sell_finish(const double* __restrict__ part, unsigned nparts, SellState* st,
+template <int MODE, int NT>
+__global__ void __launch_bounds__(NT) k_sell_finish(const double* __restrict__ part, unsigned nparts, SellState* st,
                                                      int zero, double rtol, int maxit) {
     __shared__ double scratch[32];
     if ((MODE == FIN_ALPHA || MODE == FIN_BETA) && st->done) return;
     double v[2] = {0.0, 0.0};
-    for (unsigned i = threadIdx.x; i < nparts; i += FNT) {
+    for (unsigned i = threadIdx.x; i < nparts; i += NT) {
         v[0] += part[2 * i];
         v[1] += part[2 * i + 1];
     }
@@ -443,6 +443,17 @@ __global__ void __launch_bounds__(FNT) k_sell_finish(const double* __restrict__ 
         s.true_rr = v[0];
     }
     *st = s;
+}
+
+// One finisher launch: 1024 threads for more than 4096 partial pairs, else
+// 256 (a smaller work-group starts sooner).
+template <int MODE>
+void launch_finish(hipStream_t s, const double* part, unsigned nparts, SellState* st, int zero, double rtol,
+                   int maxit) {
+    if (nparts > 4096)
+        hipLaunchKernelGGL((k_sell_finish<MODE, FNT>), dim3(1), dim3(FNT), 0, s, part, nparts, st, zero, rtol, maxit);
+    else
+        hipLaunchKernelGGL((k_sell_finish<MODE, SNT>), dim3(1), dim3(SNT), 0, s, part, nparts, st, zero, rtol, maxit);
 }
 
 unsigned stream_grid(int64_t n) {
@@ -701,9 +712,9 @@ pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, in
     auto enqueue = [&](int k, hipStream_t es) -> hipError_t {
         for (int it = 0; it < k; ++it) {
             q_kernel(false, es);
-            hipLaunchKernelGGL(k_sell_finish<FIN_ALPHA>, dim3(1), dim3(FNT), 0, es, A->part, gq, A->st, 0, 0.0, 0);
+            launch_finish<FIN_ALPHA>(es, A->part, gq, A->st, 0, 0.0, 0);
             hipLaunchKernelGGL(k_sell_update, dim3(gs), bs, 0, es, n, A->p, A->q, A->r, x, A->dinv, A->part, A->st);
-            hipLaunchKernelGGL(k_sell_finish<FIN_BETA>, dim3(1), dim3(FNT), 0, es, A->part, gs, A->st, 0, 0.0, 0);
+            launch_finish<FIN_BETA>(es, A->part, gs, A->st, 0, 0.0, 0);
             hipLaunchKernelGGL(k_sell_direction, dim3(gs), bs, 0, es, n, A->r, A->dinv, A->p, A->st);
         }
         return hipGetLastError();
@@ -739,7 +750,7 @@ pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, in
     double rel_true = 0.0;
     for (int zero = 1;; zero = 0) {
         hipLaunchKernelGGL(k_sell_start, dim3(gs), bs, 0, s, n, b, A->r, x, A->dinv, A->p, A->part, zero);
-        hipLaunchKernelGGL(k_sell_finish<FIN_START>, dim3(1), dim3(FNT), 0, s, A->part, gs, A->st, zero, rtol, maxit);
+        launch_finish<FIN_START>(s, A->part, gs, A->st, zero, rtol, maxit);
         SCHK(read_state());
         while (!hs.done && hs.iters < maxit) {
             const int k = std::min(BATCH, maxit - hs.iters);
@@ -753,7 +764,7 @@ pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, in
         }
         // FP64 true residual; r = fl32(b - A x) is the restart residual.
         q_kernel(true, s);
-        hipLaunchKernelGGL(k_sell_finish<FIN_TRUE>, dim3(1), dim3(FNT), 0, s, A->part, gq, A->st, 0, rtol, maxit);
+        launch_finish<FIN_TRUE>(s, A->part, gq, A->st, 0, rtol, maxit);
         SCHK(read_state());
         rel_true = hs.bb > 0.0 ? std::sqrt(hs.true_rr / hs.bb) : 0.0;
         if (hs.done == 1 && rel_true > rtol && restarts < 3 && hs.iters < maxit) {
