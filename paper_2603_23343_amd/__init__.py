@@ -13,4 +13,4 @@ from ._binding import (  # noqa: F401
     dot, dot_f64, dtype_code, lib, pcg_create, pcg_destroy, pcg_get_history, pcg_last_error,
     pcg_options_default, pcg_make_pairs, pcg_refine_history, pcg_set_coefficients, pcg_solve, pcg_solve_flexible, pcg_solve_refined,
     pcg_solve_snapshots, stencil_apply,
-    Sell, pcg_sell_build, pcg_sell_create, pcg_sell_destroy, pcg_sell_set_graph, pcg_sell_solve, pcg_sell_spmv)
+    REFINE_RTOL_INNER, Sell, pcg_sell_build, pcg_sell_create, pcg_sell_destroy, pcg_sell_set_graph, pcg_sell_solve, pcg_sell_spmv)

@@ -32,7 +32,8 @@ def _system(orc, n):
 def test_refined_matches_emulation(P, orc, n, dtype, fmt, acc):
     """Inner correction accumulated in FP32 (default) or in the storage type."""
     shape, xs, b = _system(orc, n)
-    ref = orc.ir_emulate(shape, b, fmt=fmt, rtol_outer=1e-10, d_fmt="f32" if acc == "f32" else None)
+    ref = orc.ir_emulate(shape, b, fmt=fmt, rtol_outer=1e-10, rtol_in=P.REFINE_RTOL_INNER[dtype],
+                         d_fmt="f32" if acc == "f32" else None)
     ctx = P.pcg_create(n, n, n, dtype, x_accum=torch.float32 if acc == "f32" else dtype)
     b64 = torch.from_numpy(b).cuda()
     x64 = torch.empty_like(b64)
