@@ -250,8 +250,9 @@ def pcg_get_history(ctx: Context, n=1 << 20):
     return buf[: cnt.value].copy()
 
 
-# Default inner tolerance of refinement per storage type: the fastest to both
-# 1e-6 and 1e-10 in a sweep at 256^3 (BF16: 5e-2 .. 2e-3; FP16: 1e-2 .. 1e-4).
+# Default inner tolerance of refinement per storage type, from a sweep at
+# 256^3 (BF16 5e-2 .. 2e-3: the fastest to 1e-6 and to 1e-10; FP16 1e-2 ..
+# 1e-4: the fastest to 1e-10).
 REFINE_RTOL_INNER = {torch.bfloat16: 5e-3, torch.float16: 3e-3}
 
 
