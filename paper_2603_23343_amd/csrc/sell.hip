@@ -11,6 +11,11 @@
 // is XCD-aware: each XCD walks a contiguous range of rows, so the x lines a
 // row's neighbours share (for a grid operator, the planes above and below)
 // stay in that XCD's L2.
+//
+// The same slot loop serves Jacobi-PCG on a stored SPD matrix
+// (pcg_sell_solve): product with p.q, update, direction, each reducing pass
+// followed by a one-work-group finisher, device-resident scalars, and batches
+// of 16 iterations replayed from a captured HIP graph.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
