@@ -256,3 +256,28 @@ def test_random_spd_large_ragged(P, orc, large_spd, sigma):
     assert got["status"] == P.PCG_OK and ref["status"] == orc.OK
     assert abs(got["iters"] - ref["iters"]) <= 2 + 2 * got["restarts"], (got["iters"], ref["iters"])
     assert got["rel_res_true_fp64"] <= 1e-6
+
+
+def test_sell_on_a_side_stream(P, orc):
+    """A handle bound to its own stream runs the product and the solve there."""
+    rowptr, col, val = synthetic.random_spd_csr(30011, seed=60)
+    n = rowptr.size - 1
+    x32 = synthetic.uniform_f32(61, n)
+    b32 = synthetic.uniform_f32(62, n)
+    x, b = dev(x32), dev(b32)
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    xs = torch.zeros(n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    A = P.pcg_sell_create(rowptr, col, val, n, sigma=256, stream=side)
+    P.pcg_sell_spmv(A, x, y)
+    side.synchronize()
+    ref = orc.csr_spmv(rowptr, col, val, x32.astype(np.float64))
+    lens = np.maximum(np.diff(rowptr), 1).astype(np.float64)
+    tol = 1.01 * lens * U32 * _abs_bound(orc, rowptr, col, val, x32.astype(np.float64))
+    assert np.all(np.abs(host64(y) - ref) <= tol)
+    got = P.pcg_sell_solve(A, b, xs, 1e-6, 500)
+    oref = orc.csr_pcg(rowptr, col, val, b32.astype(np.float64), rtol=1e-6, maxit=500)
+    assert got["status"] == P.PCG_OK and abs(got["iters"] - oref["iters"]) <= 2 + 2 * got["restarts"]
+    assert got["rel_res_true_fp64"] <= 1e-6
+    A.close()
