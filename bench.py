@@ -60,9 +60,10 @@ BYTES_DIRECTION = 12
 BYTES_UPDATE = 28
 
 
-# Sources that define the PCG iteration kernels; counter-measured traffic in
-# profiles/traffic.json is used only while these files are unchanged.
-ITER_KERNEL_SOURCES = ["common.hpp", "zmarch.hpp", "ops.hpp", "zkernel.hpp", "pcg.hip", "internal.hpp"]
+# Sources that define the PCG iteration kernels and their launch plans;
+# counter-measured traffic in profiles/traffic.json is used only while these
+# files are unchanged.
+ITER_KERNEL_SOURCES = ["common.hpp", "zmarch.hpp", "ops.hpp", "zkernel.hpp", "pcg.hip", "internal.hpp", "runtime.hip"]
 
 
 def kernel_source_hash() -> str:

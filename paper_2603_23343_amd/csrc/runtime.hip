@@ -92,7 +92,9 @@ struct pcg_ctx_s {
     hipStream_t capture = nullptr;  // private stream used only to capture graphs
     pcg_options opt{};
     Plan plan{};
-    Geometry geo{};      // iteration kernels
+    Geometry geo{};      // iteration kernels (the direction kernel's)
+    Plan plan_upd{};
+    Geometry geo_upd{};  // the update kernel's (a taller z-chunk by default)
     Plan plan_res{};
     Geometry geo_res{};  // FP64 residual kernel
     // workspace
@@ -279,21 +281,22 @@ hipError_t enqueue_iters(pcg_ctx c, int first, int count, hipStream_t s, hipEven
     SolveState* s1 = c->st + 1;
     double* pdir = c->partials;
     double* pupd = c->partials + c->partials_cap / 2;
-    const unsigned nb = c->geo.nblocks;
+    const unsigned nbd = c->geo.nblocks, nbu = c->geo_upd.nblocks;
     for (int i = first; i < first + count; ++i) {
         void* pold = c->p[(i - 1) & 1];
         void* pnew = c->p[i & 1];
         if (evs) (void)hipEventRecord(evs[3 * (i - first)], s);
-        const Chain dch = i == first ? Chain{nullptr, nb, s0, s0, c->hist, pdir} : Chain{pupd, nb, s1, s0, c->hist, pdir};
+        const Chain dch =
+            i == first ? Chain{nullptr, nbu, s0, s0, c->hist, pdir} : Chain{pupd, nbu, s1, s0, c->hist, pdir};
         hipError_t e = launch_pcg_direction(c->dt, c->plan, c->geo, op_of(c), c->r, pold, pnew, dch, s);
         if (e != hipSuccess) return e;
         if (evs) (void)hipEventRecord(evs[3 * (i - first) + 1], s);
-        const Chain uch{pdir, nb, s0, s1, c->hist, pupd};
-        e = launch_pcg_update(c->dt, c->plan, c->geo, op_of(c), pnew, c->xacc, c->opt.x_accum, c->r, uch, s);
+        const Chain uch{pdir, nbd, s0, s1, c->hist, pupd};
+        e = launch_pcg_update(c->dt, c->plan_upd, c->geo_upd, op_of(c), pnew, c->xacc, c->opt.x_accum, c->r, uch, s);
         if (e != hipSuccess) return e;
         if (evs) (void)hipEventRecord(evs[3 * (i - first) + 2], s);
     }
-    return launch_pcg_close(op_of(c).kc != nullptr, Chain{pupd, nb, s1, s0, c->hist, nullptr}, s);
+    return launch_pcg_close(op_of(c).kc != nullptr, Chain{pupd, nbu, s1, s0, c->hist, nullptr}, s);
 }
 
 pcg_status ensure_chunk(pcg_ctx c) {
@@ -523,13 +526,27 @@ pcg_status pcg_create(pcg_ctx* out, int nx, int ny, int nz, pcg_dtype storage, v
     c->opt = o;
     c->plan = default_plan(nx, ny, nz, storage, o);
     c->geo = make_geometry(nx, ny, nz, c->plan, storage);
+    // The update kernel (stencil, two axpys and a norm per point) streams
+    // better with twice the planes per work-group while the launch keeps at
+    // least 256 work-groups (256^3 FP32: 80.6 -> 76.7 us), while the direction
+    // kernel is faster with the shorter chunk (36.5 against 45.6 us).
+    c->plan_upd = c->plan;
+    if (o.zchunk_update > 0) {
+        c->plan_upd.zc = o.zchunk_update;
+    } else if (o.zchunk_update == 0 && o.zchunk <= 0) {
+        Plan t = c->plan;
+        t.zc = 2 * c->plan.zc;
+        if (t.zc <= nz && make_geometry(nx, ny, nz, t, storage).nblocks >= 256) c->plan_upd = t;
+    }
+    c->geo_upd = make_geometry(nx, ny, nz, c->plan_upd, storage);
     c->plan_res = Plan{TILE_CFGS[c->plan.cfg].vec && (nx % 2 == 0) ? 2 : 5, c->plan.zc};
     c->geo_res = make_geometry(nx, ny, nz, c->plan_res, DT_F64);
     c->chunk_iters = o.chunk_iters;
 
     const size_t es = dt_size(storage);
     const size_t xs = dt_size(o.x_accum);
-    size_t maxblk = std::max<size_t>({(size_t)c->geo.nblocks, (size_t)c->geo_res.nblocks, (size_t)DOT_MAX_BLOCKS});
+    size_t maxblk = std::max<size_t>({(size_t)c->geo.nblocks, (size_t)c->geo_upd.nblocks, (size_t)c->geo_res.nblocks,
+                                      (size_t)DOT_MAX_BLOCKS});
     c->partials_cap = (size_t)MAX_RED_COMPONENTS * maxblk;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMalloc(&c->r, es * n);
