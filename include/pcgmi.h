@@ -75,9 +75,11 @@ typedef struct {
                           PCG, the same iterates in exact arithmetic; moves 48 instead of
                           40 bytes per point); -1 = default (chosen by grid size) */
     int zchunk_update;  /* z planes per work-group of the two-kernel form's update kernel:
-                          0 = default (twice the direction kernel's while the launch keeps
-                          at least 256 work-groups; the direction kernel's when zchunk is
-                          given); -1 = the direction kernel's; > 0 = this many */
+                          0 = default (twice the direction kernel's when r, p, p' and x
+                          exceed the 256 MiB last-level cache and the launch keeps at least
+                          256 work-groups, else the direction kernel's; the direction
+                          kernel's when zchunk is given); -1 = the direction kernel's;
+                          > 0 = this many */
 } pcg_options;
 
 typedef struct {

@@ -526,14 +526,18 @@ pcg_status pcg_create(pcg_ctx* out, int nx, int ny, int nz, pcg_dtype storage, v
     c->opt = o;
     c->plan = default_plan(nx, ny, nz, storage, o);
     c->geo = make_geometry(nx, ny, nz, c->plan, storage);
-    // The update kernel (stencil, two axpys and a norm per point) streams
-    // better with twice the planes per work-group while the launch keeps at
-    // least 256 work-groups (256^3 FP32: 80.6 -> 76.7 us), while the direction
-    // kernel is faster with the shorter chunk (36.5 against 45.6 us).
+    // When an iteration's vectors (r, p twice, x) exceed the last-level
+    // cache, the update kernel (stencil, two axpys and a norm per point)
+    // streams better with twice the planes per work-group while the launch
+    // keeps at least 256 work-groups (256^3 FP32: 80.6 -> 76.7 us), while the
+    // direction kernel stays faster with the shorter chunk (36.5 against
+    // 45.6 us). With cache-resident vectors the taller chunk measured slower
+    // (192^3 FP32: 60.9 -> 62.7 us per iteration).
     c->plan_upd = c->plan;
     if (o.zchunk_update > 0) {
         c->plan_upd.zc = o.zchunk_update;
-    } else if (o.zchunk_update == 0 && o.zchunk <= 0) {
+    } else if (o.zchunk_update == 0 && o.zchunk <= 0 &&
+               (size_t)n * (3 * dt_size(storage) + dt_size(o.x_accum)) > LLC_BYTES) {
         Plan t = c->plan;
         t.zc = 2 * c->plan.zc;
         if (t.zc <= nz && make_geometry(nx, ny, nz, t, storage).nblocks >= 256) c->plan_upd = t;
