@@ -103,6 +103,19 @@ def build_rhs(P, torch, n):
     return b64.to(torch.float32), b64
 
 
+def warm_up(torch, fn, seconds=0.05):
+    """Launch fn until `seconds` of wall time have passed (at least 10
+    launches): after seconds of host-side input generation the GPU needs tens
+    of milliseconds of work to return to its working clocks."""
+    t0 = time.perf_counter()
+    k = 0
+    while k < 10 or time.perf_counter() - t0 < seconds:
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        k += 10
+
+
 def time_kernels_512(P, torch, n, reps):
     """Standalone kernels at n^3: achieved GB/s of algorithmic bytes."""
     import synthetic
@@ -121,8 +134,7 @@ def time_kernels_512(P, torch, n, reps):
             "dot": (lambda: P.dot(ctx, N, x, y, d), 2 * es),
         }
         for op, (fn, bpp) in ops.items():
-            for _ in range(3):
-                fn()
+            warm_up(torch, fn)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
@@ -161,8 +173,7 @@ def bench_sell(P, torch, reps, grids=((256, 256, 256), None), b256=None, mf_solv
         res = {"grid": [nx, ny, nz], "nnz": A.nnz, "slots": A.nslots}
         for name, fn, nbytes in (("sell_spmv", lambda: P.pcg_sell_spmv(A, x, y), 8 * A.nnz + 8 * N),
                                  ("matrix_free_stencil", lambda: P.stencil_apply(ctx, x, y), 8 * N)):
-            for _ in range(3):
-                fn()
+            warm_up(torch, fn)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
@@ -207,8 +218,7 @@ def bench_sell(P, torch, reps, grids=((256, 256, 256), None), b256=None, mf_solv
     ragged = {"rows": N, "nnz": int(rowptr[-1])}
     for sigma in (1, 4096):
         A = P.pcg_sell_create(rowptr, col, val, N, sigma=sigma)
-        for _ in range(3):
-            P.pcg_sell_spmv(A, x, y)
+        warm_up(torch, lambda: P.pcg_sell_spmv(A, x, y))
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
