@@ -448,8 +448,7 @@ def bench_learned(P, torch, n_works, rounds, n_kernel=128, oracle_cpu=False):
     r = torch.from_numpy(synthetic.uniform_f32(1, N)).cuda()
     g = torch.from_numpy(synthetic.gaussian_random_field(nk).astype(np.float32)).cuda()
     z = torch.empty(N, device="cuda")
-    for _ in range(3):
-        P.cnn_forward(net, (nk, nk, nk), r, g, z)
+    warm_up(torch, lambda: P.cnn_forward(net, (nk, nk, nk), r, g, z))
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record()
