@@ -29,7 +29,10 @@ Also reported on the same JSON line:
                    achieved GB/s of algorithmic bytes;
   sell_spmv     -- general sparse SpMV (sliced ELLPACK) of the explicitly
                    stored seven-point matrix at 256^3 and on the paper's
-                   comparison grid, beside the matrix-free stencil;
+                   comparison grid, beside the matrix-free stencil; Jacobi-PCG
+                   on the stored matrix at 256^3 (the same b) and 32^3 beside
+                   the matrix-free solves; a ragged random SPD matrix (1 M rows)
+                   with and without sigma sorting;
   batched       -- 64 uneven problems (edges log-uniform in [16, 128], seed 5;
                    b_i ~ U[-1,1], seeds 1000 + i) in one persistent
                    hipGraph-captured launch: solves/s, per-problem latency,
