@@ -347,6 +347,31 @@ def cpu_baseline(b64_host, n, gpu_iters, budget_s=15.0):
                           f"first {its} iterations timed ({tm:.1f} s), scaled to the GPU's {gpu_iters} iterations"))}
 
 
+def cpu_baseline_sell(b32_host, n, gpu_iters, reps=3):
+    """The oracle beside the stored-matrix rows: its compressed-row SpMV of
+    the 256^3 seven-point matrix (FP64, `reps` products) and its Jacobi-PCG
+    on the same b, 4 iterations timed and scaled to the GPU's count."""
+    import oracle
+    import synthetic
+
+    rowptr, col, val = synthetic.poisson7_csr(n, n, n)
+    x = synthetic.uniform_f32(synthetic.SEED_C2_X, n ** 3).astype("float64")
+    oracle.csr_spmv(rowptr, col, val, x)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.csr_spmv(rowptr, col, val, x)
+    spmv_s = (time.perf_counter() - t0) / reps
+    b64 = b32_host.astype("float64")
+    t0 = time.perf_counter()
+    out = oracle.csr_pcg(rowptr, col, val, b64, rtol=0.0, maxit=4)
+    it_s = (time.perf_counter() - t0) / max(out["iters"], 1)
+    return {"cores": oracle.threads(), "kind": "oracle", "spmv_ms": round(spmv_s * 1e3, 1),
+            "pcg_s_estimate": round(it_s * gpu_iters, 2),
+            "sample": (f"FP64 oracle on the stored {n}^3 seven-point matrix: {reps} products timed; "
+                       f"Jacobi-PCG on the same b, 4 iterations timed (setup included) and scaled to the "
+                       f"GPU's {gpu_iters} iterations")}
+
+
 def bench_batched(P, torch, reps, oracle_budget_s=0.0):
     """The 64-problem batch: graph replays timed with torch events on the
     stream the batch was created on (the current stream)."""
@@ -652,6 +677,9 @@ def main():
     sell = None
     if not args.no_sell:
         sell = bench_sell(P, torch, args.kernel_reps, b256=b if n == 256 else None, mf_solve_s=dt_solve)
+        if not args.no_cpu_baseline and n == 256:
+            g_it = sell["256x256x256"]["pcg_solve"]["iters"]
+            sell["cpu_baseline"] = cpu_baseline_sell(b.cpu().numpy(), n, g_it)
         print(f"# sell: {sell}", file=sys.stderr, flush=True)
 
     kern = None
