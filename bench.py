@@ -193,15 +193,16 @@ def bench_sell(P, torch, reps, grids=((256, 256, 256), None), b256=None, mf_solv
             # iteration 8 B per entry + 60 B per row (q = A p: x and q 8;
             # update: p, q, r, r', D^-1 20 and x 16; direction: r, D^-1, p, p' 16).
             xs = torch.zeros(N, dtype=torch.float64, device="cuda")
-            P.pcg_sell_solve(A, b256, xs, 1e-6, 5000)
+            P.pcg_sell_solve(A, b256, xs, 1e-6, 5000, raise_on_error=False)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            info = P.pcg_sell_solve(A, b256, xs, 1e-6, 5000)
+            info = P.pcg_sell_solve(A, b256, xs, 1e-6, 5000, raise_on_error=False)
             torch.cuda.synchronize()
             s = time.perf_counter() - t0
             it = max(info["iters"], 1)
             per_it = 8 * A.nnz + 60 * N
             res["pcg_solve"] = {"iters": info["iters"], "restarts": info["restarts"], "ms": round(s * 1e3, 2),
+                                "status": P.STATUS_NAMES[info["status"]],
                                 "us_per_iteration": round(s * 1e6 / it, 1),
                                 "iteration_GB/s": round(per_it * it / s / 1e9, 1),
                                 "true_relres": info["rel_res_true_fp64"],
@@ -244,8 +245,8 @@ def bench_sell(P, torch, reps, grids=((256, 256, 256), None), b256=None, mf_solv
     xs = torch.zeros(N, dtype=torch.float64, device="cuda")
     ctx = P.pcg_create(n1, n1, n1, torch.float32, x_dtype=torch.float64, single_reduction=0)
     small = {}
-    for name, fn in (("stored_matrix", lambda: P.pcg_sell_solve(A, b, xs, 1e-6, 500)),
-                     ("matrix_free", lambda: P.pcg_solve(ctx, b, xs, 1e-6, 500))):
+    for name, fn in (("stored_matrix", lambda: P.pcg_sell_solve(A, b, xs, 1e-6, 500, raise_on_error=False)),
+                     ("matrix_free", lambda: P.pcg_solve(ctx, b, xs, 1e-6, 500, raise_on_error=False))):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -309,16 +310,16 @@ def bench_small_grid(P, torch, steps, n=32):
     for name, sr in (("two_kernel", 0), ("single_reduction", 1)):
         ctx = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64, single_reduction=sr)
         x = torch.empty(N, dtype=torch.float64, device="cuda")
-        P.pcg_solve(ctx, b, x, 1e-6, 500)
+        P.pcg_solve(ctx, b, x, 1e-6, 500, raise_on_error=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            info = P.pcg_solve(ctx, b, x, 1e-6, 500)
+            info = P.pcg_solve(ctx, b, x, 1e-6, 500, raise_on_error=False)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) / steps * 1e3
         out[name] = {"iters": info["iters"], "ms_per_solve": round(ms, 4),
                      "us_per_iteration": round(ms * 1e3 / max(info["iters"], 1), 2),
-                     "true_relres": info["rel_res_true_fp64"]}
+                     "true_relres": info["rel_res_true_fp64"], "status": P.STATUS_NAMES[info["status"]]}
         P.pcg_destroy(ctx)
     return out
 
@@ -387,12 +388,12 @@ def bench_batched(P, torch, reps, oracle_budget_s=0.0):
         bt.view(b, i).copy_(torch.from_numpy(synthetic.uniform_f32(synthetic.SEED_C4_B_BASE + i, m ** 3)))
     x = torch.zeros(bt.total, dtype=torch.float64, device="cuda")
     for _ in range(2):
-        r = P.pcg_batch_solve(bt, b, x, rtol=1e-6, maxit=5000)
+        r = P.pcg_batch_solve(bt, b, x, rtol=1e-6, maxit=5000, raise_on_error=False)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record()
     for _ in range(reps):
-        r = P.pcg_batch_solve(bt, b, x, rtol=1e-6, maxit=5000)
+        r = P.pcg_batch_solve(bt, b, x, rtol=1e-6, maxit=5000, raise_on_error=False)
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / reps
@@ -404,12 +405,12 @@ def bench_batched(P, torch, reps, oracle_budget_s=0.0):
         ctx = P.pcg_create(m, m, m, torch.float32, x_dtype=torch.float64)
         ctxs.append((ctx, torch.empty(m ** 3, dtype=torch.float64, device="cuda")))
     for i, (ctx, xi) in enumerate(ctxs):
-        P.pcg_solve(ctx, bt.view(b, i), xi, 1e-6, 5000)
+        P.pcg_solve(ctx, bt.view(b, i), xi, 1e-6, 5000, raise_on_error=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     seq_iters = []
     for i, (ctx, xi) in enumerate(ctxs):
-        seq_iters.append(P.pcg_solve(ctx, bt.view(b, i), xi, 1e-6, 5000)["iters"])
+        seq_iters.append(P.pcg_solve(ctx, bt.view(b, i), xi, 1e-6, 5000, raise_on_error=False)["iters"])
     torch.cuda.synchronize()
     seq = time.perf_counter() - t0
     for ctx, _ in ctxs:
@@ -420,6 +421,7 @@ def bench_batched(P, torch, reps, oracle_budget_s=0.0):
                           "max": round(lat[-1] * 1e3, 3)},
            "effective_GB/s": round(traffic / (ms * 1e-3) / 1e9, 1),
            "iters_total": int(sum(r["iters"])), "restarts_total": int(sum(r["restarts"])),
+           "status": P.STATUS_NAMES[r["status"]],
            "max_true_relres": max(r["relres"]), "sequential_ms": round(seq * 1e3, 2),
            "speedup_vs_sequential": round(seq * 1e3 / ms, 3),
            "iters_equal_sequential": int(sum(1 for a, c in zip(r["iters"], seq_iters) if a == c)),
@@ -527,8 +529,8 @@ def learned_workflow(P, torch, n, rounds, oracle_cpu):
     P.pcg_set_coefficients(ctx, kd)
     x = torch.empty(N, dtype=torch.float64, device="cuda")
     b = torch.from_numpy(synthetic.uniform_f32(synthetic.SEED_C5_HELDOUT_BASE, N)).cuda()
-    P.pcg_solve(ctx, b, x, 1e-6, 20000)
-    jac = P.pcg_solve(ctx, b, x, 1e-6, 20000)
+    P.pcg_solve(ctx, b, x, 1e-6, 20000, raise_on_error=False)
+    jac = P.pcg_solve(ctx, b, x, 1e-6, 20000, raise_on_error=False)
     P.pcg_solve_flexible(ctx, net, gd, b, x, 1e-6, 20000, raise_on_error=False)
     fcg = P.pcg_solve_flexible(ctx, net, gd, b, x, 1e-6, 20000, raise_on_error=False)
     oracle_out = None
@@ -603,12 +605,12 @@ def main():
     ctx = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64)
     x = torch.empty(N, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
-        P.pcg_solve(ctx, b, x, 1e-6, args.maxit)
+        P.pcg_solve(ctx, b, x, 1e-6, args.maxit, raise_on_error=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
     for _ in range(args.steps):
-        infos.append(P.pcg_solve(ctx, b, x, 1e-6, args.maxit))
+        infos.append(P.pcg_solve(ctx, b, x, 1e-6, args.maxit, raise_on_error=False))
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     dt_solve = dt
@@ -620,7 +622,7 @@ def main():
     # Per-kernel durations: the same solve with HIP events around every
     # iteration kernel (eager launches on the same stream).
     tctx = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64, kernel_timing=1)
-    tinfo = P.pcg_solve(tctx, b, x, 1e-6, args.maxit)
+    tinfo = P.pcg_solve(tctx, b, x, 1e-6, args.maxit, raise_on_error=False)
     k2_us = tinfo["k2_ms"] * 1e3 / max(tinfo["k2_launches"], 1)
     k1_us = tinfo["k1_ms"] * 1e3 / max(tinfo["k1_launches"], 1)
     achieved = BYTES_UPDATE * N / (k2_us * 1e-6) / 1e9
@@ -701,6 +703,7 @@ def main():
                                 "(restarts from r = b - A x when the recursion drifts), FP64 x accumulator"),
                    "grid": [n, n, n], "iters": iters, "rel_res_recursive": info["rel_res_recursive"],
                    "rel_res_true_fp64": info["rel_res_true_fp64"], "restarts": info["restarts"],
+                   "status": P.STATUS_NAMES[info["status"]],
                    "per_iteration_us": round(dt * 1e6 / max(iters, 1), 2)},
         "roofline": roofline,
         "refined": refined or None,

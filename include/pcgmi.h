@@ -41,7 +41,10 @@ typedef enum {
     PCG_E_NOCONV = 3,      /* maxit reached; the last iterate is left in x */
     PCG_E_BREAKDOWN = 4,   /* p.Ap <= 0 or a non-finite scalar (e.g. NaN in b) */
     PCG_E_NOMEM = 5,       /* workspace allocation failed */
-    PCG_E_UNSUPPORTED = 6  /* combination not implemented (e.g. dtype for an op) */
+    PCG_E_UNSUPPORTED = 6, /* combination not implemented (e.g. dtype for an op) */
+    PCG_E_TRUE_RESIDUAL = 7 /* the recursion met ||r|| <= rtol ||b||, but the FP64 true residual
+                              ||b - A x|| / ||b|| of the returned x is still above rtol after the
+                              allowed restarts; x holds that last iterate */
 } pcg_status;
 
 /* Storage type of the vectors. Arithmetic is FP32 for F32/BF16/F16 (values
@@ -117,9 +120,11 @@ pcg_status pcg_destroy(pcg_ctx ctx);
  * FP64 for F64. */
 pcg_status stencil_apply(pcg_ctx ctx, const void *x, void *y);
 
-/* z = alpha x + y over n elements of the storage type (paper Sec. IV). z may
- * equal x or y; other partial overlaps are PCG_E_ARG. n >= 0. */
-pcg_status axpy(pcg_ctx ctx, int64_t n, float alpha, const void *x, const void *y, void *z);
+/* z = alpha x + y over n elements of the storage type (paper Sec. IV). alpha
+ * is rounded once to the arithmetic type (FP32 for F32/BF16/F16 storage, kept
+ * FP64 for F64). z may equal x or y; other partial overlaps are PCG_E_ARG.
+ * n >= 0. */
+pcg_status axpy(pcg_ctx ctx, int64_t n, double alpha, const void *x, const void *y, void *z);
 
 /* *out_dev = sum_i x_i y_i over n elements of the storage type (paper Sec. V):
  * per-lane FP32 accumulation (FP64 for F64 storage), wavefront and
@@ -137,7 +142,10 @@ pcg_status dot_f64(pcg_ctx ctx, int64_t n, const void *x, const void *y, double 
  * included); then recomputes the true residual ||b - A x|| / ||b|| in FP64
  * and, while it exceeds rtol, restarts from x (opt->max_restarts).
  * b = 0 gives x = 0, iters = 0.
- * Returns PCG_OK, PCG_E_NOCONV (last iterate left in x) or PCG_E_BREAKDOWN.
+ * Returns PCG_OK only when that FP64 true residual is <= rtol;
+ * PCG_E_TRUE_RESIDUAL when the recursion converged but the true residual is
+ * still above rtol; PCG_E_NOCONV (maxit reached) or PCG_E_BREAKDOWN. In every
+ * case the last iterate is left in x and info is filled.
  * info may be NULL. Blocks until the solve is finished. */
 pcg_status pcg_solve(pcg_ctx ctx, const void *b, void *x, double rtol, int maxit, pcg_info *info);
 
@@ -253,7 +261,10 @@ pcg_status cnn_train_step(cnn_net net, int nx, int ny, int nz, const void *pairs
  * from the current x. The context needs F32 storage and an FP64 x
  * accumulator; the network must use the context's stream; g: DEVICE FP32
  * network channel (may be NULL). info: fallback_used = 0 (none), 1 (switched
- * to Jacobi; outer_iters = the iteration), 2 (Jacobi-PCG continuation). */
+ * to Jacobi; outer_iters = the iteration), 2 (Jacobi-PCG continuation).
+ * Returns PCG_OK only when the final FP64 true residual is <= rtol, else
+ * PCG_E_TRUE_RESIDUAL, PCG_E_NOCONV or PCG_E_BREAKDOWN (x holds the last
+ * iterate in every case). */
 pcg_status pcg_solve_flexible(pcg_ctx ctx, cnn_net net, const float *g, const void *b, void *x, double rtol,
                               int maxit, pcg_info *info);
 
@@ -335,8 +346,10 @@ pcg_status pcg_batch_layout(pcg_batch batch, int64_t *offsets, int64_t *total, i
  * ||b - A x|| / ||b||), latency_s double[nprob] (device wall clock from the
  * earliest problem's start to this problem's end), restarts int[nprob],
  * seconds (host wall time of the call). Returns after the launch has ended;
- * PCG_E_NOCONV / PCG_E_BREAKDOWN if any problem did not converge (outputs
- * still written); PCG_E_HIP if a group barrier wait exceeded its bound. */
+ * The status is the worst over the problems: PCG_E_BREAKDOWN, then
+ * PCG_E_NOCONV (maxit), then PCG_E_TRUE_RESIDUAL (a recursion converged but
+ * its FP64 true residual is above rtol after the restarts); outputs are
+ * written in every case. PCG_E_HIP if a group barrier wait exceeded its bound. */
 pcg_status pcg_batch_solve(pcg_batch batch, const float *b, double *x, double rtol, int maxit, int use_graph,
                            int *iters, double *relres, double *latency_s, int *restarts, double *seconds);
 
@@ -397,19 +410,24 @@ pcg_status pcg_sell_spmv(pcg_sell A, const float *x, float *y);
  * FP32, the products and updates FP32, the inner products accumulated in
  * FP64, x accumulated in FP64. When the recursion has converged but the FP64
  * true residual ||b - A x|| is above rtol ||b||, the solve restarts from x
- * with r = fl32(b - A x) (at most 3 times). b: DEVICE float[n]; x: DEVICE
+ * with r = fl32(b - A x) (at most 3 times; pcg_sell_set_restarts). b: DEVICE float[n]; x: DEVICE
  * double[n] (written). The first call allocates the workspace (4 FP32 vectors)
  * and checks the diagonal: PCG_E_ARG if a row's diagonal is missing or not
  * positive. Returns after the solve with info filled (iters, status,
- * rel_res_recursive, rel_res_true_fp64, restarts, seconds); PCG_E_NOCONV or
- * PCG_E_BREAKDOWN (p.Ap <= 0 or a non-finite value) keep the last iterate in
- * x. Iterations are enqueued 16 at a time; the kernels of iterations past the
+ * rel_res_recursive, rel_res_true_fp64, restarts, seconds); PCG_OK only when
+ * the FP64 true residual is <= rtol; PCG_E_TRUE_RESIDUAL (the recursion
+ * converged, the true residual did not), PCG_E_NOCONV or PCG_E_BREAKDOWN
+ * (p.Ap <= 0 or a non-finite value) keep the last iterate in x. Iterations are enqueued 16 at a time; the kernels of iterations past the
  * end return at once. */
 pcg_status pcg_sell_solve(pcg_sell A, const float *b, double *x, double rtol, int maxit, pcg_info *info);
 /* use_graph = 1 (default): full batches of 16 iterations are captured once
  * as a HIP graph on a private stream and replayed (recaptured when x
  * changes); 0: every kernel is launched eagerly. Same results either way. */
 pcg_status pcg_sell_set_graph(pcg_sell A, int use_graph);
+/* FP64-residual restarts of pcg_sell_solve after the recursion has converged:
+ * 0 = never (the recursion alone decides when to stop, as the oracle's
+ * Jacobi-PCG does), -1 = default (3). PCG_E_ARG below -1. */
+pcg_status pcg_sell_set_restarts(pcg_sell A, int max_restarts);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *pcg_last_error(void);

@@ -17,11 +17,14 @@ import torch  # loads the HIP runtime the library binds to
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libpcgmi.so")
 
-PCG_OK, PCG_E_ARG, PCG_E_HIP, PCG_E_NOCONV, PCG_E_BREAKDOWN, PCG_E_NOMEM, PCG_E_UNSUPPORTED = range(7)
+(PCG_OK, PCG_E_ARG, PCG_E_HIP, PCG_E_NOCONV, PCG_E_BREAKDOWN, PCG_E_NOMEM, PCG_E_UNSUPPORTED,
+ PCG_E_TRUE_RESIDUAL) = range(8)
+# Outcomes of a solve that still fill its outputs (raise_on_error=False returns them).
+SOLVE_OUTCOMES = (PCG_E_NOCONV, PCG_E_BREAKDOWN, PCG_E_TRUE_RESIDUAL)
 PCG_F32, PCG_BF16, PCG_F16, PCG_F64 = range(4)
 
 STATUS_NAMES = {0: "PCG_OK", 1: "PCG_E_ARG", 2: "PCG_E_HIP", 3: "PCG_E_NOCONV", 4: "PCG_E_BREAKDOWN",
-                5: "PCG_E_NOMEM", 6: "PCG_E_UNSUPPORTED"}
+                5: "PCG_E_NOMEM", 6: "PCG_E_UNSUPPORTED", 7: "PCG_E_TRUE_RESIDUAL"}
 
 _TORCH_DT = {torch.float32: PCG_F32, torch.bfloat16: PCG_BF16, torch.float16: PCG_F16, torch.float64: PCG_F64}
 DT_TORCH = {v: k for k, v in _TORCH_DT.items()}
@@ -63,7 +66,7 @@ def _load():
         "pcg_create": ([ctypes.POINTER(vp), i, i, i, i, vp, ctypes.POINTER(PcgOptions)], i),
         "pcg_destroy": ([vp], i),
         "stencil_apply": ([vp, vp, vp], i),
-        "axpy": ([vp, i64, f, vp, vp, vp], i),
+        "axpy": ([vp, i64, d, vp, vp, vp], i),
         "dot": ([vp, i64, vp, vp, vp], i),
         "dot_f64": ([vp, i64, vp, vp, vp], i),
         "pcg_solve": ([vp, vp, vp, d, i, ctypes.POINTER(PcgInfo)], i),
@@ -97,6 +100,7 @@ def _load():
         "pcg_sell_spmv": ([vp, vp, vp], i),
         "pcg_sell_solve": ([vp, vp, vp, d, i, ctypes.POINTER(PcgInfo)], i),
         "pcg_sell_set_graph": ([vp, i], i),
+        "pcg_sell_set_restarts": ([vp, i], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -212,7 +216,7 @@ def stencil_apply(ctx: Context, x, y):
 def axpy(ctx: Context, n, alpha, x, y, z):
     for t, nm in ((x, "x"), (y, "y"), (z, "z")):
         _need(t, n, nm, ctx.dtype)
-    _check(lib.axpy(ctx.handle, int(n), float(alpha), _ptr(x), _ptr(y), _ptr(z)))
+    _check(lib.axpy(ctx.handle, int(n), float(alpha), _ptr(x), _ptr(y), _ptr(z)))  # alpha passed as a C double
 
 
 def dot(ctx: Context, n, x, y, out):
@@ -236,7 +240,7 @@ def pcg_solve(ctx: Context, b, x, rtol=1e-6, maxit=500, raise_on_error=True) -> 
     st = lib.pcg_solve(ctx.handle, _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(info))
     out = info.as_dict()
     out["status"] = st
-    if st != PCG_OK and (raise_on_error or st not in (PCG_E_NOCONV, PCG_E_BREAKDOWN)):
+    if st != PCG_OK and (raise_on_error or st not in SOLVE_OUTCOMES):
         raise PcgError(st, pcg_last_error())
     return out
 
@@ -269,7 +273,7 @@ def pcg_solve_refined(ctx: Context, b64, x64, rtol_outer=1e-10, rtol_inner=None,
                                int(max_outer), int(maxit_inner), ctypes.byref(info))
     out = info.as_dict()
     out["status"] = st
-    if st != PCG_OK and (raise_on_error or st not in (PCG_E_NOCONV, PCG_E_BREAKDOWN)):
+    if st != PCG_OK and (raise_on_error or st not in SOLVE_OUTCOMES):
         raise PcgError(st, pcg_last_error())
     return out
 
@@ -387,7 +391,7 @@ def pcg_solve_flexible(ctx: Context, net, g, b, x, rtol=1e-6, maxit=2000, raise_
                                 float(rtol), int(maxit), ctypes.byref(info))
     out = info.as_dict()
     out["status"] = st
-    if st != PCG_OK and (raise_on_error or st not in (PCG_E_NOCONV, PCG_E_BREAKDOWN)):
+    if st != PCG_OK and (raise_on_error or st not in SOLVE_OUTCOMES):
         raise PcgError(st, pcg_last_error())
     return out
 
@@ -483,7 +487,7 @@ def pcg_batch_solve(batch: Batch, b, x, rtol=1e-6, maxit=500, use_graph=True, ra
     secs = ctypes.c_double()
     st = lib.pcg_batch_solve(batch.handle, _ptr(b), _ptr(x), float(rtol), int(maxit), 1 if use_graph else 0, its, rel,
                              lat, rst, ctypes.byref(secs))
-    if raise_on_error and st != PCG_OK:
+    if st != PCG_OK and (raise_on_error or st not in SOLVE_OUTCOMES):
         _check(st)
     grid = (ctypes.c_int * 3)()
     _check(lib.pcg_batch_layout(batch.handle, None, None, None, grid))
@@ -569,10 +573,15 @@ def pcg_sell_solve(A: Sell, b, x, rtol=1e-6, maxit=500, raise_on_error=True) -> 
     st = lib.pcg_sell_solve(A.handle, _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(info))
     out = info.as_dict()
     out["status"] = st
-    if st != PCG_OK and (raise_on_error or st not in (PCG_E_NOCONV, PCG_E_BREAKDOWN)):
+    if st != PCG_OK and (raise_on_error or st not in SOLVE_OUTCOMES):
         raise PcgError(st, pcg_last_error())
     return out
 
 
 def pcg_sell_set_graph(A: Sell, use_graph: bool):
     _check(lib.pcg_sell_set_graph(A.handle, 1 if use_graph else 0))
+
+
+def pcg_sell_set_restarts(A: Sell, max_restarts: int):
+    """FP64-residual restarts of pcg_sell_solve (0 = never, -1 = default 3)."""
+    _check(lib.pcg_sell_set_restarts(A.handle, int(max_restarts)))

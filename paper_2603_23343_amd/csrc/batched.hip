@@ -867,6 +867,10 @@ pcg_status pcg_batch_layout(pcg_batch bt, int64_t* offsets, int64_t* total, int*
     return PCG_OK;
 }
 
+static int status_rank(pcg_status s) {
+    return s == PCG_E_BREAKDOWN ? 3 : s == PCG_E_NOCONV ? 2 : s == PCG_E_TRUE_RESIDUAL ? 1 : 0;
+}
+
 pcg_status pcg_batch_solve(pcg_batch bt, const float* b, double* x, double rtol, int maxit, int use_graph,
                            int* iters, double* relres, double* latency_s, int* restarts, double* seconds) {
     if (!bt || !b || !x) return berr(PCG_E_ARG, "pcg_batch_solve: null argument");
@@ -925,10 +929,16 @@ pcg_status pcg_batch_solve(pcg_batch bt, const float* b, double* x, double rtol,
         if (relres) relres[i] = o.rr0 > 0 ? std::sqrt(o.rr_true / o.rr0) : 0.0;
         if (restarts) restarts[i] = o.restarts;
         if (latency_s) latency_s[i] = (double)(o.t_done - tmin) / (B.clock_khz * 1e3);
-        if (ret == PCG_OK && o.done == 2) ret = PCG_E_BREAKDOWN;
-        else if (ret == PCG_OK && o.done != 1) ret = PCG_E_NOCONV;
+        // worst outcome over the problems: breakdown, then maxit, then a
+        // converged recursion whose FP64 true residual is above rtol
+        const pcg_status pst = o.done == 2 ? PCG_E_BREAKDOWN
+                               : o.done != 1 ? PCG_E_NOCONV
+                               : !(o.rr_true <= rtol2 * o.rr0) ? PCG_E_TRUE_RESIDUAL : PCG_OK;
+        if (status_rank(pst) > status_rank(ret)) ret = pst;
     }
-    if (ret != PCG_OK) berr(ret, "pcg_batch_solve: some problems did not converge");
+    if (ret == PCG_E_TRUE_RESIDUAL)
+        berr(ret, "pcg_batch_solve: some problems stopped with an FP64 true residual above rtol");
+    else if (ret != PCG_OK) berr(ret, "pcg_batch_solve: some problems did not converge");
     return ret;
 }
 

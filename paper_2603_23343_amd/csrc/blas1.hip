@@ -21,7 +21,7 @@ constexpr int NT = STREAM_THREADS;
 constexpr int AXPY_UNROLL = 4;
 
 template <typename T>
-__global__ void __launch_bounds__(NT) k_axpy(int64_t n, float alpha, const T* x, const T* y, T* z) {
+__global__ void __launch_bounds__(NT) k_axpy(int64_t n, typename Traits<T>::C alpha, const T* x, const T* y, T* z) {
     using C = typename Traits<T>::C;
     constexpr int W = Traits<T>::W;
     const int64_t nvec = n / W;
@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(NT) k_axpy(int64_t n, float alpha, const T* x,
             load_vec_nt<T>(y + i * W, yv[u]);
         }
     }
-    const C a = (C)alpha;
+    const C a = alpha;
 #pragma unroll
     for (int u = 0; u < AXPY_UNROLL; ++u) {
         const int64_t i = base + (int64_t)u * NT;
@@ -205,13 +205,15 @@ inline unsigned stream_blocks(int64_t nvec, int64_t per_block, int64_t cap) {
 
 }  // namespace
 
-hipError_t launch_axpy(int dt, int64_t n, float alpha, const void* x, const void* y, void* z, hipStream_t s) {
+hipError_t launch_axpy(int dt, int64_t n, double alpha, const void* x, const void* y, void* z, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     return dispatch_dt(dt, [&](auto tag) {
         using T = decltype(tag);
         const int64_t nvec = n / Traits<T>::W;
         const unsigned nb = stream_blocks(nvec, (int64_t)NT * AXPY_UNROLL, INT32_MAX);
-        hipLaunchKernelGGL(k_axpy<T>, dim3(nb), dim3(NT), 0, s, n, alpha, static_cast<const T*>(x),
+        // alpha in the arithmetic type: FP32 for 32- and 16-bit storage, FP64 for FP64
+        const typename Traits<T>::C a = (typename Traits<T>::C)alpha;
+        hipLaunchKernelGGL(k_axpy<T>, dim3(nb), dim3(NT), 0, s, n, a, static_cast<const T*>(x),
                            static_cast<const T*>(y), static_cast<T*>(z));
         return hipGetLastError();
     });

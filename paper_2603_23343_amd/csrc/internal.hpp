@@ -128,7 +128,7 @@ hipError_t launch_cast_scaled(int dt, const Plan& pres, const Geometry& gres, Op
 hipError_t launch_correct(int ddt, int64_t n, const void* d, double scale, double* x, hipStream_t s);
 
 // ---- streaming kernels ----
-hipError_t launch_axpy(int dt, int64_t n, float alpha, const void* x, const void* y, void* z, hipStream_t s);
+hipError_t launch_axpy(int dt, int64_t n, double alpha, const void* x, const void* y, void* z, hipStream_t s);
 // out_f32 and/or out_f64 (device) receive the dot; either may be null.
 hipError_t launch_dot(int dt, int64_t n, const void* x, const void* y, float* out_f32, double* out_f64, Red red,
                       hipStream_t s);

@@ -600,7 +600,7 @@ pcg_status stencil_apply(pcg_ctx c, const void* x, void* y) {
     return PCG_OK;
 }
 
-pcg_status axpy(pcg_ctx c, int64_t n, float alpha, const void* x, const void* y, void* z) {
+pcg_status axpy(pcg_ctx c, int64_t n, double alpha, const void* x, const void* y, void* z) {
     if (!c) return fail(PCG_E_ARG, "axpy: null context");
     if (n < 0) return fail(PCG_E_ARG, "axpy: negative length");
     if (n == 0) return PCG_OK;
@@ -677,9 +677,11 @@ pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, 
     res.fin.iters = total_iters;
     const SolveState& fin = res.fin;
 
+    // The FP64 true residual of the returned x decides success.
     pcg_status ret = PCG_OK;
     if (fin.done == 2) ret = PCG_E_BREAKDOWN;
     else if (fin.done != 1) ret = PCG_E_NOCONV;
+    else if (!(c->hres[0] <= rtol * rtol * fin.rr0)) ret = PCG_E_TRUE_RESIDUAL;
     if (info) {
         std::memset(info, 0, sizeof *info);
         info->iters = fin.iters;
@@ -695,6 +697,9 @@ pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, 
     }
     if (ret == PCG_E_BREAKDOWN) fail(ret, "pcg_solve: breakdown (p.Ap <= 0 or a non-finite value) at iteration %d", fin.iters + 1);
     else if (ret == PCG_E_NOCONV) fail(ret, "pcg_solve: no convergence in %d iterations", maxit);
+    else if (ret == PCG_E_TRUE_RESIDUAL)
+        fail(ret, "pcg_solve: the recursion converged but the FP64 true residual %.3e is above rtol %.3e after %d restarts",
+             info ? info->rel_res_true_fp64 : std::sqrt(c->hres[0] / fin.rr0), rtol, restarts);
     return ret;
 }
 
@@ -941,7 +946,8 @@ pcg_status pcg_solve_flexible(pcg_ctx c, cnn_net net, const float* g, const void
     else HIPCHK(launch_convert(DT_F64, c->opt.x_dtype, c->n, xacc, x, st));
     HIPCHK(hipStreamSynchronize(st));
     c->last_iters = fin.iters;
-    pcg_status ret = status == 1 ? PCG_OK : status == 2 ? PCG_E_BREAKDOWN : PCG_E_NOCONV;
+    pcg_status ret = status == 1 ? (true_rel <= rtol ? PCG_OK : PCG_E_TRUE_RESIDUAL)
+                   : status == 2 ? PCG_E_BREAKDOWN : PCG_E_NOCONV;
     if (info) {
         std::memset(info, 0, sizeof *info);
         info->iters = iters;
@@ -954,6 +960,8 @@ pcg_status pcg_solve_flexible(pcg_ctx c, cnn_net net, const float* g, const void
     }
     if (ret == PCG_E_BREAKDOWN) fail(ret, "pcg_solve_flexible: breakdown");
     else if (ret == PCG_E_NOCONV) fail(ret, "pcg_solve_flexible: no convergence in %d iterations", maxit);
+    else if (ret == PCG_E_TRUE_RESIDUAL)
+        fail(ret, "pcg_solve_flexible: the FP64 true residual %.3e is above rtol %.3e", true_rel, rtol);
     return ret;
 }
 

@@ -71,6 +71,7 @@ struct pcg_sell_s {
     // 16 iterations captured as one HIP graph (on a private stream), replayed
     // while the caller's x stays the same
     int use_graph = 1;
+    int max_restarts = 3;  // FP64-residual restarts after the recursion has converged
     hipStream_t capture = nullptr;
     hipGraphExec_t batch = nullptr;
     const double* batch_x = nullptr;
@@ -772,14 +773,15 @@ pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, in
         launch_finish<FIN_TRUE>(s, A->part, gq, A->st, 0, rtol, maxit);
         SCHK(read_state());
         rel_true = hs.bb > 0.0 ? std::sqrt(hs.true_rr / hs.bb) : 0.0;
-        if (hs.done == 1 && rel_true > rtol && restarts < 3 && hs.iters < maxit) {
+        if (hs.done == 1 && rel_true > rtol && restarts < A->max_restarts && hs.iters < maxit) {
             ++restarts;
             continue;
         }
         break;
     }
 #undef SCHK
-    const pcg_status status = hs.done == 1 ? PCG_OK : hs.done == 2 ? PCG_E_BREAKDOWN : PCG_E_NOCONV;
+    const pcg_status status = hs.done == 1 ? (rel_true <= rtol ? PCG_OK : PCG_E_TRUE_RESIDUAL)
+                              : hs.done == 2 ? PCG_E_BREAKDOWN : PCG_E_NOCONV;
     out.iters = hs.iters;
     out.status = status;
     out.rel_res_recursive = hs.bb > 0.0 ? std::sqrt(hs.rr / hs.bb) : 0.0;
@@ -789,12 +791,22 @@ pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, in
     if (info) *info = out;
     if (status == PCG_E_BREAKDOWN) serr(status, "pcg_sell_solve: breakdown (p.Ap <= 0 or a non-finite value)");
     if (status == PCG_E_NOCONV) serr(status, "pcg_sell_solve: %d iterations without convergence", hs.iters);
+    if (status == PCG_E_TRUE_RESIDUAL)
+        serr(status, "pcg_sell_solve: the FP64 true residual %.3e is above rtol %.3e after %d restarts", rel_true, rtol,
+             restarts);
     return status;
 }
 
 pcg_status pcg_sell_set_graph(pcg_sell A, int use_graph) {
     if (!A) return serr(PCG_E_ARG, "pcg_sell_set_graph: null handle");
     A->use_graph = use_graph ? 1 : 0;
+    return PCG_OK;
+}
+
+pcg_status pcg_sell_set_restarts(pcg_sell A, int max_restarts) {
+    if (!A) return serr(PCG_E_ARG, "pcg_sell_set_restarts: null handle");
+    if (max_restarts < -1) return serr(PCG_E_ARG, "pcg_sell_set_restarts: max_restarts must be >= -1");
+    A->max_restarts = max_restarts < 0 ? 3 : max_restarts;
     return PCG_OK;
 }
 

@@ -34,6 +34,13 @@ def make_vec(seed, n, dtype, kind="uniform", lo=-2, hi=2, density=1.0):
     raise ValueError(dtype)
 
 
+def check_status(P, info, rtol):
+    """A solve that stopped on its recursion reports PCG_OK exactly when its
+    FP64 true residual meets rtol, PCG_E_TRUE_RESIDUAL otherwise."""
+    assert info["status"] in (P.PCG_OK, P.PCG_E_TRUE_RESIDUAL), info["status"]
+    assert (info["status"] == P.PCG_OK) == (info["rel_res_true_fp64"] <= rtol), info
+
+
 def host64(t):
     return t.detach().to("cpu").to(torch.float64).numpy().reshape(-1)
 

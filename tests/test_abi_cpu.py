@@ -55,7 +55,7 @@ def test_argument_validation_without_gpu(lib):
     vp = ctypes.c_void_p
     lib.stencil_apply.argtypes = [vp, vp, vp]
     assert lib.stencil_apply(None, None, None) == 1
-    lib.axpy.argtypes = [vp, ctypes.c_int64, ctypes.c_float, vp, vp, vp]
+    lib.axpy.argtypes = [vp, ctypes.c_int64, ctypes.c_double, vp, vp, vp]
     assert lib.axpy(None, 4, 1.0, None, None, None) == 1
     lib.dot.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
     assert lib.dot(None, 4, None, None, None) == 1
@@ -123,5 +123,7 @@ def test_sell_argument_validation_without_gpu(lib):
     assert lib.pcg_sell_solve(None, None, None, 1e-6, 10, None) == 1
     lib.pcg_sell_info.argtypes = [vp, vp, vp, vp]
     assert lib.pcg_sell_info(None, None, None, None) == 1
+    lib.pcg_sell_set_restarts.argtypes = [vp, i]
+    assert lib.pcg_sell_set_restarts(None, 0) == 1
     lib.pcg_sell_destroy.argtypes = [vp]
     assert lib.pcg_sell_destroy(None) == 0

@@ -15,6 +15,7 @@ import pytest
 import torch
 
 import synthetic
+from gpu_helpers import check_status
 
 pytestmark = pytest.mark.gpu
 
@@ -126,9 +127,13 @@ def test_batch_restart_from_fp64_residual(P, orc):
         assert res["restarts"][i] == 3 or tr <= 1e-7
         ctx = P.pcg_create(d[0], d[1], d[2], torch.float32, x_dtype=torch.float64, max_restarts=0)
         xs = torch.empty(int(np.prod(d)), dtype=torch.float64, device="cuda")
-        info = P.pcg_solve(ctx, bt.view(b, i), xs, rtol=1e-7, maxit=3000)
+        info = P.pcg_solve(ctx, bt.view(b, i), xs, rtol=1e-7, maxit=3000, raise_on_error=False)
         assert tr <= info["rel_res_true_fp64"] * (1 + 1e-9)
+        check_status(P, info, 1e-7)
         ctx.close()
+    # the batch's status is PCG_OK exactly when every problem met rtol in FP64
+    assert (res["status"] == P.PCG_OK) == all(r <= 1e-7 for r in res["relres"])
+    assert res["status"] in (P.PCG_OK, P.PCG_E_TRUE_RESIDUAL)
 
 
 def test_autotuner_cache(P, tmp_path):

@@ -16,7 +16,7 @@ import pytest
 import torch
 
 import synthetic
-from gpu_helpers import host64, make_vec, ulp
+from gpu_helpers import check_status, host64, make_vec, ulp
 
 pytestmark = pytest.mark.gpu
 
@@ -92,8 +92,9 @@ def test_pcg_256_bench_configuration(P, orc):
     b = torch.from_numpy(b32).cuda()
     x = torch.empty(N, dtype=torch.float64, device="cuda")
     ctx0 = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64, max_restarts=0)
-    i0 = P.pcg_solve(ctx0, b, x, 1e-6, 5000)
+    i0 = P.pcg_solve(ctx0, b, x, 1e-6, 5000, raise_on_error=False)
     ctx0.close()
+    check_status(P, i0, 1e-6)
     ref = orc.pcg(shape, bb, rtol=1e-6, maxit=5000)
     print("iterations", i0["iters"], "oracle", ref["iters"], flush=True)
     assert abs(i0["iters"] - ref["iters"]) <= 2
@@ -119,8 +120,9 @@ def test_pcg_paper_comparison_grid(P, orc):
     x = torch.empty(N, dtype=torch.float64, device="cuda")
     print("paper grid PCG", nx, ny, nz, flush=True)
     ctx0 = P.pcg_create(nx, ny, nz, torch.float32, x_dtype=torch.float64, max_restarts=0)
-    i0 = P.pcg_solve(ctx0, b, x, 1e-6, 5000)
+    i0 = P.pcg_solve(ctx0, b, x, 1e-6, 5000, raise_on_error=False)
     ctx0.close()
+    check_status(P, i0, 1e-6)
     ref = orc.pcg(shape, bb, rtol=1e-6, maxit=5000)
     print("iterations", i0["iters"], "oracle", ref["iters"], flush=True)
     assert abs(i0["iters"] - ref["iters"]) <= 2

@@ -143,7 +143,9 @@ def test_axpy_general_alpha(P, orc, dtype):
     y, y64 = make_vec(5, n, dtype)
     z = torch.empty_like(x)
     alpha = -0.7310585786
-    a_used = float(np.float32(alpha))
+    # alpha is rounded once to the arithmetic type: FP32 for FP32 storage,
+    # unrounded for FP64 storage
+    a_used = float(np.float32(alpha)) if dtype == torch.float32 else alpha
     P.axpy(ctx, n, alpha, x, y, z)
     ref = orc.axpy(a_used, x64, y64)
     tol = (1e-6 if dtype == torch.float32 else 1e-15) * (np.abs(a_used * x64) + np.abs(y64))

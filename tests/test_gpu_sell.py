@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import synthetic
-from gpu_helpers import dev, host64
+from gpu_helpers import check_status, dev, host64
 
 pytestmark = pytest.mark.gpu
 
@@ -119,17 +119,35 @@ def test_poisson_full_size(P, orc, dims):
 # at or below rtol (the reading for FP32 storage with an FP64 x accumulator).
 # ---------------------------------------------------------------------------
 
-def _solve_pair(P, orc, rowptr, col, val, b32, rtol, maxit, sigma):
+def _solve_pair(P, orc, rowptr, col, val, b32, rtol, maxit, sigma, restarts=-1, with_oracle=True):
+    """The GPU solve (FP64-residual restarts: -1 default, 0 none) and the
+    oracle's compressed-row Jacobi-PCG of the same system."""
     n = rowptr.size - 1
     A = P.pcg_sell_create(rowptr, col, val, n, sigma=sigma)
+    P.pcg_sell_set_restarts(A, restarts)
     b = dev(b32)
     x = torch.zeros(n, dtype=torch.float64, device="cuda")
     got = P.pcg_sell_solve(A, b, x, rtol, maxit, raise_on_error=False)
     torch.cuda.synchronize()
-    ref = orc.csr_pcg(rowptr, col, val, b32.astype(np.float64), rtol=rtol, maxit=maxit)
+    ref = orc.csr_pcg(rowptr, col, val, b32.astype(np.float64), rtol=rtol, maxit=maxit) if with_oracle else None
     xh = x.cpu().numpy()
     A.close()
     return got, ref, xh
+
+
+def _parity_then_restarted(P, orc, rowptr, col, val, b32, rtol, maxit, sigma):
+    """Iterations within 2 of the oracle's with restarts off (the oracle
+    stops on its recursion too), then the default solve: PCG_OK and an FP64
+    true residual <= rtol."""
+    got0, ref, _ = _solve_pair(P, orc, rowptr, col, val, b32, rtol, maxit, sigma, restarts=0)
+    assert ref["status"] == orc.OK
+    assert got0["restarts"] == 0
+    check_status(P, got0, rtol)
+    assert abs(got0["iters"] - ref["iters"]) <= 2, (got0["iters"], ref["iters"])
+    got, _, x = _solve_pair(P, orc, rowptr, col, val, b32, rtol, maxit, sigma, with_oracle=False)
+    assert got["status"] == P.PCG_OK and got["rel_res_true_fp64"] <= rtol
+    assert got["iters"] >= got0["iters"]
+    return got, x
 
 
 @pytest.mark.parametrize("sigma", [1, 64])
@@ -140,10 +158,7 @@ def test_sell_pcg_poisson(P, orc, dims, sigma):
     print(f"sell pcg poisson {dims} sigma {sigma}", flush=True)
     rowptr, col, val = synthetic.poisson7_csr(nx, ny, nz)
     b32 = synthetic.uniform_f32(synthetic.SEED_C1_B, n)
-    got, ref, x = _solve_pair(P, orc, rowptr, col, val, b32, 1e-6, 500, sigma)
-    assert got["status"] == P.PCG_OK and ref["status"] == orc.OK
-    assert abs(got["iters"] - ref["iters"]) <= 2 + 2 * got["restarts"], (got["iters"], ref["iters"])
-    assert got["rel_res_true_fp64"] <= 1e-6
+    got, x = _parity_then_restarted(P, orc, rowptr, col, val, b32, 1e-6, 500, sigma)
     r = b32.astype(np.float64) - orc.csr_spmv(rowptr, col, val, x)
     assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b32.astype(np.float64)) * (1 + 1e-9)
 
@@ -157,10 +172,7 @@ def test_sell_pcg_random_spd(P, orc, n, partners, sigma):
     else:
         rowptr, col, val = synthetic.random_spd_csr(n, seed=51, max_partners=partners)
     b32 = synthetic.uniform_f32(52, n)
-    got, ref, x = _solve_pair(P, orc, rowptr, col, val, b32, 1e-6, 1000, sigma)
-    assert got["status"] == P.PCG_OK and ref["status"] == orc.OK
-    assert abs(got["iters"] - ref["iters"]) <= 2 + 2 * got["restarts"], (got["iters"], ref["iters"])
-    assert got["rel_res_true_fp64"] <= 1e-6
+    _parity_then_restarted(P, orc, rowptr, col, val, b32, 1e-6, 1000, sigma)
 
 
 def test_sell_pcg_status_paths(P, orc):
@@ -252,10 +264,7 @@ def test_random_spd_large_ragged(P, orc, large_spd, sigma):
     print(f"sell large ragged spd sigma {sigma}", flush=True)
     _check(P, orc, rowptr, col, val, n, sigma, synthetic.uniform_f32(58, n))
     b32 = synthetic.uniform_f32(59, n)
-    got, ref, x = _solve_pair(P, orc, rowptr, col, val, b32, 1e-6, 500, sigma)
-    assert got["status"] == P.PCG_OK and ref["status"] == orc.OK
-    assert abs(got["iters"] - ref["iters"]) <= 2 + 2 * got["restarts"], (got["iters"], ref["iters"])
-    assert got["rel_res_true_fp64"] <= 1e-6
+    _parity_then_restarted(P, orc, rowptr, col, val, b32, 1e-6, 500, sigma)
 
 
 def test_sell_on_a_side_stream(P, orc):
@@ -276,8 +285,12 @@ def test_sell_on_a_side_stream(P, orc):
     lens = np.maximum(np.diff(rowptr), 1).astype(np.float64)
     tol = 1.01 * lens * U32 * _abs_bound(orc, rowptr, col, val, x32.astype(np.float64))
     assert np.all(np.abs(host64(y) - ref) <= tol)
-    got = P.pcg_sell_solve(A, b, xs, 1e-6, 500)
+    P.pcg_sell_set_restarts(A, 0)
+    got = P.pcg_sell_solve(A, b, xs, 1e-6, 500, raise_on_error=False)
     oref = orc.csr_pcg(rowptr, col, val, b32.astype(np.float64), rtol=1e-6, maxit=500)
-    assert got["status"] == P.PCG_OK and abs(got["iters"] - oref["iters"]) <= 2 + 2 * got["restarts"]
-    assert got["rel_res_true_fp64"] <= 1e-6
+    check_status(P, got, 1e-6)
+    assert got["restarts"] == 0 and abs(got["iters"] - oref["iters"]) <= 2
+    P.pcg_sell_set_restarts(A, -1)
+    got = P.pcg_sell_solve(A, b, xs, 1e-6, 500)
+    assert got["status"] == P.PCG_OK and got["rel_res_true_fp64"] <= 1e-6
     A.close()

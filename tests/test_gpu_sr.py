@@ -13,7 +13,7 @@ import pytest
 import torch
 
 import synthetic
-from gpu_helpers import host64, make_vec
+from gpu_helpers import check_status, host64, make_vec
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +43,7 @@ def test_sr_iterations_and_residual(P, orc, shape):
     x, info, hist = _solve(P, shape, b, max_restarts=0)
     ref = orc.pcg_sr(shape, b64, rtol=1e-6, maxit=500, history=True)
     print(shape, "iters", info["iters"], "oracle", ref["iters"], flush=True)
-    assert info["status"] == P.PCG_OK
+    check_status(P, info, 1e-6)
     assert abs(info["iters"] - ref["iters"]) <= 2
     m = min(len(hist), len(ref["hist"]), 10)
     assert np.allclose(hist[:m], ref["hist"][:m], rtol=1e-4, atol=1e-7)
@@ -119,7 +119,7 @@ def test_sr_16bit_storage(P, orc, dt):
     b, b64 = make_vec(synthetic.SEED_C1_B, n, dt)
     x, info, _ = _solve(P, shape, b, rtol=1e-3, x_accum=torch.float32, max_restarts=0)
     ref = orc.pcg_sr(shape, b64, rtol=1e-3, maxit=500)
-    assert info["status"] == P.PCG_OK
+    check_status(P, info, 1e-3)
     assert abs(info["iters"] - ref["iters"]) <= 2
     # drift of 16-bit r rounding (2^-9 BF16, 2^-12 FP16 per step), as for the two-kernel form
     assert orc.true_relres(shape, b64, host64(x)) <= 2e-2

@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import synthetic
-from gpu_helpers import host64, make_vec
+from gpu_helpers import check_status, host64, make_vec
 
 pytestmark = pytest.mark.gpu
 
@@ -91,7 +91,7 @@ def test_vcoef_pcg_fp32(P, orc, n):
     kd = torch.from_numpy(k32).cuda()
     P.pcg_set_coefficients(ctx, kd)
     x = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
-    info = P.pcg_solve(ctx, b, x, 1e-6, 3000)
+    info = P.pcg_solve(ctx, b, x, 1e-6, 3000, raise_on_error=False)
     print(n, info["iters"], ref["iters"], flush=True)
     assert info["status"] == P.PCG_OK
     assert abs(info["iters"] - ref["iters"]) <= 2
@@ -111,8 +111,8 @@ def test_vcoef_pcg_fp64(P, orc):
     kd = torch.from_numpy(k32).cuda()
     P.pcg_set_coefficients(ctx, kd)
     x = torch.empty_like(b)
-    info = P.pcg_solve(ctx, b, x, 1e-10, 5000)
-    assert info["status"] == P.PCG_OK
+    info = P.pcg_solve(ctx, b, x, 1e-10, 5000, raise_on_error=False)
+    check_status(P, info, 1e-10)
     assert abs(info["iters"] - ref["iters"]) <= 2
     assert orc.true_relres(shape, b64, x.cpu().numpy(), kcell=k64) <= 1.5e-10
     assert np.max(np.abs(x.cpu().numpy() - ref["x"])) <= 1e-8 * np.max(np.abs(ref["x"]))
