@@ -136,6 +136,24 @@ pcg_status dot(pcg_ctx ctx, int64_t n, const void *x, const void *y, float *out_
 /* Same as dot with an FP64 device result. */
 pcg_status dot_f64(pcg_ctx ctx, int64_t n, const void *x, const void *y, double *out_dev);
 
+/* Allocation-free dot product, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the result of dot / dot_f64 (the same kernels and the same
+ * summation order, so the same bits) over n elements of type `storage`, with
+ * no context. x, y: DEVICE arrays, 16-byte aligned; out_f32 (DEVICE float) and
+ * out_f64 (DEVICE double) receive the sum, either may be NULL but not both.
+ * hip_stream: the stream to enqueue on (NULL = default stream), on the current
+ * device. Asynchronous.
+ * The work-group partials live in a fixed library-owned device array of 1024
+ * doubles (8 KiB) per device, held until the process ends, instead of a
+ * context's workspace; no hipMalloc, hipFree or other allocating call is made.
+ * Limit: n <= PCG_DOT_NOALLOC_MAX_N (2^40), else PCG_E_ARG.
+ * Calls that overlap on one device (on different streams or host threads)
+ * share that array and race: serialize them. */
+#define PCG_DOT_NOALLOC_MAX_N ((int64_t)1 << 40)
+pcg_status dot_noalloc(pcg_dtype storage, int64_t n, const void *x, const void *y, float *out_f32, double *out_f64,
+                       void *hip_stream);
+
 /* Solve A x = b with Jacobi-PCG (paper Sec. VII): b of the storage type, x
  * of opt->x_dtype. Stops when the recursive residual satisfies
  * ||r|| <= rtol ||b|| or after maxit iterations (in total, restarts

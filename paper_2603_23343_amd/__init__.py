@@ -10,7 +10,7 @@ from ._binding import (  # noqa: F401
     cnn_train_step,
     DT_TORCH, LIBPATH, PCG_BF16, PCG_E_ARG, PCG_E_BREAKDOWN, PCG_E_HIP, PCG_E_NOCONV, PCG_E_NOMEM,
     PCG_E_TRUE_RESIDUAL, PCG_E_UNSUPPORTED, PCG_F16, SOLVE_OUTCOMES, STATUS_NAMES, PCG_F32, PCG_F64, PCG_OK, Context, PcgError, PcgInfo, PcgOptions, axpy,
-    dot, dot_f64, dtype_code, lib, pcg_create, pcg_destroy, pcg_get_history, pcg_last_error,
+    dot, dot_f64, dot_noalloc, dtype_code, lib, pcg_create, pcg_destroy, pcg_get_history, pcg_last_error,
     pcg_options_default, pcg_make_pairs, pcg_refine_history, pcg_set_coefficients, pcg_solve, pcg_solve_flexible, pcg_solve_refined,
     pcg_solve_snapshots, stencil_apply,
     REFINE_RTOL_INNER, Sell, pcg_sell_build, pcg_sell_create, pcg_sell_destroy, pcg_sell_set_graph, pcg_sell_set_restarts, pcg_sell_solve, pcg_sell_spmv)

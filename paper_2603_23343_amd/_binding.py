@@ -69,6 +69,7 @@ def _load():
         "axpy": ([vp, i64, d, vp, vp, vp], i),
         "dot": ([vp, i64, vp, vp, vp], i),
         "dot_f64": ([vp, i64, vp, vp, vp], i),
+        "dot_noalloc": ([i, i64, vp, vp, vp, vp, vp], i),
         "pcg_solve": ([vp, vp, vp, d, i, ctypes.POINTER(PcgInfo)], i),
         "pcg_get_history": ([vp, ctypes.POINTER(d), i, ctypes.POINTER(i)], i),
         "pcg_solve_refined": ([vp, vp, vp, d, d, i, i, ctypes.POINTER(PcgInfo)], i),
@@ -231,6 +232,21 @@ def dot_f64(ctx: Context, n, x, y, out):
     _need(y, n, "y", ctx.dtype)
     _need(out, 1, "out", torch.float64)
     _check(lib.dot_f64(ctx.handle, int(n), _ptr(x), _ptr(y), _ptr(out)))
+
+
+def dot_noalloc(n, x, y, out, stream=None):
+    """Allocation-free dot product of the first n elements of x and y (same
+    dtype: FP32, BF16, FP16 or FP64) into the one-element device tensor out
+    (FP32 or FP64), on `stream` (default: the current stream)."""
+    dt = dtype_code(x.dtype)
+    _need(x, n, "x", x.dtype)
+    _need(y, n, "y", x.dtype)
+    if out.dtype not in (torch.float32, torch.float64):
+        raise PcgError(PCG_E_ARG, "out: FP32 or FP64 device tensor expected")
+    _need(out, 1, "out", out.dtype)
+    f32 = _ptr(out) if out.dtype == torch.float32 else None
+    f64 = _ptr(out) if out.dtype == torch.float64 else None
+    _check(lib.dot_noalloc(dt, int(n), _ptr(x), _ptr(y), f32, f64, _stream(stream)))
 
 
 def pcg_solve(ctx: Context, b, x, rtol=1e-6, maxit=500, raise_on_error=True) -> dict:

@@ -59,6 +59,13 @@ def test_argument_validation_without_gpu(lib):
     assert lib.axpy(None, 4, 1.0, None, None, None) == 1
     lib.dot.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
     assert lib.dot(None, 4, None, None, None) == 1
+    lib.dot_noalloc.argtypes = [ctypes.c_int, ctypes.c_int64, vp, vp, vp, vp, vp]
+    assert lib.dot_noalloc(0, -1, None, None, None, None, None) == 1  # negative length
+    assert lib.dot_noalloc(9, 4, None, None, None, None, None) == 1  # unknown storage type
+    assert lib.dot_noalloc(0, 4, 16, 32, None, None, None) == 1  # no output
+    assert lib.dot_noalloc(0, 4, 20, 32, 64, None, None) == 1  # misaligned x
+    assert lib.dot_noalloc(0, (1 << 40) + 1, 16, 32, 64, None, None) == 1  # above the maximum
+    assert b"maximum" in lib.pcg_last_error()
     lib.pcg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, vp]
     assert lib.pcg_solve(None, None, None, 1e-6, 10, None) == 1
     assert lib.pcg_destroy(None) == 0
