@@ -32,6 +32,9 @@ Contents, with the passage each follows:
   conv3d_fwd / conv3d_bwd / cnn_forward / cnn_backward / rel_mse / adam
       -> the learned preconditioner's network (3x3x3 convolutions, zero
          padding, ReLU) and its training step, FP64.
+  multigrid (VCycle, mg_pcg, hierarchy, prolong, restrict, smooth)
+      -> the geometric multigrid V-cycle (the paper's future work, Sec. VIII)
+         and PCG preconditioned by it; see oracle/multigrid.py.
 """
 from __future__ import annotations
 
@@ -615,3 +618,7 @@ def adam(w, g, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1.0 - b1 ** step)
     vh = v / (1.0 - b2 ** step)
     return w - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+from . import multigrid  # noqa: E402  (uses the operator above)
+from .multigrid import VCycle, hierarchy, mg_pcg, prolong, restrict, smooth  # noqa: E402,F401
