@@ -95,7 +95,8 @@ typedef struct {
     double seconds;          /* host wall time of the call */
     double t_1e6;            /* refinement: seconds until the true residual <= 1e-6 */
     double t_1e10;           /* refinement: seconds until the true residual <= 1e-10 */
-    double k1_ms, k2_ms;     /* kernel_timing: summed event time of the two iteration kernels */
+    double k1_ms, k2_ms;     /* kernel_timing: summed event time of the two iteration kernels
+                                (pcg_solve; the inner solves of pcg_solve_refined) */
     int k1_launches, k2_launches;
     int restarts;            /* pcg_solve: FP64 residual restarts taken (max_restarts) */
 } pcg_info;
@@ -207,6 +208,57 @@ pcg_status pcg_refine_history(pcg_ctx ctx, double *relres, int *inner_iters, int
  * (PCG_E_UNSUPPORTED otherwise). Affects stencil_apply, pcg_solve and
  * pcg_solve_refined on this context. */
 pcg_status pcg_set_coefficients(pcg_ctx ctx, const float *k_cell);
+
+/* ------------------------------------------------------------------------
+ * Geometric multigrid V-cycle preconditioner (the paper names multigrid as
+ * future work for its solver, Sec. VIII); FP32 storage. The textbook
+ * cell-centred V-cycle (Trottenberg, Oosterlee and Schueller, "Multigrid",
+ * 2001; Wesseling 1992):
+ *  - hierarchy: level l+1 halves every dimension of level l (a coarse cell
+ *    is 2 x 2 x 2 fine cells) while all three are even and level l has more
+ *    than coarse_max points; the coarsest grid may hold at most 1024 points
+ *    (PCG_E_UNSUPPORTED otherwise);
+ *  - coarse operators by rediscretisation: the seven-point operator of the
+ *    coarse grid, 4^-l A[k_l] (the unscaled operator's h^2 factor follows
+ *    the doubled spacing), with k_l the mean of the children's k (constant
+ *    coefficients stay constant);
+ *  - prolongation P: per dimension 3/4 of the coarse cell holding a fine cell
+ *    and 1/4 of the coarse cell on its other side (0 outside the grid),
+ *    restriction R = P^T / 8;
+ *  - smoother: damped Jacobi u += omega D^-1 (f - A u), nu sweeps before and
+ *    nu after the coarse correction, from u = 0; coarsest level: exact solve
+ *    (dense inverse, formed once in FP64 on the host).
+ * With equal sweeps before and after, the V-cycle is symmetric positive
+ * definite.
+ * ------------------------------------------------------------------------ */
+
+/* Build the hierarchy for the context's current operator (constant, or the
+ * coefficients of pcg_set_coefficients, which rebuilds it when they change).
+ * nu in 1..8 (sweeps on each side), omega in (0, 1] (0 = default 6/7, the best
+ * damping of the 3-D seven-point operator's high frequencies), coarse_max >= 0
+ * (0 = default 512). Allocates per level: the fine level 2-3 vectors, every
+ * coarser one 4-5 of its size, plus the coarsest inverse. Needs F32 storage. */
+pcg_status pcg_set_multigrid(pcg_ctx ctx, int nu, double omega, int coarse_max);
+
+/* Levels of the hierarchy (*nlev) and their dims (dims: host int[3 * nlev],
+ * {nx, ny, nz} finest first; may be NULL). */
+pcg_status pcg_mg_levels(pcg_ctx ctx, int *nlev, int *dims);
+
+/* u = V-cycle(g) on the context's grid: g and u DEVICE FP32 arrays of nx*ny*nz
+ * values, not overlapping; asynchronous on the context's stream. */
+pcg_status pcg_mg_apply(pcg_ctx ctx, const float *g, float *u);
+
+/* PCG with the V-cycle as preconditioner: pcg_solve_flexible's iteration
+ * (Notay's flexible CG with one stored direction, which equals PCG for a
+ * fixed symmetric preconditioner) with M(r) = V-cycle(r); b FP32, x of
+ * opt->x_dtype, FP64 x accumulator; stops on ||r|| <= rtol ||b||, then the
+ * FP64 true residual judges: while it is above rtol the same method restarts
+ * from x with r = fl32(b - A x) computed in FP64 (at most opt->max_restarts
+ * times; info.restarts); PCG_OK only when it is <= rtol, else
+ * PCG_E_TRUE_RESIDUAL; PCG_E_NOCONV, PCG_E_BREAKDOWN. A V-cycle output with
+ * z.r <= 0 (not expected) switches to Jacobi as in pcg_solve_flexible
+ * (info.fallback_used). PCG_E_ARG without pcg_set_multigrid. */
+pcg_status pcg_solve_mg(pcg_ctx ctx, const void *b, void *x, double rtol, int maxit, pcg_info *info);
 
 /* Copy the recursive relative residuals ||r_k||/||b||, k = 0..iters of the
  * last pcg_solve on this context, to the host array hist (n entries at most).
@@ -352,11 +404,21 @@ pcg_status pcg_batch_destroy(pcg_batch batch);
  * those groups use agent-scope fences)}. */
 pcg_status pcg_batch_layout(pcg_batch batch, int64_t *offsets, int64_t *total, int *plans, int *grid);
 
+/* Group-barrier form of later solves: 0 (default) = XCD-local where a group's
+ * work-groups all run on one XCD, agent-scope fences otherwise; 1 = agent-scope
+ * release / acquire fences for every group (the general form, slower; the
+ * same arithmetic, so the same results). PCG_E_ARG for another value. */
+pcg_status pcg_batch_set_barrier(pcg_batch batch, int form);
+
+/* FP64-residual restarts per problem in later solves: 0 = never (each
+ * recursion alone decides, as the oracle's Jacobi-PCG does), -1 = default (3). */
+pcg_status pcg_batch_set_restarts(pcg_batch batch, int max_restarts);
+
 /* Solve all problems from x0 = 0 with Jacobi-PCG until ||r_i|| <= rtol ||b_i||
  * (recursive residual) or maxit iterations in total. When a problem's
  * recursion stops, its FP64 true residual b - A x is computed; if that is
  * still above rtol ||b_i||, the problem restarts from x with r = fl32(b - A x)
- * and beta = 0 (at most 3 times), as pcg_solve does. b: DEVICE FP32 arena
+ * and beta = 0 (at most 3 times, pcg_batch_set_restarts), as pcg_solve does. b: DEVICE FP32 arena
  * (read only); x: DEVICE FP64 arena (written). use_graph = 1 captures
  * [barrier reset, persistent kernel] in a HIP graph on the first call and
  * replays it while (b, x, rtol, maxit) stay the same. Host outputs (NULL to

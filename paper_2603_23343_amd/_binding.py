@@ -77,6 +77,10 @@ def _load():
         "pcg_last_error": ([], ctypes.c_char_p),
         "pcg_set_coefficients": ([vp, vp], i),
         "pcg_solve_flexible": ([vp, vp, vp, vp, vp, d, i, ctypes.POINTER(PcgInfo)], i),
+        "pcg_set_multigrid": ([vp, i, d, i], i),
+        "pcg_mg_levels": ([vp, ctypes.POINTER(i), ctypes.POINTER(i)], i),
+        "pcg_mg_apply": ([vp, vp, vp], i),
+        "pcg_solve_mg": ([vp, vp, vp, d, i, ctypes.POINTER(PcgInfo)], i),
         "pcg_solve_snapshots": ([vp, vp, vp, d, i, ctypes.POINTER(i), i, vp, vp, ctypes.POINTER(PcgInfo)], i),
         "pcg_make_pairs": ([vp, i, vp, vp, vp, vp], i),
         "cnn_create": ([ctypes.POINTER(vp), vp], i),
@@ -91,6 +95,8 @@ def _load():
         "cnn_set_operator": ([vp, vp], i),
         "pcg_batch_create": ([ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.c_char_p, i, vp], i),
         "pcg_batch_destroy": ([vp], i),
+        "pcg_batch_set_barrier": ([vp, i], i),
+        "pcg_batch_set_restarts": ([vp, i], i),
         "pcg_batch_layout": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i), ctypes.POINTER(i)], i),
         "pcg_batch_solve": ([vp, vp, vp, d, i, i, ctypes.POINTER(i), ctypes.POINTER(d), ctypes.POINTER(d),
                              ctypes.POINTER(i), ctypes.POINTER(d)], i),
@@ -412,6 +418,40 @@ def pcg_solve_flexible(ctx: Context, net, g, b, x, rtol=1e-6, maxit=2000, raise_
     return out
 
 
+def pcg_set_multigrid(ctx: Context, nu=1, omega=0.0, coarse_max=0):
+    """Build the geometric multigrid hierarchy of the context's operator
+    (nu damped-Jacobi sweeps on each side, omega 0 = 6/7, coarse_max 0 = 512)."""
+    _check(lib.pcg_set_multigrid(ctx.handle, int(nu), float(omega), int(coarse_max)))
+
+
+def pcg_mg_levels(ctx: Context):
+    """[(nx, ny, nz)] of the hierarchy, finest first."""
+    nlev = ctypes.c_int(0)
+    dims = (ctypes.c_int * (3 * 16))()
+    _check(lib.pcg_mg_levels(ctx.handle, ctypes.byref(nlev), dims))
+    return [tuple(dims[3 * l:3 * l + 3]) for l in range(nlev.value)]
+
+
+def pcg_mg_apply(ctx: Context, g, u):
+    """u = V-cycle(g) (FP32 device tensors of the context's grid)."""
+    _need(g, ctx.n, "g", torch.float32)
+    _need(u, ctx.n, "u", torch.float32)
+    _check(lib.pcg_mg_apply(ctx.handle, _ptr(g), _ptr(u)))
+
+
+def pcg_solve_mg(ctx: Context, b, x, rtol=1e-6, maxit=500, raise_on_error=True) -> dict:
+    """PCG with the multigrid V-cycle preconditioner (pcg_set_multigrid first)."""
+    _need(b, ctx.n, "b", torch.float32)
+    _need(x, ctx.n, "x")
+    info = PcgInfo()
+    st = lib.pcg_solve_mg(ctx.handle, _ptr(b), _ptr(x), float(rtol), int(maxit), ctypes.byref(info))
+    out = info.as_dict()
+    out["status"] = st
+    if st != PCG_OK and (raise_on_error or st not in SOLVE_OUTCOMES):
+        raise PcgError(st, pcg_last_error())
+    return out
+
+
 def pcg_solve_snapshots(ctx: Context, b, x, snap_iters, r_snaps, x_snaps, rtol=1e-12, maxit=10000) -> dict:
     its = (ctypes.c_int * len(snap_iters))(*[int(v) for v in snap_iters])
     _need(b, ctx.n, "b", ctx.dtype)
@@ -487,6 +527,16 @@ def pcg_batch_create(dims, cfgs=None, cache_path=None, tune_iters=20, stream=Non
 
 def pcg_batch_destroy(batch: Batch):
     batch.close()
+
+
+def pcg_batch_set_restarts(batch: Batch, max_restarts: int):
+    """FP64-residual restarts per problem (0 = never, -1 = default 3)."""
+    _check(lib.pcg_batch_set_restarts(batch.handle, int(max_restarts)))
+
+
+def pcg_batch_set_barrier(batch: Batch, form: int):
+    """0: XCD-local group barriers where possible (default); 1: agent-scope fences always."""
+    _check(lib.pcg_batch_set_barrier(batch.handle, int(form)))
 
 
 def pcg_batch_solve(batch: Batch, b, x, rtol=1e-6, maxit=500, use_graph=True, raise_on_error=True) -> dict:

@@ -14,7 +14,8 @@
 //              partials, finished by a one-work-group kernel);
 //   M:         the network's correction (cnn_forward, scaled by rms(r)
 //              from the state) or nothing when Jacobi is selected;
-//   select:    z = D^-1 r, plus the correction while the network is in use,
+//   select:    z = D^-1 r, plus the correction while the network is in use
+//              (z as the multigrid V-cycle left it, for that preconditioner),
 //              then z.q and z.r ->
 //              beta, or a switch to Jacobi when z.r <= 0 or a value is not
 //              finite (the second, "redo" launch then recomputes z with
@@ -203,6 +204,7 @@ __global__ void __launch_bounds__(NT) k_flex_select(int64_t n, T* __restrict__ z
     __shared__ double scratch[32];
     using C = typename Traits<T>::C;
     const bool jac = (st->flags & FLEX_JACOBI) != 0;
+    const bool given = (st->flags & FLEX_MG) != 0;  // z is the V-cycle's output
     const C dc = (C)st->dinv;
     const int64_t stride = (int64_t)gridDim.x * NT;
     C zq = C(0), zr = C(0);
@@ -210,9 +212,9 @@ __global__ void __launch_bounds__(NT) k_flex_select(int64_t n, T* __restrict__ z
         const C rv = to_c(r[i]);
         C zv;
         const C jv = (dinv ? to_c(dinv[i]) : dc) * rv;
-        // Jacobi, or Jacobi plus the network's correction held in z
-        zv = stored<T>(jac ? jv : jv + to_c(z[i]));
-        z[i] = from_c<T>(zv);
+        // Jacobi, the V-cycle's z, or Jacobi plus the network's correction held in z
+        zv = stored<T>(jac ? jv : given ? to_c(z[i]) : jv + to_c(z[i]));
+        if (jac || !given) z[i] = from_c<T>(zv);  // the V-cycle's z is already stored
         zq += zv * to_c(q[i]);
         zr += zv * rv;
     }

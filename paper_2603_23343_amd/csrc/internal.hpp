@@ -148,6 +148,33 @@ hipError_t launch_flex_update(int64_t n, const float* p, const float* q, float* 
                               double* hist, Red red, hipStream_t s);
 hipError_t launch_flex_select(int64_t n, float* z, const float* r, const float* q, const float* dinv, SolveState* st,
                               bool redo_pass, Red red, hipStream_t s);
+// geometric multigrid V-cycle (FP32): levels finest first; level l solves the
+// unscaled seven-point system A[k_l] u = g_l, and g_(l+1) = P^T r_l / 2.
+constexpr int MG_MAX_LEVELS = 16;
+struct MgLevel {
+    int nx, ny, nz;
+    int64_t n;
+    Plan plan;
+    Geometry geo;
+    const float* k;     // cell coefficients (null: constant coefficients)
+    const float* dinv;  // 1 / diag(A[k]) (null: the constant 1/6)
+    float* g;           // right-hand side (levels >= 1; level 0 gets the caller's)
+    float* u[2];        // iterates (sweeps ping-pong)
+    float* r;           // residual (all levels but the coarsest)
+    float* out;         // result of the level's V-cycle (levels >= 1)
+};
+struct MgHierarchy {
+    int nlev = 0;
+    int nu = 1;              // damped-Jacobi sweeps before and after the correction
+    float omega = 6.f / 7.f;
+    MgLevel lv[MG_MAX_LEVELS] = {};
+    float* ainv = nullptr;   // inverse of the coarsest operator (m x m, symmetric)
+};
+// out = V-cycle(g) on level 0 (out must not alias g or the level's buffers);
+// every kernel returns at once while *done != 0.
+hipError_t launch_mg_vcycle(const MgHierarchy& H, const float* g, float* out, const int* done, hipStream_t s);
+// kc = mean of the 2 x 2 x 2 children of kf (nx, ny, nz even).
+hipError_t launch_mg_coarsen_k(const float* kf, int nx, int ny, int nz, float* kc, hipStream_t s);
 // training pairs from solver snapshots
 hipError_t launch_make_pair(int64_t n, const double* r, const double* x, const double* xs, const double* rr,
                             void* out, hipStream_t s);

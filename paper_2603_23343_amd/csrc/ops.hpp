@@ -31,7 +31,8 @@ struct SolveState {
     int fallback_at;  // iteration of the switch to Jacobi (-1: none)
     double zr;        // z.r of the last preconditioned residual
 };
-constexpr int FLEX_JACOBI = 1, FLEX_RESTART = 2, FLEX_REDO = 4;
+// FLEX_MG: the preconditioned residual z is the multigrid V-cycle's, taken as it is.
+constexpr int FLEX_JACOBI = 1, FLEX_RESTART = 2, FLEX_REDO = 4, FLEX_MG = 8;
 
 // ---------------------------------------------------------------- loaders
 // A loader provides Raw<N> (registers of one fetch of N consecutive points),

@@ -126,9 +126,9 @@ struct pcg_ctx_s {
     // flexible CG
     void* q = nullptr;  // A p (storage type)
     void* z = nullptr;  // preconditioned residual (storage type)
-    // captured flexible iterations: [0] Jacobi, [1] with the network, and
-    // what they were recorded with
-    hipGraphExec_t flex_exec[2] = {nullptr, nullptr};
+    // captured flexible iterations: [0] Jacobi, [1] with the network, [2]
+    // with the multigrid V-cycle, and what they were recorded with
+    hipGraphExec_t flex_exec[3] = {nullptr, nullptr, nullptr};
     struct FlexKey {
         cnn_net net = nullptr;
         const float* g = nullptr;
@@ -136,7 +136,15 @@ struct pcg_ctx_s {
         const void* hist = nullptr;
         const float* kc = nullptr;
         int chunk = 0;
-    } flex_key[2];
+        uint64_t mg_epoch = 0;
+    } flex_key[3];
+    // multigrid hierarchy (pcg_set_multigrid) and the memory it owns
+    MgHierarchy* mg = nullptr;
+    std::vector<void*> mg_mem;
+    int mg_nu = 1, mg_coarse_max = 512;
+    double mg_omega = 6.0 / 7.0;
+    uint64_t mg_epoch = 0;   // bumped on every rebuild (captured graphs hold its pointers)
+    int* zero_flag = nullptr;  // a device int kept at 0 (the V-cycle's "done" outside a solve)
     // iterative refinement
     void* rhat = nullptr;  // scaled residual in the storage type
     std::vector<double> ref_relres;
@@ -179,6 +187,10 @@ void free_ctx(pcg_ctx c) {
     if (c->hst) (void)hipHostFree(c->hst);
     if (c->hres) (void)hipHostFree(c->hres);
     if (c->capture) (void)hipStreamDestroy(c->capture);
+    for (void* d : c->mg_mem)
+        if (d) (void)hipFree(d);
+    if (c->zero_flag) (void)hipFree(c->zero_flag);
+    delete c->mg;
     delete c;
 }
 
@@ -475,6 +487,194 @@ pcg_status run_iterations(pcg_ctx c, const void* b, const void* x0, int x0_dt, d
 
 }  // namespace
 
+namespace {
+
+// Dense seven-point operator of an nx x ny x nz grid in FP64 (row-major):
+// face coefficients 1 (kcell empty) or the harmonic mean of the two cells'
+// k, a boundary face taking its cell's k (the operator the z-march kernels
+// apply with StencilConst / StencilVar).
+std::vector<double> dense_operator(int nx, int ny, int nz, const std::vector<float>& kcell) {
+    const int m = nx * ny * nz;
+    std::vector<double> A((size_t)m * m, 0.0);
+    auto idx = [&](int i, int j, int k) { return (k * ny + j) * nx + i; };
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int p = idx(i, j, k);
+                const double kp = kcell.empty() ? 1.0 : (double)kcell[p];
+                double diag = 0.0;
+                const int nb[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k}, {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+                for (const auto& q : nb) {
+                    const bool in = q[0] >= 0 && q[0] < nx && q[1] >= 0 && q[1] < ny && q[2] >= 0 && q[2] < nz;
+                    double kf = kp;
+                    if (in && !kcell.empty()) {
+                        const double kq = (double)kcell[idx(q[0], q[1], q[2])];
+                        kf = 2.0 * kp * kq / (kp + kq);
+                    }
+                    diag += kf;
+                    if (in) A[(size_t)p * m + idx(q[0], q[1], q[2])] -= kf;
+                }
+                A[(size_t)p * m + p] = diag;
+            }
+    return A;
+}
+
+// Inverse of a symmetric positive definite matrix (row-major, m x m) through
+// its Cholesky factor A = L L^T: columns of A^-1 from L y = e_j, L^T x = y.
+// False if a pivot is not positive.
+bool spd_inverse(const std::vector<double>& A, int m, std::vector<double>& inv) {
+    std::vector<double> L((size_t)m * m, 0.0);
+    for (int j = 0; j < m; ++j) {
+        double d = A[(size_t)j * m + j];
+        for (int k = 0; k < j; ++k) d -= L[(size_t)j * m + k] * L[(size_t)j * m + k];
+        if (!(d > 0.0)) return false;
+        const double ljj = std::sqrt(d);
+        L[(size_t)j * m + j] = ljj;
+        for (int i = j + 1; i < m; ++i) {
+            double t = A[(size_t)i * m + j];
+            const double* li = &L[(size_t)i * m];
+            const double* lj = &L[(size_t)j * m];
+            for (int k = 0; k < j; ++k) t -= li[k] * lj[k];
+            L[(size_t)i * m + j] = t / ljj;
+        }
+    }
+    inv.assign((size_t)m * m, 0.0);
+    std::vector<double> y(m);
+    for (int c = 0; c < m; ++c) {
+        for (int i = 0; i < m; ++i) {
+            double t = i == c ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) t -= L[(size_t)i * m + k] * y[k];
+            y[i] = i < c ? 0.0 : t / L[(size_t)i * m + i];
+        }
+        for (int i = m - 1; i >= 0; --i) {
+            double t = y[i];
+            for (int k = i + 1; k < m; ++k) t -= L[(size_t)k * m + i] * inv[(size_t)k * m + c];
+            inv[(size_t)i * m + c] = t / L[(size_t)i * m + i];
+        }
+    }
+    return true;
+}
+
+constexpr int MG_COARSEST_MAX = 1024;  // points of the coarsest grid (dense inverse)
+
+void free_mg(pcg_ctx c) {
+    for (void* d : c->mg_mem)
+        if (d) (void)hipFree(d);
+    c->mg_mem.clear();
+    delete c->mg;
+    c->mg = nullptr;
+    if (c->flex_exec[2]) {
+        (void)hipGraphExecDestroy(c->flex_exec[2]);
+        c->flex_exec[2] = nullptr;
+    }
+}
+
+// Builds the hierarchy for the context's current operator.
+pcg_status build_mg(pcg_ctx c) {
+    hipStream_t st = c->stream;
+    HIPCHK(hipStreamSynchronize(st));
+    free_mg(c);
+    auto alloc = [&](size_t bytes, void** out) -> hipError_t {
+        hipError_t e = hipMalloc(out, bytes);
+        if (e == hipSuccess) c->mg_mem.push_back(*out);
+        return e;
+    };
+    if (!c->zero_flag) {
+        HIPCHK(hipMalloc(&c->zero_flag, sizeof(int)));
+        HIPCHK(hipMemsetAsync(c->zero_flag, 0, sizeof(int), st));
+    }
+    MgHierarchy* H = new (std::nothrow) MgHierarchy();
+    if (!H) return fail(PCG_E_NOMEM, "pcg_set_multigrid: out of host memory");
+    c->mg = H;
+    H->nu = c->mg_nu;
+    H->omega = (float)c->mg_omega;
+    pcg_options dflt;
+    pcg_options_default(&dflt);
+    int nx = c->nx, ny = c->ny, nz = c->nz;
+    for (int l = 0; l < MG_MAX_LEVELS; ++l) {
+        MgLevel& L = H->lv[l];
+        L.nx = nx;
+        L.ny = ny;
+        L.nz = nz;
+        L.n = (int64_t)nx * ny * nz;
+        L.plan = default_plan(nx, ny, nz, DT_F32, l == 0 ? c->opt : dflt);
+        L.geo = make_geometry(nx, ny, nz, L.plan, DT_F32);
+        H->nlev = l + 1;
+        if (L.n <= c->mg_coarse_max || nx % 2 || ny % 2 || nz % 2 || l + 1 == MG_MAX_LEVELS) break;
+        nx /= 2;
+        ny /= 2;
+        nz /= 2;
+    }
+    const int last = H->nlev - 1;
+    if (H->lv[last].n > MG_COARSEST_MAX) {
+        free_mg(c);
+        return fail(PCG_E_UNSUPPORTED,
+                    "pcg_set_multigrid: the coarsest grid (%dx%dx%d) has more than %d points; every dimension must "
+                    "halve evenly down to at most that many",
+                    H->lv[last].nx, H->lv[last].ny, H->lv[last].nz, MG_COARSEST_MAX);
+    }
+    const bool var = c->kc != nullptr;
+    for (int l = 0; l <= last; ++l) {
+        MgLevel& L = H->lv[l];
+        const size_t b = sizeof(float) * (size_t)L.n;
+        void* t = nullptr;
+        if (l > 0) {
+            HIPCHK(alloc(b, &t));
+            L.g = static_cast<float*>(t);
+            HIPCHK(alloc(b, &t));
+            L.out = static_cast<float*>(t);
+        }
+        if (l < last) {
+            HIPCHK(alloc(b, &t));
+            L.u[0] = static_cast<float*>(t);
+            if (H->nu >= 2) {
+                HIPCHK(alloc(b, &t));
+                L.u[1] = static_cast<float*>(t);
+            }
+            HIPCHK(alloc(b, &t));
+            L.r = static_cast<float*>(t);
+        }
+        if (var) {
+            if (l == 0) {
+                L.k = c->kc;
+                L.dinv = static_cast<const float*>(c->dinv);
+            } else {
+                const MgLevel& F = H->lv[l - 1];
+                HIPCHK(alloc(b, &t));
+                HIPCHK(launch_mg_coarsen_k(F.k, F.nx, F.ny, F.nz, static_cast<float*>(t), st));
+                L.k = static_cast<float*>(t);
+                HIPCHK(alloc(b, &t));
+                HIPCHK(launch_var_dinv(DT_F32, L.plan, L.geo, L.k, t, st));
+                L.dinv = static_cast<float*>(t);
+            }
+        }
+    }
+    // coarsest operator, inverted on the host in FP64
+    const MgLevel& C = H->lv[last];
+    const int m = (int)C.n;
+    std::vector<float> kh;
+    if (var) {
+        kh.resize(m);
+        HIPCHK(hipMemcpyAsync(kh.data(), C.k, sizeof(float) * m, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    std::vector<double> inv;
+    if (!spd_inverse(dense_operator(C.nx, C.ny, C.nz, kh), m, inv)) {
+        free_mg(c);
+        return fail(PCG_E_ARG, "pcg_set_multigrid: the coarsest operator is not positive definite (k <= 0?)");
+    }
+    std::vector<float> inv32(inv.begin(), inv.end());
+    void* t = nullptr;
+    HIPCHK(alloc(sizeof(float) * inv32.size(), &t));
+    H->ainv = static_cast<float*>(t);
+    HIPCHK(hipMemcpyAsync(H->ainv, inv32.data(), sizeof(float) * inv32.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ++c->mg_epoch;
+    return PCG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* pcg_last_error(void) { return g_err.c_str(); }
@@ -722,6 +922,8 @@ pcg_status pcg_solve_refined(pcg_ctx c, const double* b64, double* x64, double r
     HIPCHK(launch_zero(DT_F64, c->n, x64, st));
     double nb = 0.0, t1e6 = -1.0, t1e10 = -1.0;
     int outer = 0, inner_total = 0;
+    double k1_ms = 0.0, k2_ms = 0.0;  // kernel_timing: event-timed inner iteration kernels
+    int nk = 0;
     pcg_status ret = PCG_E_NOCONV;
     for (;;) {
         HIPCHK(launch_residual64(DT_F64, DT_F64, c->plan_res, c->geo_res, op_of(c), b64, x64, c->res2, red_of(c),
@@ -752,6 +954,9 @@ pcg_status pcg_solve_refined(pcg_ctx c, const double* b64, double* x64, double r
         if (s != PCG_OK) return s;
         c->ref_inner.push_back(res.fin.iters);
         inner_total += res.fin.iters;
+        k1_ms += res.k1_ms;
+        k2_ms += res.k2_ms;
+        nk += res.nk;
         HIPCHK(launch_correct(xacc_dt, c->n, c->xacc, scale, x64, st));
         ++outer;
     }
@@ -765,6 +970,10 @@ pcg_status pcg_solve_refined(pcg_ctx c, const double* b64, double* x64, double r
         info->rel_res_recursive = info->rel_res_true_fp64;
         info->t_1e6 = t1e6;
         info->t_1e10 = t1e10;
+        info->k1_ms = k1_ms;
+        info->k2_ms = k2_ms;
+        info->k1_launches = nk;
+        info->k2_launches = nk;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     if (ret == PCG_E_NOCONV) fail(ret, "pcg_solve_refined: not converged after %d refinement steps", outer);
@@ -783,19 +992,21 @@ pcg_status pcg_refine_history(pcg_ctx c, double* relres, int* inner_iters, int n
     return PCG_OK;
 }
 
-pcg_status pcg_solve_flexible(pcg_ctx c, cnn_net net, const float* g, const void* b, void* x, double rtol,
-                              int maxit, pcg_info* info) {
+// Flexible CG with the network's preconditioner (net), the multigrid
+// V-cycle (mg) or Jacobi (neither); `name` prefixes error messages.
+static pcg_status flex_solve(pcg_ctx c, cnn_net net, bool mg, const float* g, const void* b, void* x, double rtol,
+                             int maxit, pcg_info* info, const char* name) {
     auto t0 = std::chrono::steady_clock::now();
-    if (!c) return fail(PCG_E_ARG, "pcg_solve_flexible: null context");
-    if (!b || !x) return fail(PCG_E_ARG, "pcg_solve_flexible: null pointer");
-    if (!aligned16(b) || !aligned16(x)) return fail(PCG_E_ARG, "pcg_solve_flexible: pointers must be 16-byte aligned");
-    if (!(rtol >= 0.0) || maxit < 0) return fail(PCG_E_ARG, "pcg_solve_flexible: rtol must be >= 0 and maxit >= 0");
+    if (!c) return fail(PCG_E_ARG, "%s: null context", name);
+    if (!b || !x) return fail(PCG_E_ARG, "%s: null pointer", name);
+    if (!aligned16(b) || !aligned16(x)) return fail(PCG_E_ARG, "%s: pointers must be 16-byte aligned", name);
+    if (!(rtol >= 0.0) || maxit < 0) return fail(PCG_E_ARG, "%s: rtol must be >= 0 and maxit >= 0", name);
     if (c->dt != DT_F32 || c->opt.x_accum != DT_F64)
-        return fail(PCG_E_UNSUPPORTED, "pcg_solve_flexible: needs F32 storage with an FP64 x accumulator");
+        return fail(PCG_E_UNSUPPORTED, "%s: needs F32 storage with an FP64 x accumulator", name);
     if (net && cnn_stream_of(net) != c->stream)
-        return fail(PCG_E_ARG, "pcg_solve_flexible: the network and the context must use the same stream");
+        return fail(PCG_E_ARG, "%s: the network and the context must use the same stream", name);
     const size_t xbytes = (size_t)c->n * dt_size(c->opt.x_dtype);
-    if (overlap2(b, (size_t)c->n * 4, x, xbytes)) return fail(PCG_E_ARG, "pcg_solve_flexible: b and x overlap");
+    if (overlap2(b, (size_t)c->n * 4, x, xbytes)) return fail(PCG_E_ARG, "%s: b and x overlap", name);
     pcg_status s = ensure_hist(c, maxit);
     if (s != PCG_OK) return s;
     hipStream_t st = c->stream;
@@ -808,34 +1019,49 @@ pcg_status pcg_solve_flexible(pcg_ctx c, cnn_net net, const float* g, const void
     float* z = static_cast<float*>(c->z);
     double* xacc = static_cast<double*>(c->xacc);
 
-    SolveState init{};
-    init.tol2 = rtol * rtol;
-    init.dinv = 1.0 / 6.0;
-    init.maxit = maxit;
-    init.stag = 20;
-    init.flags = FLEX_RESTART | (net ? 0 : FLEX_JACOBI);
-    init.fallback_at = -1;
-    c->hst[0] = init;
-    HIPCHK(hipMemcpyAsync(c->st, &c->hst[0], sizeof(SolveState), hipMemcpyHostToDevice, st));
-    HIPCHK(launch_pcg_start_zero(DT_F32, c->n, b, r, xacc, DT_F64, c->p[0], od.dinv, c->st, c->hist, red_of(c), st));
-    HIPCHK(launch_zero(DT_F32, c->n, q, st));
     auto precond = [&](bool use_net) -> pcg_status {
         if (use_net) {
             pcg_status ps = cnn_forward(net, c->nx, c->ny, c->nz, PCG_F32, r, g, &c->st->rr, z);
             if (ps != PCG_OK) return ps;
         }
+        if (mg) HIPCHK(launch_mg_vcycle(*c->mg, r, z, &c->st->done, st));
         HIPCHK(launch_flex_select(c->n, z, r, q, dinv, c->st, false, red_of(c), st));
         HIPCHK(launch_flex_select(c->n, z, r, q, dinv, c->st, true, red_of(c), st));
         return PCG_OK;
     };
     bool net_on = net != nullptr;
-    s = precond(net_on);
+    bool mg_on = mg;
+    // Start of a run of iterations: from x = 0, or (a restart) from the
+    // accumulator with r = fl32(b - A x) computed in FP64.
+    auto start_segment = [&](bool from_x, int seg_maxit) -> pcg_status {
+        SolveState init{};
+        init.tol2 = rtol * rtol;
+        init.dinv = 1.0 / 6.0;
+        init.maxit = seg_maxit;
+        init.stag = 20;
+        init.flags = FLEX_RESTART | (net || mg ? 0 : FLEX_JACOBI) | (mg ? FLEX_MG : 0);
+        init.fallback_at = -1;
+        c->hst[0] = init;
+        HIPCHK(hipMemcpyAsync(c->st, &c->hst[0], sizeof(SolveState), hipMemcpyHostToDevice, st));
+        if (from_x)
+            HIPCHK(launch_pcg_start_x0(DT_F32, DT_F64, c->plan_res, c->geo_res, od, b, xacc, r, c->st, c->hist,
+                                       red_of(c), st));
+        else
+            HIPCHK(launch_pcg_start_zero(DT_F32, c->n, b, r, xacc, DT_F64, c->p[0], od.dinv, c->st, c->hist,
+                                         red_of(c), st));
+        HIPCHK(launch_zero(DT_F32, c->n, q, st));
+        return precond(net_on);
+    };
+    s = start_segment(false, maxit);
     if (s != PCG_OK) return s;
 
     // Iterations k = 1..C of a chunk (C even, so iteration parity repeats) on
-    // stream s; the network launches on its own stream, swapped to s.
-    const int C = c->chunk_iters;
-    auto enqueue_chunk = [&](bool use_net, hipStream_t sq) -> pcg_status {
+    // stream s; the network launches on its own stream, swapped to s. The
+    // multigrid iteration converges in ~10-15 iterations and launches ~30
+    // kernels per iteration: chunks of 4 keep the launches past convergence
+    // (each returns at once but costs its launch) few.
+    const int C = mg ? std::min(c->chunk_iters, 4) : c->chunk_iters;
+    auto enqueue_chunk = [&](bool use_net, bool use_mg, hipStream_t sq) -> pcg_status {
         for (int k = 1; k <= C; ++k) {
             void* pold = c->p[(k - 1) & 1];
             void* pnew = c->p[k & 1];
@@ -847,6 +1073,7 @@ pcg_status pcg_solve_flexible(pcg_ctx c, cnn_net net, const float* g, const void
                 pcg_status ps = cnn_forward(net, c->nx, c->ny, c->nz, PCG_F32, r, g, &c->st->rr, z);
                 if (ps != PCG_OK) return ps;
             }
+            if (use_mg) HIPCHK(launch_mg_vcycle(*c->mg, r, z, &c->st->done, sq));
             HIPCHK(launch_flex_select(c->n, z, r, q, dinv, c->st, false, red_of(c), sq));
             HIPCHK(launch_flex_select(c->n, z, r, q, dinv, c->st, true, red_of(c), sq));
         }
@@ -861,13 +1088,13 @@ pcg_status pcg_solve_flexible(pcg_ctx c, cnn_net net, const float* g, const void
         s = cnn_prepare(net, c->nx, c->ny, c->nz, &epoch);
         if (s != PCG_OK) return s;
     }
-    auto chunk_graph = [&](bool use_net, hipGraphExec_t* out) -> pcg_status {
-        const int slot = use_net ? 1 : 0;
+    auto chunk_graph = [&](bool use_net, bool use_mg, hipGraphExec_t* out) -> pcg_status {
+        const int slot = use_mg ? 2 : use_net ? 1 : 0;
         const pcg_ctx_s::FlexKey key{use_net ? net : nullptr, use_net ? g : nullptr, use_net ? epoch : 0, c->hist,
-                                     c->kc, C};
+                                     c->kc, C, use_mg ? c->mg_epoch : 0};
         auto& have = c->flex_key[slot];
         if (c->flex_exec[slot] && have.net == key.net && have.g == key.g && have.epoch == key.epoch &&
-            have.hist == key.hist && have.kc == key.kc && have.chunk == key.chunk) {
+            have.hist == key.hist && have.kc == key.kc && have.chunk == key.chunk && have.mg_epoch == key.mg_epoch) {
             *out = c->flex_exec[slot];
             return PCG_OK;
         }
@@ -878,7 +1105,7 @@ pcg_status pcg_solve_flexible(pcg_ctx c, cnn_net net, const float* g, const void
         if (!c->capture) HIPCHK(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
         hipStream_t old = use_net ? cnn_swap_stream(net, c->capture) : nullptr;
         hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
-        pcg_status ps = e == hipSuccess ? enqueue_chunk(use_net, c->capture) : PCG_E_HIP;
+        pcg_status ps = e == hipSuccess ? enqueue_chunk(use_net, use_mg, c->capture) : PCG_E_HIP;
         hipGraph_t gr = nullptr;
         hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(c->capture, &gr) : e;
         if (use_net) (void)cnn_swap_stream(net, old);
@@ -898,38 +1125,65 @@ pcg_status pcg_solve_flexible(pcg_ctx c, cnn_net net, const float* g, const void
     };
 
     SolveState fin{};
-    int it = 0;
     const bool graph = c->opt.use_graph && !c->opt.kernel_timing;
-    for (;;) {
-        HIPCHK(hipMemcpyAsync(&c->hst[1], c->st, sizeof(SolveState), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        fin = c->hst[1];
-        if (fin.done != 0 || it >= maxit) break;
-        if (fin.flags & FLEX_JACOBI) net_on = false;
-        if (graph) {
-            hipGraphExec_t ge = nullptr;
-            s = chunk_graph(net_on, &ge);
-            if (s != PCG_OK) return s;
-            HIPCHK(hipGraphLaunch(ge, st));
-        } else {
-            s = enqueue_chunk(net_on, st);
-            if (s != PCG_OK) return s;
+    auto iterate = [&](int seg_maxit) -> pcg_status {
+        int it = 0;
+        for (;;) {
+            HIPCHK(hipMemcpyAsync(&c->hst[1], c->st, sizeof(SolveState), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            fin = c->hst[1];
+            if (fin.done != 0 || it >= seg_maxit) break;
+            if (fin.flags & FLEX_JACOBI) net_on = mg_on = false;
+            if (graph) {
+                hipGraphExec_t ge = nullptr;
+                pcg_status ps = chunk_graph(net_on, mg_on, &ge);
+                if (ps != PCG_OK) return ps;
+                HIPCHK(hipGraphLaunch(ge, st));
+            } else {
+                pcg_status ps = enqueue_chunk(net_on, mg_on, st);
+                if (ps != PCG_OK) return ps;
+            }
+            it += C;
         }
-        it += C;
-    }
-    HIPCHK(hipStreamSynchronize(st));
-    HIPCHK(hipMemcpy(&fin, c->st, sizeof(SolveState), hipMemcpyDeviceToHost));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(&fin, c->st, sizeof(SolveState), hipMemcpyDeviceToHost));
+        return PCG_OK;
+    };
+    auto true_residual = [&](double* rel) -> pcg_status {
+        HIPCHK(launch_residual64(DT_F32, DT_F64, c->plan_res, c->geo_res, od, b, xacc, c->res2, red_of(c), st));
+        HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        *rel = fin.rr0 > 0 ? std::sqrt(c->hres[0] / fin.rr0) : 0.0;
+        return PCG_OK;
+    };
+    s = iterate(maxit);
+    if (s != PCG_OK) return s;
     int iters = fin.iters;
     int fallback = fin.fallback_at >= 0 ? 1 : 0;
     int status = fin.done;
 
-    // The FP64 true residual judges the result; if the recursion converged
-    // but the true residual did not, continue with Jacobi-PCG from this x.
-    HIPCHK(launch_residual64(DT_F32, DT_F64, c->plan_res, c->geo_res, od, b, xacc, c->res2, red_of(c), st));
-    HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    double true_rel = fin.rr0 > 0 ? std::sqrt(c->hres[0] / fin.rr0) : 0.0;
-    if (status == 1 && true_rel > rtol && iters < maxit) {
+    // The FP64 true residual judges the result. With the V-cycle, a converged
+    // recursion whose true residual is above rtol restarts the same method
+    // from x with r = fl32(b - A x) (at most max_restarts times); otherwise
+    // Jacobi-PCG continues from this x.
+    double true_rel = 0.0;
+    s = true_residual(&true_rel);
+    if (s != PCG_OK) return s;
+    int restarts = 0;
+    while (mg && status == 1 && true_rel > rtol && iters < maxit && restarts < c->opt.max_restarts) {
+        ++restarts;
+        mg_on = true;
+        s = start_segment(true, maxit - iters);
+        if (s != PCG_OK) return s;
+        s = iterate(maxit - iters);
+        if (s != PCG_OK) return s;
+        iters += fin.iters;
+        status = fin.done;
+        if (fin.fallback_at >= 0) fallback = 1;
+        s = true_residual(&true_rel);
+        if (s != PCG_OK) return s;
+    }
+    if (!mg && status == 1 && true_rel > rtol && iters < maxit) {
         IterResult res;
         s = run_iterations(c, b, xacc, DT_F64, rtol, maxit - iters, 0, &res);
         if (s != PCG_OK) return s;
@@ -956,13 +1210,25 @@ pcg_status pcg_solve_flexible(pcg_ctx c, cnn_net net, const float* g, const void
         info->outer_iters = fin.fallback_at;
         info->rel_res_recursive = fin.rr0 > 0 ? std::sqrt(fin.rr / fin.rr0) : 0.0;
         info->rel_res_true_fp64 = true_rel;
+        info->restarts = restarts;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
-    if (ret == PCG_E_BREAKDOWN) fail(ret, "pcg_solve_flexible: breakdown");
-    else if (ret == PCG_E_NOCONV) fail(ret, "pcg_solve_flexible: no convergence in %d iterations", maxit);
+    if (ret == PCG_E_BREAKDOWN) fail(ret, "%s: breakdown", name);
+    else if (ret == PCG_E_NOCONV) fail(ret, "%s: no convergence in %d iterations", name, maxit);
     else if (ret == PCG_E_TRUE_RESIDUAL)
-        fail(ret, "pcg_solve_flexible: the FP64 true residual %.3e is above rtol %.3e", true_rel, rtol);
+        fail(ret, "%s: the FP64 true residual %.3e is above rtol %.3e", name, true_rel, rtol);
     return ret;
+}
+
+pcg_status pcg_solve_flexible(pcg_ctx c, cnn_net net, const float* g, const void* b, void* x, double rtol,
+                              int maxit, pcg_info* info) {
+    return flex_solve(c, net, false, g, b, x, rtol, maxit, info, "pcg_solve_flexible");
+}
+
+pcg_status pcg_solve_mg(pcg_ctx c, const void* b, void* x, double rtol, int maxit, pcg_info* info) {
+    if (!c) return fail(PCG_E_ARG, "pcg_solve_mg: null context");
+    if (!c->mg) return fail(PCG_E_ARG, "pcg_solve_mg: no multigrid hierarchy (call pcg_set_multigrid first)");
+    return flex_solve(c, nullptr, true, nullptr, b, x, rtol, maxit, info, "pcg_solve_mg");
 }
 
 pcg_status pcg_solve_snapshots(pcg_ctx c, const void* b, void* x, double rtol, int maxit, const int* snap_iters,
@@ -1040,6 +1306,11 @@ pcg_status pcg_set_coefficients(pcg_ctx c, const float* k_cell) {
     if (!c) return fail(PCG_E_ARG, "pcg_set_coefficients: null context");
     if (!k_cell) {
         c->kc = nullptr;
+        if (c->chunk) {
+            HIPCHK(hipGraphExecDestroy(c->chunk));
+            c->chunk = nullptr;
+        }
+        if (c->mg) return build_mg(c);
         return PCG_OK;
     }
     if (!aligned16(k_cell)) return fail(PCG_E_ARG, "pcg_set_coefficients: k must be 16-byte aligned");
@@ -1052,6 +1323,43 @@ pcg_status pcg_set_coefficients(pcg_ctx c, const float* k_cell) {
         HIPCHK(hipGraphExecDestroy(c->chunk));
         c->chunk = nullptr;
     }
+    if (c->mg) return build_mg(c);  // the hierarchy follows the operator
+    return PCG_OK;
+}
+
+pcg_status pcg_set_multigrid(pcg_ctx c, int nu, double omega, int coarse_max) {
+    if (!c) return fail(PCG_E_ARG, "pcg_set_multigrid: null context");
+    if (nu < 1 || nu > 8) return fail(PCG_E_ARG, "pcg_set_multigrid: nu must be in 1..8 (got %d)", nu);
+    if (omega == 0.0) omega = 6.0 / 7.0;
+    if (!(omega > 0.0 && omega <= 1.0)) return fail(PCG_E_ARG, "pcg_set_multigrid: omega must be in (0, 1]");
+    if (coarse_max < 0) return fail(PCG_E_ARG, "pcg_set_multigrid: coarse_max must be >= 0");
+    if (c->dt != DT_F32) return fail(PCG_E_UNSUPPORTED, "pcg_set_multigrid: needs F32 storage");
+    c->mg_nu = nu;
+    c->mg_omega = omega;
+    c->mg_coarse_max = coarse_max == 0 ? 512 : coarse_max;
+    return build_mg(c);
+}
+
+pcg_status pcg_mg_apply(pcg_ctx c, const float* g, float* u) {
+    if (!c) return fail(PCG_E_ARG, "pcg_mg_apply: null context");
+    if (!c->mg) return fail(PCG_E_ARG, "pcg_mg_apply: no multigrid hierarchy (call pcg_set_multigrid first)");
+    if (!g || !u) return fail(PCG_E_ARG, "pcg_mg_apply: null pointer");
+    if (!aligned16(g) || !aligned16(u)) return fail(PCG_E_ARG, "pcg_mg_apply: pointers must be 16-byte aligned");
+    if (overlap(g, u, sizeof(float) * (size_t)c->n)) return fail(PCG_E_ARG, "pcg_mg_apply: g and u overlap");
+    HIPCHK(launch_mg_vcycle(*c->mg, g, u, c->zero_flag, c->stream));
+    return PCG_OK;
+}
+
+pcg_status pcg_mg_levels(pcg_ctx c, int* nlev, int* dims) {
+    if (!c || !nlev) return fail(PCG_E_ARG, "pcg_mg_levels: null argument");
+    if (!c->mg) return fail(PCG_E_ARG, "pcg_mg_levels: no multigrid hierarchy (call pcg_set_multigrid first)");
+    *nlev = c->mg->nlev;
+    if (dims)
+        for (int l = 0; l < c->mg->nlev; ++l) {
+            dims[3 * l] = c->mg->lv[l].nx;
+            dims[3 * l + 1] = c->mg->lv[l].ny;
+            dims[3 * l + 2] = c->mg->lv[l].nz;
+        }
     return PCG_OK;
 }
 
