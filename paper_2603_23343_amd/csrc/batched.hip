@@ -60,7 +60,7 @@ struct BatchOut {
     unsigned long long t_begin, t_done;
 };
 
-// Restarts from the FP64 residual per problem at most.
+// Restarts from the FP64 residual per problem at most (default).
 constexpr int BATCH_MAX_RESTARTS = 3;
 
 namespace {
@@ -195,7 +195,8 @@ __global__ void __launch_bounds__(BT) k_batch_pcg(const BatchProb* __restrict__ 
                                                    const float* __restrict__ b, double* __restrict__ x, float* r,
                                                    float* p0, float* p1, double* xacc, double* partials, int maxg,
                                                    int part_stride, unsigned* bar,
-                                                   BatchOut* out, double rtol2, int maxit, int* err) {
+                                                   BatchOut* out, double rtol2, int maxit, int* err,
+                                                   int force_agent, int max_restarts) {
     __shared__ __attribute__((aligned(16))) float lds[3168];
     __shared__ double rs[32];
     const int2 m = wgmap[blockIdx.x];
@@ -239,7 +240,9 @@ __global__ void __launch_bounds__(BT) k_batch_pcg(const BatchProb* __restrict__ 
         bb = group_sum(partC, G, rs);
     }
     // every member reads the flag after the same barrier: one decision per group
-    const bool xl = __popc(__hip_atomic_load(xcd_mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 1;
+    // (force_agent keeps the general form even for a group on one XCD)
+    const bool xl = !force_agent &&
+                    __popc(__hip_atomic_load(xcd_mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 1;
     const double tol2 = rtol2 * bb;
     double rho = bb / 6.0, beta = 0.0, rr = bb, rrt = bb;
     int it = 0, restarts = 0, done = 0, io = 0;
@@ -310,7 +313,7 @@ __global__ void __launch_bounds__(BT) k_batch_pcg(const BatchProb* __restrict__ 
         if (!group_barrier(cnt, gen, G, my_gen, err, xl)) return;
         rrt = group_sum(partC, G, rs);
         const double rrs = group_sum(partC + maxg, G, rs);
-        if (rrt <= tol2 || rr > tol2 || restarts >= BATCH_MAX_RESTARTS || it >= maxit) {
+        if (rrt <= tol2 || rr > tol2 || restarts >= max_restarts || it >= maxit) {
             done = rr <= tol2 ? 1 : 3;
             break;
         }
@@ -380,6 +383,8 @@ struct BatchImpl {
     std::string device_tag;
     int tuned = 0;  // problems whose tile shape was measured (not cached/given)
     int xcd_local = 0;  // problems whose barriers ran XCD-local in the last solve
+    int force_agent = 0;  // 1: every group barrier takes the agent-scope fence form
+    int max_restarts = BATCH_MAX_RESTARTS;  // FP64-residual restarts per problem
 };
 
 namespace {
@@ -596,7 +601,8 @@ hipError_t enqueue_batch(BatchImpl& B, const float* b, double* x, double rtol2, 
     hipLaunchKernelGGL(k_fill_u32, dim3((nbar + 255) / 256), dim3(256), 0, s, B.bar, nbar, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned*>(B.err), 1, 0u);
     hipLaunchKernelGGL(k_batch_pcg, dim3(B.grid), dim3(BT), 0, s, B.d_probs, B.d_wgmap, b, x, B.r, B.p0, B.p1,
-                       B.xacc, B.partials, B.maxg, part_stride(B), B.bar, B.out, rtol2, maxit, B.err);
+                       B.xacc, B.partials, B.maxg, part_stride(B), B.bar, B.out, rtol2, maxit, B.err,
+                       B.force_agent, B.max_restarts);
     return hipGetLastError();
 }
 
@@ -869,6 +875,31 @@ pcg_status pcg_batch_layout(pcg_batch bt, int64_t* offsets, int64_t* total, int*
 
 static int status_rank(pcg_status s) {
     return s == PCG_E_BREAKDOWN ? 3 : s == PCG_E_NOCONV ? 2 : s == PCG_E_TRUE_RESIDUAL ? 1 : 0;
+}
+
+pcg_status pcg_batch_set_barrier(pcg_batch bt, int form) {
+    if (!bt) return berr(PCG_E_ARG, "pcg_batch_set_barrier: null batch");
+    if (form != 0 && form != 1) return berr(PCG_E_ARG, "pcg_batch_set_barrier: form must be 0 or 1 (got %d)", form);
+    BatchImpl& B = bt->impl;
+    if (B.force_agent != form && B.graph) {  // the captured launch holds the old form
+        BCHK(hipGraphExecDestroy(B.graph));
+        B.graph = nullptr;
+    }
+    B.force_agent = form;
+    return PCG_OK;
+}
+
+pcg_status pcg_batch_set_restarts(pcg_batch bt, int max_restarts) {
+    if (!bt) return berr(PCG_E_ARG, "pcg_batch_set_restarts: null batch");
+    if (max_restarts < -1) return berr(PCG_E_ARG, "pcg_batch_set_restarts: max_restarts must be >= -1");
+    BatchImpl& B = bt->impl;
+    const int v = max_restarts < 0 ? BATCH_MAX_RESTARTS : max_restarts;
+    if (B.max_restarts != v && B.graph) {
+        BCHK(hipGraphExecDestroy(B.graph));
+        B.graph = nullptr;
+    }
+    B.max_restarts = v;
+    return PCG_OK;
 }
 
 pcg_status pcg_batch_solve(pcg_batch bt, const float* b, double* x, double rtol, int maxit, int use_graph,
