@@ -36,12 +36,23 @@ template <> struct Traits<bf16> {
     static constexpr int W = 8;
 };
 
+// An FP32 value kept as FP32 for the conversion that follows: without the
+// (empty) barrier the compiler merges an FP64 -> FP32 narrowing in front of
+// a 16-bit conversion into a single FP64 -> 16-bit rounding, while the
+// library rounds twice (FP64 -> FP32 -> 16 bits), as the oracle does.
+__device__ __forceinline__ float keep_f32(float f) {
+    __asm__("" : "+v"(f));
+    return f;
+}
+
 // Round FP32 to BF16, nearest with ties to even; NaN stays a quiet NaN.
+// gfx950 converts in hardware (v_cvt_pk_bf16_f32, two values per
+// instruction; equal to the integer rounding on all 2^32 inputs); the integer
+// form it replaces took five operations and a NaN test per value, which
+// showed in the 16-bit direction kernel (the loader rounds p = D^-1 r +
+// beta p_old to BF16 for the tile and its halo).
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)keep_f32(f));
 }
 
 __device__ __forceinline__ float to_c(float v) { return v; }
@@ -52,7 +63,7 @@ __device__ __forceinline__ float to_c(bf16 v) { return __uint_as_float(((uint32_
 template <typename T> __device__ __forceinline__ T from_c(typename Traits<T>::C v);
 template <> __device__ __forceinline__ float from_c<float>(float v) { return v; }
 template <> __device__ __forceinline__ double from_c<double>(double v) { return v; }
-template <> __device__ __forceinline__ _Float16 from_c<_Float16>(float v) { return (_Float16)v; }
+template <> __device__ __forceinline__ _Float16 from_c<_Float16>(float v) { return (_Float16)keep_f32(v); }
 template <> __device__ __forceinline__ bf16 from_c<bf16>(float v) { return bf16{f32_to_bf16_bits(v)}; }
 
 // Value after a round trip through the storage type (what a later load sees).
