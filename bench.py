@@ -6,6 +6,8 @@ of the 256^3 seven-point Poisson system b = A x*, x* = lowest sine mode
 + 1e-3 U[-1,1] noise (seed 4). `value` = seconds per solve (lower is better).
 
 Also reported on the same JSON line:
+  multigrid     -- PCG with the geometric multigrid V-cycle preconditioner on
+                   the same system (constant coefficients), beside Jacobi-PCG;
   refined       -- FP64 iterative refinement around BF16 / FP16 Jacobi-PCG on
                    the same system: seconds to FP64 true residual 1e-6 and
                    1e-10 (the FP32 solve's own true residual is in config);
@@ -18,7 +20,8 @@ Also reported on the same JSON line:
                    TFLOP/s against the dense BF16 peak), and the whole
                    workflow (FP64 pair generation, on-policy rounds, A-norm
                    training, flexible CG on a held-out right-hand side)
-                   against Jacobi-PCG at each grid of --learned-n (64 and 128
+                   against Jacobi-PCG and multigrid-preconditioned PCG at
+                   each grid of --learned-n (64 and 128
                    by default);
   paper_grid    -- PCG time per iteration on the paper's 512 x 112 x 64
                    comparison grid (FP32 with two kernels or the
@@ -298,6 +301,53 @@ def bench_paper_grid(P, torch, steps):
     return out
 
 
+def bench_multigrid(P, torch, b, n, steps, jacobi_s, nu=1, oracle_budget_s=0.0):
+    """PCG with the geometric multigrid V-cycle preconditioner on the
+    benchmark's n^3 system (constant coefficients): time to the FP64 true
+    residual 1e-6 beside the Jacobi-PCG solve. Algorithmic bytes per
+    iteration (FP32 vectors, FP64 x): the flexible iteration's direction (z,
+    p_old, r read; p, q written: 20 B/pt), update (p, q, r, x read; r, x
+    written: 36 B/pt) and select (z, r, q: 12 B/pt), plus the V-cycle:
+    fine level 36 B/pt with one sweep per side (start sweep fused with the
+    residual: g read, u and r written; restriction reads r; prolongation reads
+    and writes u; the last sweep reads u and g and writes z), coarser levels
+    the same over 1/8 of the points each."""
+    N = n ** 3
+    ctx = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64)
+    t0 = time.perf_counter()
+    P.pcg_set_multigrid(ctx, nu=nu)
+    setup_s = time.perf_counter() - t0
+    levels = P.pcg_mg_levels(ctx)
+    x = torch.zeros(N, dtype=torch.float64, device="cuda")
+    P.pcg_solve_mg(ctx, b, x, 1e-6, 200, raise_on_error=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = P.pcg_solve_mg(ctx, b, x, 1e-6, 200, raise_on_error=False)
+    torch.cuda.synchronize()
+    s = (time.perf_counter() - t0) / steps
+    it = max(info["iters"], 1)
+    fine = 20 + 36 + 12 + (36 if nu == 1 else 56)
+    per_it = fine * N * (1 + 1 / 7)  # coarser levels add about 1/7 of the fine level's V-cycle bytes
+    out = {"grid": n, "nu": nu, "levels": [list(l) for l in levels], "setup_s": round(setup_s, 4),
+           "iters": info["iters"], "ms": round(s * 1e3, 3), "us_per_iteration": round(s * 1e6 / it, 1),
+           "true_relres": info["rel_res_true_fp64"], "status": P.STATUS_NAMES[info["status"]],
+           "jacobi_pcg_ms": round(jacobi_s * 1e3, 3), "speedup_vs_jacobi_pcg": round(jacobi_s / s, 2),
+           "iteration_GB/s_estimate": round(per_it / (s / it) / 1e9, 1)}
+    ctx.close()
+    if oracle_budget_s > 0:
+        import oracle
+
+        bh = b.double().cpu().numpy()
+        t0 = time.perf_counter()
+        ref = oracle.mg_pcg((n, n, n), bh, rtol=0.0, maxit=2)
+        t2 = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(t2 / 2 * info["iters"], 2), "unit": "s", "cores": oracle.threads(),
+                               "kind": "oracle", "sample": f"FP64 oracle MG-PCG on the same {n}^3 system: 2 "
+                               f"iterations timed (set-up included), scaled to the GPU's {info['iters']}"}
+    return out
+
+
 def bench_small_grid(P, torch, steps, n=32):
     """The small workload (n^3, b ~ U[-1, 1] seed 1, FP32 to 1e-6): solve time
     with two kernels per iteration and with the single-reduction form (the
@@ -324,12 +374,28 @@ def bench_small_grid(P, torch, steps, n=32):
     return out
 
 
-def cpu_baseline(b64_host, n, gpu_iters, budget_s=15.0):
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo) and its logical CPU count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{name} ({os.cpu_count()} logical CPUs visible)"
+
+
+def cpu_baseline(b64_host, n, gpu_iters, budget_s=15.0, single_budget_s=4.0):
     """The FP64 oracle's Jacobi-PCG on the same system: time a bounded number
-    of iterations and scale to the iteration count of the solve."""
+    of iterations with all of the oracle's threads and scale to the iteration
+    count of the solve; then the same at one thread on a shorter sample."""
     import oracle
 
     shape = (n, n, n)
+    cores = oracle.threads()
     t0 = time.perf_counter()
     oracle.pcg(shape, b64_host, rtol=0.0, maxit=2)
     t2 = time.perf_counter() - t0
@@ -342,7 +408,21 @@ def cpu_baseline(b64_host, n, gpu_iters, budget_s=15.0):
     full = out["status"] == oracle.OK
     per_iter = tm / max(its, 1)
     est = tm if full else per_iter * gpu_iters
-    return {"value": round(est, 3), "unit": "s", "cores": oracle.threads(), "kind": "oracle",
+    # one thread: a few iterations, scaled the same way
+    oracle.set_threads(1)
+    try:
+        m1 = int(max(2, min(gpu_iters, single_budget_s / max(per_iter * cores, 1e-9))))
+        t0 = time.perf_counter()
+        o1 = oracle.pcg(shape, b64_host, rtol=0.0, maxit=m1)
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    est1 = t1 / max(o1["iters"], 1) * gpu_iters
+    return {"value": round(est, 3), "unit": "s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": round(est1, 2), "unit": "s", "cores": 1,
+                              "sample": f"first {o1['iters']} iterations at one thread ({t1:.1f} s), scaled to "
+                                        f"the GPU's {gpu_iters} iterations"},
             "sample": (f"FP64 oracle Jacobi-PCG on the same {n}^3 system: "
                        + (f"full solve, {its} iterations" if full else
                           f"first {its} iterations timed ({tm:.1f} s), scaled to the GPU's {gpu_iters} iterations"))}
@@ -533,6 +613,10 @@ def learned_workflow(P, torch, n, rounds, oracle_cpu):
     jac = P.pcg_solve(ctx, b, x, 1e-6, 20000, raise_on_error=False)
     P.pcg_solve_flexible(ctx, net, gd, b, x, 1e-6, 20000, raise_on_error=False)
     fcg = P.pcg_solve_flexible(ctx, net, gd, b, x, 1e-6, 20000, raise_on_error=False)
+    # the non-learned baseline: PCG with the geometric multigrid V-cycle
+    P.pcg_set_multigrid(ctx)
+    P.pcg_solve_mg(ctx, b, x, 1e-6, 500, raise_on_error=False)
+    mgi = P.pcg_solve_mg(ctx, b, x, 1e-6, 500, raise_on_error=False)
     oracle_out = None
     if oracle_cpu:
         import oracle
@@ -551,6 +635,8 @@ def learned_workflow(P, torch, n, rounds, oracle_cpu):
            "flexible_cg_learned": {"iters": fcg["iters"], "ms": round(fcg["seconds"] * 1e3, 3),
                                    "fallback_used": fcg["fallback_used"],
                                    "true_relres": fcg["rel_res_true_fp64"]},
+           "multigrid_pcg": {"iters": mgi["iters"], "ms": round(mgi["seconds"] * 1e3, 3),
+                             "true_relres": mgi["rel_res_true_fp64"], "status": P.STATUS_NAMES[mgi["status"]]},
            "iteration_ratio": round(fcg["iters"] / max(jac["iters"], 1), 3)}
     net.close()
     ctx.close()
@@ -572,6 +658,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-paper-grid", action="store_true")
     ap.add_argument("--no-sell", action="store_true")
+    ap.add_argument("--no-multigrid", action="store_true")
     ap.add_argument("--learned-n", default="64,128",
                     help="comma-separated grid sizes of the learned-preconditioner workflow")
     ap.add_argument("--learned-rounds", type=int, default=12)
@@ -655,8 +742,30 @@ def main():
                              "final_true_relres": r["rel_res_true_fp64"],
                              "speedup_vs_fp32_pcg_to_1e-6_recursive": round(dt_solve / max(r["t_1e6"], 1e-9), 3)}
             P.pcg_destroy(rctx)
+            # per-kernel times of the inner iterations: the same refinement
+            # with HIP events around every inner iteration kernel. Algorithmic
+            # bytes per point with e-byte storage and the FP32 correction d:
+            # direction reads r, p_old and writes p (3e); update reads p, r,
+            # d and writes r, d (3e + 8).
+            tctx = P.pcg_create(n, n, n, rdt, x_accum=torch.float32, kernel_timing=1)
+            tr = P.pcg_solve_refined(tctx, b64, x64, rtol_outer=1e-10)
+            es = 2
+            k1 = tr["k1_ms"] * 1e3 / max(tr["k1_launches"], 1)
+            k2 = tr["k2_ms"] * 1e3 / max(tr["k2_launches"], 1)
+            refined[name]["inner_kernels"] = {
+                "direction_us": round(k1, 2), "direction_GB/s": round(3 * es * N / (k1 * 1e-6) / 1e9, 1),
+                "update_us": round(k2, 2), "update_GB/s": round((3 * es + 8) * N / (k2 * 1e-6) / 1e9, 1),
+                "iteration_GB/s": round((6 * es + 8) * N / ((k1 + k2) * 1e-6) / 1e9, 1),
+                "launches": tr["k1_launches"]}
+            P.pcg_destroy(tctx)
             del x64
         print(f"# refined: {refined}", file=sys.stderr, flush=True)
+
+    multigrid = None
+    if not args.no_multigrid:
+        multigrid = bench_multigrid(P, torch, b, n, max(args.steps, 3), dt_solve,
+                                    oracle_budget_s=0.0 if args.no_cpu_baseline else 1.0)
+        print(f"# multigrid: {multigrid}", file=sys.stderr, flush=True)
 
     batched = None
     if not args.no_batched:
@@ -707,6 +816,7 @@ def main():
                    "per_iteration_us": round(dt * 1e6 / max(iters, 1), 2)},
         "roofline": roofline,
         "refined": refined or None,
+        "multigrid": multigrid,
         "batched": batched,
         "paper_grid": paper_grid,
         "small_grid": small_grid,

@@ -83,6 +83,8 @@ def _load():
     lib.oracle_residual.argtypes = [i, i, i, _dp, _dp, _dp, _dp,
                                     ctypes.POINTER(d), ctypes.POINTER(d)]
     lib.oracle_threads.restype = i
+    lib.oracle_set_threads.argtypes = [i]
+    lib.oracle_set_threads.restype = None
     _lib = lib
     return lib
 
@@ -90,6 +92,12 @@ def _load():
 def threads() -> int:
     """OpenMP threads used by the C oracle's loops."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the C oracle's loops from now on (fixed-order reductions:
+    the results do not depend on it)."""
+    _load().oracle_set_threads(int(n))
 
 
 def _f64(a) -> np.ndarray:

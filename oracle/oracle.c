@@ -52,6 +52,17 @@ int oracle_threads(void)
 #endif
 }
 
+/* Use n threads in the parallel loops from now on (n >= 1); the reductions
+ * keep their fixed order, so results do not depend on it. */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 static inline double nb_val(const double *x, int nx, int ny, int nz, int i, int j, int k)
 {
     if (i < 0 || i >= nx || j < 0 || j >= ny || k < 0 || k >= nz)
