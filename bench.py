@@ -306,12 +306,12 @@ def bench_multigrid(P, torch, b, n, steps, jacobi_s, nu=1, oracle_budget_s=0.0):
     benchmark's n^3 system (constant coefficients): time to the FP64 true
     residual 1e-6 beside the Jacobi-PCG solve. Algorithmic bytes per
     iteration (FP32 vectors, FP64 x): the flexible iteration's direction (z,
-    p_old, r read; p, q written: 20 B/pt), update (p, q, r, x read; r, x
-    written: 36 B/pt) and select (z, r, q: 12 B/pt), plus the V-cycle:
-    fine level 36 B/pt with one sweep per side (start sweep fused with the
-    residual: g read, u and r written; restriction reads r; prolongation reads
-    and writes u; the last sweep reads u and g and writes z), coarser levels
-    the same over 1/8 of the points each."""
+    p_old, r read; p, q written: 20 B/pt) and update (p, q, r, x read; r, x
+    written: 36 B/pt), plus the V-cycle: fine level 40 B/pt with one sweep
+    per side (start sweep fused with the residual: g read, u and r written;
+    restriction reads r; prolongation reads and writes u; the last sweep,
+    which also does the flexible select step, reads u, g and q and writes z),
+    coarser levels the same over 1/8 of the points each (8/7 in all)."""
     N = n ** 3
     ctx = P.pcg_create(n, n, n, torch.float32, x_dtype=torch.float64)
     t0 = time.perf_counter()
@@ -327,8 +327,8 @@ def bench_multigrid(P, torch, b, n, steps, jacobi_s, nu=1, oracle_budget_s=0.0):
     torch.cuda.synchronize()
     s = (time.perf_counter() - t0) / steps
     it = max(info["iters"], 1)
-    fine = 20 + 36 + 12 + (36 if nu == 1 else 56)
-    per_it = fine * N * (1 + 1 / 7)  # coarser levels add about 1/7 of the fine level's V-cycle bytes
+    vcycle = 40 if nu == 1 else 60
+    per_it = (20 + 36 + vcycle * 8 / 7) * N
     out = {"grid": n, "nu": nu, "levels": [list(l) for l in levels], "setup_s": round(setup_s, 4),
            "iters": info["iters"], "ms": round(s * 1e3, 3), "us_per_iteration": round(s * 1e6 / it, 1),
            "true_relres": info["rel_res_true_fp64"], "status": P.STATUS_NAMES[info["status"]],
@@ -724,7 +724,13 @@ def main():
                 "iteration_GB/s": round((BYTES_DIRECTION + BYTES_UPDATE) * N / (dt_solve / iters) / 1e9, 1),
                 "iteration_frac": round((BYTES_DIRECTION + BYTES_UPDATE) * N / (dt_solve / iters) / 1e9
                                         / HBM_PEAK_GBS, 4),
-                "event_timed_solve_ms": round(tinfo["seconds"] * 1e3, 2)}
+                "event_timed_solve_ms": round(tinfo["seconds"] * 1e3, 2),
+                # q = Ap is recomputed, never stored: 40 B/pt per iteration here
+                # against 52 for the textbook fused iteration that stores q
+                "bytes_convention": "design 12+28 = 40 B/pt per iteration (q never stored); "
+                                    "the textbook count with q stored is 52 B/pt",
+                "iteration_frac_at_52B": round(52 * N / (dt_solve / iters) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic_note": "FETCH_SIZE counts L2 fills, last-level-cache hits included"}
     P.pcg_destroy(tctx)
 
     # Mixed-precision refinement on the same system: FP64 outer loop, BF16 /

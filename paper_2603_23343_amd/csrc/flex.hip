@@ -146,25 +146,6 @@ struct FinFlexRes {
     }
 };
 
-// After z.q and z.r: beta, or a switch to Jacobi when z is not a descent
-// preconditioner (z.r <= 0) or not finite.
-struct FinFlexBeta {
-    SolveState* st;
-    bool redo_pass;
-    __device__ void operator()(const double* tot) const {
-        const double zq = tot[0], zr = tot[1];
-        st->zr = zr;
-        if (redo_pass) st->flags &= ~FLEX_REDO;
-        const bool jac = st->flags & FLEX_JACOBI;
-        if (!jac && (!(zr > 0.0) || !isfinite(zr) || !isfinite(zq))) {
-            st->flags |= FLEX_JACOBI | FLEX_RESTART | FLEX_REDO;
-            st->fallback_at = st->iters;
-            return;
-        }
-        st->beta = (st->flags & FLEX_RESTART) ? 0.0 : -zq / st->sigma;
-    }
-};
-
 constexpr int NT = STREAM_THREADS;
 
 // x += alpha p; r = stored(r - alpha q); ||r||^2.

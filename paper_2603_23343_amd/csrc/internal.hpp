@@ -170,9 +170,19 @@ struct MgHierarchy {
     MgLevel lv[MG_MAX_LEVELS] = {};
     float* ainv = nullptr;   // inverse of the coarsest operator (m x m, symmetric)
 };
+// The flexible iteration's select step fused into the V-cycle's last sweep:
+// q = A p, the solve state and the reduction workspace.
+struct MgSelect {
+    const float* q;
+    SolveState* st;
+    Red red;
+};
 // out = V-cycle(g) on level 0 (out must not alias g or the level's buffers);
-// every kernel returns at once while *done != 0.
-hipError_t launch_mg_vcycle(const MgHierarchy& H, const float* g, float* out, const int* done, hipStream_t s);
+// every kernel returns at once while *done != 0. With sel (two or more
+// levels) the last sweep also forms z.q and z.r and applies the flexible
+// iteration's beta step (FinFlexBeta).
+hipError_t launch_mg_vcycle(const MgHierarchy& H, const float* g, float* out, const int* done, hipStream_t s,
+                           const MgSelect* sel = nullptr);
 // kc = mean of the 2 x 2 x 2 children of kf (nx, ny, nz even).
 hipError_t launch_mg_coarsen_k(const float* kf, int nx, int ny, int nz, float* kc, hipStream_t s);
 // training pairs from solver snapshots

@@ -125,6 +125,45 @@ template <int VX, bool STORE_U> struct OpMgResidual {
     }
 };
 
+// The fine level's last sweep fused with the flexible iteration's select
+// step: z = u + omega D^-1 (g - A u) with g = r, plus z.q and z.r for
+// FinFlexBeta (split grid reduction). After a switch to Jacobi (FLEX_JACOBI)
+// it writes z = D^-1 r instead, as the select step would.
+template <int VX, bool VAR> struct OpMgSmoothSelect {
+    using C = float;
+    struct Raw {
+        RawN<float, VX> g, q;
+        RawN<float, VAR ? VX : 1> d;
+    };
+    const float* __restrict__ g;
+    const float* __restrict__ dinv;
+    const float* __restrict__ q;
+    float* __restrict__ out;
+    const SolveState* st;
+    float wd;  // omega / 6 (constant coefficients) or omega
+    bool jac;
+    __device__ void init() { jac = (st->flags & FLEX_JACOBI) != 0; }
+    __device__ __forceinline__ void fetch(int64_t i, Raw& raw) const {
+        raw.g.load(g + i);
+        raw.q.load(q + i);
+        if constexpr (VAR) raw.d.load(dinv + i);
+    }
+    template <int NC, class Cell>
+    __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const Cell* c, const C* ax, C (&acc)[NC]) const {
+        C o[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            const C gv = raw.g.get(v);
+            const C dv = VAR ? raw.d.get(v) : C(1) / C(6);
+            const C w = VAR ? wd * dv : wd;
+            o[v] = jac ? dv * gv : cell_u(c[v]) + w * (gv - ax[v]);
+            acc[0] += o[v] * raw.q.get(v);
+            acc[1] += o[v] * gv;
+        }
+        st_pts<float, VX>(out, i, o);
+    }
+};
+
 template <int FAM, class SP, int BX, int BY, int VX, class L, class O>
 hipError_t run_mg(const Geometry& g, const L& ld, const O& op, const int* done, hipStream_t s) {
     if (g.nblocks == 0) return hipSuccess;
@@ -138,6 +177,16 @@ hipError_t run_mg(const Geometry& g, const L& ld, const O& op, const int* done, 
     return hipGetLastError();
 }
 
+// The fused last sweep: a reducing z-march (two components) whose finishing
+// step applies FinFlexBeta (a one-work-group kernel after it from 64
+// work-groups on, else the last work-group).
+template <class SP, int BX, int BY, int VX, class L, class O>
+hipError_t run_mg_select(const Geometry& g, const L& ld, const O& op, const MgSelect& sel, const int* done,
+                         hipStream_t s) {
+    return run_zmarch<ZF_MG_SELECT, float, SP, BX, BY, VX, 2, 0u, true>(g, ld, op, FinFlexBeta{sel.st, false}, sel.red,
+                                                                     done, s);
+}
+
 // ---------------------------------------------------------------- transfers
 
 // Transfers launch one thread per coarse cell (restriction) or per four
@@ -148,11 +197,39 @@ constexpr int TX = 64, TY = 4;  // threads per work-group: 64 along x, 4 rows
 
 // g_c = P^T r / 2: each coarse cell gathers the 4 x 4 x 4 fine cells 2I-1 ..
 // 2I+2 per dimension with 1-D weights (1/4, 3/4, 3/4, 1/4), those inside.
+// V2 (nx % 4 == 0): two coarse cells 2t, 2t+1 per thread from one 16-byte
+// load of fine 4t..4t+3 per row plus the two cells beside it.
+template <bool V2>
 __global__ void __launch_bounds__(TX* TY) k_mg_restrict(const float* __restrict__ r, int nx, int ny, int nz,
                                                        float* __restrict__ gc, const int* done) {
     if (*done) return;
     const int cx = nx / 2, cy = ny / 2;
-    const int I = blockIdx.x * TX + threadIdx.x, J = blockIdx.y * TY + threadIdx.y, K = blockIdx.z;
+    const int t = blockIdx.x * TX + threadIdx.x, J = blockIdx.y * TY + threadIdx.y, K = blockIdx.z;
+    if constexpr (V2) {
+        if (4 * t >= nx || J >= cy) return;
+        float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+        for (int dz = 0; dz < 4; ++dz) {
+            const int k = 2 * K - 1 + dz;
+            if (k < 0 || k >= nz) continue;
+            const float wz = (dz == 0 || dz == 3) ? 0.25f : 0.75f;
+#pragma unroll
+            for (int dy = 0; dy < 4; ++dy) {
+                const int j = 2 * J - 1 + dy;
+                if (j < 0 || j >= ny) continue;
+                const float w = wz * ((dy == 0 || dy == 3) ? 0.25f : 0.75f);
+                const float* row = r + ((int64_t)k * ny + j) * nx;
+                const float4 v = *reinterpret_cast<const float4*>(row + 4 * t);
+                const float lo = t > 0 ? row[4 * t - 1] : 0.f;
+                const float hi = 4 * t + 4 < nx ? row[4 * t + 4] : 0.f;
+                a0 += w * (0.25f * lo + 0.75f * v.x + 0.75f * v.y + 0.25f * v.z);
+                a1 += w * (0.25f * v.y + 0.75f * v.z + 0.75f * v.w + 0.25f * hi);
+            }
+        }
+        *reinterpret_cast<float2*>(gc + ((int64_t)K * cy + J) * cx + 2 * t) = make_float2(0.5f * a0, 0.5f * a1);
+        return;
+    }
+    const int I = t;
     if (I >= cx || J >= cy) return;
     float acc = 0.f;
 #pragma unroll
@@ -281,6 +358,17 @@ struct MgStep {
     const int* done;
     hipStream_t s;
 
+    // the last sweep of the fine level with the select step fused (u stored)
+    hipError_t sweep_select(const float* g, const float* u, float* out, const MgSelect& sel) const {
+        return dispatch_cfg<4>(L.plan.cfg, [&]<int BX, int BY, int VX>() -> hipError_t {
+            if (L.k) {
+                OpMgSmoothSelect<VX, true> op{g, L.dinv, sel.q, out, sel.st, omega, false};
+                return run_mg_select<StencilVar<float>, BX, BY, VX>(L.geo, LoadMgUK{u, L.k}, op, sel, done, s);
+            }
+            OpMgSmoothSelect<VX, false> op{g, nullptr, sel.q, out, sel.st, omega / 6.f, false};
+            return run_mg_select<StencilConst<float>, BX, BY, VX>(L.geo, LoadMgU{u}, op, sel, done, s);
+        });
+    }
     hipError_t sweep(const float* g, const float* u, float* out) const {
         return dispatch_cfg<4>(L.plan.cfg, [&]<int BX, int BY, int VX>() -> hipError_t {
             if (L.k) {
@@ -323,8 +411,10 @@ struct MgStep {
         if (e_ != hipSuccess) return e_;     \
     } while (0)
 
-// V-cycle from level l with right-hand side g, result written to out.
-hipError_t vcycle(const MgHierarchy& H, int l, const float* g, float* out, const int* done, hipStream_t s) {
+// V-cycle from level l with right-hand side g, result written to out; with
+// sel (level 0 only) the last sweep also does the flexible select step.
+hipError_t vcycle(const MgHierarchy& H, int l, const float* g, float* out, const int* done, hipStream_t s,
+                  const MgSelect* sel) {
     const MgLevel& L = H.lv[l];
     if (l == H.nlev - 1) {
         hipLaunchKernelGGL(k_mg_dense, dim3((unsigned)((L.n + 3) / 4)), dim3(256), 0, s, H.ainv, g, out, (int)L.n,
@@ -348,10 +438,14 @@ hipError_t vcycle(const MgHierarchy& H, int l, const float* g, float* out, const
     }
     // coarse-grid correction
     const MgLevel& Lc = H.lv[l + 1];
-    hipLaunchKernelGGL(k_mg_restrict, grid_xyz(Lc.nx, Lc.ny, Lc.nz), dim3(TX, TY), 0, s, L.r, L.nx, L.ny, L.nz, Lc.g,
-                       done);
+    if (L.nx % 4 == 0)
+        hipLaunchKernelGGL(k_mg_restrict<true>, grid_xyz(Lc.nx / 2, Lc.ny, Lc.nz), dim3(TX, TY), 0, s, L.r, L.nx, L.ny,
+                           L.nz, Lc.g, done);
+    else
+        hipLaunchKernelGGL(k_mg_restrict<false>, grid_xyz(Lc.nx, Lc.ny, Lc.nz), dim3(TX, TY), 0, s, L.r, L.nx, L.ny,
+                           L.nz, Lc.g, done);
     MGCHK(hipGetLastError());
-    MGCHK(vcycle(H, l + 1, Lc.g, Lc.out, done, s));
+    MGCHK(vcycle(H, l + 1, Lc.g, Lc.out, done, s, nullptr));
     if (L.nx % 4 == 0)
         hipLaunchKernelGGL(k_mg_prolong<true>, grid_xyz(L.nx / 4, L.ny, L.nz), dim3(TX, TY), 0, s, cur, L.nx, L.ny, L.nz,
                            Lc.out, done);
@@ -362,7 +456,8 @@ hipError_t vcycle(const MgHierarchy& H, int l, const float* g, float* out, const
     // post-smoothing; the last sweep writes out
     for (int k = 1; k <= nu; ++k) {
         float* nxt = k == nu ? out : (cur == L.u[0] ? L.u[1] : L.u[0]);
-        MGCHK(st.sweep(g, cur, nxt));
+        if (k == nu && sel) MGCHK(st.sweep_select(g, cur, nxt, *sel));
+        else MGCHK(st.sweep(g, cur, nxt));
         cur = nxt;
     }
     return hipSuccess;
@@ -370,9 +465,10 @@ hipError_t vcycle(const MgHierarchy& H, int l, const float* g, float* out, const
 
 }  // namespace
 
-hipError_t launch_mg_vcycle(const MgHierarchy& H, const float* g, float* out, const int* done, hipStream_t s) {
-    if (H.nlev < 1) return hipErrorInvalidValue;
-    return vcycle(H, 0, g, out, done, s);
+hipError_t launch_mg_vcycle(const MgHierarchy& H, const float* g, float* out, const int* done, hipStream_t s,
+                           const MgSelect* sel) {
+    if (H.nlev < 1 || (sel && H.nlev < 2)) return hipErrorInvalidValue;
+    return vcycle(H, 0, g, out, done, s, sel);
 }
 
 hipError_t launch_mg_coarsen_k(const float* kf, int nx, int ny, int nz, float* kc, hipStream_t s) {

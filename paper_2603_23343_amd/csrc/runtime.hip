@@ -1019,13 +1019,21 @@ static pcg_status flex_solve(pcg_ctx c, cnn_net net, bool mg, const float* g, co
     float* z = static_cast<float*>(c->z);
     double* xacc = static_cast<double*>(c->xacc);
 
+    // With two or more levels the V-cycle's last sweep also does the select
+    // step (saves a pass over z, r and q per iteration).
+    const bool mg_fused = mg && c->mg && c->mg->nlev >= 2;
     auto precond = [&](bool use_net) -> pcg_status {
         if (use_net) {
             pcg_status ps = cnn_forward(net, c->nx, c->ny, c->nz, PCG_F32, r, g, &c->st->rr, z);
             if (ps != PCG_OK) return ps;
         }
-        if (mg) HIPCHK(launch_mg_vcycle(*c->mg, r, z, &c->st->done, st));
-        HIPCHK(launch_flex_select(c->n, z, r, q, dinv, c->st, false, red_of(c), st));
+        if (mg_fused) {  // the V-cycle's last sweep does the select step
+            const MgSelect sel{q, c->st, red_of(c)};
+            HIPCHK(launch_mg_vcycle(*c->mg, r, z, &c->st->done, st, &sel));
+        } else {
+            if (mg) HIPCHK(launch_mg_vcycle(*c->mg, r, z, &c->st->done, st));
+            HIPCHK(launch_flex_select(c->n, z, r, q, dinv, c->st, false, red_of(c), st));
+        }
         HIPCHK(launch_flex_select(c->n, z, r, q, dinv, c->st, true, red_of(c), st));
         return PCG_OK;
     };
@@ -1073,8 +1081,13 @@ static pcg_status flex_solve(pcg_ctx c, cnn_net net, bool mg, const float* g, co
                 pcg_status ps = cnn_forward(net, c->nx, c->ny, c->nz, PCG_F32, r, g, &c->st->rr, z);
                 if (ps != PCG_OK) return ps;
             }
-            if (use_mg) HIPCHK(launch_mg_vcycle(*c->mg, r, z, &c->st->done, sq));
-            HIPCHK(launch_flex_select(c->n, z, r, q, dinv, c->st, false, red_of(c), sq));
+            if (use_mg && mg_fused) {
+                const MgSelect sel{q, c->st, red_of(c)};
+                HIPCHK(launch_mg_vcycle(*c->mg, r, z, &c->st->done, sq, &sel));
+            } else {
+                if (use_mg) HIPCHK(launch_mg_vcycle(*c->mg, r, z, &c->st->done, sq));
+                HIPCHK(launch_flex_select(c->n, z, r, q, dinv, c->st, false, red_of(c), sq));
+            }
             HIPCHK(launch_flex_select(c->n, z, r, q, dinv, c->st, true, red_of(c), sq));
         }
         return PCG_OK;

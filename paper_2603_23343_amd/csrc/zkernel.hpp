@@ -87,8 +87,9 @@ PCGMI_ZKERNEL(k_residual64)
 PCGMI_ZKERNEL(k_start_x0)
 PCGMI_ZKERNEL(k_sr_start)
 PCGMI_ZKERNEL(k_zgeneric)
+PCGMI_ZKERNEL(k_mg_smooth_select)
 
-enum ZFamily { ZF_STENCIL, ZF_FLEX_DIRECTION, ZF_RESIDUAL64, ZF_START_X0, ZF_SR_START, ZF_GENERIC };
+enum ZFamily { ZF_STENCIL, ZF_FLEX_DIRECTION, ZF_RESIDUAL64, ZF_START_X0, ZF_SR_START, ZF_GENERIC, ZF_MG_SELECT };
 
 template <int FAM, typename C, class SP, int BX, int BY, int VX, int NC, unsigned MM, bool RED, class L, class O,
           class F>
@@ -108,6 +109,8 @@ hipError_t run_zmarch(const Grid3& g, const L& ld, const O& op, const F& fin, Re
         hipLaunchKernelGGL((k_sr_start<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
     else if constexpr (FAM == ZF_START_X0)
         hipLaunchKernelGGL((k_start_x0<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
+    else if constexpr (FAM == ZF_MG_SELECT)
+        hipLaunchKernelGGL((k_mg_smooth_select<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
     else
         hipLaunchKernelGGL((k_zgeneric<C, SP, BX, BY, VX, NC, MM, RED, L, O, F>), grid, block, 0, s, g, ld, op, fin, red, done, split);
     if (split) hipLaunchKernelGGL((k_zfinish<NC, MM, F>), dim3(1), block, 0, s, red.partials, g.nblocks, fin, done);
