@@ -787,7 +787,7 @@ def main():
 
     learned = None
     if not args.no_learned:
-        sizes = [int(v) for v in args.learned_n.split(",")]
+        sizes = [int(v) for v in args.learned_n.split(",") if v.strip()]
         learned = bench_learned(P, torch, sizes, args.learned_rounds, oracle_cpu=not args.no_cpu_baseline)
         print(f"# learned: {learned}", file=sys.stderr, flush=True)
 

@@ -311,6 +311,11 @@ pcg_status cnn_loss_grad(cnn_net net, int nx, int ny, int nz, const void *pairs,
  * pairs come from); NULL restores the relative-MSE loss. The context must
  * outlive its use here. */
 pcg_status cnn_set_operator(cnn_net net, pcg_ctx ctx);
+/* Normaliser of the A-norm loss: mode 0 (default) rh.D^-1 rh; mode 1 rh.eh,
+ * which is the error's energy eh.A eh when rh = A eh (pairs from a solve:
+ * r = b - A x and e = x* - x), so every pair counts by its relative A-norm
+ * error whatever its smoothness. PCG_E_ARG for another mode. */
+pcg_status cnn_set_loss_norm(cnn_net net, int mode);
 /* One Adam step (lr, beta = (0.9, 0.999), eps = 1e-8, bias-corrected) on the
  * master weights with gradient grad_dev (NULL: the network's own). */
 pcg_status cnn_adam_step(cnn_net net, const float *grad_dev, float lr);
@@ -326,7 +331,7 @@ pcg_status cnn_train_step(cnn_net net, int nx, int ny, int nz, const void *pairs
  *   stop on ||r|| <= rtol ||b||; z = M(r); beta = -(z.q)/sigma; p = z + beta p.
  * Fallback: M switches to D^-1 for the rest of the solve (restarting the
  * direction recurrence) when z.r <= 0, a value is not finite, or the best
- * residual has not improved by 10% for 20 iterations. When the recursion has
+ * residual has not improved by 10% for 100 iterations. When the recursion has
  * converged, the FP64 true residual judges: above rtol, Jacobi-PCG continues
  * from the current x. The context needs F32 storage and an FP64 x
  * accumulator; the network must use the context's stream; g: DEVICE FP32

@@ -427,7 +427,7 @@ def ir_emulate(shape, b, fmt: str = "bf16", rtol_outer: float = 1e-10, rtol_in: 
 # Flexible CG with one stored direction and a Jacobi fallback
 # ----------------------------------------------------------------------------
 
-def fcg(shape, b, precond, rtol=1e-6, maxit=2000, kcell=None, stag_window=20, stag_drop=0.9):
+def fcg(shape, b, precond, rtol=1e-6, maxit=2000, kcell=None, stag_window=100, stag_drop=0.9):
     """Flexible CG (Notay 2000, truncation m = 1):
 
       r = b - A x; z = M(r); p = z
@@ -436,8 +436,9 @@ def fcg(shape, b, precond, rtol=1e-6, maxit=2000, kcell=None, stag_window=20, st
             z = M(r); beta = -(z.q)/sigma; p = z + beta p
 
     M falls back to D^-1 for the rest of the solve when z.r <= 0, a value is
-    not finite, or the best ||r|| so far has not improved by 10% for 20
-    iterations; the direction recurrence restarts from p = z at the switch.
+    not finite, or the best ||r|| so far has not improved by 10% for
+    stag_window iterations (100: plateaus of plain Jacobi-PCG at 128^3 last
+    longer than 20); the direction recurrence restarts from p = z at the switch.
     precond(r) -> z. Returns dict(x, iters, status, relres, fallback_at).
     """
     op = (lambda v: stencil(v, shape)) if kcell is None else (lambda v: vstencil(kcell, v, shape))
@@ -598,11 +599,12 @@ def rel_mse(pred, target):
     return loss, grads
 
 
-def anorm_loss(pred, rh, eh, shape, kcell=None):
+def anorm_loss(pred, rh, eh, shape, kcell=None, energy=False):
     """A-norm error of the preconditioner z = D^-1 rh + pred as an
     approximation of eh (the error belonging to the residual rh), per sample
-    normalised by rh.D^-1 rh:
-        u = pred + D^-1 rh - eh,  L = u.A u / (rh.D^-1 rh),  dL/dpred = 2 A u / (rh.D^-1 rh)
+    normalised by den = rh.D^-1 rh, or with energy=True by den = rh.eh (the
+    error's energy eh.A eh when rh = A eh):
+        u = pred + D^-1 rh - eh,  L = u.A u / den,  dL/dpred = 2 A u / den
     (A symmetric). Returns (sum over samples of L, list of gradients)."""
     op = (lambda v: stencil(v, shape)) if kcell is None else (lambda v: vstencil(kcell, v, shape))
     n = int(np.prod(shape))
@@ -613,7 +615,7 @@ def anorm_loss(pred, rh, eh, shape, kcell=None):
         p, r, e = (np.asarray(a, dtype=np.float64).reshape(-1) for a in (p, r, e))
         u = p + dinv * r - e
         au = op(u)
-        den = float(np.sum(dinv * r * r))
+        den = float(np.dot(r, e)) if energy else float(np.sum(dinv * r * r))
         loss += float(np.dot(u, au)) / den
         grads.append(2.0 * au / den)
     return loss, grads

@@ -93,6 +93,7 @@ def _load():
         "cnn_adam_step": ([vp, vp, ctypes.c_float], i),
         "cnn_train_step": ([vp, i, i, i, vp, vp, i, ctypes.c_float, vp], i),
         "cnn_set_operator": ([vp, vp], i),
+        "cnn_set_loss_norm": ([vp, i], i),
         "pcg_batch_create": ([ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.c_char_p, i, vp], i),
         "pcg_batch_destroy": ([vp], i),
         "pcg_batch_set_barrier": ([vp, i], i),
@@ -387,6 +388,11 @@ def cnn_set_operator(net: Cnn, ctx):
     keeps a reference to ctx so that it outlives its use."""
     _check(lib.cnn_set_operator(net.handle, None if ctx is None else ctx.handle))
     net.op_ctx = ctx
+
+
+def cnn_set_loss_norm(net: Cnn, mode: int):
+    """A-norm loss normaliser: 0 = rh.D^-1 rh (default), 1 = rh.eh (the error's energy)."""
+    _check(lib.cnn_set_loss_norm(net.handle, int(mode)))
 
 
 def cnn_adam_step(net: Cnn, grad=None, lr=1e-3):

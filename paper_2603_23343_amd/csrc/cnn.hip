@@ -7,27 +7,31 @@
 // t = 9 dz + 3 dy + dx (offsets -1..1). The network is 2 -> 16 -> 16 -> 16
 // -> 1 with ReLU after the first three layers.
 //
-// Forward conv (implicit GEMM): M = voxels, N = Cout = 16, K = 27 * Cin.
-// One v_mfma_f32_16x16x32_bf16 multiplies a 16 x 32 block of the patch
-// matrix (16 voxels x 32 values of K) by a 32 x 16 block of the weights.
-// Operand lane layout (lane l): A[l % 16][8 (l / 16) + j], B[8 (l / 16) + j][l
-// % 16] for j < 8, D[4 (l / 16) + i][l % 16] for i < 4. For Cin = 16 a K
-// chunk covers two taps, so each lane's 8 A values are 8 consecutive
-// channels of one neighbour: one 16-byte load. For Cin = 2 (the packed
-// input) a chunk covers 16 taps and a lane gathers four (tap, 2-channel)
-// pairs. Taps beyond 27 and neighbours outside the grid contribute zero.
-// Weights are pre-swizzled into exactly the B lane layout, so each lane
-// reads its 16 bytes per chunk with one load and keeps all chunks in
-// registers. A work-group owns a 16 x 8 x 4 block of output voxels: it
-// stages the block's input with its one-voxel halo (18 x 10 x 6 voxels) in
-// LDS once, so every input voxel crosses L2 about twice instead of 27 times,
-// and each wavefront computes 8 tiles of 16 voxels (x-rows of the block)
-// from LDS. The 16 x 16 FP32 results go through LDS so each voxel's 16
-// channels leave as two 16-byte stores.
+// Forward conv (implicit GEMM): voxels x Cout = 16, K = 27 * Cin, computed
+// transposed: one v_mfma_f32_16x16x32_bf16 multiplies a 16 x 32 block of the
+// weights (16 output channels x 32 values of K, the A operand) by a 32 x 16
+// block of the patch matrix (32 values of K x 16 voxels, B). Operand lane
+// layout (lane l): A[l % 16][8 (l / 16) + j], B[8 (l / 16) + j][l % 16] for
+// j < 8, D[4 (l / 16) + i][l % 16] for i < 4: lane l reads K values of voxel
+// l % 16 and ends with output channels 4 (l / 16) .. + 3 of that voxel. For
+// Cin = 16 a K chunk covers two taps, so each lane's 8 patch values are 8
+// consecutive channels of one neighbour: one 16-byte LDS load. For Cin = 2
+// (the packed input) a chunk covers 16 taps and a lane gathers four (tap,
+// 2-channel) pairs. Taps beyond 27 have zero weights; neighbours outside the
+// grid are staged as zero. Weights are pre-swizzled into exactly the A lane
+// layout, so each lane reads its 16 bytes per chunk with one load and keeps
+// all chunks in registers. A work-group owns a 16 x 8 x 4 block of output
+// voxels: it stages the block's input with its one-voxel halo (18 x 10 x 6
+// voxels) in LDS once, so every input voxel crosses L2 about twice instead of
+// 27 times, and each wavefront computes 8 tiles of 16 voxels (x-rows of the
+// block) from LDS. Each lane stores its voxel's 4 channels (8 bytes), so a
+// tile's 16 voxels x 16 channels leave as 512 contiguous bytes.
 //
 // The transposed convolution of the backward pass (input gradient) is the
 // same kernel with the taps mirrored and Cin/Cout swapped in the swizzle.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "common.hpp"
 #include "internal.hpp"
@@ -42,9 +46,14 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 constexpr int CONV_WAVES = 4;     // wavefronts per work-group
 constexpr int CONV_NT = 64 * CONV_WAVES;
 
-__device__ __forceinline__ __bf16 bits_to_bf16(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
 __device__ __forceinline__ uint16_t bf16_bits(float f) { return f32_to_bf16_bits(f); }
 __device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+// Two floats to BF16 (round to nearest even) in one conversion, low half first.
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+    typedef __attribute__((ext_vector_type(2))) float f2_t;
+    typedef __attribute__((ext_vector_type(2))) __bf16 b2_t;
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2_t{lo, hi}, b2_t));
+}
 
 struct Dims {
     int nx, ny, nz;
@@ -69,7 +78,7 @@ constexpr int CH_VOX = CH_X * CH_Y * CH_Z;
 constexpr int CB_ROWS = CB_Y * CB_Z;                 // 16-voxel x-rows (tiles) per block
 constexpr int CB_TILES = CB_ROWS / CONV_WAVES;       // tiles per wavefront
 
-// in: [nvox][CIN] bf16 bits. wsw: [CHUNKS][64 lanes][8] bf16 bits (B operand).
+// in: [nvox][CIN] bf16 bits. wsw: [CHUNKS][64 lanes][8] bf16 bits (the A operand).
 template <int CIN, int MODE>
 __global__ void __launch_bounds__(CONV_NT) k_conv3d(Dims d, int nbx, int nby, const uint16_t* __restrict__ in,
                                                     const uint16_t* __restrict__ wsw, void* __restrict__ out,
@@ -78,130 +87,167 @@ __global__ void __launch_bounds__(CONV_NT) k_conv3d(Dims d, int nbx, int nby, co
     constexpr int NCH = ConvK<CIN>::CHUNKS;
     constexpr int VB = CIN * 2;  // bytes per staged voxel (32 or 4)
     __shared__ __attribute__((aligned(16))) unsigned char halo[CH_VOX * VB];
-    __shared__ float lds_d[CONV_WAVES][16][17];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, bz = blockIdx.x / (nbx * nby);
+    // XCD-aware order: work-group b runs on XCD b mod 8, so with a grid that
+    // is a multiple of 8 each XCD takes a contiguous range of blocks, whose
+    // shared halo voxels then meet in that XCD's L2.
+    const unsigned nblk = gridDim.x;
+    const unsigned lb = nblk % 8 == 0 ? (blockIdx.x % 8) * (nblk / 8) + blockIdx.x / 8 : blockIdx.x;
+    const int bx = (int)(lb % nbx), by = (int)((lb / nbx) % nby), bz = (int)(lb / (nbx * nby));
     const int x0 = bx * CB_X, y0 = by * CB_Y, z0 = bz * CB_Z;
 
-    // Stage the halo block (zero outside the grid).
+    // A operands: all weight chunks in registers (loads issued first, so
+    // they are in flight together with the halo loads).
+    bf16x8_t bw[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) bw[c] = *reinterpret_cast<const bf16x8_t*>(wsw + ((size_t)c * 64 + lane) * 8);
+
+    // Stage the halo block (zero outside the grid). Every load of a thread
+    // is issued before its first LDS store, so a work-group waits for one
+    // load latency, not one per piece (a loop that stored each piece before
+    // loading the next serialised them).
+    // Voxel offsets are 32-bit (the launcher checks the grid size); a piece
+    // outside the grid or past the block loads voxel 0 and stores zero, so
+    // every load is issued without a branch.
+    auto halo_voxel = [&](int h, bool& ok) {
+        const int hx = h % CH_X, hr = h / CH_X, hy = hr % CH_Y, hz = hr / CH_Y;
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+        // bitwise, not short-circuit: a select, not a branch per piece
+        ok = (h < CH_VOX) & ((unsigned)gx < (unsigned)d.nx) & ((unsigned)gy < (unsigned)d.ny) &
+             ((unsigned)gz < (unsigned)d.nz);
+        const int vox = (gz * d.ny + gy) * d.nx + gx;
+        return ok ? vox : 0;
+    };
     if constexpr (CIN == 16) {
-        for (int it = tid; it < CH_VOX * 2; it += CONV_NT) {
-            const int h = it >> 1, half = it & 1;
-            const int hx = h % CH_X, hy = (h / CH_X) % CH_Y, hz = h / (CH_X * CH_Y);
-            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz)
-                v = *reinterpret_cast<const uint4*>(in + (((int64_t)gz * d.ny + gy) * d.nx + gx) * 16 + 8 * half);
-            *reinterpret_cast<uint4*>(halo + (size_t)it * 16) = v;
-        }
+        // Wavefront w stages halo rows w, w + 4, ...: a row is 18 voxels x 32
+        // bytes, contiguous in memory, loaded by lanes 0-35 (16 bytes each);
+        // the row's coordinates are wave-uniform, so each load costs a few
+        // vector instructions.
+        constexpr int RPW = CH_Y * CH_Z / CONV_WAVES;
+        static_assert(RPW * CONV_WAVES == CH_Y * CH_Z, "halo rows per wavefront");
+        const int wu = __builtin_amdgcn_readfirstlane(wid);
+        const int hx = lane >> 1, half = lane & 1, gx = x0 + hx - 1;
+        const bool xok = lane < 2 * CH_X && (unsigned)gx < (unsigned)d.nx;
+        // two batches of rows keep the staging registers below the compute's
+        constexpr int B1 = (RPW + 1) / 2;
+        auto stage_rows = [&](auto first, auto count) {
+            constexpr int J0 = decltype(first)::value, NJ = decltype(count)::value;
+            uint4 v[NJ];
+            bool ok[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int r = wu + CONV_WAVES * (J0 + j), hy = r % CH_Y, hz = r / CH_Y;
+                const int gy = y0 + hy - 1, gz = z0 + hz - 1;
+                ok[j] = xok & ((unsigned)gy < (unsigned)d.ny) & ((unsigned)gz < (unsigned)d.nz);
+                const int vox = ok[j] ? (gz * d.ny + gy) * d.nx + gx : 0;
+                v[j] = *reinterpret_cast<const uint4*>(in + (size_t)vox * 16 + 8 * half);
+            }
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int r = wu + CONV_WAVES * (J0 + j);
+                // channel halves in separate planes: a wavefront's 16 lanes of
+                // one half read 16 consecutive 16-byte slots
+                if (lane < 2 * CH_X)
+                    *reinterpret_cast<uint4*>(halo + (size_t)half * (CH_VOX * 16) + (size_t)(r * CH_X + hx) * 16) =
+                        ok[j] ? v[j] : make_uint4(0, 0, 0, 0);
+            }
+        };
+        stage_rows(std::integral_constant<int, 0>{}, std::integral_constant<int, B1>{});
+        stage_rows(std::integral_constant<int, B1>{}, std::integral_constant<int, RPW - B1>{});
     } else {
-        for (int h = tid; h < CH_VOX; h += CONV_NT) {
-            const int hx = h % CH_X, hy = (h / CH_X) % CH_Y, hz = h / (CH_X * CH_Y);
-            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
-            uint32_t v = 0u;
-            if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz)
-                v = *reinterpret_cast<const uint32_t*>(in + (((int64_t)gz * d.ny + gy) * d.nx + gx) * 2);
-            *reinterpret_cast<uint32_t*>(halo + (size_t)h * 4) = v;
+        constexpr int NP = (CH_VOX + CONV_NT - 1) / CONV_NT;
+        uint32_t v[NP];
+        bool ok[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const int vox = halo_voxel(tid + j * CONV_NT, ok[j]);
+            v[j] = *reinterpret_cast<const uint32_t*>(in + (size_t)vox * 2);
+        }
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const int h = tid + j * CONV_NT;
+            if (h < CH_VOX) *reinterpret_cast<uint32_t*>(halo + (size_t)h * 4) = ok[j] ? v[j] : 0u;
         }
     }
 
-    // B operands: all weight chunks in registers.
-    bf16x8_t bw[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        const uint16_t* p = wsw + ((size_t)c * 64 + lane) * 8;
-        Vec16<bf16> raw = *reinterpret_cast<const Vec16<bf16>*>(p);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) bw[c][j] = bits_to_bf16(raw.e[j].bits);
-    }
     __syncthreads();
 
     const int row = lane & 15, kgrp = lane >> 4;  // A: voxel row (x within the tile), K group of 8
+    // Tile tt of wavefront wid is the block's x-row (yl, zl) = (wid + 4 (tt & 1),
+    // tt / 2): the wavefront's part goes into a per-lane base address and the
+    // tile's part is a constant, so every A-operand read is one LDS load at a
+    // fixed offset from a few per-lane addresses. Taps past 26 read a voxel of
+    // the block (any finite value): their weights are zero.
+    static_assert(CB_Y == 2 * CONV_WAVES && CB_TILES == 2 * CB_Z, "tile mapping");
+    auto tile_off = [](int tt) { return ((tt >> 1) * CH_Y + 4 * (tt & 1)) * CH_X; };
+    auto tap_off = [](int t) { return t < 27 ? ((t / 9) * CH_Y + (t / 3) % 3) * CH_X + t % 3 : 0; };
     f32x4_t acc[CB_TILES];
 #pragma unroll
     for (int tt = 0; tt < CB_TILES; ++tt) acc[tt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    if constexpr (CIN == 16) {
+        // lanes 0-31 take tap 2c, lanes 32-63 tap 2c + 1; channels 0-7 / 8-15 by (kgrp & 1)
+        const unsigned char* hb = halo + (size_t)(kgrp & 1) * (CH_VOX * 16) + (size_t)(wid * CH_X + row) * 16;
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
+        for (int c = 0; c < NCH; ++c) {
+            const unsigned char* hc = hb + (size_t)((kgrp >> 1) ? tap_off(2 * c + 1) : tap_off(2 * c)) * 16;
 #pragma unroll
-        for (int tt = 0; tt < CB_TILES; ++tt) {
-            const int q = wid + CONV_WAVES * tt;  // tile row in the block
-            const int yl = q % CB_Y, zl = q / CB_Y;
-            bf16x8_t a;
-            if constexpr (CIN == 16) {
-                const int tap = 2 * c + (kgrp >> 1);
-                const int tq = tap < 27 ? tap : 0;
-                const int h = ((zl + tq / 9) * CH_Y + (yl + (tq / 3) % 3)) * CH_X + row + tq % 3;
-                const uint4 raw = *reinterpret_cast<const uint4*>(halo + (size_t)h * 32 + 16 * (kgrp & 1));
-                const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t v = tap < 27 ? w[j] : 0u;
-                    a[2 * j] = bits_to_bf16((uint16_t)(v & 0xffffu));
-                    a[2 * j + 1] = bits_to_bf16((uint16_t)(v >> 16));
-                }
-            } else {
-                // k = 2 tap + channel; lane's 8 values: taps 16 c + 4 kgrp + (0..3), 2 channels each
-#pragma unroll
-                for (int qq = 0; qq < 4; ++qq) {
-                    const int tap = 16 * c + 4 * kgrp + qq;
-                    const int tq = tap < 27 ? tap : 0;
-                    const int h = ((zl + tq / 9) * CH_Y + (yl + (tq / 3) % 3)) * CH_X + row + tq % 3;
-                    const uint32_t w2 = *reinterpret_cast<const uint32_t*>(halo + (size_t)h * 4);
-                    const uint32_t v = tap < 27 ? w2 : 0u;
-                    a[2 * qq] = bits_to_bf16((uint16_t)(v & 0xffffu));
-                    a[2 * qq + 1] = bits_to_bf16((uint16_t)(v >> 16));
-                }
+            for (int tt = 0; tt < CB_TILES; ++tt) {
+                const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(hc + (size_t)tile_off(tt) * 16);
+                acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], a, acc[tt], 0, 0, 0);
             }
-            acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[c], acc[tt], 0, 0, 0);
+        }
+    } else {
+        // k = 2 tap + channel; the lane's 8 values: taps 16 c + 4 kgrp + (0..3), 2 channels each
+        const unsigned char* hb = halo + (size_t)(wid * CH_X + row) * 4;
+        int toff[NCH][4];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) toff[c][qq] = tap_off(16 * c + 4 * kgrp + qq);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+            for (int tt = 0; tt < CB_TILES; ++tt) {
+                uint32_t w[4];
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq)
+                    w[qq] = *reinterpret_cast<const uint32_t*>(hb + (size_t)(tile_off(tt) + toff[c][qq]) * 4);
+                const bf16x8_t a = __builtin_bit_cast(bf16x8_t, make_uint4(w[0], w[1], w[2], w[3]));
+                acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], a, acc[tt], 0, 0, 0);
+            }
         }
     }
 
-    // Results: lane holds D[4 kgrp + i][row] (voxel 4 kgrp + i of the tile, channel row).
+    // Results. The product is W^T P^T (weights as the A operand, the patch
+    // rows as B, the same lane layouts), so lane (kgrp, row) holds output
+    // channels 4 kgrp .. 4 kgrp + 3 of voxel `row` of the tile: each lane
+    // writes its 4 channels as 8 bytes and a tile leaves as 512 contiguous
+    // bytes, with no transpose through LDS.
     float scale = 0.f;
     if constexpr (MODE == OUT_SCALED_F32) scale = (float)(scale_rms2 ? sqrt(*scale_rms2) * scale_mul : scale_mul);
+    const int wo = __builtin_amdgcn_readfirstlane(wid);
 #pragma unroll
     for (int tt = 0; tt < CB_TILES; ++tt) {
-        const int q = wid + CONV_WAVES * tt;
-        const int gy = y0 + q % CB_Y, gz = z0 + q / CB_Y;
-        const bool rok = gy < d.ny && gz < d.nz;
-        const int64_t vrow = ((int64_t)gz * d.ny + gy) * d.nx;
+        const int gy = y0 + wo + 4 * (tt & 1), gz = z0 + (tt >> 1), gx = x0 + row;
+        if (!(gy < d.ny && gz < d.nz)) continue;  // wave-uniform
+        if (gx >= d.nx) continue;
+        const size_t v = (size_t)((gz * d.ny + gy) * d.nx) + gx;
         if constexpr (MODE == OUT_SCALED_F32) {
-            if (row == 0 && rok) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int gx = x0 + 4 * kgrp + i;
-                    if (gx < d.nx) static_cast<float*>(out)[vrow + gx] = scale * acc[tt][i];
-                }
-            }
+            if (kgrp == 0) static_cast<float*>(out)[v] = scale * acc[tt][0];
         } else {
+            float val[4];
+            uint2 m = make_uint2(0u, 0u);
+            if constexpr (MODE == OUT_MASK_BF16) m = *reinterpret_cast<const uint2*>(mask + v * 16 + 4 * kgrp);
+            const uint32_t mw[2] = {m.x, m.y};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) lds_d[wid][4 * kgrp + i][row] = acc[tt][i];
-            // wavefront-scope LDS hand-off (this wavefront's lanes read what its other lanes wrote)
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // lanes 0..31 write the tile's 16 voxels x 16 channels as 8-channel (16-byte) pieces.
-            if (lane < 32) {
-                const int vi = lane >> 1, c0 = 8 * (lane & 1);
-                const int gx = x0 + vi;
-                if (rok && gx < d.nx) {
-                    const int64_t v = vrow + gx;
-                    Vec16<bf16> o;
-                    Vec16<bf16> m;
-                    if constexpr (MODE == OUT_MASK_BF16) m = *reinterpret_cast<const Vec16<bf16>*>(mask + v * 16 + c0);
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        float val = lds_d[wid][vi][c0 + j];
-                        if constexpr (MODE == OUT_RELU_BF16) val = val > 0.f ? val : 0.f;
-                        if constexpr (MODE == OUT_MASK_BF16) val = bf16_val(m.e[j].bits) > 0.f ? val : 0.f;
-                        o.e[j].bits = bf16_bits(val);
-                    }
-                    *reinterpret_cast<Vec16<bf16>*>(static_cast<uint16_t*>(out) + v * 16 + c0) = o;
-                }
+            for (int i = 0; i < 4; ++i) {
+                val[i] = acc[tt][i];
+                if constexpr (MODE == OUT_RELU_BF16) val[i] = val[i] > 0.f ? val[i] : 0.f;
+                if constexpr (MODE == OUT_MASK_BF16)
+                    val[i] = bf16_val((uint16_t)((i & 1) ? mw[i >> 1] >> 16 : mw[i >> 1] & 0xffffu)) > 0.f ? val[i] : 0.f;
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const uint2 o = make_uint2(pack_bf16x2(val[0], val[1]), pack_bf16x2(val[2], val[3]));
+            *reinterpret_cast<uint2*>(static_cast<uint16_t*>(out) + v * 16 + 4 * kgrp) = o;
         }
     }
 }
@@ -262,7 +308,7 @@ hipError_t launch_conv3d(int nx, int ny, int nz, int cin, int mode, const void* 
     if (d.nvox == 0) return hipSuccess;
     const int nbx = (nx + CB_X - 1) / CB_X, nby = (ny + CB_Y - 1) / CB_Y, nbz = (nz + CB_Z - 1) / CB_Z;
     const int64_t nb = (int64_t)nbx * nby * nbz;
-    if (nb > INT32_MAX) return hipErrorInvalidValue;
+    if (nb > INT32_MAX || d.nvox > INT32_MAX) return hipErrorInvalidValue;  // 32-bit voxel offsets
     auto in16 = static_cast<const uint16_t*>(in);
     auto w16 = static_cast<const uint16_t*>(wsw);
     auto m16 = static_cast<const uint16_t*>(mask);

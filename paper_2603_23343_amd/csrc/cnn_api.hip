@@ -24,15 +24,16 @@ hipError_t launch_swizzle_weights(const float* w, int cin, int cout, int CIN, in
 int conv_swizzle_elems(int CIN);
 int wgrad_groups(int nx, int ny, int nz);
 hipError_t launch_wgrad(int nx, int ny, int nz, int cx, int cy, const void* X, const void* dY, bool dy_f32,
-                        float* partials, int groups, hipStream_t s);
+                        const void* zeros, float* partials, int groups, hipStream_t s);
 hipError_t launch_reduce_partials(const float* partials, int groups, int len, float scale, bool accumulate,
                                   float* grad, hipStream_t s);
 hipError_t launch_loss(int64_t n, const float* out, const void* tgt, double* loss_acc, double* coef, float* dout,
                        void* dpack, Red red, hipStream_t s);
 hipError_t launch_adam(int n, float* w, const float* g, float* m, float* v, float lr, int step, hipStream_t s);
 hipError_t launch_anorm_u(int64_t n, const float* out, const void* pair, const float* dinv, float* u, hipStream_t s);
-hipError_t launch_anorm_loss(int64_t n, const float* u, const float* au, const void* rh, const float* dinv,
-                             double* loss_acc, double* coef, float* dout, void* dpack, Red red, hipStream_t s);
+hipError_t launch_anorm_loss(int64_t n, const float* u, const float* au, const void* rh, bool energy,
+                             const float* dinv, double* loss_acc, double* coef, float* dout, void* dpack, Red red,
+                             hipStream_t s);
 hipError_t ctx_apply_f32(pcg_ctx c, const float* u, float* y);
 const float* ctx_dinv_f32(pcg_ctx c);
 bool ctx_is_f32_grid(pcg_ctx c, int nx, int ny, int nz);
@@ -84,10 +85,12 @@ struct cnn_s {
     int groups = 0;
     double* scal = nullptr;  // {loss accumulator, gradient coefficient}
     double* rpart = nullptr;
+    void* zeros = nullptr;  // 64 zero bytes: read in place of points outside the grid
     unsigned* ticket = nullptr;
     // A-norm loss: the operator's context (null: relative-MSE loss) and
     // the vectors u = N + D^-1 rh - eh and A u
     pcg_ctx op = nullptr;
+    bool energy = false;  // normaliser rh.eh (the error's energy) instead of rh.D^-1 rh
     float *u = nullptr, *au = nullptr;
     uint64_t grid_epoch = 0;  // bumped whenever the grid workspace is reallocated
 };
@@ -202,6 +205,8 @@ pcg_status cnn_create(cnn_net* out, void* hip_stream) {
     if (e == hipSuccess) e = hipMalloc(&n->scal, 4 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&n->rpart, sizeof(double) * 2 * DOT_MAX_BLOCKS);
     if (e == hipSuccess) e = hipMalloc(&n->ticket, 256);
+    if (e == hipSuccess) e = hipMalloc(&n->zeros, 64);
+    if (e == hipSuccess) e = hipMemsetAsync(n->zeros, 0, 64, n->stream);
     if (e == hipSuccess) e = hipMemsetAsync(n->w, 0, sizeof(float) * NW, n->stream);
     if (e == hipSuccess) e = hipMemsetAsync(n->m, 0, sizeof(float) * NW, n->stream);
     if (e == hipSuccess) e = hipMemsetAsync(n->v, 0, sizeof(float) * NW, n->stream);
@@ -219,7 +224,7 @@ pcg_status cnn_destroy(cnn_net n) {
     if (!n) return PCG_OK;
     (void)hipStreamSynchronize(n->stream);
     free_grid(n);
-    void* p[] = {n->w, n->grad, n->m, n->v, n->scal, n->rpart, n->ticket};
+    void* p[] = {n->w, n->grad, n->m, n->v, n->scal, n->rpart, n->ticket, n->zeros};
     for (void* q : p)
         if (q) (void)hipFree(q);
     for (int l = 0; l < NL; ++l) {
@@ -287,26 +292,27 @@ pcg_status cnn_loss_grad(cnn_net n, int nx, int ny, int nz, const void* pairs, c
             const float* dinv = ctx_dinv_f32(n->op);
             CHK(launch_anorm_u(nv, n->out, rh, dinv, n->u, s));
             CHK(ctx_apply_f32(n->op, n->u, n->au));
-            CHK(launch_anorm_loss(nv, n->u, n->au, rh, dinv, &n->scal[0], &n->scal[1], n->dout, n->dpack, red, s));
+            CHK(launch_anorm_loss(nv, n->u, n->au, rh, n->energy, dinv, &n->scal[0], &n->scal[1], n->dout, n->dpack,
+                                  red, s));
         } else {
             CHK(launch_loss(nv, n->out, eh, &n->scal[0], &n->scal[1], n->dout, n->dpack, red, s));
         }
         const bool acc = b > 0;
         const int X = nx, Y = ny, Z = nz;
         // layer 4: dW4 from (h3, dOut); dh3 = conv(dOut, mirrored W4) * (h3 > 0)
-        CHK(launch_wgrad(X, Y, Z, 16, 1, n->h3, n->dout, true, n->partials, n->groups, s));
+        CHK(launch_wgrad(X, Y, Z, 16, 1, n->h3, n->dout, true, n->zeros, n->partials, n->groups, s));
         CHK(launch_reduce_partials(n->partials, n->groups, 27 * 16, inv_b, acc, G + WOFF[3], s));
         CHK(launch_conv3d(X, Y, Z, 2, OUT_MASK, n->dpack, n->wb[3], n->da, n->h3, nullptr, 1.0, s));
         // layer 3
-        CHK(launch_wgrad(X, Y, Z, 16, 16, n->h2, n->da, false, n->partials, n->groups, s));
+        CHK(launch_wgrad(X, Y, Z, 16, 16, n->h2, n->da, false, n->zeros, n->partials, n->groups, s));
         CHK(launch_reduce_partials(n->partials, n->groups, 27 * 256, inv_b, acc, G + WOFF[2], s));
         CHK(launch_conv3d(X, Y, Z, 16, OUT_MASK, n->da, n->wb[2], n->db, n->h2, nullptr, 1.0, s));
         // layer 2
-        CHK(launch_wgrad(X, Y, Z, 16, 16, n->h1, n->db, false, n->partials, n->groups, s));
+        CHK(launch_wgrad(X, Y, Z, 16, 16, n->h1, n->db, false, n->zeros, n->partials, n->groups, s));
         CHK(launch_reduce_partials(n->partials, n->groups, 27 * 256, inv_b, acc, G + WOFF[1], s));
         CHK(launch_conv3d(X, Y, Z, 16, OUT_MASK, n->db, n->wb[1], n->da, n->h1, nullptr, 1.0, s));
         // layer 1
-        CHK(launch_wgrad(X, Y, Z, 2, 16, n->in0, n->da, false, n->partials, n->groups, s));
+        CHK(launch_wgrad(X, Y, Z, 2, 16, n->in0, n->da, false, n->zeros, n->partials, n->groups, s));
         CHK(launch_reduce_partials(n->partials, n->groups, 27 * 32, inv_b, acc, G + WOFF[0], s));
     }
     if (loss_dev) {
@@ -326,6 +332,13 @@ pcg_status cnn_set_operator(cnn_net n, pcg_ctx ctx) {
     if (ctx && ctx_stream(ctx) != n->stream)
         return err(PCG_E_ARG, "cnn_set_operator: the network and the context must use the same stream");
     n->op = ctx;
+    return PCG_OK;
+}
+
+pcg_status cnn_set_loss_norm(cnn_net n, int mode) {
+    if (!n) return err(PCG_E_ARG, "cnn_set_loss_norm: null network");
+    if (mode != 0 && mode != 1) return err(PCG_E_ARG, "cnn_set_loss_norm: mode must be 0 or 1 (got %d)", mode);
+    n->energy = mode == 1;
     return PCG_OK;
 }
 

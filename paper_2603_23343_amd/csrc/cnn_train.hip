@@ -33,46 +33,76 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 constexpr int WGM_K = 128;           // points of a row per staged chunk
 constexpr int WGM_SP = WGM_K + 8;    // LDS row pitch (bf16), padded against bank conflicts
 
-template <int CX> __device__ __forceinline__ void load_x16(const uint16_t* __restrict__ X, int64_t v, uint16_t (&c)[16]) {
-    if constexpr (CX == 16) {
-        uint4 a = make_uint4(0, 0, 0, 0), b = make_uint4(0, 0, 0, 0);
-        if (v >= 0) {
-            a = *reinterpret_cast<const uint4*>(X + v * 16);
-            b = *reinterpret_cast<const uint4*>(X + v * 16 + 8);
-        }
+// One voxel's channels as loaded: C = 16 BF16 channels (two 16-byte loads),
+// C = 2 (one 4-byte load) or one FP32 channel (rounded to BF16 when staged).
+// A voxel outside the grid or the chunk loads from a zeroed page instead, so
+// the loads are unconditional and nothing is masked afterwards. word(i)
+// holds channels 2i (low half) and 2i + 1 (high half).
+template <int C, typename S> struct Vox;
+template <> struct Vox<16, uint16_t> {
+    static constexpr int WORDS = 8;
+    uint4 a, b;
+    __device__ __forceinline__ void load(const uint16_t* __restrict__ p, int64_t v, bool ok, const void* zeros) {
+        const uint16_t* q = ok ? p + v * 16 : static_cast<const uint16_t*>(zeros);
+        a = *reinterpret_cast<const uint4*>(q);
+        b = *reinterpret_cast<const uint4*>(q + 8);
+    }
+    __device__ __forceinline__ uint32_t word(int i) const {
         const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        return w[i];
+    }
+};
+template <> struct Vox<2, uint16_t> {
+    static constexpr int WORDS = 1;
+    uint32_t w;
+    __device__ __forceinline__ void load(const uint16_t* __restrict__ p, int64_t v, bool ok, const void* zeros) {
+        w = *reinterpret_cast<const uint32_t*>(ok ? p + v * 2 : static_cast<const uint16_t*>(zeros));
+    }
+    __device__ __forceinline__ uint32_t word(int) const { return w; }
+};
+template <> struct Vox<1, float> {
+    static constexpr int WORDS = 1;
+    float f;
+    __device__ __forceinline__ void load(const float* __restrict__ p, int64_t v, bool ok, const void* zeros) {
+        f = *(ok ? p + v : static_cast<const float*>(zeros));
+    }
+    __device__ __forceinline__ uint32_t word(int) const { return (uint32_t)f32_to_bf16_bits(f); }
+};
+
+// Stage points xp and xp + 1 of a row into the [channel][x] LDS layout: the
+// 32-bit word at (channel c, xp) holds (c of point xp, c of point xp + 1).
+// One byte permute per channel: from the words (2i, 2i + 1) of both points,
+// selector 0x05040100 takes the low halves, 0x07060302 the high halves.
+// Channels past the voxel's own stay zero (they were zeroed once).
+template <class V>
+__device__ __forceinline__ void stage_pair(uint16_t* __restrict__ lds_row0, const V& pa, const V& pb) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            c[2 * i] = (uint16_t)(w[i] & 0xffffu);
-            c[2 * i + 1] = (uint16_t)(w[i] >> 16);
-        }
-    } else {
-        const uint32_t w = v >= 0 ? *reinterpret_cast<const uint32_t*>(X + v * 2) : 0u;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) c[i] = 0;
-        c[0] = (uint16_t)(w & 0xffffu);
-        c[1] = (uint16_t)(w >> 16);
+    for (int i = 0; i < V::WORDS; ++i) {
+        const uint32_t wa = pa.word(i), wb = pb.word(i);
+        *reinterpret_cast<uint32_t*>(lds_row0 + (2 * i) * WGM_SP) = __builtin_amdgcn_perm(wb, wa, 0x05040100u);
+        *reinterpret_cast<uint32_t*>(lds_row0 + (2 * i + 1) * WGM_SP) = __builtin_amdgcn_perm(wb, wa, 0x07060302u);
     }
 }
 
-template <int CY, typename Y>
-__device__ __forceinline__ void load_dy16(const Y* __restrict__ dY, int64_t v, uint16_t (&c)[16]) {
-    if constexpr (CY == 16) {
-        load_x16<16>(reinterpret_cast<const uint16_t*>(dY), v, c);
-    } else {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) c[i] = 0;
-        c[0] = v >= 0 ? f32_to_bf16_bits(dY[v]) : (uint16_t)0;
-    }
-}
+// A staged chunk: a row (y, z) of the output and points [x0, x0 + len).
+struct WgItem {
+    int y, z, row, x0, len, kp;  // kp: len rounded up to 32 (the products' K)
+};
 
+// Rows staged per item: the 9 neighbour rows of X (q = 3 dz + dy) and the 3
+// shifted copies of dY (q = 9 + shift), 64 point pairs each: wavefront w
+// stages rows q = w, w + 4, w + 8, every lane the same pair column.
 template <int CX, int CY, typename Y>
-__global__ void __launch_bounds__(256) k_wgrad_mfma(int nx, int ny, int nz, const uint16_t* __restrict__ X,
-                                                    const Y* __restrict__ dY, float* __restrict__ partials) {
+__global__ void __launch_bounds__(256, 2) k_wgrad_mfma(int nx, int ny, int nz, const uint16_t* __restrict__ X,
+                                                    const Y* __restrict__ dY, const void* __restrict__ zeros,
+                                                    float* __restrict__ partials) {
+    static_assert(WGM_K == 128, "one pair column per lane");
     __shared__ __attribute__((aligned(16))) uint16_t xs[9 * 16 * WGM_SP];
     __shared__ __attribute__((aligned(16))) uint16_t ys[3 * 16 * WGM_SP];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int m = lane & 15, kg = lane >> 4;
+    const int xp = 2 * lane;  // this lane's pair column
     f32x4_t acc[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
@@ -88,62 +118,103 @@ __global__ void __launch_bounds__(256) k_wgrad_mfma(int nx, int ny, int nz, cons
         last = (int)((int64_t)nitems * (xcd + 1) / 8);
         step = per;
     }
-    for (int item = first; item < last; item += step) {
-        const int ch = item % nch, row = item / nch;
-        const int y = row % ny, z = row / ny;
-        const int x0 = ch * WGM_K;
-        const int len = min(WGM_K, nx - x0);
-        const int kp = (len + 31) & ~31;  // K of this chunk, zero-padded to 32
-        const int npairs = kp / 2;
-        __syncthreads();  // the previous chunk's fragments have been read
-        for (int idx = tid; idx < 9 * npairs; idx += 256) {
-            const int r = idx / npairs, xp = (idx - r * npairs) * 2;
-            const int zz = z + r / 3 - 1, yy = y + r % 3 - 1;
-            const bool rok = zz >= 0 && zz < nz && yy >= 0 && yy < ny;
-            const int64_t base = ((int64_t)zz * ny + yy) * nx + x0;
-            uint16_t a[16], b[16];
-            load_x16<CX>(X, rok && xp < len ? base + xp : -1, a);
-            load_x16<CX>(X, rok && xp + 1 < len ? base + xp + 1 : -1, b);
+    auto geom = [&](int item) {
+        WgItem it;
+        const int ch = item % nch;
+        it.row = item / nch;
+        it.y = it.row % ny;
+        it.z = it.row / ny;
+        it.x0 = ch * WGM_K;
+        it.len = min(WGM_K, nx - it.x0);
+        it.kp = (it.len + 31) & ~31;
+        return it;
+    };
+    // The next item's points are loaded into registers while the current
+    // item's products run; a loop that stored each piece into LDS before
+    // loading the next waited for every load in turn.
+    Vox<CX, uint16_t> xa[3], xb[3];
+    Vox<CY, Y> ya, yb;
+    // Every load is issued on every path (a slot a wavefront does not use
+    // reads the zero page): loads under branches kept these registers in
+    // scratch memory.
+    auto fetch = [&](const WgItem& it) {
+        const bool pa = xp < it.len, pb = xp + 1 < it.len;
 #pragma unroll
-            for (int c = 0; c < 16; ++c)
-                *reinterpret_cast<uint32_t*>(&xs[(r * 16 + c) * WGM_SP + xp]) = (uint32_t)a[c] | ((uint32_t)b[c] << 16);
+        for (int j = 0; j < 3; ++j) {
+            const int q = wu + 4 * j;  // wave-uniform; rows q < 9 are X rows
+            const int qx = q < 9 ? q : 0;
+            const int zz = it.z + qx / 3 - 1, yy = it.y + qx % 3 - 1;
+            const bool rok = q < 9 && zz >= 0 && zz < nz && yy >= 0 && yy < ny;
+            const int64_t base = ((int64_t)zz * ny + yy) * nx + it.x0 + xp;
+            xa[j].load(X, base, rok && pa, zeros);
+            xb[j].load(X, base + 1, rok && pb, zeros);
         }
-        for (int idx = tid; idx < 3 * npairs; idx += 256) {
-            const int sft = idx / npairs, xp = (idx - sft * npairs) * 2;
-            const int64_t base = (int64_t)row * nx;
-            const int xa = x0 + xp - (sft - 1), xb = xa + 1;  // dY column feeding x' = x0 + xp (+1)
-            uint16_t a[16], b[16];
-            load_dy16<CY, Y>(dY, (xp < len && xa >= 0 && xa < nx) ? base + xa : -1, a);
-            load_dy16<CY, Y>(dY, (xp + 1 < len && xb >= 0 && xb < nx) ? base + xb : -1, b);
-#pragma unroll
-            for (int c = 0; c < 16; ++c)
-                *reinterpret_cast<uint32_t*>(&ys[(sft * 16 + c) * WGM_SP + xp]) = (uint32_t)a[c] | ((uint32_t)b[c] << 16);
-        }
-        __syncthreads();
+        // the dY row of wavefronts 1-3 (their third row q = 9 + shift)
+        const int sft = wu - 1;
+        const int ca = it.x0 + xp - (sft - 1);  // dY column feeding x' = x0 + xp (+1)
+        const int64_t base = (int64_t)it.row * nx + ca;
+        ya.load(dY, base, wu > 0 && pa && ca >= 0 && ca < nx, zeros);
+        yb.load(dY, base + 1, wu > 0 && pb && ca + 1 >= 0 && ca + 1 < nx, zeros);
+    };
+    // LDS: [row or shift][channel][x], transposed from the voxel-major input.
+    auto stage = [&]() {
+        stage_pair(&xs[(wu * 16) * WGM_SP + xp], xa[0], xb[0]);
+        stage_pair(&xs[((wu + 4) * 16) * WGM_SP + xp], xa[1], xb[1]);
+        if (wu == 0) stage_pair(&xs[(8 * 16) * WGM_SP + xp], xa[2], xb[2]);
+        else stage_pair(&ys[((wu - 1) * 16) * WGM_SP + xp], ya, yb);
+    };
+    // Channels a narrow input never writes (CX = 2, CY = 1) stay zero.
+    if constexpr (CX < 16 || CY < 16) {
+        for (int i = tid; i < 9 * 16 * WGM_SP / 2; i += 256) reinterpret_cast<uint32_t*>(xs)[i] = 0u;
+        for (int i = tid; i < 3 * 16 * WGM_SP / 2; i += 256) reinterpret_cast<uint32_t*>(ys)[i] = 0u;
+    }
+    // Products of one item for wavefront W: its taps t = W + 4 j (j < 7, t <
+    // 27; t = 3 r + shift with r = 3 dz + dy) are compile-time constants, so
+    // every LDS read is at a fixed offset and the three dY fragments are
+    // shared by the taps with the same shift.
+    auto products = [&]<int W>(int kp) {
         for (int kb = 0; kb < kp; kb += 32) {
             const int ko = kb + 8 * kg;
-            // tap t = 3 r + sft (r = 3 dz + dy): both loops unrolled, so the
-            // accumulator acc[t / 4] of the wave owning t (t % 4 == wid) is
-            // a fixed register block
+            bf16x8_t b[3];
 #pragma unroll
-            for (int sft = 0; sft < 3; ++sft) {
-                const bf16x8_t b = *reinterpret_cast<const bf16x8_t*>(&ys[(sft * 16 + m) * WGM_SP + ko]);
+            for (int sft = 0; sft < 3; ++sft)
+                b[sft] = *reinterpret_cast<const bf16x8_t*>(&ys[(sft * 16 + m) * WGM_SP + ko]);
 #pragma unroll
-                for (int r = 0; r < 9; ++r) {
-                    const int t = 3 * r + sft;
-                    if ((t & 3) == wid) {
-                        const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&xs[(r * 16 + m) * WGM_SP + ko]);
-                        acc[t >> 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t >> 2], 0, 0, 0);
-                    }
+            for (int j = 0; j < 7; ++j) {
+                const int t = W + 4 * j;  // a constant once unrolled
+                if (t < 27) {
+                    const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&xs[((t / 3) * 16 + m) * WGM_SP + ko]);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[t % 3], acc[j], 0, 0, 0);
                 }
             }
         }
+    };
+    WgItem cur{};
+    if (first < last) {
+        cur = geom(first);
+        fetch(cur);
     }
-    // lane holds C[ci = 4 kg + i][co = m] of each of its taps t = wid + 4 j
+    for (int item = first; item < last; item += step) {
+        __syncthreads();  // the previous item's fragments have been read
+        stage();
+        __syncthreads();
+        const int kp = cur.kp;
+        if (item + step < last) {
+            cur = geom(item + step);
+            fetch(cur);
+        }
+        switch (wu) {
+            case 0: products.template operator()<0>(kp); break;
+            case 1: products.template operator()<1>(kp); break;
+            case 2: products.template operator()<2>(kp); break;
+            default: products.template operator()<3>(kp); break;
+        }
+    }
+    // lane holds C[ci = 4 kg + i][co = m] of each of its taps t = wu + 4 j
     float* out = partials + (size_t)blockIdx.x * 27 * CX * CY;
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
-        const int t = wid + 4 * j;
+        const int t = wu + 4 * j;
         if (t < 27) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -155,22 +226,35 @@ __global__ void __launch_bounds__(256) k_wgrad_mfma(int nx, int ny, int nz, cons
 }
 
 // grad[j] (+)= scale * sum_g partials[g][j]. A work-group owns 64 outputs;
-// thread (q, j) with q = tid / 64 sums
-// groups q, q + 4, q + 8, ... for output j in FP64, and the 4 sums are added
-// in q order, so the result does not depend on timing.
-__global__ void __launch_bounds__(256) k_reduce_partials(const float* __restrict__ partials, int ngroups, int len,
-                                                         float scale, int accumulate, float* __restrict__ grad) {
-    __shared__ double part[4][64];
+// thread (q, j) with q = tid / 64 < RP_WAVES sums groups q, q + RP_WAVES,
+// ... for output j in FP64 (four independent loads in flight), and the
+// RP_WAVES sums are added pairwise in a fixed tree, so the result does not
+// depend on timing.
+constexpr int RP_WAVES = 16;
+__global__ void __launch_bounds__(64 * RP_WAVES) k_reduce_partials(const float* __restrict__ partials, int ngroups,
+                                                                   int len, float scale, int accumulate,
+                                                                   float* __restrict__ grad) {
+    __shared__ double part[RP_WAVES][64];
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int j = blockIdx.x * 64 + lane;
-    double s = 0.0;
-    if (j < len)
-        for (int g = q; g < ngroups; g += 4) s += (double)partials[(size_t)g * len + j];
-    part[q][lane] = s;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (j < len) {
+        int g = q;
+        for (; g + 3 * RP_WAVES < ngroups; g += 4 * RP_WAVES) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s[u] += (double)partials[(size_t)(g + u * RP_WAVES) * len + j];
+        }
+        for (; g < ngroups; g += RP_WAVES) s[0] += (double)partials[(size_t)g * len + j];
+    }
+    part[q][lane] = (s[0] + s[1]) + (s[2] + s[3]);
     __syncthreads();
+#pragma unroll
+    for (int w = RP_WAVES / 2; w >= 1; w /= 2) {
+        if (q < w) part[q][lane] += part[q + w][lane];
+        __syncthreads();
+    }
     if (q == 0 && j < len) {
-        const double t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
-        const float v = (float)(t * (double)scale);
+        const float v = (float)(part[0][lane] * (double)scale);
         grad[j] = accumulate ? grad[j] + v : v;
     }
 }
@@ -217,7 +301,8 @@ __global__ void __launch_bounds__(256) k_loss_grad(int64_t n, const float* __res
 // dinv (null: the constant 1/6):
 //   u = N + dinv rh - eh                          (k_anorm_u)
 //   L = u.Au / (rh.dinv rh),  dL/dN = 2 Au / (rh.dinv rh)
-// k_anorm_sums reduces u.Au and rh.dinv rh (given Au) into loss_acc and coef.
+// k_anorm_sums reduces u.Au and the normaliser into loss_acc and coef: rh.dinv rh,
+// or (eh given) rh.eh, the error's energy e.Ae when rh = A eh.
 __global__ void __launch_bounds__(256) k_anorm_u(int64_t n, const float* __restrict__ out,
                                                  const uint16_t* __restrict__ rh, const uint16_t* __restrict__ eh,
                                                  const float* __restrict__ dinv, float* __restrict__ u) {
@@ -230,15 +315,15 @@ __global__ void __launch_bounds__(256) k_anorm_u(int64_t n, const float* __restr
 
 __global__ void __launch_bounds__(256) k_anorm_sums(int64_t n, const float* __restrict__ u,
                                                     const float* __restrict__ au, const uint16_t* __restrict__ rh,
-                                                    const float* __restrict__ dinv, double* loss_acc, double* coef,
-                                                    Red red) {
+                                                    const uint16_t* __restrict__ eh, const float* __restrict__ dinv,
+                                                    double* loss_acc, double* coef, Red red) {
     __shared__ double scratch[32];
     const int64_t stride = (int64_t)gridDim.x * 256;
     double a = 0.0, b = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
         const double r = (double)bf16v(rh[i]);
         a += (double)u[i] * (double)au[i];
-        b += (dinv ? (double)dinv[i] : 1.0 / 6.0) * r * r;
+        b += eh ? r * (double)bf16v(eh[i]) : (dinv ? (double)dinv[i] : 1.0 / 6.0) * r * r;
     }
     double v[2] = {a, b};
     block_reduce<2, 0u>(v, scratch);
@@ -320,22 +405,24 @@ hipError_t launch_make_pair(int64_t n, const double* r, const double* x, const d
 int wgrad_groups(int nx, int ny, int nz) {
     const int64_t items = (int64_t)ny * nz * ((nx + WGM_K - 1) / WGM_K);
     if (items < 64) return (int)(items < 1 ? 1 : items);
-    const int64_t g = items > 512 ? 512 : items;
+    const int64_t g = items > 768 ? 768 : items;  // three 52 KB-LDS work-groups per CU
     return (int)(g / 8 * 8);
 }
 
+// zeros: a device buffer of at least 32 zero bytes (read in place of
+// points outside the grid).
 hipError_t launch_wgrad(int nx, int ny, int nz, int cx, int cy, const void* X, const void* dY, bool dy_f32,
-                        float* partials, int groups, hipStream_t s) {
+                        const void* zeros, float* partials, int groups, hipStream_t s) {
     auto x16 = static_cast<const uint16_t*>(X);
     if (cx == 16 && cy == 16 && !dy_f32)
         hipLaunchKernelGGL((k_wgrad_mfma<16, 16, uint16_t>), dim3(groups), dim3(256), 0, s, nx, ny, nz, x16,
-                           static_cast<const uint16_t*>(dY), partials);
+                           static_cast<const uint16_t*>(dY), zeros, partials);
     else if (cx == 2 && cy == 16 && !dy_f32)
         hipLaunchKernelGGL((k_wgrad_mfma<2, 16, uint16_t>), dim3(groups), dim3(256), 0, s, nx, ny, nz, x16,
-                           static_cast<const uint16_t*>(dY), partials);
+                           static_cast<const uint16_t*>(dY), zeros, partials);
     else if (cx == 16 && cy == 1 && dy_f32)
         hipLaunchKernelGGL((k_wgrad_mfma<16, 1, float>), dim3(groups), dim3(256), 0, s, nx, ny, nz, x16,
-                           static_cast<const float*>(dY), partials);
+                           static_cast<const float*>(dY), zeros, partials);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -343,7 +430,7 @@ hipError_t launch_wgrad(int nx, int ny, int nz, int cx, int cy, const void* X, c
 
 hipError_t launch_reduce_partials(const float* partials, int groups, int len, float scale, bool accumulate,
                                   float* grad, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3((len + 63) / 64), dim3(256), 0, s, partials, groups, len, scale,
+    hipLaunchKernelGGL(k_reduce_partials, dim3((len + 63) / 64), dim3(64 * RP_WAVES), 0, s, partials, groups, len, scale,
                        accumulate ? 1 : 0, grad);
     return hipGetLastError();
 }
@@ -370,13 +457,15 @@ hipError_t launch_anorm_u(int64_t n, const float* out, const void* pair, const f
     return hipGetLastError();
 }
 
-hipError_t launch_anorm_loss(int64_t n, const float* u, const float* au, const void* rh, const float* dinv,
-                             double* loss_acc, double* coef, float* dout, void* dpack, Red red, hipStream_t s) {
+hipError_t launch_anorm_loss(int64_t n, const float* u, const float* au, const void* rh, bool energy,
+                             const float* dinv, double* loss_acc, double* coef, float* dout, void* dpack, Red red,
+                             hipStream_t s) {
     int64_t nb = (n + 1023) / 1024;
     nb = nb < 1 ? 1 : (nb > DOT_MAX_BLOCKS ? DOT_MAX_BLOCKS : nb);
     if ((size_t)2 * nb > red.cap) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_anorm_sums, dim3((unsigned)nb), dim3(256), 0, s, n, u, au,
-                       static_cast<const uint16_t*>(rh), dinv, loss_acc, coef, red);
+    auto r16 = static_cast<const uint16_t*>(rh);
+    hipLaunchKernelGGL(k_anorm_sums, dim3((unsigned)nb), dim3(256), 0, s, n, u, au, r16, energy ? r16 + n : nullptr,
+                       dinv, loss_acc, coef, red);
     hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, s, red.partials, (unsigned)nb, loss_acc, coef);
     hipLaunchKernelGGL(k_scale_grad, dim3((unsigned)nb), dim3(256), 0, s, n, au, coef, dout,
                        static_cast<uint32_t*>(dpack));

@@ -33,6 +33,11 @@ struct SolveState {
 };
 // FLEX_MG: the preconditioned residual z is the multigrid V-cycle's, taken as it is.
 constexpr int FLEX_JACOBI = 1, FLEX_RESTART = 2, FLEX_REDO = 4, FLEX_MG = 8;
+// Flexible CG falls back to Jacobi when the best residual has not improved
+// by 10% for this many iterations. CG plateaus on the 128^3
+// variable-coefficient operator outlast 20 iterations even with plain
+// Jacobi (measured), so the window is the one refinement's inner stop uses.
+constexpr int FLEX_STAG_WINDOW = 100;
 
 // ---------------------------------------------------------------- loaders
 // A loader provides Raw<N> (registers of one fetch of N consecutive points),

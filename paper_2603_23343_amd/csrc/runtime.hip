@@ -1046,7 +1046,7 @@ static pcg_status flex_solve(pcg_ctx c, cnn_net net, bool mg, const float* g, co
         init.tol2 = rtol * rtol;
         init.dinv = 1.0 / 6.0;
         init.maxit = seg_maxit;
-        init.stag = 20;
+        init.stag = FLEX_STAG_WINDOW;
         init.flags = FLEX_RESTART | (net || mg ? 0 : FLEX_JACOBI) | (mg ? FLEX_MG : 0);
         init.fallback_at = -1;
         c->hst[0] = init;

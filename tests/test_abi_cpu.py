@@ -134,3 +134,5 @@ def test_sell_argument_validation_without_gpu(lib):
     assert lib.pcg_sell_set_restarts(None, 0) == 1
     lib.pcg_sell_destroy.argtypes = [vp]
     assert lib.pcg_sell_destroy(None) == 0
+    lib.cnn_set_loss_norm.argtypes = [vp, i]
+    assert lib.cnn_set_loss_norm(None, 0) == 1

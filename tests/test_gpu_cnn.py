@@ -215,11 +215,12 @@ def test_loss_and_gradients(P, orc, shape, batch):
         assert rel <= 1e-2
 
 
-@pytest.mark.parametrize("var", [False, True])
-def test_anorm_loss_and_gradients(P, orc, var):
+@pytest.mark.parametrize("var,energy", [(False, False), (True, False), (True, True)])
+def test_anorm_loss_and_gradients(P, orc, var, energy):
     """A-norm loss of the Jacobi-plus-correction preconditioner (operator from
     an F32 context) against the oracle's anorm_loss with the GPU's BF16
-    roundings emulated; same bars as the relative-MSE test."""
+    roundings emulated, with either normaliser; same bars as the
+    relative-MSE test."""
     shape = (10, 9, 12)
     nz, ny, nx = shape
     n = int(np.prod(shape))
@@ -229,8 +230,11 @@ def test_anorm_loss_and_gradients(P, orc, var):
     k32 = synthetic.coefficient_field(12)[:n].copy() if var else None
     pairs = []
     for b in range(batch):
-        pairs += [synthetic.f32_to_bf16_bits(synthetic.uniform_f32(52 + b, n)),
-                  synthetic.f32_to_bf16_bits(synthetic.uniform_f32(62 + b, n))]
+        rr = synthetic.uniform_f32(52 + b, n)
+        ee = synthetic.uniform_f32(62 + b, n)
+        if energy:
+            ee = (np.abs(ee) * np.sign(rr)).astype(np.float32)  # rh.eh > 0
+        pairs += [synthetic.f32_to_bf16_bits(rr), synthetic.f32_to_bf16_bits(ee)]
     from gpu_helpers import bf16_tensor
 
     ctx = P.pcg_create(nx, ny, nz, torch.float32)
@@ -239,6 +243,7 @@ def test_anorm_loss_and_gradients(P, orc, var):
     net = P.cnn_create()
     P.cnn_set_weights(net, torch.from_numpy(_flat(ws)).cuda())
     P.cnn_set_operator(net, ctx)
+    P.cnn_set_loss_norm(net, 1 if energy else 0)
     grad = torch.zeros(P.cnn_num_weights(), dtype=torch.float32, device="cuda")
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     P.cnn_loss_grad(net, shape, bf16_tensor(np.concatenate(pairs)).cuda(), torch.from_numpy(g).cuda(), batch,
@@ -250,7 +255,7 @@ def test_anorm_loss_and_gradients(P, orc, var):
         eh = synthetic.bf16_bits_to_f32(pairs[2 * b + 1]).astype(np.float64)
         inp = np.stack([rh.reshape(shape), g.astype(np.float64).reshape(shape)], axis=-1)
         out, acts, wb = _fwd_emulated(orc, ws, inp)
-        l, dl = orc.anorm_loss([out.reshape(-1)], [rh], [eh], shape, kcell=k64)
+        l, dl = orc.anorm_loss([out.reshape(-1)], [rh], [eh], shape, kcell=k64, energy=energy)
         ref_loss += l / batch
         gr = _bwd_emulated(orc, wb, acts, dl[0].reshape(*shape, 1))
         for i in range(4):

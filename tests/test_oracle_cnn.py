@@ -180,16 +180,35 @@ def test_anorm_loss_eigenvector_closed_form(orc, mode):
     assert abs(loss - (lam - 6.0) ** 2 / (6.0 * lam)) <= 1e-12 * max(1.0, loss)
 
 
-def test_anorm_loss_gradient_finite_differences(orc):
+@pytest.mark.parametrize("mode", [(1, 1, 1), (2, 3, 1), (4, 5, 6)])
+def test_anorm_loss_energy_eigenvector_closed_form(orc, mode):
+    """The energy normaliser on the same eigenvector pair: den = rh.eh =
+    lambda |v|^2 and u.Au = (lambda/6 - 1)^2 lambda |v|^2, so L = (1 - lambda/6)^2;
+    it also equals the relative A-norm error u.Au / eh.A eh."""
+    nz, ny, nx = 6, 7, 8
+    a, b, c = mode
+    v = synthetic.sine_mode(nx, ny, nz, a, b, c)
+    lam = 6.0 - 2 * np.cos(a * np.pi / (nx + 1)) - 2 * np.cos(b * np.pi / (ny + 1)) - 2 * np.cos(c * np.pi / (nz + 1))
+    loss, _ = orc.anorm_loss([np.zeros(v.size)], [lam * v], [v], (nz, ny, nx), energy=True)
+    assert abs(loss - (1.0 - lam / 6.0) ** 2) <= 1e-12 * max(1.0, loss)
+    u = v / 6.0 * lam - v
+    ref = float(np.dot(u, orc.stencil(u, (nz, ny, nx)))) / float(np.dot(v, orc.stencil(v, (nz, ny, nx))))
+    assert abs(loss - ref) <= 1e-12 * max(1.0, loss)
+
+
+@pytest.mark.parametrize("energy", [False, True])
+def test_anorm_loss_gradient_finite_differences(orc, energy):
     shape = (3, 4, 5)
     n = 60
     k = np.exp(synthetic.uniform(21, n))
     rh, eh, p = synthetic.uniform(22, n), synthetic.uniform(23, n), synthetic.uniform(24, n)
-    _, g = orc.anorm_loss([p], [rh], [eh], shape, kcell=k)
+    if energy:
+        eh = np.abs(eh) * np.sign(rh)  # rh.eh > 0
+    _, g = orc.anorm_loss([p], [rh], [eh], shape, kcell=k, energy=energy)
     h = 1e-6
     for j in (0, 7, 31, 59):
         dp = np.zeros(n)
         dp[j] = h
-        lp, _ = orc.anorm_loss([p + dp], [rh], [eh], shape, kcell=k)
-        lm, _ = orc.anorm_loss([p - dp], [rh], [eh], shape, kcell=k)
+        lp, _ = orc.anorm_loss([p + dp], [rh], [eh], shape, kcell=k, energy=energy)
+        lm, _ = orc.anorm_loss([p - dp], [rh], [eh], shape, kcell=k, energy=energy)
         assert abs((lp - lm) / (2 * h) - g[0][j]) <= 1e-6 * max(1.0, abs(g[0][j]))
