@@ -86,7 +86,11 @@ __global__ void __launch_bounds__(CONV_NT) k_conv3d(Dims d, int nbx, int nby, co
                                                     double scale_mul) {
     constexpr int NCH = ConvK<CIN>::CHUNKS;
     constexpr int VB = CIN * 2;  // bytes per staged voxel (32 or 4)
-    __shared__ __attribute__((aligned(16))) unsigned char halo[CH_VOX * VB];
+    // CIN = 16: two planes of 16-byte channel halves, the second 17408 bytes
+    // in (a multiple of 256): measured on MI355X, with the planes 17280 bytes
+    // apart each of the products' ds_read_b128 took 1.6x as long (bank conflicts)
+    constexpr int HPLANE = CH_VOX * 16 + 128;
+    __shared__ __attribute__((aligned(16))) unsigned char halo[CIN == 16 ? 2 * HPLANE : CH_VOX * VB];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     // XCD-aware order: work-group b runs on XCD b mod 8, so with a grid that
     // is a multiple of 8 each XCD takes a contiguous range of blocks, whose
@@ -148,7 +152,7 @@ __global__ void __launch_bounds__(CONV_NT) k_conv3d(Dims d, int nbx, int nby, co
                 // channel halves in separate planes: a wavefront's 16 lanes of
                 // one half read 16 consecutive 16-byte slots
                 if (lane < 2 * CH_X)
-                    *reinterpret_cast<uint4*>(halo + (size_t)half * (CH_VOX * 16) + (size_t)(r * CH_X + hx) * 16) =
+                    *reinterpret_cast<uint4*>(halo + (size_t)half * HPLANE + (size_t)(r * CH_X + hx) * 16) =
                         ok[j] ? v[j] : make_uint4(0, 0, 0, 0);
             }
         };
@@ -186,7 +190,7 @@ __global__ void __launch_bounds__(CONV_NT) k_conv3d(Dims d, int nbx, int nby, co
     for (int tt = 0; tt < CB_TILES; ++tt) acc[tt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     if constexpr (CIN == 16) {
         // lanes 0-31 take tap 2c, lanes 32-63 tap 2c + 1; channels 0-7 / 8-15 by (kgrp & 1)
-        const unsigned char* hb = halo + (size_t)(kgrp & 1) * (CH_VOX * 16) + (size_t)(wid * CH_X + row) * 16;
+        const unsigned char* hb = halo + (size_t)(kgrp & 1) * HPLANE + (size_t)(wid * CH_X + row) * 16;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const unsigned char* hc = hb + (size_t)((kgrp >> 1) ? tap_off(2 * c + 1) : tap_off(2 * c)) * 16;
