@@ -195,18 +195,20 @@ void free_ctx(pcg_ctx c) {
 }
 
 // Default plan (measured on MI355X with the split reductions): when the x-y
-// plane is small (<= 65536 points, e.g. 256^3) a footprint 128 points wide
-// (FP32 128 x 8, 16-bit 128 x 16, FP64 128 x 4) with 32-plane chunks (8 for
-// 16-bit storage); on
-// larger planes 256 x 4 FP32 / 128 x 16 16-bit / 128 x 4 FP64 footprints
-// with 16-plane chunks; chunks halved while the launch has fewer than 256
-// work-groups; the scalar shape when nx is not a multiple of the 16-byte
-// vector width.
+// plane is small (<= 65536 points, e.g. 256^3) FP32 128 x 8 and FP64 128 x 4
+// footprints with 32-plane chunks, 16-bit 256 x 8 with 16-plane chunks; on
+// larger planes 256 x 4 FP32 / 512 x 4 16-bit / 128 x 4 FP64 footprints
+// with 16-plane chunks (8 for 16-bit); chunks halved while the launch has
+// fewer than 256 work-groups; the scalar shape when nx is not a multiple of
+// the 16-byte vector width. 16-bit sweeps: the BF16 refinement's inner
+// iteration at 256^3 ran at 5.15 TB/s with 256 x 8 / 16 planes against 4.86
+// with 128 x 16 / 8 planes (18 plans, 4.04-5.15); the 512^3 BF16 stencil took
+// 77.5 us with 512 x 4 / 8 planes against 85.1 with 128 x 16 / 16.
 Plan default_plan(int nx, int ny, int nz, int dt, const pcg_options& o) {
     const bool small_plane = (int64_t)nx * ny <= 65536;
     const int w = dt_width(dt);  // 4 FP32, 8 16-bit, 2 FP64
-    Plan p{2, small_plane ? (w == 8 ? 8 : 32) : 16};
-    if (w == 8) p.cfg = 0;                       // 16 x 16 threads: 128 x 16 points
+    Plan p{2, small_plane ? (w == 8 ? 16 : 32) : (w == 8 ? 8 : 16)};
+    if (w == 8 && small_plane) p.cfg = 1;        // 32 x 8 threads: 256 x 8 points
     else if (w == 4 && small_plane) p.cfg = 1;   // 32 x 8 threads: 128 x 8 points
     // narrower vector shapes while the footprint is wider than nx
     if (plan_tx(p, dt) > nx && p.cfg == 2) p.cfg = 1;
