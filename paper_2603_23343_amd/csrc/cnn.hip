@@ -20,15 +20,16 @@
 // 2-channel) pairs. Taps beyond 27 have zero weights; neighbours outside the
 // grid are staged as zero. Weights are pre-swizzled into exactly the A lane
 // layout, so each lane reads its 16 bytes per chunk with one load and keeps
-// all chunks in registers. A work-group owns a 16 x 8 x 4 block of output
-// voxels: it stages the block's input with its one-voxel halo (18 x 10 x 6
-// voxels) in LDS once, so every input voxel crosses L2 about twice instead of
-// 27 times, and each wavefront computes 8 tiles of 16 voxels (x-rows of the
-// block) from LDS. Each lane stores its voxel's 4 channels (8 bytes), so a
-// tile's 16 voxels x 16 channels leave as 512 contiguous bytes.
+// all chunks in registers. The 16-channel input layers march up z
+// (k_conv3d_z): a work-group owns a 16 x 8 footprint and a chunk of planes and
+// keeps a ring of input planes with their x/y halo in LDS, so each input
+// plane is staged once per chunk. The 2-channel input layer stages a
+// 16 x 8 x 4 output block with its one-voxel halo (18 x 10 x 6 voxels) per
+// work-group (k_conv3d). Each lane stores its voxel's 4 channels (8 bytes),
+// so a tile's 16 voxels x 16 channels leave as 512 contiguous bytes.
 //
 // The transposed convolution of the backward pass (input gradient) is the
-// same kernel with the taps mirrored and Cin/Cout swapped in the swizzle.
+// same kernels with the taps mirrored and Cin/Cout swapped in the swizzle.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -78,19 +79,16 @@ constexpr int CH_VOX = CH_X * CH_Y * CH_Z;
 constexpr int CB_ROWS = CB_Y * CB_Z;                 // 16-voxel x-rows (tiles) per block
 constexpr int CB_TILES = CB_ROWS / CONV_WAVES;       // tiles per wavefront
 
+// The 2-channel input layer: one 16 x 8 x 4 block of outputs per work-group.
 // in: [nvox][CIN] bf16 bits. wsw: [CHUNKS][64 lanes][8] bf16 bits (the A operand).
 template <int CIN, int MODE>
 __global__ void __launch_bounds__(CONV_NT) k_conv3d(Dims d, int nbx, int nby, const uint16_t* __restrict__ in,
                                                     const uint16_t* __restrict__ wsw, void* __restrict__ out,
                                                     const uint16_t* __restrict__ mask, const double* scale_rms2,
                                                     double scale_mul) {
+    static_assert(CIN == 2, "the 16-channel input layers run k_conv3d_z");
     constexpr int NCH = ConvK<CIN>::CHUNKS;
-    constexpr int VB = CIN * 2;  // bytes per staged voxel (32 or 4)
-    // CIN = 16: two planes of 16-byte channel halves, the second 17408 bytes
-    // in (a multiple of 256): measured on MI355X, with the planes 17280 bytes
-    // apart each of the products' ds_read_b128 took 1.6x as long (bank conflicts)
-    constexpr int HPLANE = CH_VOX * 16 + 128;
-    __shared__ __attribute__((aligned(16))) unsigned char halo[CIN == 16 ? 2 * HPLANE : CH_VOX * VB];
+    __shared__ __attribute__((aligned(16))) unsigned char halo[CH_VOX * 4];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     // XCD-aware order: work-group b runs on XCD b mod 8, so with a grid that
     // is a multiple of 8 each XCD takes a contiguous range of blocks, whose
@@ -122,56 +120,18 @@ __global__ void __launch_bounds__(CONV_NT) k_conv3d(Dims d, int nbx, int nby, co
         const int vox = (gz * d.ny + gy) * d.nx + gx;
         return ok ? vox : 0;
     };
-    if constexpr (CIN == 16) {
-        // Wavefront w stages halo rows w, w + 4, ...: a row is 18 voxels x 32
-        // bytes, contiguous in memory, loaded by lanes 0-35 (16 bytes each);
-        // the row's coordinates are wave-uniform, so each load costs a few
-        // vector instructions.
-        constexpr int RPW = CH_Y * CH_Z / CONV_WAVES;
-        static_assert(RPW * CONV_WAVES == CH_Y * CH_Z, "halo rows per wavefront");
-        const int wu = __builtin_amdgcn_readfirstlane(wid);
-        const int hx = lane >> 1, half = lane & 1, gx = x0 + hx - 1;
-        const bool xok = lane < 2 * CH_X && (unsigned)gx < (unsigned)d.nx;
-        // two batches of rows keep the staging registers below the compute's
-        constexpr int B1 = (RPW + 1) / 2;
-        auto stage_rows = [&](auto first, auto count) {
-            constexpr int J0 = decltype(first)::value, NJ = decltype(count)::value;
-            uint4 v[NJ];
-            bool ok[NJ];
+    constexpr int NP = (CH_VOX + CONV_NT - 1) / CONV_NT;
+    uint32_t v[NP];
+    bool ok[NP];
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                const int r = wu + CONV_WAVES * (J0 + j), hy = r % CH_Y, hz = r / CH_Y;
-                const int gy = y0 + hy - 1, gz = z0 + hz - 1;
-                ok[j] = xok & ((unsigned)gy < (unsigned)d.ny) & ((unsigned)gz < (unsigned)d.nz);
-                const int vox = ok[j] ? (gz * d.ny + gy) * d.nx + gx : 0;
-                v[j] = *reinterpret_cast<const uint4*>(in + (size_t)vox * 16 + 8 * half);
-            }
+    for (int j = 0; j < NP; ++j) {
+        const int vox = halo_voxel(tid + j * CONV_NT, ok[j]);
+        v[j] = *reinterpret_cast<const uint32_t*>(in + (size_t)vox * 2);
+    }
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                const int r = wu + CONV_WAVES * (J0 + j);
-                // channel halves in separate planes: a wavefront's 16 lanes of
-                // one half read 16 consecutive 16-byte slots
-                if (lane < 2 * CH_X)
-                    *reinterpret_cast<uint4*>(halo + (size_t)half * HPLANE + (size_t)(r * CH_X + hx) * 16) =
-                        ok[j] ? v[j] : make_uint4(0, 0, 0, 0);
-            }
-        };
-        stage_rows(std::integral_constant<int, 0>{}, std::integral_constant<int, B1>{});
-        stage_rows(std::integral_constant<int, B1>{}, std::integral_constant<int, RPW - B1>{});
-    } else {
-        constexpr int NP = (CH_VOX + CONV_NT - 1) / CONV_NT;
-        uint32_t v[NP];
-        bool ok[NP];
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-            const int vox = halo_voxel(tid + j * CONV_NT, ok[j]);
-            v[j] = *reinterpret_cast<const uint32_t*>(in + (size_t)vox * 2);
-        }
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-            const int h = tid + j * CONV_NT;
-            if (h < CH_VOX) *reinterpret_cast<uint32_t*>(halo + (size_t)h * 4) = ok[j] ? v[j] : 0u;
-        }
+    for (int j = 0; j < NP; ++j) {
+        const int h = tid + j * CONV_NT;
+        if (h < CH_VOX) *reinterpret_cast<uint32_t*>(halo + (size_t)h * 4) = ok[j] ? v[j] : 0u;
     }
 
     __syncthreads();
@@ -188,37 +148,23 @@ __global__ void __launch_bounds__(CONV_NT) k_conv3d(Dims d, int nbx, int nby, co
     f32x4_t acc[CB_TILES];
 #pragma unroll
     for (int tt = 0; tt < CB_TILES; ++tt) acc[tt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    if constexpr (CIN == 16) {
-        // lanes 0-31 take tap 2c, lanes 32-63 tap 2c + 1; channels 0-7 / 8-15 by (kgrp & 1)
-        const unsigned char* hb = halo + (size_t)(kgrp & 1) * HPLANE + (size_t)(wid * CH_X + row) * 16;
+    // k = 2 tap + channel; the lane's 8 values: taps 16 c + 4 kgrp + (0..3), 2 channels each
+    const unsigned char* hb = halo + (size_t)(wid * CH_X + row) * 4;
+    int toff[NCH][4];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            const unsigned char* hc = hb + (size_t)((kgrp >> 1) ? tap_off(2 * c + 1) : tap_off(2 * c)) * 16;
+    for (int c = 0; c < NCH; ++c)
 #pragma unroll
-            for (int tt = 0; tt < CB_TILES; ++tt) {
-                const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(hc + (size_t)tile_off(tt) * 16);
-                acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], a, acc[tt], 0, 0, 0);
-            }
-        }
-    } else {
-        // k = 2 tap + channel; the lane's 8 values: taps 16 c + 4 kgrp + (0..3), 2 channels each
-        const unsigned char* hb = halo + (size_t)(wid * CH_X + row) * 4;
-        int toff[NCH][4];
+        for (int qq = 0; qq < 4; ++qq) toff[c][qq] = tap_off(16 * c + 4 * kgrp + qq);
 #pragma unroll
-        for (int c = 0; c < NCH; ++c)
+    for (int c = 0; c < NCH; ++c) {
 #pragma unroll
-            for (int qq = 0; qq < 4; ++qq) toff[c][qq] = tap_off(16 * c + 4 * kgrp + qq);
+        for (int tt = 0; tt < CB_TILES; ++tt) {
+            uint32_t w[4];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-#pragma unroll
-            for (int tt = 0; tt < CB_TILES; ++tt) {
-                uint32_t w[4];
-#pragma unroll
-                for (int qq = 0; qq < 4; ++qq)
-                    w[qq] = *reinterpret_cast<const uint32_t*>(hb + (size_t)(tile_off(tt) + toff[c][qq]) * 4);
-                const bf16x8_t a = __builtin_bit_cast(bf16x8_t, make_uint4(w[0], w[1], w[2], w[3]));
-                acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], a, acc[tt], 0, 0, 0);
-            }
+            for (int qq = 0; qq < 4; ++qq)
+                w[qq] = *reinterpret_cast<const uint32_t*>(hb + (size_t)(tile_off(tt) + toff[c][qq]) * 4);
+            const bf16x8_t a = __builtin_bit_cast(bf16x8_t, make_uint4(w[0], w[1], w[2], w[3]));
+            acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], a, acc[tt], 0, 0, 0);
         }
     }
 
@@ -253,6 +199,150 @@ __global__ void __launch_bounds__(CONV_NT) k_conv3d(Dims d, int nbx, int nby, co
             const uint2 o = make_uint2(pack_bf16x2(val[0], val[1]), pack_bf16x2(val[2], val[3]));
             *reinterpret_cast<uint2*>(static_cast<uint16_t*>(out) + v * 16 + 4 * kgrp) = o;
         }
+    }
+}
+
+// 16-channel input, marching up z. A work-group owns a 16 x 8 footprint of
+// output voxels and a chunk of ZC_CONV output planes; it keeps the input
+// planes z - 1, z, z + 1 (with their one-voxel x/y halo, 18 x 10 voxels) in a
+// ring of four LDS plane slots, so each input plane is staged once per chunk
+// instead of once per 4-plane block (a block per work-group, as the 2-channel
+// kernel above, read 2.5x its input through the fabric: 18 x 10 x 6 halo
+// voxels per 16 x 8 x 4 outputs; 44 -> 34 us per 16 -> 16 layer at 128^3).
+// The slots' channel halves sit 3072 bytes apart (a multiple of 256): with
+// halves 17280 bytes apart the products' ds_read_b128 took 1.6x as long
+// (bank conflicts, measured).
+// Step z computes output plane z from the three resident slots while plane
+// z + 3 is loaded into one register set; the other set (plane z + 2, loaded
+// during step z - 1) goes into the slot plane z - 2 used, then one barrier.
+// (With one plane of look-ahead each step waited for its plane's load: the
+// step's products are shorter than a load's latency.) Wavefront w computes
+// the plane's x-rows w and w + 4.
+// Same operand layout, epilogues and results as k_conv3d<16, MODE>.
+constexpr int ZC_CONV = 16;
+constexpr int ZS_HALF = 3072;           // one channel half of a plane slot: 18 x 10 x 16 bytes, padded to 256 B
+constexpr int ZS_SLOT = 2 * ZS_HALF;    // a plane slot: both halves
+
+template <int MODE>
+__global__ void __launch_bounds__(CONV_NT, 4) k_conv3d_z(Dims d, int nbx, int nby, const uint16_t* __restrict__ in,
+                                                      const uint16_t* __restrict__ wsw, void* __restrict__ out,
+                                                      const uint16_t* __restrict__ mask, const double* scale_rms2,
+                                                      double scale_mul) {
+    constexpr int NCH = ConvK<16>::CHUNKS;
+    static_assert(CH_X * CH_Y * 16 <= ZS_HALF && ZS_HALF % 256 == 0, "plane slot layout");
+    __shared__ __attribute__((aligned(16))) unsigned char slots[4 * ZS_SLOT];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const unsigned nblk = gridDim.x;
+    const unsigned lb = nblk % 8 == 0 ? (blockIdx.x % 8) * (nblk / 8) + blockIdx.x / 8 : blockIdx.x;
+    const int bx = (int)(lb % nbx), by = (int)((lb / nbx) % nby), bz = (int)(lb / (nbx * nby));
+    const int x0 = bx * CB_X, y0 = by * CB_Y, z0 = bz * ZC_CONV;
+    const int z1 = min(z0 + ZC_CONV, d.nz);
+
+    bf16x8_t bw[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) bw[c] = *reinterpret_cast<const bf16x8_t*>(wsw + ((size_t)c * 64 + lane) * 8);
+
+    // Plane staging: wavefront w takes halo rows w, w + 4, w + 8 (< 10) of a
+    // plane; lanes 0-35 load one 16-byte channel half each (the row is 18
+    // voxels x 32 bytes, contiguous). Points outside the grid load voxel 0
+    // and are stored as zero.
+    const int hx = lane >> 1, half = lane & 1, gx = x0 + hx - 1;
+    const bool xok = lane < 2 * CH_X && (unsigned)gx < (unsigned)d.nx;
+    constexpr int RPW = (CH_Y + CONV_WAVES - 1) / CONV_WAVES;  // 3
+    struct PlaneRegs {
+        uint4 v[RPW];
+        bool ok[RPW];
+    };
+    auto fetch_plane = [&](int gz, PlaneRegs& pr) {
+#pragma unroll
+        for (int j = 0; j < RPW; ++j) {
+            const int r = wu + CONV_WAVES * j, gy = y0 + r - 1;
+            pr.ok[j] = xok & (r < CH_Y) & ((unsigned)gy < (unsigned)d.ny) & ((unsigned)gz < (unsigned)d.nz);
+            const int vox = pr.ok[j] ? (gz * d.ny + gy) * d.nx + gx : 0;
+            pr.v[j] = *reinterpret_cast<const uint4*>(in + (size_t)vox * 16 + 8 * half);
+        }
+    };
+    auto store_plane = [&](int slot, const PlaneRegs& pr) {
+        unsigned char* base = slots + (size_t)slot * ZS_SLOT + (size_t)half * ZS_HALF;
+#pragma unroll
+        for (int j = 0; j < RPW; ++j) {
+            const int r = wu + CONV_WAVES * j;
+            if (lane < 2 * CH_X && r < CH_Y)
+                *reinterpret_cast<uint4*>(base + (size_t)(r * CH_X + hx) * 16) =
+                    pr.ok[j] ? pr.v[j] : make_uint4(0, 0, 0, 0);
+        }
+    };
+    // prologue: planes z0 - 1, z0, z0 + 1 into slots (plane + 4) % 4, plane
+    // z0 + 2 into register set A
+    PlaneRegs ra, rb;
+    fetch_plane(z0 - 1, ra);
+    fetch_plane(z0, rb);
+    store_plane((z0 + 3) & 3, ra);
+    store_plane(z0 & 3, rb);
+    fetch_plane(z0 + 1, ra);
+    store_plane((z0 + 1) & 3, ra);
+    fetch_plane(z0 + 2, ra);
+    __syncthreads();
+
+    const int row = lane & 15, kgrp = lane >> 4;
+    // the lane's channel half and x-row of the tiles: rows wu and wu + 4
+    const int lane_off = (kgrp & 1) * ZS_HALF + (wu * CH_X + row) * 16;
+    // per chunk, the lane's tap (2c or 2c + 1): its plane (dz) and in-plane offset
+    auto tap_dz = [](int t) { return t < 27 ? t / 9 : 1; };
+    auto tap_in = [](int t) { return t < 27 ? (((t / 3) % 3) * CH_X + t % 3) * 16 : 0; };
+    float scale = 0.f;
+    if constexpr (MODE == OUT_SCALED_F32) scale = (float)(scale_rms2 ? sqrt(*scale_rms2) * scale_mul : scale_mul);
+    // step z: load plane z + 3 into `ld` (in flight during the products),
+    // store plane z + 2 from `st`
+    auto step = [&](int z, PlaneRegs& ld, const PlaneRegs& st) {
+        if (z + 3 <= z1) fetch_plane(z + 3, ld);
+        // slot offsets of planes z - 1, z, z + 1
+        const int so[3] = {((z + 3) & 3) * ZS_SLOT, (z & 3) * ZS_SLOT, ((z + 1) & 3) * ZS_SLOT};
+        f32x4_t acc[2] = {f32x4_t{0.f, 0.f, 0.f, 0.f}, f32x4_t{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int ta = 2 * c, tb = 2 * c + 1;
+            const int off = (kgrp >> 1) ? so[tap_dz(tb)] + tap_in(tb) : so[tap_dz(ta)] + tap_in(ta);
+            const unsigned char* pa = slots + lane_off + off;
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(pa + tt * 4 * CH_X * 16);
+                acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], a, acc[tt], 0, 0, 0);
+            }
+        }
+        // results of plane z: lane (kgrp, row) holds channels 4 kgrp .. + 3 of voxel `row`
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            const int gy = y0 + wu + 4 * tt, gxo = x0 + row;
+            if (gy >= d.ny || gxo >= d.nx) continue;
+            const size_t v = (size_t)((z * d.ny + gy) * d.nx) + gxo;
+            if constexpr (MODE == OUT_SCALED_F32) {
+                if (kgrp == 0) static_cast<float*>(out)[v] = scale * acc[tt][0];
+            } else {
+                float val[4];
+                uint2 m = make_uint2(0u, 0u);
+                if constexpr (MODE == OUT_MASK_BF16) m = *reinterpret_cast<const uint2*>(mask + v * 16 + 4 * kgrp);
+                const uint32_t mw[2] = {m.x, m.y};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    val[i] = acc[tt][i];
+                    if constexpr (MODE == OUT_RELU_BF16) val[i] = val[i] > 0.f ? val[i] : 0.f;
+                    if constexpr (MODE == OUT_MASK_BF16)
+                        val[i] = bf16_val((uint16_t)((i & 1) ? mw[i >> 1] >> 16 : mw[i >> 1] & 0xffffu)) > 0.f ? val[i] : 0.f;
+                }
+                *reinterpret_cast<uint2*>(static_cast<uint16_t*>(out) + v * 16 + 4 * kgrp) =
+                    make_uint2(pack_bf16x2(val[0], val[1]), pack_bf16x2(val[2], val[3]));
+            }
+        }
+        // plane z + 2 goes into the slot plane z - 2 used (read by no one at
+        // step z: the last reads of it were at step z - 1, before its barrier)
+        if (z + 2 <= z1) store_plane((z + 2) & 3, st);
+        __syncthreads();
+    };
+    for (int z = z0; z < z1; z += 2) {
+        step(z, rb, ra);
+        if (z + 1 < z1) step(z + 1, ra, rb);
     }
 }
 
@@ -319,12 +409,16 @@ hipError_t launch_conv3d(int nx, int ny, int nz, int cin, int mode, const void* 
 #define PCGMI_CONV(CI, MO) \
     hipLaunchKernelGGL((k_conv3d<CI, MO>), dim3((unsigned)nb), dim3(CONV_NT), 0, s, d, nbx, nby, in16, w16, out, m16, \
                        scale_rms2, scale_mul)
+#define PCGMI_CONVZ(MO) \
+    hipLaunchKernelGGL((k_conv3d_z<MO>), dim3((unsigned)nbzm), dim3(CONV_NT), 0, s, d, nbx, nby, in16, w16, out, m16, \
+                       scale_rms2, scale_mul)
     if (cin == 16) {
+        const int64_t nbzm = (int64_t)nbx * nby * ((nz + ZC_CONV - 1) / ZC_CONV);
         switch (mode) {
-            case OUT_RELU_BF16: PCGMI_CONV(16, OUT_RELU_BF16); break;
-            case OUT_SCALED_F32: PCGMI_CONV(16, OUT_SCALED_F32); break;
-            case OUT_MASK_BF16: PCGMI_CONV(16, OUT_MASK_BF16); break;
-            case OUT_LINEAR_BF16: PCGMI_CONV(16, OUT_LINEAR_BF16); break;
+            case OUT_RELU_BF16: PCGMI_CONVZ(OUT_RELU_BF16); break;
+            case OUT_SCALED_F32: PCGMI_CONVZ(OUT_SCALED_F32); break;
+            case OUT_MASK_BF16: PCGMI_CONVZ(OUT_MASK_BF16); break;
+            case OUT_LINEAR_BF16: PCGMI_CONVZ(OUT_LINEAR_BF16); break;
             default: return hipErrorInvalidValue;
         }
     } else if (cin == 2) {
@@ -339,6 +433,7 @@ hipError_t launch_conv3d(int nx, int ny, int nz, int cin, int mode, const void* 
         return hipErrorInvalidValue;
     }
 #undef PCGMI_CONV
+#undef PCGMI_CONVZ
     return hipGetLastError();
 }
 
