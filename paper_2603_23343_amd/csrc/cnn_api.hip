@@ -17,7 +17,9 @@ using namespace pcgmi;
 
 namespace pcgmi {
 hipError_t launch_conv3d(int nx, int ny, int nz, int cin, int mode, const void* in, const void* wsw, void* out,
-                         const void* mask, const double* scale_rms2, double scale_mul, hipStream_t s);
+                         const void* mask, const double* scale_rms2, double scale_mul, const void* zeros, hipStream_t s);
+hipError_t launch_conv3d_input(int nx, int ny, int nz, int dt, const void* r, const float* g, const double* rr,
+                               const void* wsw, void* out, hipStream_t s);
 hipError_t launch_pack_input(int dt, int64_t n, const void* r, const float* g, const double* rr, void* out,
                              hipStream_t s);
 hipError_t launch_swizzle_weights(const float* w, int cin, int cout, int CIN, int mirror, void* out, hipStream_t s);
@@ -149,15 +151,17 @@ pcg_status ensure_swizzled(cnn_net n) {
     return PCG_OK;
 }
 
-// Forward through the four layers from n->in0; last layer writes `out` scaled
-// by sqrt(*rr) * mul (or mul when rr is null).
-pcg_status forward(cnn_net n, float* out, const double* rr, double mul) {
+// Forward through the four layers from n->in0 (or, with first_done, from
+// layer 1's output already in n->h1); the last layer writes `out` scaled by
+// sqrt(*rr) * mul (or mul when rr is null).
+pcg_status forward(cnn_net n, float* out, const double* rr, double mul, bool first_done = false) {
     const int X = n->nx, Y = n->ny, Z = n->nz;
     hipStream_t s = n->stream;
-    CHK(launch_conv3d(X, Y, Z, 2, OUT_RELU, n->in0, n->wf[0], n->h1, nullptr, nullptr, 1.0, s));
-    CHK(launch_conv3d(X, Y, Z, 16, OUT_RELU, n->h1, n->wf[1], n->h2, nullptr, nullptr, 1.0, s));
-    CHK(launch_conv3d(X, Y, Z, 16, OUT_RELU, n->h2, n->wf[2], n->h3, nullptr, nullptr, 1.0, s));
-    CHK(launch_conv3d(X, Y, Z, 16, OUT_SCALED, n->h3, n->wf[3], out, nullptr, rr, mul, s));
+    if (!first_done)
+        CHK(launch_conv3d(X, Y, Z, 2, OUT_RELU, n->in0, n->wf[0], n->h1, nullptr, nullptr, 1.0, n->zeros, s));
+    CHK(launch_conv3d(X, Y, Z, 16, OUT_RELU, n->h1, n->wf[1], n->h2, nullptr, nullptr, 1.0, n->zeros, s));
+    CHK(launch_conv3d(X, Y, Z, 16, OUT_RELU, n->h2, n->wf[2], n->h3, nullptr, nullptr, 1.0, n->zeros, s));
+    CHK(launch_conv3d(X, Y, Z, 16, OUT_SCALED, n->h3, n->wf[3], out, nullptr, rr, mul, n->zeros, s));
     return PCG_OK;
 }
 
@@ -263,8 +267,9 @@ pcg_status cnn_forward(cnn_net n, int nx, int ny, int nz, pcg_dtype rdt, const v
     if (st != PCG_OK) return st;
     st = ensure_swizzled(n);
     if (st != PCG_OK) return st;
-    CHK(launch_pack_input(rdt, n->nvox, r, g, rr_dev, n->in0, n->stream));
-    return forward(n, z, rr_dev, rr_dev ? 1.0 / std::sqrt((double)n->nvox) : 1.0);
+    // layer 1 packs its input from r and g itself (no pass through in0)
+    CHK(launch_conv3d_input(n->nx, n->ny, n->nz, rdt, r, g, rr_dev, n->wf[0], n->h1, n->stream));
+    return forward(n, z, rr_dev, rr_dev ? 1.0 / std::sqrt((double)n->nvox) : 1.0, true);
 }
 
 pcg_status cnn_loss_grad(cnn_net n, int nx, int ny, int nz, const void* pairs, const float* g, int batch,
@@ -302,15 +307,15 @@ pcg_status cnn_loss_grad(cnn_net n, int nx, int ny, int nz, const void* pairs, c
         // layer 4: dW4 from (h3, dOut); dh3 = conv(dOut, mirrored W4) * (h3 > 0)
         CHK(launch_wgrad(X, Y, Z, 16, 1, n->h3, n->dout, true, n->zeros, n->partials, n->groups, s));
         CHK(launch_reduce_partials(n->partials, n->groups, 27 * 16, inv_b, acc, G + WOFF[3], s));
-        CHK(launch_conv3d(X, Y, Z, 2, OUT_MASK, n->dpack, n->wb[3], n->da, n->h3, nullptr, 1.0, s));
+        CHK(launch_conv3d(X, Y, Z, 2, OUT_MASK, n->dpack, n->wb[3], n->da, n->h3, nullptr, 1.0, n->zeros, s));
         // layer 3
         CHK(launch_wgrad(X, Y, Z, 16, 16, n->h2, n->da, false, n->zeros, n->partials, n->groups, s));
         CHK(launch_reduce_partials(n->partials, n->groups, 27 * 256, inv_b, acc, G + WOFF[2], s));
-        CHK(launch_conv3d(X, Y, Z, 16, OUT_MASK, n->da, n->wb[2], n->db, n->h2, nullptr, 1.0, s));
+        CHK(launch_conv3d(X, Y, Z, 16, OUT_MASK, n->da, n->wb[2], n->db, n->h2, nullptr, 1.0, n->zeros, s));
         // layer 2
         CHK(launch_wgrad(X, Y, Z, 16, 16, n->h1, n->db, false, n->zeros, n->partials, n->groups, s));
         CHK(launch_reduce_partials(n->partials, n->groups, 27 * 256, inv_b, acc, G + WOFF[1], s));
-        CHK(launch_conv3d(X, Y, Z, 16, OUT_MASK, n->db, n->wb[1], n->da, n->h1, nullptr, 1.0, s));
+        CHK(launch_conv3d(X, Y, Z, 16, OUT_MASK, n->db, n->wb[1], n->da, n->h1, nullptr, 1.0, n->zeros, s));
         // layer 1
         CHK(launch_wgrad(X, Y, Z, 2, 16, n->in0, n->da, false, n->zeros, n->partials, n->groups, s));
         CHK(launch_reduce_partials(n->partials, n->groups, 27 * 32, inv_b, acc, G + WOFF[0], s));

@@ -115,6 +115,32 @@ def test_forward_scaled(P, orc):
     assert np.linalg.norm(got - rho * ref.reshape(-1)) <= 1e-3 * np.linalg.norm(rho * ref)
 
 
+@pytest.mark.parametrize("scaled", [False, True])
+def test_forward_input_dtypes(P, scaled):
+    """The first layer forms its input from r itself: r given as FP64 or BF16
+    holding the same values as an FP32 r (BF16-representable values) gives
+    bit-identical outputs, with and without the rms scaling."""
+    shape = (9, 13, 20)
+    n = int(np.prod(shape))
+    ws = _init_weights(7)
+    r, g = _inputs(shape, 30)
+    bits = synthetic.f32_to_bf16_bits(r * 5.0)
+    r32 = (bits.astype(np.uint32) << 16).view(np.float32)
+    net = P.cnn_create()
+    P.cnn_set_weights(net, torch.from_numpy(_flat(ws)).cuda())
+    gd = torch.from_numpy(g).cuda()
+    rr = torch.tensor([float(np.dot(r32.astype(np.float64), r32))], dtype=torch.float64, device="cuda") if scaled else None
+    outs = []
+    for rt in (torch.from_numpy(r32).cuda(), torch.from_numpy(r32.astype(np.float64)).cuda(),
+               torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16)):
+        z = torch.empty(n, dtype=torch.float32, device="cuda")
+        P.cnn_forward(net, shape, rt, gd, z, rr=rr)
+        outs.append(z.cpu().numpy())
+    assert np.abs(outs[0]).max() > 0
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))
+    assert np.array_equal(outs[0].view(np.uint32), outs[2].view(np.uint32))
+
+
 @pytest.mark.parametrize("n", [64, 128])
 def test_forward_full_size_sampled(P, orc, n):
     """The scaled forward at the learned-preconditioner workload's grid sizes
