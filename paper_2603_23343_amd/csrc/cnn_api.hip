@@ -17,13 +17,15 @@ using namespace pcgmi;
 
 namespace pcgmi {
 hipError_t launch_conv3d(int nx, int ny, int nz, int cin, int mode, const void* in, const void* wsw, void* out,
-                         const void* mask, const double* scale_rms2, double scale_mul, const void* zeros, hipStream_t s);
+                         const void* mask, const double* scale_rms2, double scale_mul, const void* zeros, void* sink,
+                         hipStream_t s);
 hipError_t launch_conv3d_input(int nx, int ny, int nz, int dt, const void* r, const float* g, const double* rr,
-                               const void* wsw, void* out, hipStream_t s);
+                               const void* wsw, void* out, const void* zeros, void* sink, hipStream_t s);
 hipError_t launch_pack_input(int dt, int64_t n, const void* r, const float* g, const double* rr, void* out,
                              hipStream_t s);
 hipError_t launch_swizzle_weights(const float* w, int cin, int cout, int CIN, int mirror, void* out, hipStream_t s);
 int conv_swizzle_elems(int CIN);
+int conv_sink_bytes();
 int wgrad_groups(int nx, int ny, int nz);
 hipError_t launch_wgrad(int nx, int ny, int nz, int cx, int cy, const void* X, const void* dY, bool dy_f32,
                         const void* zeros, float* partials, int groups, hipStream_t s);
@@ -88,6 +90,7 @@ struct cnn_s {
     double* scal = nullptr;  // {loss accumulator, gradient coefficient}
     double* rpart = nullptr;
     void* zeros = nullptr;  // 64 zero bytes: read in place of points outside the grid
+    void* sink = nullptr;   // written in place of outputs outside the grid (never read)
     unsigned* ticket = nullptr;
     // A-norm loss: the operator's context (null: relative-MSE loss) and
     // the vectors u = N + D^-1 rh - eh and A u
@@ -158,10 +161,10 @@ pcg_status forward(cnn_net n, float* out, const double* rr, double mul, bool fir
     const int X = n->nx, Y = n->ny, Z = n->nz;
     hipStream_t s = n->stream;
     if (!first_done)
-        CHK(launch_conv3d(X, Y, Z, 2, OUT_RELU, n->in0, n->wf[0], n->h1, nullptr, nullptr, 1.0, n->zeros, s));
-    CHK(launch_conv3d(X, Y, Z, 16, OUT_RELU, n->h1, n->wf[1], n->h2, nullptr, nullptr, 1.0, n->zeros, s));
-    CHK(launch_conv3d(X, Y, Z, 16, OUT_RELU, n->h2, n->wf[2], n->h3, nullptr, nullptr, 1.0, n->zeros, s));
-    CHK(launch_conv3d(X, Y, Z, 16, OUT_SCALED, n->h3, n->wf[3], out, nullptr, rr, mul, n->zeros, s));
+        CHK(launch_conv3d(X, Y, Z, 2, OUT_RELU, n->in0, n->wf[0], n->h1, nullptr, nullptr, 1.0, n->zeros, n->sink, s));
+    CHK(launch_conv3d(X, Y, Z, 16, OUT_RELU, n->h1, n->wf[1], n->h2, nullptr, nullptr, 1.0, n->zeros, n->sink, s));
+    CHK(launch_conv3d(X, Y, Z, 16, OUT_RELU, n->h2, n->wf[2], n->h3, nullptr, nullptr, 1.0, n->zeros, n->sink, s));
+    CHK(launch_conv3d(X, Y, Z, 16, OUT_SCALED, n->h3, n->wf[3], out, nullptr, rr, mul, n->zeros, n->sink, s));
     return PCG_OK;
 }
 
@@ -211,6 +214,7 @@ pcg_status cnn_create(cnn_net* out, void* hip_stream) {
     if (e == hipSuccess) e = hipMalloc(&n->ticket, 256);
     if (e == hipSuccess) e = hipMalloc(&n->zeros, 64);
     if (e == hipSuccess) e = hipMemsetAsync(n->zeros, 0, 64, n->stream);
+    if (e == hipSuccess) e = hipMalloc(&n->sink, conv_sink_bytes());
     if (e == hipSuccess) e = hipMemsetAsync(n->w, 0, sizeof(float) * NW, n->stream);
     if (e == hipSuccess) e = hipMemsetAsync(n->m, 0, sizeof(float) * NW, n->stream);
     if (e == hipSuccess) e = hipMemsetAsync(n->v, 0, sizeof(float) * NW, n->stream);
@@ -228,7 +232,7 @@ pcg_status cnn_destroy(cnn_net n) {
     if (!n) return PCG_OK;
     (void)hipStreamSynchronize(n->stream);
     free_grid(n);
-    void* p[] = {n->w, n->grad, n->m, n->v, n->scal, n->rpart, n->ticket, n->zeros};
+    void* p[] = {n->w, n->grad, n->m, n->v, n->scal, n->rpart, n->ticket, n->zeros, n->sink};
     for (void* q : p)
         if (q) (void)hipFree(q);
     for (int l = 0; l < NL; ++l) {
@@ -268,7 +272,7 @@ pcg_status cnn_forward(cnn_net n, int nx, int ny, int nz, pcg_dtype rdt, const v
     st = ensure_swizzled(n);
     if (st != PCG_OK) return st;
     // layer 1 packs its input from r and g itself (no pass through in0)
-    CHK(launch_conv3d_input(n->nx, n->ny, n->nz, rdt, r, g, rr_dev, n->wf[0], n->h1, n->stream));
+    CHK(launch_conv3d_input(n->nx, n->ny, n->nz, rdt, r, g, rr_dev, n->wf[0], n->h1, n->zeros, n->sink, n->stream));
     return forward(n, z, rr_dev, rr_dev ? 1.0 / std::sqrt((double)n->nvox) : 1.0, true);
 }
 
@@ -307,15 +311,15 @@ pcg_status cnn_loss_grad(cnn_net n, int nx, int ny, int nz, const void* pairs, c
         // layer 4: dW4 from (h3, dOut); dh3 = conv(dOut, mirrored W4) * (h3 > 0)
         CHK(launch_wgrad(X, Y, Z, 16, 1, n->h3, n->dout, true, n->zeros, n->partials, n->groups, s));
         CHK(launch_reduce_partials(n->partials, n->groups, 27 * 16, inv_b, acc, G + WOFF[3], s));
-        CHK(launch_conv3d(X, Y, Z, 2, OUT_MASK, n->dpack, n->wb[3], n->da, n->h3, nullptr, 1.0, n->zeros, s));
+        CHK(launch_conv3d(X, Y, Z, 2, OUT_MASK, n->dpack, n->wb[3], n->da, n->h3, nullptr, 1.0, n->zeros, n->sink, s));
         // layer 3
         CHK(launch_wgrad(X, Y, Z, 16, 16, n->h2, n->da, false, n->zeros, n->partials, n->groups, s));
         CHK(launch_reduce_partials(n->partials, n->groups, 27 * 256, inv_b, acc, G + WOFF[2], s));
-        CHK(launch_conv3d(X, Y, Z, 16, OUT_MASK, n->da, n->wb[2], n->db, n->h2, nullptr, 1.0, n->zeros, s));
+        CHK(launch_conv3d(X, Y, Z, 16, OUT_MASK, n->da, n->wb[2], n->db, n->h2, nullptr, 1.0, n->zeros, n->sink, s));
         // layer 2
         CHK(launch_wgrad(X, Y, Z, 16, 16, n->h1, n->db, false, n->zeros, n->partials, n->groups, s));
         CHK(launch_reduce_partials(n->partials, n->groups, 27 * 256, inv_b, acc, G + WOFF[1], s));
-        CHK(launch_conv3d(X, Y, Z, 16, OUT_MASK, n->db, n->wb[1], n->da, n->h1, nullptr, 1.0, n->zeros, s));
+        CHK(launch_conv3d(X, Y, Z, 16, OUT_MASK, n->db, n->wb[1], n->da, n->h1, nullptr, 1.0, n->zeros, n->sink, s));
         // layer 1
         CHK(launch_wgrad(X, Y, Z, 2, 16, n->in0, n->da, false, n->zeros, n->partials, n->groups, s));
         CHK(launch_reduce_partials(n->partials, n->groups, 27 * 32, inv_b, acc, G + WOFF[0], s));
