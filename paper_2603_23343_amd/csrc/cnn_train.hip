@@ -24,7 +24,8 @@ __device__ __forceinline__ float bf16v(uint16_t b) { return __uint_as_float(((ui
 // the tap's x offset. A work-group stages, per chunk of up to WGM_K points
 // of a row, the 9 neighbour rows of X and the 3 shifted copies of dY in LDS,
 // transposed to [channel][x] (channels beyond CX / CY are zero); wave w
-// accumulates taps w, w + 4, ... (acc[t / 4]) over all its rows in registers. Rows are
+// accumulates all 27 taps over K-step w of every item in registers, and the
+// four wavefronts' sums are added in a fixed order at the end. Rows are
 // dealt to work-groups round-robin; partials[g][27][CX][CY] feed the
 // fixed-order reduction, so the result is deterministic.
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
@@ -101,15 +102,16 @@ __global__ void __launch_bounds__(256, 2) k_wgrad_mfma(int nx, int ny, int nz, c
                                                     const Y* __restrict__ dY, const void* __restrict__ zeros,
                                                     float* __restrict__ partials) {
     static_assert(WGM_K == 128, "one pair column per lane");
-    __shared__ __attribute__((aligned(16))) uint16_t xs[9 * 16 * WGM_SP];
-    __shared__ __attribute__((aligned(16))) uint16_t ys[3 * 16 * WGM_SP];
+    __shared__ __attribute__((aligned(16))) uint16_t lds[12 * 16 * WGM_SP];
+    uint16_t* const xs = lds;                    // the 9 neighbour rows of X
+    uint16_t* const ys = lds + 9 * 16 * WGM_SP;  // the 3 shifted rows of dY
     const int tid = threadIdx.x, lane = tid & 63;
     const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int m = lane & 15, kg = lane >> 4;
     const int xp = 2 * lane;  // this lane's pair column
-    f32x4_t acc[7];
+    f32x4_t acc[27];
 #pragma unroll
-    for (int j = 0; j < 7; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 27; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     const int nch = (nx + WGM_K - 1) / WGM_K;
     const int nitems = ny * nz * nch;
     // XCD-aware dealing: work-group b runs on XCD b mod 8; with a grid that is
@@ -172,25 +174,25 @@ __global__ void __launch_bounds__(256, 2) k_wgrad_mfma(int nx, int ny, int nz, c
         for (int i = tid; i < 9 * 16 * WGM_SP / 2; i += 256) reinterpret_cast<uint32_t*>(xs)[i] = 0u;
         for (int i = tid; i < 3 * 16 * WGM_SP / 2; i += 256) reinterpret_cast<uint32_t*>(ys)[i] = 0u;
     }
-    // Products of one item for wavefront W: its taps t = W + 4 j (j < 7, t <
-    // 27; t = 3 r + shift with r = 3 dz + dy) are compile-time constants, so
-    // every LDS read is at a fixed offset and the three dY fragments are
-    // shared by the taps with the same shift.
-    auto products = [&]<int W>(int kp) {
-        for (int kb = 0; kb < kp; kb += 32) {
-            const int ko = kb + 8 * kg;
-            bf16x8_t b[3];
+    // Wavefront w takes K-step w (points 32 w .. + 31) of every item for all
+    // 27 taps: 9 X fragments and 3 dY fragments feed 27 products, each
+    // fragment read once per work-group. (Taps dealt to wavefronts, each
+    // wavefront running every K-step, read each X fragment three times and
+    // measured 1.15x slower per 16 -> 16 layer.)
+    auto products = [&](int kp) {
+        const int kb = 32 * wu;
+        if (kb >= kp) return;
+        const int ko = kb + 8 * kg;
+        bf16x8_t b[3];
+#pragma unroll
+        for (int sft = 0; sft < 3; ++sft)
+            b[sft] = *reinterpret_cast<const bf16x8_t*>(&ys[(sft * 16 + m) * WGM_SP + ko]);
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&xs[(r * 16 + m) * WGM_SP + ko]);
 #pragma unroll
             for (int sft = 0; sft < 3; ++sft)
-                b[sft] = *reinterpret_cast<const bf16x8_t*>(&ys[(sft * 16 + m) * WGM_SP + ko]);
-#pragma unroll
-            for (int j = 0; j < 7; ++j) {
-                const int t = W + 4 * j;  // a constant once unrolled
-                if (t < 27) {
-                    const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(&xs[((t / 3) * 16 + m) * WGM_SP + ko]);
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[t % 3], acc[j], 0, 0, 0);
-                }
-            }
+                acc[3 * r + sft] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[sft], acc[3 * r + sft], 0, 0, 0);
         }
     };
     WgItem cur{};
@@ -207,24 +209,41 @@ __global__ void __launch_bounds__(256, 2) k_wgrad_mfma(int nx, int ny, int nz, c
             cur = geom(item + step);
             fetch(cur);
         }
-        switch (wu) {
-            case 0: products.template operator()<0>(kp); break;
-            case 1: products.template operator()<1>(kp); break;
-            case 2: products.template operator()<2>(kp); break;
-            default: products.template operator()<3>(kp); break;
-        }
+        products(kp);
     }
-    // lane holds C[ci = 4 kg + i][co = m] of each of its taps t = wu + 4 j
+    // Sum the four wavefronts' accumulators in a fixed order through LDS
+    // (the staging area holds two wavefronts' 27 x 64 x 4 floats): waves 2, 3
+    // hand theirs to 0, 1, then wave 1 to wave 0.
+    float* red = reinterpret_cast<float*>(lds);
+    static_assert(sizeof(lds) >= 2 * 27 * 64 * 4 * sizeof(float), "reduction area");
+    __syncthreads();
+    if (wu >= 2) {
+#pragma unroll
+        for (int t = 0; t < 27; ++t)
+            *reinterpret_cast<f32x4_t*>(&red[(((wu - 2) * 27 + t) * 64 + lane) * 4]) = acc[t];
+    }
+    __syncthreads();
+    if (wu < 2) {
+#pragma unroll
+        for (int t = 0; t < 27; ++t) acc[t] += *reinterpret_cast<const f32x4_t*>(&red[((wu * 27 + t) * 64 + lane) * 4]);
+    }
+    __syncthreads();
+    if (wu == 1) {
+#pragma unroll
+        for (int t = 0; t < 27; ++t) *reinterpret_cast<f32x4_t*>(&red[(t * 64 + lane) * 4]) = acc[t];
+    }
+    __syncthreads();
+    if (wu != 0) return;
+#pragma unroll
+    for (int t = 0; t < 27; ++t) acc[t] += *reinterpret_cast<const f32x4_t*>(&red[(t * 64 + lane) * 4]);
+    // lane holds C[ci = 4 kg + i][co = m] of every tap
     float* out = partials + (size_t)blockIdx.x * 27 * CX * CY;
 #pragma unroll
-    for (int j = 0; j < 7; ++j) {
-        const int t = wu + 4 * j;
-        if (t < 27) {
+    for (int t = 0; t < 27; ++t) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int ci = 4 * kg + i;
-                if (ci < CX && m < CY) out[(t * CX + ci) * CY + m] = acc[j][i];
-            }
+        for (int i = 0; i < 4; ++i) {
+            const int ci = 4 * kg + i;
+            if (ci < CX && m < CY) out[(t * CX + ci) * CY + m] = acc[t][i];
         }
     }
 }
