@@ -29,7 +29,8 @@ Also reported on the same JSON line:
                    paper's own per-iteration times (context, other hardware);
   small_grid    -- the 32^3 workload with both iteration forms;
   kernels_512   -- standalone stencil / axpy / dot at 512^3 (FP32 and BF16),
-                   achieved GB/s of algorithmic bytes;
+                   achieved GB/s of algorithmic bytes, beside torch's device
+                   copy of the same size (the one-read-one-write reference);
   sell_spmv     -- general sparse SpMV (sliced ELLPACK) of the explicitly
                    stored seven-point matrix at 256^3 and on the paper's
                    comparison grid, beside the matrix-free stencil; Jacobi-PCG
@@ -138,6 +139,9 @@ def time_kernels_512(P, torch, n, reps):
             "stencil": (lambda: P.stencil_apply(ctx, x, z), 2 * es),
             "axpy": (lambda: P.axpy(ctx, N, 0.5, x, y, z), 3 * es),
             "dot": (lambda: P.dot(ctx, N, x, y, d), 2 * es),
+            # reference, not this library's kernel: torch's device copy, the
+            # same one-read-one-write stream pattern as the stencil
+            "torch_copy": (lambda: z.copy_(x), 2 * es),
         }
         for op, (fn, bpp) in ops.items():
             warm_up(torch, fn)
