@@ -28,6 +28,10 @@ Also reported on the same JSON line:
                    single-reduction form, and BF16 storage), beside the
                    paper's own per-iteration times (context, other hardware);
   small_grid    -- the 32^3 workload with both iteration forms;
+  slab          -- one GPU's share of the 256^3 system split in z over 8
+                   GPUs (256 x 256 x 32 planes): the iteration kernels on that
+                   shape, the stencil over the slab with its two halo planes,
+                   and the halo bytes an iteration would exchange;
   kernels_512   -- standalone stencil / axpy / dot at 512^3 (FP32 and BF16),
                    achieved GB/s of algorithmic bytes, beside torch's device
                    copy of the same size (the one-read-one-write reference);
@@ -303,6 +307,49 @@ def bench_paper_grid(P, torch, steps):
                      "true_relres": info["rel_res_true_fp64"]}
         P.pcg_destroy(ctx)
     return out
+
+
+def bench_slab(P, torch, n=256, parts=8, iters=100):
+    """One GPU's share of the n^3 system split into `parts` z-slabs: the two
+    iteration kernels timed with HIP events on an n x n x n/parts grid (a
+    fixed number of iterations), the standalone stencil over the slab with
+    its two halo planes (n/parts + 2 planes), and the bytes one iteration
+    would exchange with the two neighbours (one plane of r and of p_old each
+    way: the direction kernel forms p on the fly from both)."""
+    import synthetic
+
+    nzs = n // parts
+    N = n * n * nzs
+    b = torch.from_numpy(synthetic.uniform_f32(synthetic.SEED_C1_B, N)).cuda()
+    x = torch.empty(N, dtype=torch.float64, device="cuda")
+    ctx = P.pcg_create(n, n, nzs, torch.float32, x_dtype=torch.float64, kernel_timing=1, max_restarts=0)
+    P.pcg_solve(ctx, b, x, 1e-30, 20, raise_on_error=False)
+    info = P.pcg_solve(ctx, b, x, 1e-30, iters, raise_on_error=False)
+    k1 = info["k1_ms"] * 1e3 / max(info["k1_launches"], 1)
+    k2 = info["k2_ms"] * 1e3 / max(info["k2_launches"], 1)
+    P.pcg_destroy(ctx)
+    sctx = P.pcg_create(n, n, nzs + 2, torch.float32)
+    xs = torch.from_numpy(synthetic.uniform_f32(2, n * n * (nzs + 2))).cuda()
+    ys = torch.empty_like(xs)
+    warm_up(torch, lambda: P.stencil_apply(sctx, xs, ys))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(50):
+        P.stencil_apply(sctx, xs, ys)
+    e1.record()
+    e1.synchronize()
+    st_us = e0.elapsed_time(e1) * 1e3 / 50
+    P.pcg_destroy(sctx)
+    halo = 2 * 2 * n * n * 4  # r and p_old, one plane to each neighbour, FP32
+    return {"slab": [n, n, nzs], "of": [n, n, n], "parts": parts, "iterations_timed": info["k2_launches"],
+            "status": P.STATUS_NAMES[info["status"]],
+            "direction_us": round(k1, 2), "update_us": round(k2, 2), "iteration_kernels_us": round(k1 + k2, 2),
+            "iteration_GB/s": round((BYTES_DIRECTION + BYTES_UPDATE) * N / ((k1 + k2) * 1e-6) / 1e9, 1),
+            "stencil_with_halo_planes_us": round(st_us, 2),
+            "halo_bytes_per_iteration_each_way": halo,
+            "halo_note": "one plane of r and p_old to each z-neighbour per iteration (plus two scalar all-reduces); "
+                         "not sent here: this build runs one GPU"}
 
 
 def bench_multigrid(P, torch, b, n, steps, jacobi_s, nu=1, oracle_budget_s=0.0):
@@ -663,6 +710,7 @@ def main():
     ap.add_argument("--no-paper-grid", action="store_true")
     ap.add_argument("--no-sell", action="store_true")
     ap.add_argument("--no-multigrid", action="store_true")
+    ap.add_argument("--no-slab", action="store_true")
     ap.add_argument("--learned-n", default="64,128",
                     help="comma-separated grid sizes of the learned-preconditioner workflow")
     ap.add_argument("--learned-rounds", type=int, default=12)
@@ -771,6 +819,11 @@ def main():
             del x64
         print(f"# refined: {refined}", file=sys.stderr, flush=True)
 
+    slab = None
+    if not args.no_slab:
+        slab = bench_slab(P, torch)
+        print(f"# slab: {slab}", file=sys.stderr, flush=True)
+
     multigrid = None
     if not args.no_multigrid:
         multigrid = bench_multigrid(P, torch, b, n, max(args.steps, 3), dt_solve,
@@ -830,6 +883,7 @@ def main():
         "batched": batched,
         "paper_grid": paper_grid,
         "small_grid": small_grid,
+        "slab": slab,
         "learned": learned,
         "kernels_512": kern,
         "sell_spmv": sell,
