@@ -556,7 +556,11 @@ def bench_batched(P, torch, reps, oracle_budget_s=0.0):
            "max_true_relres": max(r["relres"]), "sequential_ms": round(seq * 1e3, 2),
            "speedup_vs_sequential": round(seq * 1e3 / ms, 3),
            "iters_equal_sequential": int(sum(1 for a, c in zip(r["iters"], seq_iters) if a == c)),
-           "work_groups": bt.grid, "create_and_tune_s": round(t_create, 3)}
+           "work_groups": bt.grid, "create_and_tune_s": round(t_create, 3),
+           # per problem: edge, iterations, work-groups, latency (ms), in finishing order
+           "per_problem": sorted(([m, int(it), int(bt.plans[i][2]), round(lt * 1e3, 2)]
+                                  for i, (m, it, lt) in enumerate(zip(sizes, r["iters"], r["latency_s"]))),
+                                 key=lambda e: e[3])}
     bt.close()
     if oracle_budget_s > 0:
         out["oracle"] = batched_oracle(sizes, r["iters"], oracle_budget_s)
@@ -685,6 +689,8 @@ def learned_workflow(P, torch, n, rounds, oracle_cpu):
                           "true_relres": jac["rel_res_true_fp64"]},
            "flexible_cg_learned": {"iters": fcg["iters"], "ms": round(fcg["seconds"] * 1e3, 3),
                                    "fallback_used": fcg["fallback_used"],
+                                   # iteration at which Jacobi-PCG took over (-1: never)
+                                   "fallback_at": fcg["outer_iters"] if fcg["fallback_used"] == 1 else -1,
                                    "true_relres": fcg["rel_res_true_fp64"]},
            "multigrid_pcg": {"iters": mgi["iters"], "ms": round(mgi["seconds"] * 1e3, 3),
                              "true_relres": mgi["rel_res_true_fp64"], "status": P.STATUS_NAMES[mgi["status"]]},
