@@ -441,18 +441,22 @@ void set_plan(BatchProb& p, int cfg) {
 // estimated iterations), then each XCD's resident work-groups are dealt out
 // greedily to the problem with the longest estimated solve time, which
 // balances finish times. The estimate is a model, used only for this split,
-// with constants fitted (least squares) to the measured per-problem times of
-// the 64-problem batch on MI355X:
+// with constants fitted (least squares on the relative error) to the
+// measured per-iteration times of the 64 problems of the uneven batch on
+// MI355X:
 //   iterations ~ 2.8 max(nx, ny, nz)  (Jacobi-PCG iterations grow with the
 //                                      square root of the condition number)
-//   one plane step of a work-group ~ 0.81 us + 1.06 ns per point of its tile
+//   one plane step of a work-group ~ 1.07 us + 1.15 ns per point of its tile
 //   a phase = (busiest work-group's tiles) x (zc + 3 start-up planes) steps
-//   an iteration = 2 phases + ~45 us of latency (2 group barriers, the
-//   partial sums, pipeline start-up), whatever the group size.
+//   an iteration = 2 phases + 2 x 0.45 us (the group barriers and partial
+//   sums are absorbed into the per-step cost by the fit), whatever the
+//   group size. (An absolute-error fit, 0.90 us + 1.11 ns and 27 us per
+//   iteration, overestimates the largest problems; with the former
+//   constants the batch took 54.6 ms, with these 53.8.)
 namespace {
 
 struct CostModel {
-    double step0 = 0.81, step_pt = 0.00106, barrier = 22.7;
+    double step0 = 1.067, step_pt = 0.00115, barrier = 0.45;
 };
 
 int model_cfg(const BatchProb& p) { return p.nx > 128 ? 2 : (p.nx > 64 ? 1 : 0); }
