@@ -141,6 +141,27 @@ def test_forward_input_dtypes(P, scaled):
     assert np.array_equal(outs[0].view(np.uint32), outs[2].view(np.uint32))
 
 
+def test_forward_unaligned_output(P):
+    """The last layer stores four voxels per lane with one 16-byte store when
+    the output row allows it; an output pointer off 16-byte alignment takes
+    the element-wise path and must give the same bits."""
+    shape = (12, 16, 32)
+    n = int(np.prod(shape))
+    ws = _init_weights(11)
+    r, g = _inputs(shape, 40)
+    net = P.cnn_create()
+    P.cnn_set_weights(net, torch.from_numpy(_flat(ws)).cuda())
+    rd, gd = torch.from_numpy(r).cuda(), torch.from_numpy(g).cuda()
+    za = torch.empty(n, dtype=torch.float32, device="cuda")
+    P.cnn_forward(net, shape, rd, gd, za)
+    zfull = torch.zeros(n + 1, dtype=torch.float32, device="cuda")
+    zu = zfull[1:]
+    assert zu.data_ptr() % 16 != 0
+    P.cnn_forward(net, shape, rd, gd, zu)
+    assert float(zfull[0]) == 0.0
+    assert np.array_equal(za.cpu().numpy().view(np.uint32), zu.cpu().numpy().view(np.uint32))
+
+
 @pytest.mark.parametrize("n", [64, 128])
 def test_forward_full_size_sampled(P, orc, n):
     """The scaled forward at the learned-preconditioner workload's grid sizes
