@@ -280,6 +280,7 @@ typedef struct cnn_s *cnn_net;
 
 /* Create a network (weights zero) whose work is enqueued on hip_stream. */
 pcg_status cnn_create(cnn_net *out, void *hip_stream);
+/* Release the network (waits for its stream). NULL is a no-op. */
 pcg_status cnn_destroy(cnn_net net);
 /* Number of weights (15120). */
 int cnn_num_weights(void);
@@ -287,6 +288,15 @@ int cnn_num_weights(void);
  * weights resets the Adam moments and step count. */
 pcg_status cnn_set_weights(cnn_net net, const float *w_dev);
 pcg_status cnn_get_weights(cnn_net net, float *w_dev);
+/* Training checkpoint: Adam's state (Kingma & Ba 2015), the first and second
+ * moment estimates (15120 FP32 values each, DEVICE buffers) and the step
+ * count. cnn_get_adam copies them out (step may be NULL); cnn_set_adam
+ * restores them (call it after cnn_set_weights, which resets them), so that
+ * training resumes exactly where the checkpoint was taken. Errors: PCG_E_ARG
+ * for a null network or buffer or a step outside [0, 2^31). Both enqueue on
+ * the network's stream. */
+pcg_status cnn_get_adam(cnn_net net, float *m_dev, float *v_dev, int64_t *step);
+pcg_status cnn_set_adam(cnn_net net, const float *m_dev, const float *v_dev, int64_t step);
 /* z = s N(r / s, g) on an nx*ny*nz grid: r of type rdt (F32, F64 or BF16),
  * g FP32 (NULL: zero channel), z FP32, all DEVICE arrays of nx*ny*nz
  * values. rr_dev: DEVICE pointer to ||r||^2 (FP64) giving s = rms(r) =
@@ -398,6 +408,7 @@ typedef struct pcg_batch_s *pcg_batch;
  * more problems than resident work-groups fall on one XCD. */
 pcg_status pcg_batch_create(pcg_batch *out, int nprob, const int *dims, const int *cfgs,
                             const char *cache_path, int tune_iters, void *hip_stream);
+/* Release the batch (waits for its stream). NULL is a no-op. */
 pcg_status pcg_batch_destroy(pcg_batch batch);
 
 /* Host outputs, each optional (NULL): offsets int64[nprob] (element offset of
@@ -476,6 +487,7 @@ pcg_status pcg_sell_build(int64_t nrows, int64_t ncols, const int64_t *rowptr, c
  * stream). PCG_E_NOMEM if the device memory cannot be allocated. */
 pcg_status pcg_sell_create(pcg_sell *out, int64_t nrows, int64_t ncols, const int64_t *rowptr,
                            const int32_t *colidx, const float *values, int sigma, void *hip_stream);
+/* Release the matrix's device memory. NULL is a no-op. */
 pcg_status pcg_sell_destroy(pcg_sell A);
 /* Host outputs, each optional: stored entries, slots (padding included),
  * chunks. */

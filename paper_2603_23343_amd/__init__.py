@@ -6,7 +6,7 @@ requires the built library and raises otherwise.
 """
 from ._binding import (  # noqa: F401
     Batch, pcg_batch_create, pcg_batch_destroy, pcg_batch_set_barrier, pcg_batch_set_restarts, pcg_batch_solve,
-    Cnn, cnn_adam_step, cnn_create, cnn_forward, cnn_get_weights, cnn_loss_grad, cnn_num_weights, cnn_set_operator, cnn_set_loss_norm, cnn_set_weights,
+    Cnn, cnn_adam_step, cnn_create, cnn_forward, cnn_get_adam, cnn_get_weights, cnn_set_adam, cnn_loss_grad, cnn_num_weights, cnn_set_operator, cnn_set_loss_norm, cnn_set_weights,
     cnn_train_step,
     DT_TORCH, LIBPATH, PCG_BF16, PCG_E_ARG, PCG_E_BREAKDOWN, PCG_E_HIP, PCG_E_NOCONV, PCG_E_NOMEM,
     PCG_E_TRUE_RESIDUAL, PCG_E_UNSUPPORTED, PCG_F16, SOLVE_OUTCOMES, STATUS_NAMES, PCG_F32, PCG_F64, PCG_OK, Context, PcgError, PcgInfo, PcgOptions, axpy,

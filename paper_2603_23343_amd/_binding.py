@@ -88,6 +88,8 @@ def _load():
         "cnn_num_weights": ([], i),
         "cnn_set_weights": ([vp, vp], i),
         "cnn_get_weights": ([vp, vp], i),
+        "cnn_get_adam": ([vp, vp, vp, ctypes.POINTER(i64)], i),
+        "cnn_set_adam": ([vp, vp, vp, i64], i),
         "cnn_forward": ([vp, i, i, i, i, vp, vp, vp, vp], i),
         "cnn_loss_grad": ([vp, i, i, i, vp, vp, i, vp, vp], i),
         "cnn_adam_step": ([vp, vp, ctypes.c_float], i),
@@ -361,6 +363,23 @@ def cnn_get_weights(net: Cnn, w=None):
     _need(w, cnn_num_weights(), "w", torch.float32)
     _check(lib.cnn_get_weights(net.handle, _ptr(w)))
     return w
+
+
+def cnn_get_adam(net: Cnn):
+    """Adam's state for a training checkpoint: (m, v, step), m and v FP32
+    device tensors of cnn_num_weights() values."""
+    m = torch.empty(cnn_num_weights(), dtype=torch.float32, device="cuda")
+    v = torch.empty_like(m)
+    step = ctypes.c_int64()
+    _check(lib.cnn_get_adam(net.handle, _ptr(m), _ptr(v), ctypes.byref(step)))
+    return m, v, int(step.value)
+
+
+def cnn_set_adam(net: Cnn, m, v, step: int):
+    """Restore Adam's state (after cnn_set_weights, which resets it)."""
+    _need(m, cnn_num_weights(), "m", torch.float32)
+    _need(v, cnn_num_weights(), "v", torch.float32)
+    _check(lib.cnn_set_adam(net.handle, _ptr(m), _ptr(v), int(step)))
 
 
 def cnn_forward(net: Cnn, shape, r, g, z, rr=None):

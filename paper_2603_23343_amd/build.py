@@ -46,7 +46,10 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    # ROCTx (solver-phase ranges) from the ROCm install the library runs with
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(HIPCC))), "lib")
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
+           "-L", rocm_lib, "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{rocm_lib}"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     if verbose:

@@ -32,6 +32,7 @@
 #include <string>
 #include <vector>
 
+#include "trace.hpp"
 #include "zkernel.hpp"
 
 namespace pcgmi {
@@ -691,6 +692,7 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
 // problem keeps the shape with the shortest wall-clock time from its start to
 // its last iteration (best of `reps` launches).
 pcg_status autotune(BatchImpl& B, std::vector<int>& todo, std::vector<double>& best_us, int iters, int reps) {
+    Range range("batched: autotune");
     const int cands[4] = {0, 1, 2, 5};
     float* tb = nullptr;
     double* tx = nullptr;
@@ -738,6 +740,7 @@ extern "C" {
 
 pcg_status pcg_batch_create(pcg_batch* out, int nprob, const int* dims, const int* cfgs, const char* cache_path,
                             int tune_iters, void* hip_stream) {
+    Range range("pcg_batch_create");
     if (!out || nprob < 1 || !dims) return berr(PCG_E_ARG, "pcg_batch_create: bad argument");
     *out = nullptr;
     for (int i = 0; i < nprob; ++i) {
@@ -908,6 +911,7 @@ pcg_status pcg_batch_set_restarts(pcg_batch bt, int max_restarts) {
 
 pcg_status pcg_batch_solve(pcg_batch bt, const float* b, double* x, double rtol, int maxit, int use_graph,
                            int* iters, double* relres, double* latency_s, int* restarts, double* seconds) {
+    Range range("pcg_batch_solve");
     if (!bt || !b || !x) return berr(PCG_E_ARG, "pcg_batch_solve: null argument");
     if (!(rtol >= 0.0) || maxit < 0) return berr(PCG_E_ARG, "pcg_batch_solve: bad tolerance or iteration limit");
     BatchImpl& B = bt->impl;

@@ -12,6 +12,7 @@
 
 #include "internal.hpp"
 #include "pcgmi.h"
+#include "trace.hpp"
 
 using namespace pcgmi;
 
@@ -261,6 +262,23 @@ pcg_status cnn_get_weights(cnn_net n, float* w_dev) {
     return PCG_OK;
 }
 
+pcg_status cnn_get_adam(cnn_net n, float* m_dev, float* v_dev, int64_t* step) {
+    if (!n || !m_dev || !v_dev) return err(PCG_E_ARG, "cnn_get_adam: null argument");
+    CHK(hipMemcpyAsync(m_dev, n->m, sizeof(float) * NW, hipMemcpyDeviceToDevice, n->stream));
+    CHK(hipMemcpyAsync(v_dev, n->v, sizeof(float) * NW, hipMemcpyDeviceToDevice, n->stream));
+    if (step) *step = n->step;
+    return PCG_OK;
+}
+
+pcg_status cnn_set_adam(cnn_net n, const float* m_dev, const float* v_dev, int64_t step) {
+    if (!n || !m_dev || !v_dev) return err(PCG_E_ARG, "cnn_set_adam: null argument");
+    if (step < 0 || step > INT32_MAX) return err(PCG_E_ARG, "cnn_set_adam: step %lld out of range", (long long)step);
+    CHK(hipMemcpyAsync(n->m, m_dev, sizeof(float) * NW, hipMemcpyDeviceToDevice, n->stream));
+    CHK(hipMemcpyAsync(n->v, v_dev, sizeof(float) * NW, hipMemcpyDeviceToDevice, n->stream));
+    n->step = (int)step;
+    return PCG_OK;
+}
+
 pcg_status cnn_forward(cnn_net n, int nx, int ny, int nz, pcg_dtype rdt, const void* r, const float* g,
                        const double* rr_dev, float* z) {
     if (!n || !r || !z) return err(PCG_E_ARG, "cnn_forward: null argument");
@@ -278,6 +296,7 @@ pcg_status cnn_forward(cnn_net n, int nx, int ny, int nz, pcg_dtype rdt, const v
 
 pcg_status cnn_loss_grad(cnn_net n, int nx, int ny, int nz, const void* pairs, const float* g, int batch,
                          float* grad_dev, double* loss_dev) {
+    Range range("cnn_loss_grad");
     if (!n || !pairs || batch < 1) return err(PCG_E_ARG, "cnn_loss_grad: bad argument");
     if (n->op && !ctx_is_f32_grid(n->op, nx, ny, nz))
         return err(PCG_E_ARG, "cnn_loss_grad: the operator's context is not an F32 context on this grid");
@@ -352,6 +371,7 @@ pcg_status cnn_set_loss_norm(cnn_net n, int mode) {
 }
 
 pcg_status cnn_adam_step(cnn_net n, const float* grad_dev, float lr) {
+    Range range("cnn_adam_step");
     if (!n) return err(PCG_E_ARG, "cnn_adam_step: null network");
     n->step += 1;
     CHK(launch_adam(NW, n->w, grad_dev ? grad_dev : n->grad, n->m, n->v, lr, n->step, n->stream));
@@ -361,6 +381,7 @@ pcg_status cnn_adam_step(cnn_net n, const float* grad_dev, float lr) {
 
 pcg_status cnn_train_step(cnn_net n, int nx, int ny, int nz, const void* pairs, const float* g, int batch, float lr,
                           double* loss_dev) {
+    Range range("cnn_train_step");
     pcg_status st = cnn_loss_grad(n, nx, ny, nz, pairs, g, batch, nullptr, loss_dev);
     if (st != PCG_OK) return st;
     return cnn_adam_step(n, nullptr, lr);

@@ -22,6 +22,7 @@
 #include "internal.hpp"
 #include "ops.hpp"
 #include "pcgmi.h"
+#include "trace.hpp"
 
 using namespace pcgmi;
 
@@ -319,6 +320,7 @@ pcg_status ensure_chunk(pcg_ctx c) {
         c->chunk = nullptr;
     }
     if (c->chunk) return PCG_OK;
+    Range range("graph capture: PCG iterations");
     c->chunk_sr = c->sr_active;
     if (!c->capture) HIPCHK(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
@@ -573,6 +575,7 @@ void free_mg(pcg_ctx c) {
 
 // Builds the hierarchy for the context's current operator.
 pcg_status build_mg(pcg_ctx c) {
+    Range range("multigrid setup");
     hipStream_t st = c->stream;
     HIPCHK(hipStreamSynchronize(st));
     free_mg(c);
@@ -837,6 +840,7 @@ pcg_status dot_f64(pcg_ctx c, int64_t n, const void* x, const void* y, double* o
 
 pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, pcg_info* info) {
     auto t0 = std::chrono::steady_clock::now();
+    Range range("pcg_solve");
     if (!c) return fail(PCG_E_ARG, "pcg_solve: null context");
     if (!b || !x) return fail(PCG_E_ARG, "pcg_solve: null pointer");
     if (!aligned16(b) || !aligned16(x)) return fail(PCG_E_ARG, "pcg_solve: pointers must be 16-byte aligned");
@@ -852,7 +856,11 @@ pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, 
     int x0_dt = c->opt.x_dtype;
     for (;;) {
         IterResult seg;  // run_iterations accumulates its kernel times into a fresh result
-        pcg_status s = run_iterations(c, b, x0, x0_dt, rtol, maxit - total_iters, 0, &seg);
+        pcg_status s;
+        {
+            Range r(restarts ? "PCG iterations (restart)" : "PCG iterations");
+            s = run_iterations(c, b, x0, x0_dt, rtol, maxit - total_iters, 0, &seg);
+        }
         if (s != PCG_OK) return s;
         total_iters += seg.fin.iters;
         res.k1_ms += seg.k1_ms;
@@ -861,6 +869,7 @@ pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, 
         res.fin = seg.fin;
 
         // Result to the caller's x, then the FP64 true residual of what is returned.
+        Range rr("FP64 true residual");
         if (c->opt.x_dtype == xacc_dt) HIPCHK(hipMemcpyAsync(x, c->xacc, xbytes, hipMemcpyDeviceToDevice, st));
         else HIPCHK(launch_convert(xacc_dt, c->opt.x_dtype, c->n, c->xacc, x, st));
         if (res.fin.rr0 == 0.0) HIPCHK(launch_zero(c->opt.x_dtype, c->n, x, st));
@@ -908,6 +917,7 @@ pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, 
 pcg_status pcg_solve_refined(pcg_ctx c, const double* b64, double* x64, double rtol_outer, double rtol_inner,
                              int max_outer, int maxit_inner, pcg_info* info) {
     auto t0 = std::chrono::steady_clock::now();
+    Range range("pcg_solve_refined");
     if (!c) return fail(PCG_E_ARG, "pcg_solve_refined: null context");
     if (!b64 || !x64) return fail(PCG_E_ARG, "pcg_solve_refined: null pointer");
     if (!aligned16(b64) || !aligned16(x64)) return fail(PCG_E_ARG, "pcg_solve_refined: pointers must be 16-byte aligned");
@@ -928,10 +938,13 @@ pcg_status pcg_solve_refined(pcg_ctx c, const double* b64, double* x64, double r
     int nk = 0;
     pcg_status ret = PCG_E_NOCONV;
     for (;;) {
-        HIPCHK(launch_residual64(DT_F64, DT_F64, c->plan_res, c->geo_res, op_of(c), b64, x64, c->res2, red_of(c),
-                                 st));
-        HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        {
+            Range r("refinement: FP64 residual");
+            HIPCHK(launch_residual64(DT_F64, DT_F64, c->plan_res, c->geo_res, op_of(c), b64, x64, c->res2,
+                                     red_of(c), st));
+            HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
         const double rn = std::sqrt(c->hres[0]), amax = c->hres[1];
         if (outer == 0) nb = rn;  // x = 0: the residual is b
         const double t = nb > 0.0 ? rn / nb : 0.0;
@@ -952,7 +965,11 @@ pcg_status pcg_solve_refined(pcg_ctx c, const double* b64, double* x64, double r
         const double scale = 1.0 / amax;
         HIPCHK(launch_cast_scaled(c->dt, c->plan_res, c->geo_res, op_of(c), b64, x64, scale, c->rhat, st));
         IterResult res;
-        pcg_status s = run_iterations(c, c->rhat, nullptr, c->dt, rtol_inner, maxit_inner, c->opt.stag_window, &res);
+        pcg_status s;
+        {
+            Range r("refinement: low-precision inner solve");
+            s = run_iterations(c, c->rhat, nullptr, c->dt, rtol_inner, maxit_inner, c->opt.stag_window, &res);
+        }
         if (s != PCG_OK) return s;
         c->ref_inner.push_back(res.fin.iters);
         inner_total += res.fin.iters;
@@ -999,6 +1016,7 @@ pcg_status pcg_refine_history(pcg_ctx c, double* relres, int* inner_iters, int n
 static pcg_status flex_solve(pcg_ctx c, cnn_net net, bool mg, const float* g, const void* b, void* x, double rtol,
                              int maxit, pcg_info* info, const char* name) {
     auto t0 = std::chrono::steady_clock::now();
+    Range range(name);
     if (!c) return fail(PCG_E_ARG, "%s: null context", name);
     if (!b || !x) return fail(PCG_E_ARG, "%s: null pointer", name);
     if (!aligned16(b) || !aligned16(x)) return fail(PCG_E_ARG, "%s: pointers must be 16-byte aligned", name);
@@ -1117,6 +1135,7 @@ static pcg_status flex_solve(pcg_ctx c, cnn_net net, bool mg, const float* g, co
             HIPCHK(hipGraphExecDestroy(c->flex_exec[slot]));
             c->flex_exec[slot] = nullptr;
         }
+        Range range("graph capture: flexible iterations");
         if (!c->capture) HIPCHK(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
         hipStream_t old = use_net ? cnn_swap_stream(net, c->capture) : nullptr;
         hipError_t e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
@@ -1142,6 +1161,7 @@ static pcg_status flex_solve(pcg_ctx c, cnn_net net, bool mg, const float* g, co
     SolveState fin{};
     const bool graph = c->opt.use_graph && !c->opt.kernel_timing;
     auto iterate = [&](int seg_maxit) -> pcg_status {
+        Range r("flexible iterations");
         int it = 0;
         for (;;) {
             HIPCHK(hipMemcpyAsync(&c->hst[1], c->st, sizeof(SolveState), hipMemcpyDeviceToHost, st));
@@ -1165,6 +1185,7 @@ static pcg_status flex_solve(pcg_ctx c, cnn_net net, bool mg, const float* g, co
         return PCG_OK;
     };
     auto true_residual = [&](double* rel) -> pcg_status {
+        Range r("FP64 true residual");
         HIPCHK(launch_residual64(DT_F32, DT_F64, c->plan_res, c->geo_res, od, b, xacc, c->res2, red_of(c), st));
         HIPCHK(hipMemcpyAsync(c->hres, c->res2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -1199,6 +1220,7 @@ static pcg_status flex_solve(pcg_ctx c, cnn_net net, bool mg, const float* g, co
         if (s != PCG_OK) return s;
     }
     if (!mg && status == 1 && true_rel > rtol && iters < maxit) {
+        Range r("Jacobi-PCG continuation");
         IterResult res;
         s = run_iterations(c, b, xacc, DT_F64, rtol, maxit - iters, 0, &res);
         if (s != PCG_OK) return s;

@@ -136,3 +136,7 @@ def test_sell_argument_validation_without_gpu(lib):
     assert lib.pcg_sell_destroy(None) == 0
     lib.cnn_set_loss_norm.argtypes = [vp, i]
     assert lib.cnn_set_loss_norm(None, 0) == 1
+    lib.cnn_get_adam.argtypes = [vp, vp, vp, vp]
+    assert lib.cnn_get_adam(None, None, None, None) == 1
+    lib.cnn_set_adam.argtypes = [vp, vp, vp, ctypes.c_int64]
+    assert lib.cnn_set_adam(None, None, None, 0) == 1

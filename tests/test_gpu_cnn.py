@@ -357,3 +357,46 @@ def test_training_reduces_loss(P):
         losses.append(loss.item())
     print("losses", losses[0], losses[-1], flush=True)
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_adam_checkpoint_resume(P):
+    """Weights plus Adam's moments and step count restore training exactly:
+    resuming from a checkpoint reproduces the uninterrupted run bit for bit
+    (the training kernels reduce in a fixed order, with no atomics)."""
+    shape = (16, 16, 16)
+    n = int(np.prod(shape))
+    from gpu_helpers import bf16_tensor
+
+    g = torch.from_numpy(synthetic.uniform_f32(90, n)).cuda()
+    pairs = np.concatenate([synthetic.f32_to_bf16_bits(synthetic.uniform_f32(91, n)),
+                            synthetic.f32_to_bf16_bits(synthetic.uniform_f32(92, n))])
+    pt = bf16_tensor(pairs).cuda()
+    net = P.cnn_create()
+    P.cnn_set_weights(net, torch.from_numpy(_flat(_init_weights(41))).cuda())
+    for _ in range(2):
+        P.cnn_train_step(net, shape, pt, g, 1, lr=3e-3)
+    w_ck = P.cnn_get_weights(net).clone()
+    m_ck, v_ck, step_ck = P.cnn_get_adam(net)
+    assert step_ck == 2
+    assert torch.count_nonzero(v_ck) > 0
+    for _ in range(2):
+        P.cnn_train_step(net, shape, pt, g, 1, lr=3e-3)
+    w_ref = P.cnn_get_weights(net).cpu()
+
+    # a second network resumes from the checkpoint
+    net2 = P.cnn_create()
+    P.cnn_set_weights(net2, w_ck)
+    P.cnn_set_adam(net2, m_ck, v_ck, step_ck)
+    for _ in range(2):
+        P.cnn_train_step(net2, shape, pt, g, 1, lr=3e-3)
+    assert torch.equal(P.cnn_get_weights(net2).cpu(), w_ref)
+    assert P.cnn_get_adam(net2)[2] == 4
+
+    # without the moments (set_weights resets them) the run differs
+    net3 = P.cnn_create()
+    P.cnn_set_weights(net3, w_ck)
+    for _ in range(2):
+        P.cnn_train_step(net3, shape, pt, g, 1, lr=3e-3)
+    assert not torch.equal(P.cnn_get_weights(net3).cpu(), w_ref)
+    with pytest.raises(RuntimeError):
+        P.cnn_set_adam(net3, m_ck, v_ck, -1)
