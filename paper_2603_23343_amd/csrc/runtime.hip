@@ -524,38 +524,52 @@ std::vector<double> dense_operator(int nx, int ny, int nz, const std::vector<flo
 }
 
 // Inverse of a symmetric positive definite matrix (row-major, m x m) through
-// its Cholesky factor A = L L^T: columns of A^-1 from L y = e_j, L^T x = y.
+// its Cholesky factor A = L L^T: Y = L^-1 (lower triangular, row i from rows
+// 0..i-1 of Y), then A^-1 = Y^T Y, summed as outer products of Y's rows. Every
+// inner loop runs along a row, so the m^3 work streams through memory.
 // False if a pivot is not positive.
 bool spd_inverse(const std::vector<double>& A, int m, std::vector<double>& inv) {
-    std::vector<double> L((size_t)m * m, 0.0);
+    const size_t M = (size_t)m;
+    std::vector<double> L(M * M, 0.0);
     for (int j = 0; j < m; ++j) {
-        double d = A[(size_t)j * m + j];
-        for (int k = 0; k < j; ++k) d -= L[(size_t)j * m + k] * L[(size_t)j * m + k];
+        const double* lj = &L[j * M];
+        double d = A[j * M + j];
+        for (int k = 0; k < j; ++k) d -= lj[k] * lj[k];
         if (!(d > 0.0)) return false;
         const double ljj = std::sqrt(d);
-        L[(size_t)j * m + j] = ljj;
+        L[j * M + j] = ljj;
         for (int i = j + 1; i < m; ++i) {
-            double t = A[(size_t)i * m + j];
-            const double* li = &L[(size_t)i * m];
-            const double* lj = &L[(size_t)j * m];
+            const double* li = &L[i * M];
+            double t = A[i * M + j];
             for (int k = 0; k < j; ++k) t -= li[k] * lj[k];
-            L[(size_t)i * m + j] = t / ljj;
+            L[i * M + j] = t / ljj;
         }
     }
-    inv.assign((size_t)m * m, 0.0);
-    std::vector<double> y(m);
-    for (int c = 0; c < m; ++c) {
-        for (int i = 0; i < m; ++i) {
-            double t = i == c ? 1.0 : 0.0;
-            for (int k = c; k < i; ++k) t -= L[(size_t)i * m + k] * y[k];
-            y[i] = i < c ? 0.0 : t / L[(size_t)i * m + i];
+    // Y = L^-1: Y[i][0..i] = (e_i - sum_{k<i} L[i][k] Y[k][0..k]) / L[i][i]
+    std::vector<double> Y(M * M, 0.0);
+    for (int i = 0; i < m; ++i) {
+        double* yi = &Y[i * M];
+        yi[i] = 1.0;
+        for (int k = 0; k < i; ++k) {
+            const double lik = L[i * M + k];
+            const double* yk = &Y[k * M];
+            for (int c = 0; c <= k; ++c) yi[c] -= lik * yk[c];
         }
-        for (int i = m - 1; i >= 0; --i) {
-            double t = y[i];
-            for (int k = i + 1; k < m; ++k) t -= L[(size_t)k * m + i] * inv[(size_t)k * m + c];
-            inv[(size_t)i * m + c] = t / L[(size_t)i * m + i];
+        const double r = 1.0 / L[i * M + i];
+        for (int c = 0; c <= i; ++c) yi[c] *= r;
+    }
+    // A^-1 = Y^T Y: lower triangle from the rows' outer products, then mirrored
+    inv.assign(M * M, 0.0);
+    for (int i = 0; i < m; ++i) {
+        const double* yi = &Y[i * M];
+        for (int a = 0; a <= i; ++a) {
+            const double ya = yi[a];
+            double* row = &inv[(size_t)a * M];
+            for (int b = 0; b <= a; ++b) row[b] += ya * yi[b];
         }
     }
+    for (int a = 0; a < m; ++a)
+        for (int b = 0; b < a; ++b) inv[(size_t)b * M + a] = inv[(size_t)a * M + b];
     return true;
 }
 

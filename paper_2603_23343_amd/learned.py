@@ -18,6 +18,7 @@ import numpy as np
 import torch
 
 from . import _binding as B
+from . import checkpoint
 
 
 def snapshot_iterations(first: int, last: int, count: int) -> list[int]:
@@ -151,11 +152,14 @@ def onpolicy_pairs(net, n: int, kcell: torch.Tensor, g: torch.Tensor, rhs_seeds,
 
 def train_onpolicy(net, n: int, kcell: torch.Tensor, g: torch.Tensor, train_seeds, rounds: int = 4,
                    epochs: int = 3, batch: int = 8, lr: float = 1e-3, snaps_per_rhs: int = 16,
-                   onpolicy_seeds: int = 4, onpolicy_iters=None, seed: int = 0, stream=None):
+                   onpolicy_seeds: int = 4, onpolicy_iters=None, seed: int = 0, stream=None,
+                   checkpoint_path: str | None = None):
     """A-norm training (cnn_set_operator) of the Jacobi-plus-correction
     network: FP64 Jacobi-PCG snapshot pairs, then `rounds` rounds of
     `epochs` epochs, each followed by on-policy pairs from flexible-CG
     trajectories of `onpolicy_seeds` training right-hand sides (cycled).
+    With checkpoint_path, the weights and Adam state are written there after
+    every round (checkpoint.save; metadata: round, grid, loss, pairs).
     Returns a log dict (losses per round, pair counts, seconds)."""
     ctx = B.pcg_create(n, n, n, torch.float32, stream=stream)
     B.pcg_set_coefficients(ctx, kcell)
@@ -171,6 +175,9 @@ def train_onpolicy(net, n: int, kcell: torch.Tensor, g: torch.Tensor, train_seed
         log["losses"].append(hist[-1])
         log["pairs"].append(pairs.numel() // (2 * N))
         log["train_s"] += tt
+        if checkpoint_path:
+            checkpoint.save(net, checkpoint_path, meta={"round": rnd + 1, "grid": n, "loss": hist[-1],
+                                                        "pairs": log["pairs"][-1]})
         if rnd + 1 == rounds:
             break
         pick = [seeds[(rnd * onpolicy_seeds + j) % len(seeds)] for j in range(onpolicy_seeds)]

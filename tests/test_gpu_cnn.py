@@ -359,10 +359,11 @@ def test_training_reduces_loss(P):
     assert losses[-1] < 0.5 * losses[0]
 
 
-def test_adam_checkpoint_resume(P):
+def test_adam_checkpoint_resume(P, tmp_path):
     """Weights plus Adam's moments and step count restore training exactly:
-    resuming from a checkpoint reproduces the uninterrupted run bit for bit
-    (the training kernels reduce in a fixed order, with no atomics)."""
+    resuming from a checkpoint (in memory, or through a checkpoint file)
+    reproduces the uninterrupted run bit for bit (the training kernels reduce
+    in a fixed order, with no atomics)."""
     shape = (16, 16, 16)
     n = int(np.prod(shape))
     from gpu_helpers import bf16_tensor
@@ -377,6 +378,10 @@ def test_adam_checkpoint_resume(P):
         P.cnn_train_step(net, shape, pt, g, 1, lr=3e-3)
     w_ck = P.cnn_get_weights(net).clone()
     m_ck, v_ck, step_ck = P.cnn_get_adam(net)
+    from paper_2603_23343_amd import checkpoint
+
+    ck_path = str(tmp_path / "net.ckpt")
+    checkpoint.save(net, ck_path, meta={"steps": 2})
     assert step_ck == 2
     assert torch.count_nonzero(v_ck) > 0
     for _ in range(2):
@@ -391,6 +396,13 @@ def test_adam_checkpoint_resume(P):
         P.cnn_train_step(net2, shape, pt, g, 1, lr=3e-3)
     assert torch.equal(P.cnn_get_weights(net2).cpu(), w_ref)
     assert P.cnn_get_adam(net2)[2] == 4
+
+    # the same through the checkpoint file
+    net4 = P.cnn_create()
+    assert checkpoint.load(net4, ck_path) == {"steps": 2}
+    for _ in range(2):
+        P.cnn_train_step(net4, shape, pt, g, 1, lr=3e-3)
+    assert torch.equal(P.cnn_get_weights(net4).cpu(), w_ref)
 
     # without the moments (set_weights resets them) the run differs
     net3 = P.cnn_create()
