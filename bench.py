@@ -65,10 +65,23 @@ METRIC = "PCG seconds to 1e-6 rel resid @256³; stencil/dot/axpy achieved HBM GB
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per grid point of the two iteration kernels (FP32
-# storage, FP64 x accumulator): direction reads r, p_old and writes p;
-# update reads p, r, x(FP64) and writes r, x(FP64).
+# storage, FP64 x accumulator): direction reads r, p_old and writes p. The
+# update advances x every second iteration: an odd iteration's update reads
+# p, r and writes r (12); the next reads p, p_prev, r, x(FP64) and writes r,
+# x(FP64) (32). The batched kernel advances x in every update (28).
 BYTES_DIRECTION = 12
-BYTES_UPDATE = 28
+BYTES_UPDATE_SKIP = 12
+BYTES_UPDATE_PAIR = 32
+BYTES_UPDATE_X = 28
+
+
+def update_bytes(launches: int, es: int = 4, xs: int = 8) -> float:
+    """Mean algorithmic bytes per point of `launches` consecutive update
+    launches from the first iteration (odd ones skip x, even ones add two
+    steps); es: storage bytes, xs: accumulator bytes."""
+    skip, pair = 3 * es, 4 * es + 2 * xs
+    n_pair = launches // 2
+    return (skip * (launches - n_pair) + pair * n_pair) / max(launches, 1)
 
 
 # Sources that define the PCG iteration kernels and their launch plans;
@@ -345,7 +358,8 @@ def bench_slab(P, torch, n=256, parts=8, iters=100):
     return {"slab": [n, n, nzs], "of": [n, n, n], "parts": parts, "iterations_timed": info["k2_launches"],
             "status": P.STATUS_NAMES[info["status"]],
             "direction_us": round(k1, 2), "update_us": round(k2, 2), "iteration_kernels_us": round(k1 + k2, 2),
-            "iteration_GB/s": round((BYTES_DIRECTION + BYTES_UPDATE) * N / ((k1 + k2) * 1e-6) / 1e9, 1),
+            "iteration_GB/s": round((BYTES_DIRECTION + update_bytes(info["k2_launches"])) * N / ((k1 + k2) * 1e-6)
+                                    / 1e9, 1),
             "stencil_with_halo_planes_us": round(st_us, 2),
             "halo_bytes_per_iteration_each_way": halo,
             "halo_note": "one plane of r and p_old to each z-neighbour per iteration (plus two scalar all-reduces); "
@@ -529,7 +543,7 @@ def bench_batched(P, torch, reps, oracle_budget_s=0.0):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / reps
     lat = sorted(r["latency_s"])
-    traffic = sum(float(BYTES_DIRECTION + BYTES_UPDATE) * m ** 3 * it for m, it in zip(sizes, r["iters"]))
+    traffic = sum(float(BYTES_DIRECTION + BYTES_UPDATE_X) * m ** 3 * it for m, it in zip(sizes, r["iters"]))
     # the same 64 problems one after another through pcg_solve
     ctxs = []
     for i, m in enumerate(sizes):
@@ -770,22 +784,27 @@ def main():
     tinfo = P.pcg_solve(tctx, b, x, 1e-6, args.maxit, raise_on_error=False)
     k2_us = tinfo["k2_ms"] * 1e3 / max(tinfo["k2_launches"], 1)
     k1_us = tinfo["k1_ms"] * 1e3 / max(tinfo["k1_launches"], 1)
-    achieved = BYTES_UPDATE * N / (k2_us * 1e-6) / 1e9
+    bytes_upd = update_bytes(tinfo["k2_launches"])
+    achieved = bytes_upd * N / (k2_us * 1e-6) / 1e9
+    bytes_iter = BYTES_DIRECTION + update_bytes(iters)
     traffic = load_traffic("pcg_update")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "pcg_update (k_pcg_update<..., OpUpdate, FinAlpha>: finishes p.Ap, then the update)",
-                "bytes_per_launch": BYTES_UPDATE * N, "avg_us": round(k2_us, 2),
+                "bytes_per_launch": round(bytes_upd * N), "avg_us": round(k2_us, 2),
+                "update_bytes_per_point": {"odd (x left)": BYTES_UPDATE_SKIP, "even (x += two steps)": BYTES_UPDATE_PAIR,
+                                           "mean over the solve's launches": round(bytes_upd, 3)},
                 "direction_kernel_avg_us": round(k1_us, 2),
                 "direction_kernel_GB/s": round(BYTES_DIRECTION * N / (k1_us * 1e-6) / 1e9, 1),
                 # both kernels' algorithmic bytes over the timed solve's time per iteration
-                "iteration_GB/s": round((BYTES_DIRECTION + BYTES_UPDATE) * N / (dt_solve / iters) / 1e9, 1),
-                "iteration_frac": round((BYTES_DIRECTION + BYTES_UPDATE) * N / (dt_solve / iters) / 1e9
-                                        / HBM_PEAK_GBS, 4),
+                "iteration_GB/s": round(bytes_iter * N / (dt_solve / iters) / 1e9, 1),
+                "iteration_frac": round(bytes_iter * N / (dt_solve / iters) / 1e9 / HBM_PEAK_GBS, 4),
                 "event_timed_solve_ms": round(tinfo["seconds"] * 1e3, 2),
-                # q = Ap is recomputed, never stored: 40 B/pt per iteration here
-                # against 52 for the textbook fused iteration that stores q
-                "bytes_convention": "design 12+28 = 40 B/pt per iteration (q never stored); "
+                # q = Ap is recomputed, never stored, and x advances every second
+                # iteration: 34 B/pt per iteration here against 40 with x in every
+                # update and 52 for the textbook fused iteration that stores q
+                "bytes_convention": "design 12 + (12 or 32) = 34 B/pt per iteration on average (q never "
+                                    "stored, x advanced every second iteration); 40 with x in every update; "
                                     "the textbook count with q stored is 52 B/pt",
                 "iteration_frac_at_52B": round(52 * N / (dt_solve / iters) / 1e9 / HBM_PEAK_GBS, 4),
                 "traffic_note": "FETCH_SIZE counts L2 fills, last-level-cache hits included"}
@@ -809,8 +828,9 @@ def main():
             # per-kernel times of the inner iterations: the same refinement
             # with HIP events around every inner iteration kernel. Algorithmic
             # bytes per point with e-byte storage and the FP32 correction d:
-            # direction reads r, p_old and writes p (3e); update reads p, r,
-            # d and writes r, d (3e + 8).
+            # direction reads r, p_old and writes p (3e); update reads p, r
+            # and writes r (3e), and every second one also reads p_prev and
+            # reads and writes d (4e + 8).
             tctx = P.pcg_create(n, n, n, rdt, x_accum=torch.float32, kernel_timing=1)
             tr = P.pcg_solve_refined(tctx, b64, x64, rtol_outer=1e-10)
             es = 2
@@ -818,8 +838,10 @@ def main():
             k2 = tr["k2_ms"] * 1e3 / max(tr["k2_launches"], 1)
             refined[name]["inner_kernels"] = {
                 "direction_us": round(k1, 2), "direction_GB/s": round(3 * es * N / (k1 * 1e-6) / 1e9, 1),
-                "update_us": round(k2, 2), "update_GB/s": round((3 * es + 8) * N / (k2 * 1e-6) / 1e9, 1),
-                "iteration_GB/s": round((6 * es + 8) * N / ((k1 + k2) * 1e-6) / 1e9, 1),
+                "update_us": round(k2, 2),
+                "update_GB/s": round(update_bytes(tr["k2_launches"], es, 4) * N / (k2 * 1e-6) / 1e9, 1),
+                "iteration_GB/s": round((3 * es + update_bytes(tr["k2_launches"], es, 4)) * N / ((k1 + k2) * 1e-6)
+                                        / 1e9, 1),
                 "launches": tr["k1_launches"]}
             P.pcg_destroy(tctx)
             del x64

@@ -83,6 +83,13 @@ typedef struct {
                           256 work-groups, else the direction kernel's; the direction
                           kernel's when zchunk is given); -1 = the direction kernel's;
                           > 0 = this many */
+    int x_defer;        /* two-kernel form: 1 (default) = the x accumulator advances every
+                          second iteration (an odd iteration's update leaves x, the next
+                          adds alpha_{k-1} p_{k-1} + alpha_k p_k; nothing in the recursion
+                          reads x), so the update moves 12 and 32 bytes per point in turn
+                          instead of 28 each time (FP32 storage, FP64 x); same bits of x
+                          for an FP64 accumulator. 0 = x current after every iteration
+                          (the same kernels plus one x += alpha p pass per iteration) */
 } pcg_options;
 
 typedef struct {

@@ -35,7 +35,7 @@ class PcgOptions(ctypes.Structure):
                 ("use_x0", ctypes.c_int), ("use_graph", ctypes.c_int), ("kernel_timing", ctypes.c_int),
                 ("tile_x", ctypes.c_int), ("tile_y", ctypes.c_int), ("zchunk", ctypes.c_int),
                 ("stag_window", ctypes.c_int), ("max_restarts", ctypes.c_int), ("single_reduction", ctypes.c_int),
-                ("zchunk_update", ctypes.c_int)]
+                ("zchunk_update", ctypes.c_int), ("x_defer", ctypes.c_int)]
 
 
 class PcgInfo(ctypes.Structure):

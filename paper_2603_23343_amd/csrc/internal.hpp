@@ -87,11 +87,16 @@ struct Chain {
 // p_old (rounded to storage) and partials of p.Ap.
 hipError_t launch_pcg_direction(int dt, const Plan& p, const Geometry& g, OpDesc od, const void* r,
                                 const void* pold, void* pnew, const Chain& ch, hipStream_t s);
-// Iteration kernel 2: finishes p.Ap into alpha; then q = A p, x += alpha p,
-// r -= alpha q and partials of r.r (and r.z). x (the accumulator) is of type
-// xdt: FP64, FP32 or the storage type.
+// Iteration kernel 2: finishes p.Ap into alpha; then q = A p, r -= alpha q
+// and partials of r.r (and r.z). x (the accumulator) is of type xdt: FP64,
+// FP32 or the storage type. xmode 1: x is left as it is; xmode 2: x +=
+// alpha_prev pprev + alpha p (pprev: the previous iteration's direction).
 hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, OpDesc od, const void* pdir, void* x,
-                             int xdt, void* r, const Chain& ch, hipStream_t s);
+                             int xdt, void* r, int xmode, const void* pprev, const Chain& ch, hipStream_t s);
+// x += alpha p (alpha from *st) over n points; with check_done, nothing when
+// the state records a finished solve.
+hipError_t launch_x_finish(int dt, int xdt, int64_t n, void* x, const void* p, const SolveState* st,
+                           bool check_done, hipStream_t s);
 // Finishes the last update's partials of a chain (beta, count, convergence).
 hipError_t launch_pcg_close(bool var, const Chain& ch, hipStream_t s);
 

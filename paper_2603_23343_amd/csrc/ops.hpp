@@ -30,6 +30,7 @@ struct SolveState {
     int flags;        // FLEX_JACOBI: preconditioner is D^-1; FLEX_RESTART: next beta = 0; FLEX_REDO
     int fallback_at;  // iteration of the switch to Jacobi (-1: none)
     double zr;        // z.r of the last preconditioned residual
+    double alpha_prev;  // alpha of the iteration before (x advanced every second iteration)
 };
 // FLEX_MG: the preconditioned residual z is the multigrid V-cycle's, taken as it is.
 constexpr int FLEX_JACOBI = 1, FLEX_RESTART = 2, FLEX_REDO = 4, FLEX_MG = 8;
@@ -319,19 +320,28 @@ template <typename T, int VX> struct OpDirection {
     }
 };
 
-// Iteration kernel 2: with q = A p recomputed from p, x += alpha p and
-// r = stored(r - alpha q); accumulate r.r of the stored residual and, with a
-// variable Jacobi scale (dinv != null), r.z = sum dinv r^2 as component 1.
+// Iteration kernel 2: with q = A p recomputed from p, r = stored(r - alpha q);
+// accumulate r.r of the stored residual and, with a variable Jacobi scale
+// (dinv != null), r.z = sum dinv r^2 as component 1. The x accumulator (XM):
+//   XM = 0: x += alpha p every iteration;
+//   XM = 1: x untouched (an odd iteration when x advances every second one);
+//   XM = 2: x += alpha_prev p_prev + alpha p (the even iteration after it,
+//           p_prev the previous direction, still in the other p buffer).
+// Nothing in the recursion reads x, so it may lag one iteration: advancing it
+// every second iteration takes the x stream (16 B/pt in FP64) out of every
+// other update. With an FP64 accumulator XM = 2 performs exactly the two
+// FP64 steps XM = 0 would, so x keeps its bits.
 // NTX: x is loaded and stored non-temporally. When an iteration's vectors
 // exceed the last-level cache, x (read again only one iteration later, and
 // the widest stream) then leaves the cache to r and p, which the next
 // kernel re-reads: measured 126 -> 119 us per iteration at 256^3.
-template <typename T, typename X, int VX, bool VAR = false, bool NTX = false> struct OpUpdate {
+template <typename T, typename X, int VX, bool VAR = false, bool NTX = false, int XM = 0> struct OpUpdate {
     using C = typename Traits<T>::C;
     struct Raw {
         RawN<T, VX> r;
-        RawN<X, VX> x;
+        RawN<X, XM == 1 ? 1 : VX> x;
         RawN<T, VAR ? VX : 1> d;
+        RawN<T, XM == 2 ? VX : 1> pp;
     };
     X* __restrict__ x;
     T* __restrict__ r;
@@ -339,15 +349,21 @@ template <typename T, typename X, int VX, bool VAR = false, bool NTX = false> st
     const T* __restrict__ dinv;
     C alpha;
     double alpha_d;
+    const T* __restrict__ pprev = nullptr;  // XM = 2: the previous direction
+    double alpha_prev_d = 0.0;
     __device__ void init() {
         alpha = (C)st->alpha;
         alpha_d = (double)alpha;
+        if constexpr (XM == 2) alpha_prev_d = (double)(C)st->alpha_prev;
     }
     __device__ __forceinline__ void fetch(int64_t i, Raw& raw) const {
         raw.r.load(r + i);
-        if constexpr (NTX) raw.x.load_nt(x + i);
-        else raw.x.load(x + i);
+        if constexpr (XM != 1) {
+            if constexpr (NTX) raw.x.load_nt(x + i);
+            else raw.x.load(x + i);
+        }
         if constexpr (VAR) raw.d.load(dinv + i);
+        if constexpr (XM == 2) raw.pp.load(pprev + i);
     }
     template <int NC, class Cell>
     __device__ __forceinline__ void apply(int64_t i, const Raw& raw, const Cell* c, const C* ax, C (&acc)[NC]) const {
@@ -355,13 +371,20 @@ template <typename T, typename X, int VX, bool VAR = false, bool NTX = false> st
         double xv[VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
-            xv[v] = (double)raw.x.get(v) + alpha_d * (double)cell_u(c[v]);
+            if constexpr (XM == 0) {
+                xv[v] = (double)raw.x.get(v) + alpha_d * (double)cell_u(c[v]);
+            } else if constexpr (XM == 2) {
+                const double t = (double)raw.x.get(v) + alpha_prev_d * (double)raw.pp.get(v);
+                xv[v] = t + alpha_d * (double)cell_u(c[v]);
+            }
             rv[v] = stored<T>(raw.r.get(v) - alpha * ax[v]);
             acc[0] += rv[v] * rv[v];
             if constexpr (VAR) acc[NC - 1] += raw.d.get(v) * rv[v] * rv[v];
         }
-        if constexpr (NTX) st_any_nt<X, VX>(x, i, xv);
-        else st_any<X, VX>(x, i, xv);
+        if constexpr (XM != 1) {
+            if constexpr (NTX) st_any_nt<X, VX>(x, i, xv);
+            else st_any<X, VX>(x, i, xv);
+        }
         st_pts<T, VX>(r, i, rv);
     }
 };
@@ -558,6 +581,7 @@ struct FinAlpha {
             st->done = 2;
             return;
         }
+        st->alpha_prev = st->alpha;
         st->alpha = st->rho / sigma;
     }
 };

@@ -8,8 +8,12 @@
 //            halo; stores p; partials of sigma = p.Ap.
 //   kernel 2 (update):    finishes sigma (alpha = rho / sigma, or a
 //            breakdown); q = A p recomputed from p (cheaper than storing and
-//            re-reading q); x += alpha p; r = r - alpha q; partials of r.r
-//            (and r.z = sum dinv r^2 for a variable Jacobi scale).
+//            re-reading q); r = r - alpha q; partials of r.r (and r.z =
+//            sum dinv r^2 for a variable Jacobi scale). x advances every
+//            second iteration: odd iterations leave it, even ones add
+//            alpha_prev p_prev + alpha p (p_prev is still in the other p
+//            buffer); a run that ends after an odd iteration adds the last
+//            alpha p with k_x_finish.
 //
 // Each kernel finishes the reduction its predecessor left (chained
 // reductions: no finishing kernel between them); a run of iterations ends
@@ -19,6 +23,8 @@
 // neighbouring work-groups are overwriting in the same launch otherwise.
 // With variable coefficients (od.kc) the stencil is the harmonic-mean
 // operator and D^-1 is the array od.dinv.
+#include <algorithm>
+
 #include "zkernel.hpp"
 
 namespace pcgmi {
@@ -65,7 +71,8 @@ hipError_t launch_pcg_direction(int dt, const Plan& p, const Geometry& g, OpDesc
 }
 
 hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, OpDesc od, const void* pdir, void* x,
-                             int xdt, void* r, const Chain& ch, hipStream_t s) {
+                             int xdt, void* r, int xmode, const void* pprev, const Chain& ch, hipStream_t s) {
+    if (xmode != 1 && xmode != 2) return hipErrorInvalidValue;
     // r, p, p_old and x of one iteration against the last-level cache
     const size_t footprint = (size_t)g.nx * g.ny * g.nz * (3 * dt_size(dt) + dt_size(xdt));
     const bool ntx = footprint > LLC_BYTES;
@@ -74,20 +81,28 @@ hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, OpDesc od
         using C = typename Traits<T>::C;
         return dispatch_cfg<Traits<T>::W>(p.cfg, [&]<int BX, int BY, int VX>() {
             // NTX is compiled for the FP64 accumulator only (the widest x stream).
-            auto go_nt = [&]<bool NTX>(auto xtag) -> hipError_t {
+            auto go_x = [&]<bool NTX, int XM>(auto xtag) -> hipError_t {
                 using X = decltype(xtag);
                 if (od.kc) {
                     if constexpr (VAR_TYPE<T>) {
                         LoadUK<T> ld{static_cast<const T*>(pdir), od.kc};
-                        OpUpdate<T, X, VX, true, NTX> op{static_cast<X*>(x), static_cast<T*>(r), nullptr,
-                                                         static_cast<const T*>(od.dinv), C(0), 0.0};
+                        OpUpdate<T, X, VX, true, NTX, XM> op{static_cast<X*>(x), static_cast<T*>(r), nullptr,
+                                                             static_cast<const T*>(od.dinv), C(0), 0.0};
+                        op.pprev = static_cast<const T*>(pprev);
                         return run_chain<1, C, StencilVar<C>, BX, BY, VX, 2, 1>(g, ld, op, FinAlpha{nullptr}, ch, s);
                     }
                     return hipErrorInvalidValue;
                 }
                 LoadField<T> ld{static_cast<const T*>(pdir)};
-                OpUpdate<T, X, VX, false, NTX> op{static_cast<X*>(x), static_cast<T*>(r), nullptr, nullptr, C(0), 0.0};
+                OpUpdate<T, X, VX, false, NTX, XM> op{static_cast<X*>(x), static_cast<T*>(r), nullptr, nullptr, C(0),
+                                                      0.0};
+                op.pprev = static_cast<const T*>(pprev);
                 return run_chain<1, C, StencilConst<C>, BX, BY, VX, 1, 1>(g, ld, op, FinAlpha{nullptr}, ch, s);
+            };
+            auto go_nt = [&]<bool NTX>(auto xtag) -> hipError_t {
+                if (xmode == 2) return go_x.template operator()<NTX, 2>(xtag);
+                // x is not touched: one instantiation serves every accumulator type
+                return go_x.template operator()<false, 1>(float{});
             };
             auto go = [&](auto xtag) -> hipError_t {
                 using X = decltype(xtag);
@@ -100,6 +115,47 @@ hipError_t launch_pcg_update(int dt, const Plan& p, const Geometry& g, OpDesc od
             if (xdt == dt) return go(T{});
             return hipErrorInvalidValue;
         });
+    });
+}
+
+namespace {
+
+// x += alpha p over n points, alpha the state's (rounded to the compute type,
+// as the update kernel uses it): the step a run that ends after an odd
+// iteration still owes x, or every iteration's step when x must be current
+// after each one. check_done: skip when the state records a finished solve
+// (the update before it did not run).
+template <typename T, typename X>
+__global__ void __launch_bounds__(256) k_x_finish(int64_t n, X* __restrict__ x, const T* __restrict__ p,
+                                                  const SolveState* st, int check_done) {
+    if (check_done && st->done != 0) return;
+    using C = typename Traits<T>::C;
+    const double a = (double)(C)st->alpha;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double v = (double)to_c(x[i]) + a * (double)to_c(p[i]);
+        st_any<X, 1>(x, i, &v);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_x_finish(int dt, int xdt, int64_t n, void* x, const void* p, const SolveState* st,
+                           bool check_done, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 16384);
+    return dispatch_dt(dt, [&](auto tag) {
+        using T = decltype(tag);
+        auto go = [&](auto xtag) -> hipError_t {
+            using X = decltype(xtag);
+            hipLaunchKernelGGL((k_x_finish<T, X>), dim3((unsigned)blocks), dim3(256), 0, s, n, static_cast<X*>(x),
+                               static_cast<const T*>(p), st, check_done ? 1 : 0);
+            return hipGetLastError();
+        };
+        if (xdt == DT_F64) return go(double{});
+        if (xdt == DT_F32) return go(float{});
+        if (xdt == dt) return go(T{});
+        return hipErrorInvalidValue;
     });
 }
 

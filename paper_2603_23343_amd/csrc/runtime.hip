@@ -289,7 +289,11 @@ hipError_t enqueue_iters_sr(pcg_ctx c, int first, int count, hipStream_t s, hipE
     return launch_pcg_sr_close(Chain{part[(count - 1) & 1], nb, st[(count + 1) & 1], st[count & 1], c->hist, nullptr}, s);
 }
 
-hipError_t enqueue_iters(pcg_ctx c, int first, int count, hipStream_t s, hipEvent_t* evs) {
+// Iterations first .. first + count - 1 of the two-kernel form. x advances
+// every second iteration (x_defer; odd iterations leave it, even ones add
+// both steps); every_x, or x_defer = 0: every iteration leaves x current
+// (the update skips x and k_x_finish adds alpha p from the update's state).
+hipError_t enqueue_iters(pcg_ctx c, int first, int count, hipStream_t s, hipEvent_t* evs, bool every_x = false) {
     if (c->sr_active) return enqueue_iters_sr(c, first, count, s, evs);
     if (count <= 0) return hipSuccess;
     SolveState* s0 = c->st;
@@ -307,8 +311,15 @@ hipError_t enqueue_iters(pcg_ctx c, int first, int count, hipStream_t s, hipEven
         if (e != hipSuccess) return e;
         if (evs) (void)hipEventRecord(evs[3 * (i - first) + 1], s);
         const Chain uch{pdir, nbd, s0, s1, c->hist, pupd};
-        e = launch_pcg_update(c->dt, c->plan_upd, c->geo_upd, op_of(c), pnew, c->xacc, c->opt.x_accum, c->r, uch, s);
+        const bool defer = c->opt.x_defer && !every_x;
+        const int xmode = defer && (i & 1) == 0 ? 2 : 1;
+        e = launch_pcg_update(c->dt, c->plan_upd, c->geo_upd, op_of(c), pnew, c->xacc, c->opt.x_accum, c->r, xmode,
+                              pold, uch, s);
         if (e != hipSuccess) return e;
+        if (!defer) {
+            e = launch_x_finish(c->dt, c->opt.x_accum, c->n, c->xacc, pnew, s1, true, s);
+            if (e != hipSuccess) return e;
+        }
         if (evs) (void)hipEventRecord(evs[3 * (i - first) + 2], s);
     }
     return launch_pcg_close(op_of(c).kc != nullptr, Chain{pupd, nbu, s1, s0, c->hist, nullptr}, s);
@@ -478,6 +489,12 @@ pcg_status run_iterations(pcg_ctx c, const void* b, const void* x0, int x0_dt, d
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipMemcpy(&fin, c->st, sizeof(SolveState), hipMemcpyDeviceToHost));
     c->last_iters = fin.iters;
+    // x advances every second iteration: after an odd count it still owes
+    // the last step (its direction is in p[1], its alpha in the state).
+    if (!c->sr_active && c->opt.x_defer && (fin.iters & 1)) {
+        HIPCHK(launch_x_finish(c->dt, c->opt.x_accum, c->n, c->xacc, c->p[1], c->st, false, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
     // Only iterations that did work count (later launches of the last chunk
     // return at once).
     const int nwork = std::min<int>(fin.iters, (int)k1_each.size());
@@ -708,6 +725,7 @@ pcg_status pcg_options_default(pcg_options* o) {
     o->stag_window = -1;
     o->max_restarts = -1;
     o->single_reduction = -1;
+    o->x_defer = 1;
     return PCG_OK;
 }
 
@@ -722,6 +740,7 @@ pcg_status pcg_create(pcg_ctx* out, int nx, int ny, int nz, pcg_dtype storage, v
     pcg_options o;
     pcg_options_default(&o);
     if (opt) o = *opt;
+    o.x_defer = o.x_defer != 0;
     if (o.chunk_iters <= 0) o.chunk_iters = 16;
     if (o.chunk_iters & 1) ++o.chunk_iters;
     if (o.x_dtype < 0) o.x_dtype = storage;
@@ -1307,7 +1326,7 @@ pcg_status pcg_solve_snapshots(pcg_ctx c, const void* b, void* x, double rtol, i
     int j = 0;
     SolveState fin{};
     for (int it = 1; it <= maxit; ++it) {
-        hipError_t e = enqueue_iters(c, it, 1, st, nullptr);
+        hipError_t e = enqueue_iters(c, it, 1, st, nullptr, true);
         if (e != hipSuccess) return fail(PCG_E_HIP, "pcg_solve_snapshots: %s", hipGetErrorString(e));
         while (j < nsnap && snap_iters[j] == it) {
             HIPCHK(hipMemcpyAsync(static_cast<char*>(r_snaps) + (size_t)j * c->n * es, c->r, c->n * es,

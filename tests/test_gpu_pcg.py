@@ -199,3 +199,62 @@ def test_kernel_timing_counts_each_iteration_once(P, orc):
     _, _, info, _ = _solve(P, shape, b, rtol=1e-7, maxit=3000, x_dtype=torch.float64, kernel_timing=1)
     assert info["k1_launches"] == info["iters"] == info["k2_launches"]
     assert info["k1_ms"] + info["k2_ms"] <= info["seconds"] * 1e3
+
+
+@pytest.mark.parametrize("maxit", [7, 8, 2000])
+@pytest.mark.parametrize("var", [False, True])
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_deferred_x_same_bits(P, orc, maxit, var, use_graph):
+    """x advanced every second iteration (the default) against x advanced
+    every iteration: the FP64 accumulator performs the same FP64 steps, so x
+    is bit-identical, whether the run stops after an odd (7) or even (8)
+    iteration count or at convergence (graph replays and eager launches)."""
+    shape = (19, 24, 33)
+    nz, ny, nx = shape
+    n = nx * ny * nz
+    b, b64 = make_vec(61, n, torch.float32)
+    res = {}
+    for defer in (1, 0):
+        ctx = P.pcg_create(nx, ny, nz, torch.float32, x_dtype=torch.float64, x_defer=defer, use_graph=use_graph,
+                           single_reduction=0)
+        if var:
+            k = torch.from_numpy(np.exp(synthetic.uniform_f32(62, n).astype(np.float64)).astype(np.float32)).cuda()
+            P.pcg_set_coefficients(ctx, k)
+        x = torch.empty(n, dtype=torch.float64, device="cuda")
+        info = P.pcg_solve(ctx, b, x, 1e-6, maxit, raise_on_error=False)
+        res[defer] = (host64(x), info)
+    (x1, i1), (x0, i0) = res[1], res[0]
+    print(maxit, var, use_graph, i1["iters"], i0["iters"], i1["status"], flush=True)
+    assert i1["iters"] == i0["iters"] and i1["status"] == i0["status"]
+    assert np.array_equal(x1.view(np.uint64), x0.view(np.uint64))
+    if maxit < 100:
+        assert i1["iters"] == maxit and i1["status"] == P.PCG_E_NOCONV
+    else:
+        assert i1["status"] == P.PCG_OK
+        if not var:
+            assert orc.true_relres(shape, b64, x1) <= 1e-6
+
+
+@pytest.mark.parametrize("storage", [torch.float32, torch.bfloat16])
+def test_deferred_x_fp32_accumulator(P, orc, storage):
+    """With an FP32 (or storage-type) accumulator the deferred form rounds x
+    once per two steps instead of once per step: the recursion is unchanged
+    (same iterations and residual history; no FP64 restarts, which read x)
+    and x agrees to the accumulator's accuracy."""
+    shape = (16, 20, 24)
+    nz, ny, nx = shape
+    n = nx * ny * nz
+    b, b64 = make_vec(63, n, torch.float32)
+    b = b.to(storage)
+    out = {}
+    for defer in (1, 0):
+        ctx = P.pcg_create(nx, ny, nz, storage, x_accum=torch.float32, x_dtype=storage, x_defer=defer,
+                           single_reduction=0, max_restarts=0)
+        x = torch.empty(n, dtype=storage, device="cuda")
+        info = P.pcg_solve(ctx, b, x, 1e-3, 500, raise_on_error=False)
+        out[defer] = (x.double().cpu().numpy(), info, P.pcg_get_history(ctx))
+    (x1, i1, h1), (x0, i0, h0) = out[1], out[0]
+    assert i1["iters"] == i0["iters"]
+    assert np.array_equal(h1, h0)
+    tol = 2e-6 if storage == torch.float32 else 1e-2
+    assert np.linalg.norm(x1 - x0) <= tol * np.linalg.norm(x0)
