@@ -784,16 +784,24 @@ def main():
     tinfo = P.pcg_solve(tctx, b, x, 1e-6, args.maxit, raise_on_error=False)
     k2_us = tinfo["k2_ms"] * 1e3 / max(tinfo["k2_launches"], 1)
     k1_us = tinfo["k1_ms"] * 1e3 / max(tinfo["k1_launches"], 1)
+    # the dominant kernel: the update of even iterations (x += two steps)
+    n_even = tinfo["k2_even_launches"]
+    n_odd = tinfo["k2_launches"] - n_even
+    k2e_us = tinfo["k2_even_ms"] * 1e3 / max(n_even, 1)
+    k2o_us = (tinfo["k2_ms"] - tinfo["k2_even_ms"]) * 1e3 / max(n_odd, 1)
+    achieved = BYTES_UPDATE_PAIR * N / (k2e_us * 1e-6) / 1e9
     bytes_upd = update_bytes(tinfo["k2_launches"])
-    achieved = bytes_upd * N / (k2_us * 1e-6) / 1e9
     bytes_iter = BYTES_DIRECTION + update_bytes(iters)
-    traffic = load_traffic("pcg_update")
+    traffic = load_traffic("pcg_update_even")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "pcg_update (k_pcg_update<..., OpUpdate, FinAlpha>: finishes p.Ap, then the update)",
-                "bytes_per_launch": round(bytes_upd * N), "avg_us": round(k2_us, 2),
-                "update_bytes_per_point": {"odd (x left)": BYTES_UPDATE_SKIP, "even (x += two steps)": BYTES_UPDATE_PAIR,
-                                           "mean over the solve's launches": round(bytes_upd, 3)},
+                "kernel": "pcg_update, even iterations (k_pcg_update<..., OpUpdate<..., XM = 2>, FinAlpha>: finishes "
+                          "p.Ap, then r -= alpha A p and x += alpha_prev p_prev + alpha p)",
+                "bytes_per_launch": BYTES_UPDATE_PAIR * N, "avg_us": round(k2e_us, 2), "launches": n_even,
+                "odd_update_avg_us": round(k2o_us, 2),
+                "odd_update_GB/s": round(BYTES_UPDATE_SKIP * N / (k2o_us * 1e-6) / 1e9, 1),
+                "update_mean_bytes_per_point": round(bytes_upd, 3),
+                "update_mean_GB/s": round(bytes_upd * N / (k2_us * 1e-6) / 1e9, 1),
                 "direction_kernel_avg_us": round(k1_us, 2),
                 "direction_kernel_GB/s": round(BYTES_DIRECTION * N / (k1_us * 1e-6) / 1e9, 1),
                 # both kernels' algorithmic bytes over the timed solve's time per iteration

@@ -77,7 +77,9 @@ typedef struct {
                           reduction per iteration (Chronopoulos-Gear single-reduction
                           PCG, the same iterates in exact arithmetic; moves 48 instead of
                           40 bytes per point); -1 = default (chosen by grid size) */
-    int zchunk_update;  /* z planes per work-group of the two-kernel form's update kernel:
+    int zchunk_update;  /* z planes per work-group of the two-kernel form's update kernel
+                          when it adds to x (every second iteration with x_defer = 1; the
+                          other updates take the direction kernel's plan):
                           0 = default (twice the direction kernel's when r, p, p' and x
                           exceed the 256 MiB last-level cache and the launch keeps at least
                           256 work-groups, else the direction kernel's; the direction
@@ -106,6 +108,9 @@ typedef struct {
                                 (pcg_solve; the inner solves of pcg_solve_refined) */
     int k1_launches, k2_launches;
     int restarts;            /* pcg_solve: FP64 residual restarts taken (max_restarts) */
+    double k2_even_ms;       /* kernel_timing: the part of k2_ms spent in the updates of even
+                                iterations (those that advance x; x_defer = 1) */
+    int k2_even_launches;
 } pcg_info;
 
 /* Fill *opt with the defaults listed above. */

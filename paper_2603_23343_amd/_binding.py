@@ -44,7 +44,7 @@ class PcgInfo(ctypes.Structure):
                 ("rel_res_true_fp64", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("t_1e6", ctypes.c_double), ("t_1e10", ctypes.c_double), ("k1_ms", ctypes.c_double),
                 ("k2_ms", ctypes.c_double), ("k1_launches", ctypes.c_int), ("k2_launches", ctypes.c_int),
-                ("restarts", ctypes.c_int)]
+                ("restarts", ctypes.c_int), ("k2_even_ms", ctypes.c_double), ("k2_even_launches", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -300,29 +300,35 @@ hipError_t enqueue_iters(pcg_ctx c, int first, int count, hipStream_t s, hipEven
     SolveState* s1 = c->st + 1;
     double* pdir = c->partials;
     double* pupd = c->partials + c->partials_cap / 2;
-    const unsigned nbd = c->geo.nblocks, nbu = c->geo_upd.nblocks;
+    const unsigned nbd = c->geo.nblocks;
+    const bool defer = c->opt.x_defer && !every_x;
+    unsigned nlast = c->geo_upd.nblocks;  // partials left by the previous update
     for (int i = first; i < first + count; ++i) {
         void* pold = c->p[(i - 1) & 1];
         void* pnew = c->p[i & 1];
         if (evs) (void)hipEventRecord(evs[3 * (i - first)], s);
         const Chain dch =
-            i == first ? Chain{nullptr, nbu, s0, s0, c->hist, pdir} : Chain{pupd, nbu, s1, s0, c->hist, pdir};
+            i == first ? Chain{nullptr, nlast, s0, s0, c->hist, pdir} : Chain{pupd, nlast, s1, s0, c->hist, pdir};
         hipError_t e = launch_pcg_direction(c->dt, c->plan, c->geo, op_of(c), c->r, pold, pnew, dch, s);
         if (e != hipSuccess) return e;
         if (evs) (void)hipEventRecord(evs[3 * (i - first) + 1], s);
         const Chain uch{pdir, nbd, s0, s1, c->hist, pupd};
-        const bool defer = c->opt.x_defer && !every_x;
+        // An update that adds to x streams the most bytes and takes the
+        // update plan; one that leaves x moves what the direction kernel
+        // moves and takes its plan.
         const int xmode = defer && (i & 1) == 0 ? 2 : 1;
-        e = launch_pcg_update(c->dt, c->plan_upd, c->geo_upd, op_of(c), pnew, c->xacc, c->opt.x_accum, c->r, xmode,
-                              pold, uch, s);
+        const Plan& up = xmode == 2 ? c->plan_upd : c->plan;
+        const Geometry& ug = xmode == 2 ? c->geo_upd : c->geo;
+        e = launch_pcg_update(c->dt, up, ug, op_of(c), pnew, c->xacc, c->opt.x_accum, c->r, xmode, pold, uch, s);
         if (e != hipSuccess) return e;
+        nlast = ug.nblocks;
         if (!defer) {
             e = launch_x_finish(c->dt, c->opt.x_accum, c->n, c->xacc, pnew, s1, true, s);
             if (e != hipSuccess) return e;
         }
         if (evs) (void)hipEventRecord(evs[3 * (i - first) + 2], s);
     }
-    return launch_pcg_close(op_of(c).kc != nullptr, Chain{pupd, nbu, s1, s0, c->hist, nullptr}, s);
+    return launch_pcg_close(op_of(c).kc != nullptr, Chain{pupd, nlast, s1, s0, c->hist, nullptr}, s);
 }
 
 pcg_status ensure_chunk(pcg_ctx c) {
@@ -357,6 +363,8 @@ struct IterResult {
     SolveState fin{};
     double k1_ms = 0.0, k2_ms = 0.0;
     int nk = 0;
+    double k2e_ms = 0.0;  // the updates of even iterations (those that advance x)
+    int nke = 0;
 };
 
 // Single-reduction iterations (constant coefficients only): forced by the
@@ -501,6 +509,10 @@ pcg_status run_iterations(pcg_ctx c, const void* b, const void* x0, int x0_dt, d
     for (int i = 0; i < nwork; ++i) {
         out->k1_ms += k1_each[i];
         out->k2_ms += k2_each[i];
+        if ((i & 1) == 1) {  // iteration i + 1 is even
+            out->k2e_ms += k2_each[i];
+            ++out->nke;
+        }
     }
     out->nk = nwork;
     return PCG_OK;
@@ -765,12 +777,13 @@ pcg_status pcg_create(pcg_ctx* out, int nx, int ny, int nz, pcg_dtype storage, v
     c->plan = default_plan(nx, ny, nz, storage, o);
     c->geo = make_geometry(nx, ny, nz, c->plan, storage);
     // When an iteration's vectors (r, p twice, x) exceed the last-level
-    // cache, the update kernel (stencil, two axpys and a norm per point)
-    // streams better with twice the planes per work-group while the launch
-    // keeps at least 256 work-groups (256^3 FP32: 80.6 -> 76.7 us), while the
-    // direction kernel stays faster with the shorter chunk (36.5 against
-    // 45.6 us). With cache-resident vectors the taller chunk measured slower
-    // (192^3 FP32: 60.9 -> 62.7 us per iteration).
+    // cache, the update that adds to x (stencil, three axpys and a norm per
+    // point) streams better with twice the planes per work-group while the
+    // launch keeps at least 256 work-groups (256^3 FP32: 88.2 -> 83.6 us),
+    // while the direction kernel and the update that leaves x stay faster
+    // with the shorter chunk (36.4 against 45.6 us; 35.7 against 44.0 us).
+    // With cache-resident vectors the taller chunk measured slower (192^3
+    // FP32: 60.9 -> 62.7 us per iteration).
     c->plan_upd = c->plan;
     if (o.zchunk_update > 0) {
         c->plan_upd.zc = o.zchunk_update;
@@ -899,6 +912,8 @@ pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, 
         res.k1_ms += seg.k1_ms;
         res.k2_ms += seg.k2_ms;
         res.nk += seg.nk;
+        res.k2e_ms += seg.k2e_ms;
+        res.nke += seg.nke;
         res.fin = seg.fin;
 
         // Result to the caller's x, then the FP64 true residual of what is returned.
@@ -936,6 +951,8 @@ pcg_status pcg_solve(pcg_ctx c, const void* b, void* x, double rtol, int maxit, 
         info->k2_ms = res.k2_ms;
         info->k1_launches = res.nk;
         info->k2_launches = res.nk;
+        info->k2_even_ms = res.k2e_ms;
+        info->k2_even_launches = res.nke;
         info->restarts = restarts;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
@@ -967,7 +984,8 @@ pcg_status pcg_solve_refined(pcg_ctx c, const double* b64, double* x64, double r
     HIPCHK(launch_zero(DT_F64, c->n, x64, st));
     double nb = 0.0, t1e6 = -1.0, t1e10 = -1.0;
     int outer = 0, inner_total = 0;
-    double k1_ms = 0.0, k2_ms = 0.0;  // kernel_timing: event-timed inner iteration kernels
+    double k1_ms = 0.0, k2_ms = 0.0, k2e_ms = 0.0;  // kernel_timing: event-timed inner iteration kernels
+    int nke = 0;
     int nk = 0;
     pcg_status ret = PCG_E_NOCONV;
     for (;;) {
@@ -1009,6 +1027,8 @@ pcg_status pcg_solve_refined(pcg_ctx c, const double* b64, double* x64, double r
         k1_ms += res.k1_ms;
         k2_ms += res.k2_ms;
         nk += res.nk;
+        k2e_ms += res.k2e_ms;
+        nke += res.nke;
         HIPCHK(launch_correct(xacc_dt, c->n, c->xacc, scale, x64, st));
         ++outer;
     }
@@ -1024,6 +1044,8 @@ pcg_status pcg_solve_refined(pcg_ctx c, const double* b64, double* x64, double r
         info->t_1e10 = t1e10;
         info->k1_ms = k1_ms;
         info->k2_ms = k2_ms;
+        info->k2_even_ms = k2e_ms;
+        info->k2_even_launches = nke;
         info->k1_launches = nk;
         info->k2_launches = nk;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
