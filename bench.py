@@ -68,11 +68,10 @@ HBM_PEAK_GBS = 8000.0
 # storage, FP64 x accumulator): direction reads r, p_old and writes p. The
 # update advances x every second iteration: an odd iteration's update reads
 # p, r and writes r (12); the next reads p, p_prev, r, x(FP64) and writes r,
-# x(FP64) (32). The batched kernel advances x in every update (28).
+# x(FP64) (32). The batched kernel does the same.
 BYTES_DIRECTION = 12
 BYTES_UPDATE_SKIP = 12
 BYTES_UPDATE_PAIR = 32
-BYTES_UPDATE_X = 28
 
 
 def update_bytes(launches: int, es: int = 4, xs: int = 8) -> float:
@@ -543,7 +542,8 @@ def bench_batched(P, torch, reps, oracle_budget_s=0.0):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / reps
     lat = sorted(r["latency_s"])
-    traffic = sum(float(BYTES_DIRECTION + BYTES_UPDATE_X) * m ** 3 * it for m, it in zip(sizes, r["iters"]))
+    # the batched kernel also advances x every second update (12 or 32 B/pt)
+    traffic = sum((BYTES_DIRECTION + update_bytes(it)) * it * m ** 3 for m, it in zip(sizes, r["iters"]))
     # the same 64 problems one after another through pcg_solve
     ctxs = []
     for i, m in enumerate(sizes):

@@ -151,10 +151,13 @@ __device__ __forceinline__ float march(const BatchProb& pr, unsigned t, LF&& mkl
 // FP64 true residual of the group's problem over a contiguous range of
 // points per work-group: r = fl32(b - A x) (the restart residual), and the
 // work-group's sums of (b - A x)^2 and of the stored r^2. b is in the
-// caller's layout, x and r in the row-padded one.
+// caller's layout, x and r in the row-padded one. With po, x still owes the
+// step a_owed po (x advances every second iteration): the residual is that
+// of x + a_owed po, formed on the fly exactly as the step will be stored.
 __device__ __forceinline__ void true_residual(const BatchProb& pr, const float* __restrict__ b,
-                                              const double* __restrict__ x, float* __restrict__ r, int rank, int G,
-                                              double& rrt, double& rrs) {
+                                              const double* __restrict__ x, const float* __restrict__ po,
+                                              double a_owed, float* __restrict__ r, int rank, int G, double& rrt,
+                                              double& rrs) {
     const unsigned nx = pr.nx, ny = pr.ny, nz = pr.nz, n = nx * ny * nz, sy = pr.pitch, sz = sy * ny;
     const unsigned per = (n + G - 1) / G, lo = (unsigned)rank * per, hi = min(lo + per, n);
     rrt = 0.0;
@@ -162,13 +165,14 @@ __device__ __forceinline__ void true_residual(const BatchProb& pr, const float* 
     for (unsigned i = lo + threadIdx.x; i < hi; i += BT) {
         const unsigned ix = i % nx, row = i / nx, iy = row % ny, iz = row / ny;
         const unsigned j = row * sy + ix;
-        double ax = 6.0 * x[j];
-        if (ix > 0) ax -= x[j - 1];
-        if (ix + 1 < nx) ax -= x[j + 1];
-        if (iy > 0) ax -= x[j - sy];
-        if (iy + 1 < ny) ax -= x[j + sy];
-        if (iz > 0) ax -= x[j - sz];
-        if (iz + 1 < nz) ax -= x[j + sz];
+        auto xe = [&](unsigned k) { return po ? x[k] + a_owed * (double)po[k] : x[k]; };
+        double ax = 6.0 * xe(j);
+        if (ix > 0) ax -= xe(j - 1);
+        if (ix + 1 < nx) ax -= xe(j + 1);
+        if (iy > 0) ax -= xe(j - sy);
+        if (iy + 1 < ny) ax -= xe(j + sy);
+        if (iz > 0) ax -= xe(j - sz);
+        if (iz + 1 < nz) ax -= xe(j + sz);
         const double res = (double)b[i] - ax;
         const float rf = (float)res;
         r[j] = rf;
@@ -192,7 +196,7 @@ __device__ __forceinline__ void put_partials(double (&v)[NC], double* part, int 
 // direction phase uses A, the update phase B, the start and the FP64
 // residual steps C: a buffer is rewritten only after a barrier that every
 // reader of its previous contents has passed.
-__global__ void __launch_bounds__(BT) k_batch_pcg(const BatchProb* __restrict__ probs, const int2* __restrict__ wgmap,
+__global__ void __launch_bounds__(BT, 3) k_batch_pcg(const BatchProb* __restrict__ probs, const int2* __restrict__ wgmap,
                                                    const float* __restrict__ b, double* __restrict__ x, float* r,
                                                    float* p0, float* p1, double* xacc, double* partials, int maxg,
                                                    int part_stride, unsigned* bar,
@@ -247,6 +251,24 @@ __global__ void __launch_bounds__(BT) k_batch_pcg(const BatchProb* __restrict__ 
     const double tol2 = rtol2 * bb;
     double rho = bb / 6.0, beta = 0.0, rr = bb, rrt = bb;
     int it = 0, restarts = 0, done = 0, io = 0;
+    // x advances every second update: after one that left it, x owes
+    // alpha_owed p (p still in its buffer), added by the next update
+    // together with that update's own step, or at a stop of the recursion.
+    bool x_owed = false;
+    float alpha_owed = 0.f;
+    // Store the owed step on this work-group's points (the true residual's
+    // range, the same threads as the copy to the caller's layout below).
+    auto settle_x = [&]() {
+        if (!x_owed) return;
+        const unsigned nx = pr.nx, n = nx * pr.ny * pr.nz;
+        const unsigned per = (n + G - 1) / G, lo = (unsigned)rank * per, hi = min(lo + per, n);
+        const float* po = pp[io];
+        for (unsigned i = lo + threadIdx.x; i < hi; i += BT) {
+            const unsigned j = (i / nx) * pr.pitch + i % nx;
+            xp[j] = xp[j] + (double)alpha_owed * (double)po[j];
+        }
+        x_owed = false;
+    };
     if (!isfinite(bb)) done = 2;
     else if (bb == 0.0) done = 1;
     while (!done) {
@@ -274,18 +296,41 @@ __global__ void __launch_bounds__(BT) k_batch_pcg(const BatchProb* __restrict__ 
             break;
         }
         const float alpha = (float)(rho / sigma);
-        // Phase 2: update and r.r.
+        // Phase 2: update and r.r; x takes two steps every second update.
         acc = 0.f;
-        for (int t = rank; t < pr.ntiles; t += G) {
-            acc += march(
-                pr, (unsigned)t,
-                [&]() {
-                    LoadField<float> l{pnew};
-                    return l;
-                },
-                [&]<int VX>() { return OpUpdate<float, double, VX>{xp, rp, nullptr, nullptr, alpha, (double)alpha}; },
-                lds);
+        if (x_owed) {
+            for (int t = rank; t < pr.ntiles; t += G) {
+                acc += march(
+                    pr, (unsigned)t,
+                    [&]() {
+                        LoadField<float> l{pnew};
+                        return l;
+                    },
+                    [&]<int VX>() {
+                        OpUpdate<float, double, VX, false, false, 2> o{xp, rp, nullptr, nullptr, alpha, (double)alpha};
+                        o.pprev = pold;
+                        o.alpha_prev_d = (double)alpha_owed;
+                        return o;
+                    },
+                    lds);
+            }
+        } else {
+            for (int t = rank; t < pr.ntiles; t += G) {
+                acc += march(
+                    pr, (unsigned)t,
+                    [&]() {
+                        LoadField<float> l{pnew};
+                        return l;
+                    },
+                    [&]<int VX>() {
+                        return OpUpdate<float, double, VX, false, false, 1>{xp, rp, nullptr, nullptr, alpha,
+                                                                            (double)alpha};
+                    },
+                    lds);
+            }
         }
+        x_owed = !x_owed;
+        alpha_owed = alpha;
         {
             double v[1] = {(double)acc};
             put_partials<1>(v, partB, maxg, rank, rs);
@@ -308,12 +353,15 @@ __global__ void __launch_bounds__(BT) k_batch_pcg(const BatchProb* __restrict__ 
         // if it is above the tolerance, restart from x with r = b - A x.
         {
             double v[2];
-            true_residual(pr, bp, xp, rp, rank, G, v[0], v[1]);
+            true_residual(pr, bp, xp, x_owed ? pp[io] : nullptr, (double)alpha_owed, rp, rank, G, v[0], v[1]);
             put_partials<2>(v, partC, maxg, rank, rs);
         }
         if (!group_barrier(cnt, gen, G, my_gen, err, xl)) return;
         rrt = group_sum(partC, G, rs);
         const double rrs = group_sum(partC + maxg, G, rs);
+        // every member has read x past the barrier; the next reads of
+        // other work-groups' points come after later barriers
+        settle_x();
         if (rrt <= tol2 || rr > tol2 || restarts >= max_restarts || it >= maxit) {
             done = rr <= tol2 ? 1 : 3;
             break;
@@ -323,6 +371,8 @@ __global__ void __launch_bounds__(BT) k_batch_pcg(const BatchProb* __restrict__ 
         rho = rrs / 6.0;
         beta = 0.0;
     }
+    // a stop on a breakdown can still owe a step
+    settle_x();
     // x to the caller's layout (the last update phase is behind a barrier).
     {
         const unsigned nx = pr.nx, n = nx * pr.ny * pr.nz;
