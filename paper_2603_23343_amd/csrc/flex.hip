@@ -9,9 +9,11 @@
 // Kernels per iteration (all skip their work once the solve state is done):
 //   direction: p = z + beta p_old on the fly for the tile and its halo,
 //              q = A p stored, sigma = p.q and p.r -> alpha;
-//   update:    x += alpha p, r -= alpha q, ||r||^2 -> convergence, and the
+//   update:    r -= alpha q, ||r||^2 -> convergence, and the
 //              stagnation test that switches to Jacobi (per-work-group
-//              partials, finished by a one-work-group kernel);
+//              partials, finished by a one-work-group kernel); x advances
+//              every second iteration (x += alpha_prev p_old + alpha p; the
+//              solver adds a step still owed when it stops);
 //   M:         the network's correction (cnn_forward, scaled by rms(r)
 //              from the state) or nothing when Jacobi is selected;
 //   select:    z = D^-1 r, plus the correction while the network is in use
@@ -107,6 +109,7 @@ struct FinFlexAlpha {
             st->done = 2;
             return;
         }
+        st->alpha_prev = st->alpha;
         st->alpha = pr / sigma;
     }
 };
@@ -148,21 +151,27 @@ struct FinFlexRes {
 
 constexpr int NT = STREAM_THREADS;
 
-// x += alpha p; r = stored(r - alpha q); ||r||^2.
+// r = stored(r - alpha q); ||r||^2. x advances every second iteration: the
+// update of an odd iteration leaves it (and reads no p), that of an even one
+// adds alpha_prev p_old + alpha p, the two FP64 steps one per iteration
+// would take (the state counts the iterations before this one).
 template <typename T>
-__global__ void __launch_bounds__(NT) k_flex_update(int64_t n, const T* __restrict__ p, const T* __restrict__ q,
-                                                    T* __restrict__ r, double* __restrict__ x, SolveState* st,
-                                                    double* hist, Red red) {
+__global__ void __launch_bounds__(NT) k_flex_update(int64_t n, const T* __restrict__ p, const T* __restrict__ pold,
+                                                    const T* __restrict__ q, T* __restrict__ r,
+                                                    double* __restrict__ x, SolveState* st, double* hist, Red red) {
     if (st->done) return;
     __shared__ double scratch[16];
     using C = typename Traits<T>::C;
     const C a = (C)st->alpha;
-    const double ad = (double)a;
+    const double ad = (double)a, apd = (double)(C)st->alpha_prev;
+    const bool xstep = ((st->iters + 1) & 1) == 0;
     const int64_t stride = (int64_t)gridDim.x * NT;
     C acc = C(0);
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
-        const C pv = to_c(p[i]);
-        x[i] += ad * (double)pv;
+        if (xstep) {
+            const double t = x[i] + apd * (double)to_c(pold[i]);
+            x[i] = t + ad * (double)to_c(p[i]);
+        }
         const C rv = stored<T>(to_c(r[i]) - a * to_c(q[i]));
         r[i] = from_c<T>(rv);
         acc += rv * rv;
@@ -250,11 +259,11 @@ hipError_t launch_flex_direction(const Plan& p, const Geometry& g, OpDesc od, co
     });
 }
 
-hipError_t launch_flex_update(int64_t n, const float* p, const float* q, float* r, double* x, SolveState* st,
-                              double* hist, Red red, hipStream_t s) {
+hipError_t launch_flex_update(int64_t n, const float* p, const float* pold, const float* q, float* r, double* x,
+                              SolveState* st, double* hist, Red red, hipStream_t s) {
     const unsigned nb = nblk(n);
     if ((size_t)nb > red.cap) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_flex_update<float>, dim3(nb), dim3(NT), 0, s, n, p, q, r, x, st, hist, red);
+    hipLaunchKernelGGL(k_flex_update<float>, dim3(nb), dim3(NT), 0, s, n, p, pold, q, r, x, st, hist, red);
     hipLaunchKernelGGL((k_flex_finish<1, FinFlexRes>), dim3(1), dim3(NT), 0, s, red.partials, nb, FinFlexRes{st, hist},
                        st, 0);
     return hipGetLastError();

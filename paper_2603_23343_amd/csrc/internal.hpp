@@ -149,8 +149,8 @@ hipError_t launch_convert(int sdt, int ddt, int64_t n, const void* src, void* ds
 // flexible CG (FP32 storage)
 hipError_t launch_flex_direction(const Plan& p, const Geometry& g, OpDesc od, const float* z, const float* pold,
                                  float* pnew, float* q, const float* r, SolveState* st, Red red, hipStream_t s);
-hipError_t launch_flex_update(int64_t n, const float* p, const float* q, float* r, double* x, SolveState* st,
-                              double* hist, Red red, hipStream_t s);
+hipError_t launch_flex_update(int64_t n, const float* p, const float* pold, const float* q, float* r, double* x,
+                              SolveState* st, double* hist, Red red, hipStream_t s);
 hipError_t launch_flex_select(int64_t n, float* z, const float* r, const float* q, const float* dinv, SolveState* st,
                               bool redo_pass, Red red, hipStream_t s);
 // geometric multigrid V-cycle (FP32): levels finest first; level l solves the

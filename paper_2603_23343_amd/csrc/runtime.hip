@@ -1150,8 +1150,8 @@ static pcg_status flex_solve(pcg_ctx c, cnn_net net, bool mg, const float* g, co
             void* pnew = c->p[k & 1];
             HIPCHK(launch_flex_direction(c->plan, c->geo, od, z, static_cast<const float*>(pold),
                                          static_cast<float*>(pnew), q, r, c->st, red_of(c), sq));
-            HIPCHK(launch_flex_update(c->n, static_cast<const float*>(pnew), q, r, xacc, c->st, c->hist, red_of(c),
-                                      sq));
+            HIPCHK(launch_flex_update(c->n, static_cast<const float*>(pnew), static_cast<const float*>(pold), q, r,
+                                      xacc, c->st, c->hist, red_of(c), sq));
             if (use_net) {
                 pcg_status ps = cnn_forward(net, c->nx, c->ny, c->nz, PCG_F32, r, g, &c->st->rr, z);
                 if (ps != PCG_OK) return ps;
@@ -1237,6 +1237,12 @@ static pcg_status flex_solve(pcg_ctx c, cnn_net net, bool mg, const float* g, co
         }
         HIPCHK(hipStreamSynchronize(st));
         HIPCHK(hipMemcpy(&fin, c->st, sizeof(SolveState), hipMemcpyDeviceToHost));
+        // x advances every second iteration: after an odd count it still
+        // owes the last step (direction in p[1], alpha in the state)
+        if (fin.iters & 1) {
+            HIPCHK(launch_x_finish(DT_F32, DT_F64, c->n, xacc, c->p[1], c->st, false, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
         return PCG_OK;
     };
     auto true_residual = [&](double* rel) -> pcg_status {
