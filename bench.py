@@ -213,8 +213,9 @@ def bench_sell(P, torch, reps, grids=((256, 256, 256), None), b256=None, mf_solv
                          "frac": round(gbs / HBM_PEAK_GBS, 4)}
         if b256 is not None and (nx, ny, nz) == (256, 256, 256):
             # Jacobi-PCG on the stored matrix, the benchmark's b; per
-            # iteration 8 B per entry + 60 B per row (q = A p: x and q 8;
-            # update: p, q, r, r', D^-1 20 and x 16; direction: r, D^-1, p, p' 16).
+            # iteration 8 B per entry + 52 B per row on average (q = A p: x
+            # and q 8; update: q, r, r', D^-1 16, and every second one also
+            # p, p_prev 8 and x 16; direction: r, D^-1, p_old, p 16).
             xs = torch.zeros(N, dtype=torch.float64, device="cuda")
             P.pcg_sell_solve(A, b256, xs, 1e-6, 5000, raise_on_error=False)
             torch.cuda.synchronize()
@@ -223,7 +224,7 @@ def bench_sell(P, torch, reps, grids=((256, 256, 256), None), b256=None, mf_solv
             torch.cuda.synchronize()
             s = time.perf_counter() - t0
             it = max(info["iters"], 1)
-            per_it = 8 * A.nnz + 60 * N
+            per_it = 8 * A.nnz + 52 * N
             res["pcg_solve"] = {"iters": info["iters"], "restarts": info["restarts"], "ms": round(s * 1e3, 2),
                                 "status": P.STATUS_NAMES[info["status"]],
                                 "us_per_iteration": round(s * 1e6 / it, 1),

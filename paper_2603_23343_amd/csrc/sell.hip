@@ -50,8 +50,12 @@ struct SellState {
     int iters;       // A p products
     int done;        // 0 running, 1 converged, 2 breakdown, 3 maxit reached
     int maxit;
-    int pad;
+    int x_owed;      // x still lacks the last update's alpha p (x advances every second update)
+    double alpha_prev;  // alpha of the update before
 };
+// The direction of iteration k (k = iters + 1 while it is formed and used
+// by the product, k = iters in the update and the next direction) lives in
+// buffer k % 2 of the two p buffers.
 
 }  // namespace
 
@@ -63,7 +67,7 @@ struct pcg_sell_s {
     int32_t* perm = nullptr;       // device, nrows (null when sigma = 1)
     hipStream_t stream = nullptr;
     // solver workspace (allocated by the first pcg_sell_solve)
-    float *r = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
+    float *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr, *dinv = nullptr;
     double* part = nullptr;
     SellState* st = nullptr;
     int* bad = nullptr;
@@ -264,11 +268,15 @@ __global__ void __launch_bounds__(SELL_C * SELL_WAVES)
 }
 
 // Start of a segment: zero = 1: r = b, x = 0; zero = 0: r holds the restart
-// residual. p = D^-1 r; partials {r.z, r.r}.
+// residual. p = D^-1 r (the next iteration's direction buffer); partials
+// {r.z, r.r}.
 __global__ void __launch_bounds__(SNT) k_sell_start(int64_t n, const float* __restrict__ b, float* __restrict__ r,
                                                     double* __restrict__ x, const float* __restrict__ dinv,
-                                                    float* __restrict__ p, double* __restrict__ part, int zero) {
+                                                    float* __restrict__ p0, float* __restrict__ p1,
+                                                    const SellState* __restrict__ st, double* __restrict__ part,
+                                                    int zero) {
     __shared__ double scratch[32];
+    float* __restrict__ p = (zero ? 1 : st->iters + 1) & 1 ? p1 : p0;
     int64_t lo, hi;
     unsigned bl;
     block_range(n, lo, hi, bl);
@@ -300,11 +308,12 @@ __global__ void __launch_bounds__(SNT) k_sell_start(int64_t n, const float* __re
 template <bool PERM, bool R64>
 __global__ void __launch_bounds__(SELL_C * SELL_WAVES)
     k_sell_q(int64_t nrows, int64_t nchunks, const int64_t* __restrict__ chunk_ptr, const int32_t* __restrict__ col,
-             const float* __restrict__ val, const int32_t* __restrict__ perm, const float* __restrict__ p,
-             float* __restrict__ q, const float* __restrict__ b, const double* __restrict__ x,
-             double* __restrict__ part, const SellState* __restrict__ st) {
+             const float* __restrict__ val, const int32_t* __restrict__ perm, const float* __restrict__ p0,
+             const float* __restrict__ p1, float* __restrict__ q, const float* __restrict__ b,
+             const double* __restrict__ x, double* __restrict__ part, const SellState* __restrict__ st) {
     __shared__ double scratch[32];
     if (!R64 && st->done) return;
+    const float* __restrict__ p = (st->iters + 1) & 1 ? p1 : p0;
     int64_t lo, hi;
     unsigned bl;
     block_range(nchunks, lo, hi, bl);
@@ -355,25 +364,34 @@ __global__ void __launch_bounds__(SELL_C * SELL_WAVES)
     }
 }
 
-// x += alpha p, r -= alpha q; partials {r.r, r.z}.
-__global__ void __launch_bounds__(SNT) k_sell_update(int64_t n, const float* __restrict__ p, const float* __restrict__ q,
+// r -= alpha q; partials {r.r, r.z}. x advances every second update: one
+// that finds x_owed clear leaves x (the finisher then sets it), the next
+// adds alpha_prev p_prev + alpha p, the two FP64 steps one per update would
+// take.
+__global__ void __launch_bounds__(SNT) k_sell_update(int64_t n, const float* __restrict__ p0,
+                                                     const float* __restrict__ p1, const float* __restrict__ q,
                                                      float* __restrict__ r, double* __restrict__ x,
                                                      const float* __restrict__ dinv, double* __restrict__ part,
                                                      const SellState* __restrict__ st) {
     __shared__ double scratch[32];
     if (st->done) return;
-    const double alpha = st->alpha;
+    const double alpha = st->alpha, alpha_prev = st->alpha_prev;
     const float af = (float)alpha;
+    const bool xstep = st->x_owed != 0;
+    const float* __restrict__ p = st->iters & 1 ? p1 : p0;
+    const float* __restrict__ pprev = st->iters & 1 ? p0 : p1;
     int64_t lo, hi;
     unsigned bl;
     block_range(n, lo, hi, bl);
     double v[2] = {0.0, 0.0};
 #pragma unroll 4
     for (int64_t i = lo + threadIdx.x; i < hi; i += SNT) {
-        const float pi = p[i];
-        // x is touched once per iteration: non-temporal, leaving the caches
-        // to r, p, q and D^-1, which the next kernels read again
-        __builtin_nontemporal_store(__builtin_nontemporal_load(x + i) + alpha * (double)pi, x + i);
+        // x is touched once per two iterations: non-temporal, leaving the
+        // caches to r, p, q and D^-1, which the next kernels read again
+        if (xstep) {
+            const double t = __builtin_nontemporal_load(x + i) + alpha_prev * (double)pprev[i];
+            __builtin_nontemporal_store(t + alpha * (double)p[i], x + i);
+        }
         const float ri = __builtin_fmaf(-af, q[i], r[i]);
         r[i] = ri;
         const float z = dinv[i] * ri;
@@ -389,15 +407,30 @@ __global__ void __launch_bounds__(SNT) k_sell_update(int64_t n, const float* __r
 
 // p = D^-1 r + beta p.
 __global__ void __launch_bounds__(SNT) k_sell_direction(int64_t n, const float* __restrict__ r,
-                                                        const float* __restrict__ dinv, float* __restrict__ p,
-                                                        const SellState* __restrict__ st) {
+                                                        const float* __restrict__ dinv, float* __restrict__ p0,
+                                                        float* __restrict__ p1, const SellState* __restrict__ st) {
     if (st->done) return;
     const float beta = (float)st->beta;
+    const float* __restrict__ pold = st->iters & 1 ? p1 : p0;
+    float* __restrict__ pnew = st->iters & 1 ? p0 : p1;
     int64_t lo, hi;
     unsigned bl;
     block_range(n, lo, hi, bl);
 #pragma unroll 4
-    for (int64_t i = lo + threadIdx.x; i < hi; i += SNT) p[i] = __builtin_fmaf(beta, p[i], dinv[i] * r[i]);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += SNT) pnew[i] = __builtin_fmaf(beta, pold[i], dinv[i] * r[i]);
+}
+
+// The step a stopped solve still owes x (x_owed): x += alpha p of the last
+// update (its direction in buffer iters % 2).
+__global__ void __launch_bounds__(SNT) k_sell_settle(int64_t n, double* __restrict__ x, const float* __restrict__ p0,
+                                                     const float* __restrict__ p1, const SellState* __restrict__ st) {
+    if (!st->x_owed) return;
+    const double alpha = st->alpha;
+    const float* __restrict__ p = st->iters & 1 ? p1 : p0;
+    int64_t lo, hi;
+    unsigned bl;
+    block_range(n, lo, hi, bl);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += SNT) x[i] = x[i] + alpha * (double)p[i];
 }
 
 // One work-group: sums nparts partial pairs in index order and advances the
@@ -418,6 +451,7 @@ __global__ void __launch_bounds__(NT) k_sell_finish(const double* __restrict__ p
     if (MODE == FIN_START) {
         s.rho = v[0];
         s.rr = v[1];
+        s.x_owed = 0;  // x is complete at a segment start
         if (zero) {
             s.bb = v[1];
             s.tol2 = rtol * rtol * v[1];
@@ -430,10 +464,12 @@ __global__ void __launch_bounds__(NT) k_sell_finish(const double* __restrict__ p
         if (!(v[0] > 0.0) || !__builtin_isfinite(v[0])) {
             s.done = 2;
         } else {
+            s.alpha_prev = s.alpha;
             s.alpha = s.rho / v[0];
             s.iters += 1;
         }
     } else if (MODE == FIN_BETA) {
+        s.x_owed ^= 1;  // the update ran: it left x or added the owed step and its own
         s.rr = v[0];
         if (!__builtin_isfinite(v[0])) {
             s.done = 2;
@@ -551,6 +587,7 @@ pcg_status pcg_sell_destroy(pcg_sell A) {
     (void)hipFree(A->perm);
     (void)hipFree(A->r);
     (void)hipFree(A->p);
+    (void)hipFree(A->p2);
     (void)hipFree(A->q);
     (void)hipFree(A->dinv);
     (void)hipFree(A->part);
@@ -640,6 +677,7 @@ static pcg_status sell_prepare(pcg_sell A) {
         const size_t nparts = 2 * (size_t)std::max(stream_grid(A->nrows), chunk_grid(A->nchunks));
         hipError_t e = hipMalloc((void**)&A->r, n * 4);
         if (e == hipSuccess) e = hipMalloc((void**)&A->p, n * 4);
+        if (e == hipSuccess) e = hipMalloc((void**)&A->p2, n * 4);
         if (e == hipSuccess) e = hipMalloc((void**)&A->q, n * 4);
         if (e == hipSuccess) e = hipMalloc((void**)&A->dinv, n * 4);
         if (e == hipSuccess) e = hipMalloc((void**)&A->part, nparts * sizeof(double));
@@ -692,12 +730,13 @@ pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, in
     const dim3 bs(SNT), bq(SELL_C * SELL_WAVES);
     auto q_kernel = [&](bool r64, hipStream_t qs) {
         const float* pp = A->p;
+        const float* pp2 = A->p2;
         if (A->perm) {
-            if (r64) hipLaunchKernelGGL((k_sell_q<true, true>), dim3(gq), bq, 0, qs, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->r, b, x, A->part, A->st);
-            else hipLaunchKernelGGL((k_sell_q<true, false>), dim3(gq), bq, 0, qs, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->q, b, x, A->part, A->st);
+            if (r64) hipLaunchKernelGGL((k_sell_q<true, true>), dim3(gq), bq, 0, qs, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, pp2, A->r, b, x, A->part, A->st);
+            else hipLaunchKernelGGL((k_sell_q<true, false>), dim3(gq), bq, 0, qs, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, pp2, A->q, b, x, A->part, A->st);
         } else {
-            if (r64) hipLaunchKernelGGL((k_sell_q<false, true>), dim3(gq), bq, 0, qs, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->r, b, x, A->part, A->st);
-            else hipLaunchKernelGGL((k_sell_q<false, false>), dim3(gq), bq, 0, qs, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, A->q, b, x, A->part, A->st);
+            if (r64) hipLaunchKernelGGL((k_sell_q<false, true>), dim3(gq), bq, 0, qs, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, pp2, A->r, b, x, A->part, A->st);
+            else hipLaunchKernelGGL((k_sell_q<false, false>), dim3(gq), bq, 0, qs, n, A->nchunks, A->chunk_ptr, A->col, A->val, A->perm, pp, pp2, A->q, b, x, A->part, A->st);
         }
     };
     SellState hs{};
@@ -719,9 +758,10 @@ pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, in
         for (int it = 0; it < k; ++it) {
             q_kernel(false, es);
             launch_finish<FIN_ALPHA>(es, A->part, gq, A->st, 0, 0.0, 0);
-            hipLaunchKernelGGL(k_sell_update, dim3(gs), bs, 0, es, n, A->p, A->q, A->r, x, A->dinv, A->part, A->st);
+            hipLaunchKernelGGL(k_sell_update, dim3(gs), bs, 0, es, n, A->p, A->p2, A->q, A->r, x, A->dinv, A->part,
+                               A->st);
             launch_finish<FIN_BETA>(es, A->part, gs, A->st, 0, 0.0, 0);
-            hipLaunchKernelGGL(k_sell_direction, dim3(gs), bs, 0, es, n, A->r, A->dinv, A->p, A->st);
+            hipLaunchKernelGGL(k_sell_direction, dim3(gs), bs, 0, es, n, A->r, A->dinv, A->p, A->p2, A->st);
         }
         return hipGetLastError();
     };
@@ -755,7 +795,8 @@ pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, in
     int restarts = 0;
     double rel_true = 0.0;
     for (int zero = 1;; zero = 0) {
-        hipLaunchKernelGGL(k_sell_start, dim3(gs), bs, 0, s, n, b, A->r, x, A->dinv, A->p, A->part, zero);
+        hipLaunchKernelGGL(k_sell_start, dim3(gs), bs, 0, s, n, b, A->r, x, A->dinv, A->p, A->p2, A->st, A->part,
+                           zero);
         launch_finish<FIN_START>(s, A->part, gs, A->st, zero, rtol, maxit);
         SCHK(read_state());
         while (!hs.done && hs.iters < maxit) {
@@ -768,7 +809,9 @@ pcg_status pcg_sell_solve(pcg_sell A, const float* b, double* x, double rtol, in
             }
             SCHK(read_state());
         }
-        // FP64 true residual; r = fl32(b - A x) is the restart residual.
+        // x takes the step it still owes, then the FP64 true residual; r =
+        // fl32(b - A x) is the restart residual.
+        hipLaunchKernelGGL(k_sell_settle, dim3(gs), bs, 0, s, n, x, A->p, A->p2, A->st);
         q_kernel(true, s);
         launch_finish<FIN_TRUE>(s, A->part, gq, A->st, 0, rtol, maxit);
         SCHK(read_state());
